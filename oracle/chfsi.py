@@ -1,0 +1,116 @@
+"""Chebyshev filtered subspace iteration with locking, and the warm-started sequence (oracle).
+
+Algorithm 3 (Section 3.2), taken step by step:
+  repeat
+    filter the active block:                 V0 <- C_m(V0)                (Algorithm 1)
+    orthonormalise [locked | V0] by Householder QR
+    Rayleigh quotient on the active part:    G = Q_a^T A Q_a
+    solve G W = W Theta, rotate:             V0 <- Q_a W
+    lock converged pairs
+  until the number of locked pairs >= L
+Warm start (Section 3.2, Fig. 2 g): the block and the Ritz values come from the previous
+problem of the sorted sequence; the first problem starts from a random block.
+
+Readings (ambiguous or silent passages):
+* the damped interval is [alpha, beta] with alpha the largest current Ritz value of the block
+  and beta an upper bound of the spectrum; lambda is the smallest current Ritz value
+  (Section 2.2 places the *other* eigenvalues in [alpha, beta]); c = (alpha+beta)/2,
+  e = (beta-alpha)/2;
+* a cold start first runs one QR + Rayleigh-Ritz on the random block to obtain Ritz values;
+* G is formed on the active columns only, and the rotated Ritz vectors replace V0;
+* convergence uses the relative residual ||A v - theta v|| / ||A v|| (App. C.6 error metric);
+  the longest converged ascending prefix of the active Ritz pairs is locked;
+* all k final Ritz pairs (locked and active) are handed to the next problem;
+* after `max_iter` outer iterations the best pairs so far are returned, flagged unconverged.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+from .chebyshev import filter_block
+from .eig import canonical_sign
+from . import lanczos
+
+
+@dataclasses.dataclass
+class Result:
+    evals: np.ndarray            # (L,) ascending
+    evecs: np.ndarray            # (n, L), canonical sign
+    X_next: np.ndarray           # (n, k) all Ritz vectors (locked first)
+    theta_next: np.ndarray       # (k,)
+    iterations: int
+    converged: bool
+    filter_matvecs: int          # number of single-vector products inside the filter
+    beta: float
+
+
+def _gaussian(n: int, k: int, seed: int) -> np.ndarray:
+    return np.random.Generator(np.random.PCG64(seed)).standard_normal((n, k))
+
+
+def chfsi(A, L: int, k: int, m: int, tol: float, X0=None, theta0=None, beta=None,
+          seed: int = 0, max_iter: int = 200, lanczos_steps: int = 20) -> Result:
+    n = A.shape[0]
+    if not (0 < L < k <= n):
+        raise ValueError("need 0 < L < k <= n")
+    if beta is None:
+        beta = lanczos.upper_bound(A, lanczos_steps, seed=seed + 1)
+    if X0 is None:
+        Q, _ = np.linalg.qr(_gaussian(n, k, seed))
+        G = Q.T @ (A @ Q)
+        theta, Z = np.linalg.eigh(0.5 * (G + G.T))
+        X = Q @ Z
+    else:
+        X = np.array(X0, dtype=np.float64, copy=True)
+        theta = np.array(theta0, dtype=np.float64, copy=True)
+
+    Vl = np.zeros((n, 0))
+    thl = np.zeros(0)
+    matvecs = 0
+    it = 0
+    while it < max_iter and thl.size < L:
+        it += 1
+        lam = thl[0] if thl.size else theta[0]
+        alpha = theta[-1]
+        c, e = 0.5 * (alpha + beta), 0.5 * (beta - alpha)
+        Y = filter_block(A, X, m, lam, c, e)
+        matvecs += m * X.shape[1]
+        Q, _ = np.linalg.qr(np.hstack([Vl, Y]))
+        Qa = Q[:, Vl.shape[1]:]
+        AQ = A @ Qa
+        G = Qa.T @ AQ
+        theta, Z = np.linalg.eigh(0.5 * (G + G.T))
+        X = Qa @ Z
+        W = AQ @ Z
+        res = np.linalg.norm(W - X * theta, axis=0) / np.linalg.norm(W, axis=0)
+        j = 0
+        while j < theta.size and res[j] <= tol:
+            j += 1
+        Vl = np.hstack([Vl, X[:, :j]])
+        thl = np.concatenate([thl, theta[:j]])
+        X, theta = X[:, j:], theta[j:]
+
+    allV = np.hstack([Vl, X])
+    allth = np.concatenate([thl, theta])
+    order = np.argsort(allth[:L], kind="stable")
+    return Result(evals=allth[:L][order], evecs=canonical_sign(allV[:, :L][:, order]),
+                  X_next=allV, theta_next=allth, iterations=it, converged=thl.size >= L,
+                  filter_matvecs=matvecs, beta=float(beta))
+
+
+def scsf_sequence(mats, L: int, k: int, m: int, tol: float, order=None, warm: bool = True,
+                  seed: int = 0, max_iter: int = 200):
+    """Solve the matrices in `order`, each warm-started from the previous one (Algorithm 3)."""
+    order = list(range(len(mats))) if order is None else list(order)
+    out = {}
+    prev = None
+    for i in order:
+        if warm and prev is not None:
+            r = chfsi(mats[i], L, k, m, tol, X0=prev.X_next, theta0=prev.theta_next,
+                      seed=seed, max_iter=max_iter)
+        else:
+            r = chfsi(mats[i], L, k, m, tol, seed=seed, max_iter=max_iter)
+        out[i] = r
+        prev = r
+    return out

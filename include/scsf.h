@@ -1,0 +1,193 @@
+/*
+ * scsf.h -- C ABI of the MI355X (gfx950) SCSF hot-path library, libscsf.so.
+ *
+ * SCSF (arXiv 2510.23215) generates eigenvalue datasets: it orders a sequence of sparse
+ * symmetric operators A^(i) by a truncated-FFT greedy sort (Algorithm 2) and solves each for
+ * its L smallest eigenpairs (eq. eq_basic, Section 2.1) with Chebyshev filtered subspace
+ * iteration (Algorithm 3), warm-started from the previous operator's eigenpairs.
+ *
+ * Conventions for every entry point
+ *   - Pointers whose name ends in `_host` are host memory; every other array argument is
+ *     DEVICE memory on the handle's device.  The caller owns every buffer it passes; the
+ *     handle owns only its internal workspace (device memory it allocates and reuses).
+ *   - Blocks of vectors are column-major with leading dimension `ld` >= n (element (i, j) at
+ *     X[i + j*ld]).  Small matrices are column-major, leading dimension = their row count.
+ *   - Work is enqueued on the handle's stream.  Entry points that must read a device-side
+ *     result (lock counts, the sort order, bounds) synchronise that stream before returning.
+ *   - Every entry point returns an scsf status (0 = success, negative = error).  On an error
+ *     other than SCSF_ENOTCONV the outputs are unspecified and the handle stays usable.
+ *   - Nothing here is thread-safe per handle; use one handle per host thread.
+ */
+#ifndef SCSF_H
+#define SCSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct scsf_handle scsf_handle;
+
+enum scsf_status {
+  SCSF_OK = 0,
+  SCSF_EINVAL = -1,      /* an argument is out of range (sizes, NULL where not allowed) */
+  SCSF_ENOMEM = -2,      /* device workspace could not be allocated */
+  SCSF_ENOTCONV = -3,    /* max_iter reached; best pairs so far were written */
+  SCSF_EBREAKDOWN = -4,  /* Cholesky of a Gram matrix failed even with a shift */
+  SCSF_EHIP = -5,        /* a HIP runtime call failed */
+  SCSF_ENUMERIC = -6     /* NaN or Inf met in the iteration */
+};
+
+enum scsf_op_kind {
+  SCSF_STENCIL5 = 1,     /* conservative 5-point -div(K grad u) + v u on an nx x nx grid */
+  SCSF_STENCIL9 = 2,     /* 9-point Q1 stiffness of cell tensors / h^2 on an nx x nx grid */
+  SCSF_CSR = 3           /* general symmetric CSR matrix (both triangles stored) */
+};
+
+enum scsf_precision { SCSF_FP64 = 0, SCSF_MIXED = 1 };
+
+/*
+ * A discretised operator (Section 2.1; datasets of App. C.2).  Grid nodes are numbered
+ * row-major, p = iy*nx + ix, h = 1/(nx+1), zero Dirichlet values beyond the boundary.
+ *   STENCIL5: wx[iy*(nx+1) + f] is the coefficient of the x-face between nodes (iy, f-1) and
+ *             (iy, f) (f = 0 and f = nx are boundary faces); wy[f*nx + ix] the y-face between
+ *             (f-1, ix) and (f, ix); v[p] an optional diagonal term (NULL = 0).  The matrix is
+ *             (A u)_p = sum_faces w (u_p - u_nbr) + v_p u_p; coefficients carry 1/h^2.
+ *   STENCIL9: cell[(cy*(nx+1) + cx)*3 + {0,1,2}] = (K11, K12, K22) of cell (cy, cx), the square
+ *             between node rows cy-1, cy and columns cx-1, cx; A = Q1 stiffness / h^2.
+ *   CSR:      row_ptr[n+1], col_idx[nnz], val[nnz], symmetric.
+ * All coefficient arrays are device memory and must stay valid during the call.
+ */
+typedef struct scsf_operator {
+  int32_t kind;
+  int32_t nx;            /* grid side for the stencil kinds (n = nx*nx); 0 for CSR */
+  int64_t n;             /* matrix dimension */
+  const double *wx, *wy, *v;
+  const double *cell;
+  const int32_t *row_ptr, *col_idx;
+  const double *val;
+  int64_t nnz;
+} scsf_operator;
+
+/* Solver parameters (Algorithm 3; defaults of App. C.4: degree 20, k = L + 20% of L). */
+typedef struct scsf_params {
+  int32_t L;             /* wanted eigenpairs, 0 < L < k */
+  int32_t k;             /* block width (L + guard vectors), k <= n, k <= 256 */
+  int32_t degree;        /* Chebyshev degree m, 1..64 */
+  int32_t max_iter;      /* outer iterations before SCSF_ENOTCONV (0 -> 200) */
+  int32_t lanczos_steps; /* steps of the upper-bound Lanczos run (0 -> 20) */
+  int32_t precision;     /* scsf_precision */
+  double tol;            /* lock when ||A v - theta v|| <= tol ||A v|| (App. C.6 metric) */
+  uint64_t seed;         /* seed of the random cold-start block and Lanczos start vector */
+} scsf_params;
+
+/* Per-solve statistics (host struct). */
+typedef struct scsf_stats {
+  int32_t iterations;    /* outer iterations */
+  int32_t nconv;         /* locked pairs at exit (>= L on success) */
+  int32_t status;        /* status of this solve */
+  int32_t chol_shifts;   /* Gram matrices that needed the shifted Cholesky fallback */
+  int64_t filter_cols;   /* sum over filter calls of degree * active columns */
+  double beta;           /* upper spectral bound used by the filter */
+  double max_rel_resid;  /* max relative residual of the returned pairs */
+} scsf_stats;
+
+/* Filter-step timing: when enabled, every Chebyshev step launch of the solvers is bracketed
+ * by a pair of HIP events on the handle's stream; the elapsed times and the algorithmic bytes
+ * of those launches (read Y_i, Y_{i-1}, write Y_{i+1}, the operator coefficients once) are
+ * accumulated at the solver's existing synchronisation points. */
+typedef struct scsf_profile {
+  int64_t filter_launches;
+  double filter_ms;
+  double filter_bytes;
+} scsf_profile;
+
+/* Handle on the current HIP device, enqueueing on `hip_stream` (a hipStream_t; NULL = the
+ * null stream).  The stream must stay valid while the handle is used. */
+int scsf_create(scsf_handle **h, void *hip_stream);
+int scsf_destroy(scsf_handle *h);
+int scsf_set_stream(scsf_handle *h, void *hip_stream);
+const char *scsf_status_string(int status);
+/* Library build/version string (host). */
+const char *scsf_version(void);
+/* Turn filter-step timing on (on != 0) or off; synchronises the stream. */
+int scsf_profile_enable(scsf_handle *h, int on);
+/* Copy the accumulated filter timing to *out_host; reset != 0 clears it afterwards. */
+int scsf_profile_read(scsf_handle *h, scsf_profile *out_host, int reset);
+
+/* ---------------------------------------------------------------------------------------
+ * Step primitives of the hot path.  Each is a building block of scsf_solve, exposed so the
+ * steps can be checked one by one.
+ * ------------------------------------------------------------------------------------- */
+
+/* Y = A X for ncols columns (n x ncols blocks, leading dimensions ldx, ldy). */
+int scsf_spmm(scsf_handle *h, const scsf_operator *A, const double *X, int64_t ldx,
+              int32_t ncols, double *Y, int64_t ldy);
+
+/* Chebyshev filter, Algorithm 1 with the scaled three-term recurrence (Section 2.2):
+ * Y = C_m((A - cI)/e) X / C_m((lambda - c)/e), degree m >= 1, e > 0, lambda != c.
+ * X is not modified.  ncols <= 256. */
+int scsf_filter(scsf_handle *h, const scsf_operator *A, const double *X, int64_t ldx,
+                int32_t ncols, int32_t degree, double lambda, double c, double e,
+                double *Y, int64_t ldy);
+
+/* Orthonormalisation of Algorithm 3 (QR of [locked | active]): X (n x ncols, in place) is
+ * made orthogonal to the nlocked orthonormal columns V (twice-repeated block Gram-Schmidt),
+ * then orthonormalised by CholeskyQR2 (shifted CholeskyQR3 if the Gram matrix is not
+ * numerically positive definite).  V may be NULL when nlocked = 0.  ncols + nlocked <= 256. */
+int scsf_orthonormalize(scsf_handle *h, int64_t n, double *X, int64_t ldx, int32_t ncols,
+                        const double *V, int64_t ldv, int32_t nlocked);
+
+/* Rayleigh-Ritz and residuals (Algorithm 3, Rayleigh quotient + reduced eigenproblem +
+ * residual check): for orthonormal X (n x ncols, in place) forms G = X^T A X, solves
+ * G W = W Theta (ascending), sets X <- X W, and writes theta[ncols] and the relative residuals
+ * rel_resid[j] = ||A x_j - theta_j x_j|| / ||A x_j||.  ncols <= 256. */
+int scsf_rayleigh_ritz(scsf_handle *h, const scsf_operator *A, double *X, int64_t ldx,
+                       int32_t ncols, double *theta, double *rel_resid);
+
+/* Upper spectral bound for the filter window: out_host[0] = Gershgorin bound,
+ * out_host[1] = theta_max(T_s) + beta_s of an s-step Lanczos run from a seeded random start,
+ * out_host[2] = theta_min(T_s), out_host[3] = min(out_host[0], out_host[1]). */
+int scsf_bounds(scsf_handle *h, const scsf_operator *A, int32_t steps, uint64_t seed,
+                double *out_host);
+
+/* Truncated-FFT features of Algorithm 2: for each of n_op fields (channels x p x p real,
+ * row-major, contiguous per operator) the p0 x p0 corner k1, k2 in [0, p0) of the 2-D DFT
+ * divided by p^2.  feats: n_op x channels x p0 x p0 complex (re, im interleaved). */
+int scsf_features(scsf_handle *h, const double *fields, int32_t n_op, int32_t channels,
+                  int32_t p, int32_t p0, double *feats);
+
+/* Algorithm 2 end to end: order_host[n_op] = greedy nearest-neighbour order of the
+ * truncated-FFT features, starting at `start`; ties go to the lowest index.  p0 <= p. */
+int scsf_sort(scsf_handle *h, const double *fields, int32_t n_op, int32_t channels,
+              int32_t p, int32_t p0, int32_t start, int32_t *order_host);
+
+/* ---------------------------------------------------------------------------------------
+ * Solvers.
+ * ------------------------------------------------------------------------------------- */
+
+/* One operator, Algorithm 3.  X_prev (n x k, ld n) and theta_prev (k) are the previous
+ * problem's Ritz pairs (warm start) or both NULL (cold start from a seeded Gaussian block).
+ * Outputs: evals[L] ascending, evecs (n x L, ld n; largest-magnitude entry positive),
+ * X_next (n x k, ld n) and theta_next[k] for chaining (may alias X_prev / theta_prev).
+ * stats_host may be NULL. */
+int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
+               const double *X_prev, const double *theta_prev, double *evals, double *evecs,
+               double *X_next, double *theta_next, scsf_stats *stats_host);
+
+/* A whole dataset (Fig. 2 c-d): ops_host[n_op] (host array of operator descriptors, all of
+ * the same kind and n) are solved in the order order_host[n_op] split into `chains`
+ * contiguous chunks (App. C.5 chunking); the chunks run concurrently in lockstep, each
+ * chain warm-starting every solve from its previous one.  evals: n_op x L (row i = operator
+ * i), evecs: n_op x (n x L) (block i = operator i, ld n).  stats_host[n_op] may be NULL.
+ * Returns SCSF_ENOTCONV if any solve did not converge. */
+int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
+                        const int32_t *order_host, int32_t chains, const scsf_params *prm,
+                        double *evals, double *evecs, scsf_stats *stats_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCSF_H */

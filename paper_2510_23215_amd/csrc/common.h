@@ -1,0 +1,144 @@
+// Internal declarations shared by the HIP sources of libscsf (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+
+#include "../../include/scsf.h"
+
+namespace scsf {
+
+// Largest block width the small dense kernels handle (Gram, Cholesky, Jacobi).
+constexpr int kMaxK = 256;
+// Row chunk processed by one workgroup of the tall-skinny Gram kernel.
+constexpr int kGramChunk = 512;
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Device-side operator descriptor of one problem in a batch.
+struct OpDev {
+  int32_t kind;
+  int32_t N;          // grid side (stencil kinds)
+  int64_t n;
+  const double *wx, *wy, *v;
+  const double *cell;
+  const int32_t *row_ptr, *col_idx;
+  const double *val;
+};
+
+// Which columns of a k-wide block a batched kernel works on, per problem b:
+//   ALL            : [0, k)                         (no lock array)
+//   ACTIVE         : [lock[b], k)
+//   LOCKED         : [0, lock[b])
+enum ColMode : int32_t { COLS_ALL = 0, COLS_ACTIVE = 1, COLS_LOCKED = 2 };
+
+__host__ __device__ inline void col_range(int32_t mode, int32_t k, const int32_t *lock, int b,
+                                          int32_t &c0, int32_t &cnt) {
+  int32_t l = lock ? lock[b] : 0;
+  if (mode == COLS_LOCKED) { c0 = 0; cnt = l; }
+  else if (mode == COLS_ACTIVE) { c0 = l; cnt = k - l; }
+  else { c0 = 0; cnt = k; }
+  if (cnt < 0) cnt = 0;
+}
+
+// ----------------------------------------------------------------------------- launchers
+// All launchers enqueue on `st` and return hipSuccess or the launch error.
+
+// Y[:, c] = a*(A X[:, c]) + bcoef*X[:, c] + g*Z[:, c] for the columns selected by (mode, k,
+// lock), per problem coefficients coef[3*b + {0,1,2}] (device).  Z may be null when g == 0
+// for every problem (flag has_z = false).  Blocks of problem b start at base + b*bs.
+hipError_t spmm_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t Nmax,
+                     const double *X, const double *Z, double *Y, int64_t ld, int64_t bs,
+                     int32_t mode, int32_t k, const int32_t *lock, const double *coef,
+                     bool has_z, hipStream_t st);
+
+// Partial tall-skinny products C_b = A_b^T B_b over row chunks; then reduce.
+//   A_b = A + b*bsA + a0*ld, B_b = Bm + b*bsB + b0*ld (column ranges from modes),
+//   C_b = C + b*ldc*ldc (ldc x ldc, column-major), entries outside the ranges untouched.
+//   symmetric = true: A and B are the same block/range, only upper tiles computed and C is
+//   symmetrised.
+hipError_t gemm_tn(int B, int64_t n, int64_t ld, const double *A, int64_t bsA, int32_t modeA,
+                   const double *Bm, int64_t bsB, int32_t modeB, int32_t k, const int32_t *lock,
+                   bool symmetric, double *partial, int64_t partial_stride, double *C, int32_t ldc,
+                   const int32_t *gate, int32_t gate_mask, hipStream_t st);
+int64_t gemm_tn_partial_elems(int64_t n, int32_t ldc);
+
+// Out_b[:, cols(modeO)] = beta*Out + alpha * In_b[:, cols(modeI)] * M_b,
+// M_b = M + b*ldm*ldm, (rows = |cols(modeI)|, columns = |cols(modeO)|), column-major ldm.
+// In and Out may be the same block when beta == 0 (in-place rotation).
+// gate (nullable): only problems with gate[b] & gate_mask run; skip (nullable): problems with
+// skip[b] & skip_mask are left untouched (a failed factorisation is never applied).
+hipError_t gemm_nn(int B, int64_t n, int64_t ld, const double *In, int64_t bsI, int32_t modeI,
+                   double *Out, int64_t bsO, int32_t modeO, int32_t k, const int32_t *lock,
+                   const double *M, int32_t ldm, double alpha, double beta, const int32_t *gate,
+                   int32_t gate_mask, const int32_t *skip, int32_t skip_mask, hipStream_t st);
+
+// Per problem b (columns ACTIVE of width ka = k - lock[b]): scaled Cholesky of the Gram
+// matrix G_b (ldm x ldm) and the inverse factor M_b = D^-1 R^-1 with D = diag(sqrt(G_jj)),
+// R^T R = D^-1 G D^-1.  If a pivot is not positive the factorisation is retried once with the
+// CholeskyQR shift s = 11 (n ka + ka (ka+1)) u trace(G) (flag bit 4).  flag[b] |= 1 on
+// breakdown, 2 on NaN/Inf.  gate (nullable): only problems with gate[b] & gate_mask run.
+// scratch: B * kMaxK * (kMaxK+1) doubles (used when k is too large for LDS).
+hipError_t chol_inv(int B, int64_t n, int32_t k, const int32_t *lock, const double *G, double *M,
+                    int32_t ldm, int32_t *flag, const int32_t *gate, int32_t gate_mask,
+                    double *scratch, hipStream_t st);
+
+// Per problem: symmetric eigendecomposition of the ACTIVE projected matrix G_b (ka x ka) by
+// parallel cyclic Jacobi.  Eigenvalues ascending into theta[b*k + lock[b] + j], eigenvectors
+// into Z_b (ldm x ldm).  scratch: B * 2 * kMaxK * (kMaxK+1) doubles.
+hipError_t jacobi_eig(int B, int32_t k, const int32_t *lock, double *G, double *Z, int32_t ldm,
+                      double *theta, int32_t *flag, double *scratch, hipStream_t st);
+
+// res[b*k + c] = ||W c - theta c X c|| / ||W c|| for the active columns.
+hipError_t residuals(int B, int64_t n, int64_t ld, const double *X, const double *W,
+                     int64_t bs, int32_t k, const int32_t *lock, const double *theta, double *res,
+                     hipStream_t st);
+
+// Lock the longest converged ascending prefix of the active columns: nconv[b] grows by the
+// prefix with res <= tol.  lock[b] (first active column) follows nconv[b], and becomes k once
+// nconv[b] >= L (done[b] = 1), which makes every ACTIVE-mode kernel skip the problem.
+hipError_t lock_update(int B, int32_t k, int32_t L, double tol, int32_t *lock, int32_t *nconv,
+                       const double *res, int32_t *done, hipStream_t st);
+
+// Chebyshev step coefficients for degree m: coef[(s*B + b)*3 + {0,1,2}] for s = 0..m-1 from
+// lambda = theta[b*k], alpha = theta[b*k + k-1] (or win[] when given), beta = bounds[b*4+3].
+// win (nullable) receives (lambda, c, e) per problem.
+hipError_t cheb_coeffs(int B, int32_t k, int32_t m, const double *theta, const double *bounds,
+                       const int32_t *done, double *coef, double *win, hipStream_t st);
+// Same from explicit (lambda, c, e) per problem: win[b*3 + {0,1,2}].
+hipError_t cheb_coeffs_explicit(int B, int32_t m, const double *win, double *coef,
+                                hipStream_t st);
+
+// Gershgorin + s-step Lanczos bounds for each problem with need[b] != 0 (need may be null):
+// bounds[b*4 + {0,1,2,3}] = (gershgorin, theta_max + beta_s, theta_min, min(g, lanczos)).
+// work: B * 3 * nmax doubles.
+hipError_t bounds(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t steps,
+                  uint64_t seed, const int32_t *need, double *work, double *out, hipStream_t st);
+
+// Fill columns [0, k) of X_b (rows < n) with i.i.d. N(0,1) from Philox4x32-10 keyed by
+// (seed, b); rows [n, ld) are zeroed.
+hipError_t gaussian_fill(int B, int64_t n, int64_t ld, int64_t bs, int32_t k, double *X,
+                         uint64_t seed, hipStream_t st);
+
+// Copy ncols columns (rows < n) between blocks of different leading dimensions; zero_pad also
+// zeroes rows [n, ldd) of the destination (internal blocks only, never a caller's buffer).
+hipError_t copy_block(int64_t n, int32_t ncols, const double *src, int64_t lds, double *dst,
+                      int64_t ldd, bool zero_pad, hipStream_t st);
+// Canonical sign: flip each column so that its largest-magnitude entry (lowest index on
+// ties) is positive.
+hipError_t canonical_sign(int64_t n, int32_t ncols, double *X, int64_t ld, hipStream_t st);
+
+hipError_t fill_int(int32_t *a, int32_t v, int32_t count, hipStream_t st);
+hipError_t gather_columns(int64_t n, int32_t ncols, const double *src, int64_t lds,
+                          const int32_t *perm, double *dst, int64_t ldd, hipStream_t st);
+
+// Truncated DFT features and the greedy order.
+hipError_t dft_features(const double *fields, int32_t n_op, int32_t channels, int32_t p,
+                        int32_t p0, double *feats, hipStream_t st);
+hipError_t pair_distances(const double *feats, int32_t n_op, int32_t flen, double *D,
+                          hipStream_t st);
+hipError_t greedy_order(const double *D, int32_t n_op, int32_t start, int32_t *order,
+                        hipStream_t st);
+
+}  // namespace scsf

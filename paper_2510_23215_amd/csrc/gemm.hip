@@ -1,0 +1,263 @@
+// Tall-skinny FP64 products on the MFMA units of gfx950 (v_mfma_f64_16x16x4_f64).
+//
+//   gemm_tn : C = A^T B, A and B n x k blocks (n >> k): the Gram matrices of CholeskyQR2, the
+//             projection V^T X of block Gram-Schmidt and the Rayleigh quotient X^T (A X).
+//   gemm_nn : Out = beta Out + alpha In M with a small k x k matrix M: X R^-1, the Ritz
+//             rotation X W, and the Gram-Schmidt update X - V C.
+//
+// MFMA operand layout (one wavefront, 64 lanes, lane = i + 16*kk):
+//   A operand (16 x 4): lane holds A[i = lane%16][kk = lane/16]
+//   B operand (4 x 16): lane holds B[kk = lane/16][j = lane%16]
+//   D (16 x 16, 4 doubles per lane): lane holds D[lane/16 + 4*v][lane%16], v = 0..3
+//   (rows interleaved with stride 4; checked on gfx950 with an in-bounds probe)
+// gemm_tn contracts over rows, so the contraction index may be permuted freely: lane
+// (c, r) loads 4 consecutive rows 4r..4r+3 of column c as one 32-byte vector and feeds them
+// to 4 successive MFMAs, which keeps every load a full 128-byte segment per column.
+#include "common.h"
+
+namespace scsf {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline v4d mfma16x16x4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+enum TnSym : int32_t { TN_GENERAL = 0, TN_GRAM = 1, TN_SYMMETRISE = 2 };
+
+// grid: x = T*T output tiles of 32 x 32 (T = ldc/32), y = row chunk, z = problem.
+__global__ void __launch_bounds__(256) gemm_tn_kernel(
+    int64_t n, int64_t ld, const double *__restrict__ A, int64_t bsA, int32_t modeA,
+    const double *__restrict__ Bm, int64_t bsB, int32_t modeB, int32_t k,
+    const int32_t *__restrict__ lock, int32_t sym, double *__restrict__ partial,
+    int64_t pstride, int32_t ldc, const int32_t *__restrict__ gate, int32_t gate_mask) {
+  __shared__ double red[3][64][16];
+  const int b = blockIdx.z, s = blockIdx.y;
+  if (gate && !(gate[b] & gate_mask)) return;
+  const int T = ldc / 32;
+  const int ti = blockIdx.x % T, tj = blockIdx.x / T;
+  if (sym == TN_GRAM && ti > tj) return;
+  int32_t a0, ka, b0, kb;
+  col_range(modeA, k, lock, b, a0, ka);
+  col_range(modeB, k, lock, b, b0, kb);
+  if (ti * 32 >= ka || tj * 32 >= kb) return;
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r4 = lane >> 4, c16 = lane & 15;
+  const int64_t row_begin = (int64_t)s * kGramChunk;
+  const int64_t row_end = min(n, row_begin + kGramChunk);
+  const double *Ab = A + (int64_t)b * bsA;
+  const double *Bb = Bm + (int64_t)b * bsB;
+
+  const double *pa[2];
+  const double *pb[2];
+  bool va[2], vb[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int ca = ti * 32 + h * 16 + c16, cb = tj * 32 + h * 16 + c16;
+    va[h] = ca < ka;
+    vb[h] = cb < kb;
+    pa[h] = Ab + (int64_t)(a0 + (va[h] ? ca : 0)) * ld;
+    pb[h] = Bb + (int64_t)(b0 + (vb[h] ? cb : 0)) * ld;
+  }
+  v4d acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+  // each wave takes every 4th group of 16 rows of the chunk
+  for (int64_t r0 = row_begin + wave * 16; r0 < row_end; r0 += 64) {
+    const int64_t rr = r0 + 4 * r4;
+    v4d fa[2], fb[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      v4d xa = (v4d){0.0, 0.0, 0.0, 0.0}, xb = (v4d){0.0, 0.0, 0.0, 0.0};
+      if (rr < row_end) {
+        if (va[h]) xa = *reinterpret_cast<const v4d *>(pa[h] + rr);
+        if (vb[h]) xb = *reinterpret_cast<const v4d *>(pb[h] + rr);
+      }
+      // rows beyond n inside the last 4-row group contribute nothing
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (rr + t >= row_end) { xa[t] = 0.0; xb[t] = 0.0; }
+      }
+      fa[h] = xa;
+      fb[h] = xb;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x4(fa[x][t], fb[y][t], acc[x][y]);
+  }
+
+  // sum the four waves' tiles and store the chunk's partial 32 x 32 tile
+  if (wave > 0) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[wave - 1][lane][(x * 2 + y) * 4 + v] = acc[x][y][v];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    double *P = partial + ((int64_t)b * gridDim.y + s) * pstride;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int e = (x * 2 + y) * 4 + v;
+          const double val = acc[x][y][v] + red[0][lane][e] + red[1][lane][e] + red[2][lane][e];
+          const int i = ti * 32 + x * 16 + r4 + 4 * v;
+          const int j = tj * 32 + y * 16 + c16;
+          P[i + (int64_t)j * ldc] = val;
+        }
+  }
+}
+
+// C_b(i, j) = sum over chunks (fixed order) of the partial tiles.
+__global__ void gemm_tn_reduce_kernel(int32_t nchunks, int32_t modeA, int32_t modeB, int32_t k,
+                                      const int32_t *__restrict__ lock, int32_t sym,
+                                      const double *__restrict__ partial, int64_t pstride,
+                                      double *__restrict__ C, int32_t ldc,
+                                      const int32_t *__restrict__ gate, int32_t gate_mask) {
+  const int b = blockIdx.z;
+  if (gate && !(gate[b] & gate_mask)) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)ldc * ldc) return;
+  int32_t a0, ka, b0, kb;
+  col_range(modeA, k, lock, b, a0, ka);
+  col_range(modeB, k, lock, b, b0, kb);
+  const int i = (int)(e % ldc), j = (int)(e / ldc);
+  if (i >= ka || j >= kb) return;
+  const double *P = partial + (int64_t)b * nchunks * pstride;
+  double v = 0.0;
+  if (sym == TN_GRAM) {
+    const int lo = min(i, j), hi = max(i, j);
+    for (int s = 0; s < nchunks; ++s) v += P[(int64_t)s * pstride + lo + (int64_t)hi * ldc];
+  } else if (sym == TN_SYMMETRISE) {
+    double w = 0.0;
+    for (int s = 0; s < nchunks; ++s) {
+      v += P[(int64_t)s * pstride + i + (int64_t)j * ldc];
+      w += P[(int64_t)s * pstride + j + (int64_t)i * ldc];
+    }
+    v = 0.5 * (v + w);
+  } else {
+    for (int s = 0; s < nchunks; ++s) v += P[(int64_t)s * pstride + i + (int64_t)j * ldc];
+  }
+  C[(int64_t)b * ldc * ldc + i + (int64_t)j * ldc] = v;
+}
+
+int64_t gemm_tn_partial_elems(int64_t n, int32_t ldc) {
+  return ceil_div(n, kGramChunk) * (int64_t)ldc * ldc;
+}
+
+hipError_t gemm_tn(int B, int64_t n, int64_t ld, const double *A, int64_t bsA, int32_t modeA,
+                   const double *Bm, int64_t bsB, int32_t modeB, int32_t k, const int32_t *lock,
+                   bool symmetric, double *partial, int64_t partial_stride, double *C, int32_t ldc,
+                   const int32_t *gate, int32_t gate_mask, hipStream_t st) {
+  if (B <= 0 || n <= 0) return hipSuccess;
+  const int32_t nchunks = (int32_t)ceil_div(n, kGramChunk);
+  const int T = ldc / 32;
+  const int32_t sym = symmetric ? (A == Bm && modeA == modeB ? TN_GRAM : TN_SYMMETRISE)
+                                : TN_GENERAL;
+  dim3 g1((unsigned)(T * T), (unsigned)nchunks, (unsigned)B);
+  gemm_tn_kernel<<<g1, 256, 0, st>>>(n, ld, A, bsA, modeA, Bm, bsB, modeB, k, lock, sym, partial,
+                                     partial_stride / nchunks, ldc, gate, gate_mask);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  dim3 g2((unsigned)ceil_div((int64_t)ldc * ldc, 256), 1, (unsigned)B);
+  gemm_tn_reduce_kernel<<<g2, 256, 0, st>>>(nchunks, modeA, modeB, k, lock, sym, partial,
+                                            partial_stride / nchunks, C, ldc, gate, gate_mask);
+  return hipGetLastError();
+}
+
+// grid: x = row tiles of 64 (4 waves x 16 rows), z = problem.  NT = 16-column output tiles.
+template <int NT>
+__global__ void __launch_bounds__(256) gemm_nn_kernel(
+    int64_t n, int64_t ld, const double *In, int64_t bsI, int32_t modeI, double *Out,
+    int64_t bsO, int32_t modeO, int32_t k, const int32_t *__restrict__ lock,
+    const double *__restrict__ M, int32_t ldm, double alpha, double beta,
+    const int32_t *__restrict__ gate, int32_t gate_mask, const int32_t *__restrict__ skip,
+    int32_t skip_mask) {
+  constexpr int KC = 32;                       // rows of M staged per pass
+  constexpr int MS = NT * 16 + 2;              // padded LDS row stride
+  __shared__ double Ms[KC * MS];
+  const int b = blockIdx.z;
+  if (gate && !(gate[b] & gate_mask)) return;
+  if (skip && (skip[b] & skip_mask)) return;
+  int32_t i0, ki, o0, ko;
+  col_range(modeI, k, lock, b, i0, ki);
+  col_range(modeO, k, lock, b, o0, ko);
+  if (ko <= 0) return;
+  if (ki <= 0 && beta == 1.0) return;          // nothing to add
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r4 = lane >> 4, c16 = lane & 15;
+  const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t row = row0 + c16;
+  const bool row_ok = row < n;
+  const double *Ib = In + (int64_t)b * bsI + (int64_t)i0 * ld;
+  const double *Mb = M + (int64_t)b * ldm * ldm;
+
+  v4d acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+  for (int kk0 = 0; kk0 < ki; kk0 += KC) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < KC * NT * 16; e += 256) {
+      const int r = e % KC, c = e / KC;          // consecutive threads read down a column of M
+      const int kk = kk0 + r;
+      Ms[r * MS + c] = (kk < ki && c < ko) ? Mb[kk + (int64_t)c * ldm] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < KC; t += 4) {
+      const int kk = kk0 + t + r4;
+      const double bf = (row_ok && kk < ki) ? Ib[(int64_t)kk * ld + row] : 0.0;
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) {
+        if (ct * 16 < ko) {
+          const double af = Ms[(t + r4) * MS + ct * 16 + c16];
+          acc[ct] = mfma16x16x4(af, bf, acc[ct]);
+        }
+      }
+    }
+  }
+  if (!row_ok) return;
+  double *Ob = Out + (int64_t)b * bsO + (int64_t)o0 * ld;
+#pragma unroll
+  for (int ct = 0; ct < NT; ++ct) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int col = ct * 16 + r4 + 4 * v;
+      if (col < ko) {
+        double *o = Ob + (int64_t)col * ld + row;
+        const double r = alpha * acc[ct][v];
+        *o = (beta == 0.0) ? r : beta * (*o) + r;
+      }
+    }
+  }
+}
+
+hipError_t gemm_nn(int B, int64_t n, int64_t ld, const double *In, int64_t bsI, int32_t modeI,
+                   double *Out, int64_t bsO, int32_t modeO, int32_t k, const int32_t *lock,
+                   const double *M, int32_t ldm, double alpha, double beta, const int32_t *gate,
+                   int32_t gate_mask, const int32_t *skip, int32_t skip_mask, hipStream_t st) {
+  if (B <= 0 || n <= 0) return hipSuccess;
+  dim3 grid((unsigned)ceil_div(n, 64), 1, (unsigned)B);
+  if (k <= 128)
+    gemm_nn_kernel<8><<<grid, 256, 0, st>>>(n, ld, In, bsI, modeI, Out, bsO, modeO, k, lock, M,
+                                            ldm, alpha, beta, gate, gate_mask, skip, skip_mask);
+  else
+    gemm_nn_kernel<16><<<grid, 256, 0, st>>>(n, ld, In, bsI, modeI, Out, bsO, modeO, k, lock, M,
+                                             ldm, alpha, beta, gate, gate_mask, skip, skip_mask);
+  return hipGetLastError();
+}
+
+}  // namespace scsf

@@ -1,0 +1,354 @@
+// Per-iteration bookkeeping kernels: residual norms and locking (Algorithm 3, lock step),
+// Chebyshev window coefficients (Algorithm 1 / Section 2.2), the spectral upper bound
+// (Gershgorin and Lanczos), the seeded Gaussian start block, block copies and the output
+// sign convention.
+#include "stencil.h"
+
+namespace scsf {
+
+__device__ inline double block_sum(double v, double *sh) {
+  // sum over the block (blockDim.x a multiple of 64, <= 1024); result valid in all threads
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < nw; ++w) t += sh[w];
+  return t;
+}
+
+__device__ inline double block_max(double v, double *sh) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = sh[0];
+  for (int w = 1; w < nw; ++w) t = fmax(t, sh[w]);
+  return t;
+}
+
+// grid (k, 1, B): one workgroup per (active column, problem)
+__global__ void __launch_bounds__(256) residual_kernel(
+    int64_t n, int64_t ld, const double *__restrict__ X, const double *__restrict__ W, int64_t bs,
+    int32_t k, const int32_t *__restrict__ lock, const double *__restrict__ theta,
+    double *__restrict__ res) {
+  __shared__ double sh[16];
+  const int b = blockIdx.z;
+  const int32_t l = lock ? lock[b] : 0;
+  const int c = l + blockIdx.x;
+  if (c >= k) return;
+  const double th = theta[(int64_t)b * k + c];
+  const double *x = X + (int64_t)b * bs + (int64_t)c * ld;
+  const double *w = W + (int64_t)b * bs + (int64_t)c * ld;
+  double rr = 0.0, ww = 0.0;
+  for (int64_t p = threadIdx.x; p < n; p += blockDim.x) {
+    const double wv = w[p], d = wv - th * x[p];
+    rr += d * d;
+    ww += wv * wv;
+  }
+  rr = block_sum(rr, sh);
+  ww = block_sum(ww, sh);
+  if (threadIdx.x == 0) res[(int64_t)b * k + c] = (ww > 0.0) ? sqrt(rr / ww) : sqrt(rr);
+}
+
+hipError_t residuals(int B, int64_t n, int64_t ld, const double *X, const double *W,
+                     int64_t bs, int32_t k, const int32_t *lock, const double *theta, double *res,
+                     hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  residual_kernel<<<dim3(k, 1, B), 256, 0, st>>>(n, ld, X, W, bs, k, lock, theta, res);
+  return hipGetLastError();
+}
+
+// nconv[b]: locked pairs; lock[b]: first active column (= k once the problem is done).
+__global__ void lock_kernel(int B, int32_t k, int32_t L, double tol, int32_t *__restrict__ lock,
+                            int32_t *__restrict__ nconv, const double *__restrict__ res,
+                            int32_t *__restrict__ done) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B || done[b]) return;
+  int j = nconv[b];
+  while (j < k && res[(int64_t)b * k + j] <= tol) ++j;
+  nconv[b] = j;
+  if (j >= L) { done[b] = 1; lock[b] = k; }
+  else lock[b] = j;
+}
+
+hipError_t lock_update(int B, int32_t k, int32_t L, double tol, int32_t *lock, int32_t *nconv,
+                       const double *res, int32_t *done, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  lock_kernel<<<(B + 63) / 64, 64, 0, st>>>(B, k, L, tol, lock, nconv, res, done);
+  return hipGetLastError();
+}
+
+// Scaled recurrence of Algorithm 1: sigma_1 = e/(lambda-c), sigma_{i+1} = 1/(2/sigma_1 - sigma_i);
+// step 0: Y1 = (sigma_1/e)(A - cI) Y0; step i: Y_{i+1} = (2 sigma_{i+1}/e)(A - cI) Y_i
+//                                                  - sigma_i sigma_{i+1} Y_{i-1}.
+__device__ inline void write_coeffs(int B, int b, int32_t m, double lam, double c, double e,
+                                    double *coef) {
+  const double s1 = e / (lam - c);
+  coef[(0 * (int64_t)B + b) * 3 + 0] = s1 / e;
+  coef[(0 * (int64_t)B + b) * 3 + 1] = -s1 * c / e;
+  coef[(0 * (int64_t)B + b) * 3 + 2] = 0.0;
+  double s = s1;
+  for (int i = 1; i < m; ++i) {
+    const double sn = 1.0 / (2.0 / s1 - s);
+    coef[((int64_t)i * B + b) * 3 + 0] = 2.0 * sn / e;
+    coef[((int64_t)i * B + b) * 3 + 1] = -2.0 * sn * c / e;
+    coef[((int64_t)i * B + b) * 3 + 2] = -s * sn;
+    s = sn;
+  }
+}
+
+// Window of Section 2.2 with the reading: lambda = smallest Ritz value, alpha = largest Ritz
+// value of the block, beta = upper bound of the spectrum; c = (alpha+beta)/2, e = (beta-alpha)/2.
+__global__ void cheb_kernel(int B, int32_t k, int32_t m, const double *__restrict__ theta,
+                            const double *__restrict__ bnd, const int32_t *__restrict__ done,
+                            double *__restrict__ coef, double *__restrict__ win) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B || (done && done[b])) return;
+  const double lam = theta[(int64_t)b * k];
+  const double alpha = theta[(int64_t)b * k + k - 1];
+  double beta = bnd[b * 4 + 3];
+  const double span = fmax(fabs(alpha), fabs(lam));
+  if (!(beta > alpha + 1e-12 * span)) beta = alpha + fmax(1e-3 * span, 1e-300);
+  const double c = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
+  double l = lam;
+  if (!(l < c - 1e-12 * e)) l = c - e;       // lambda must lie below the damped interval
+  if (win) { win[b * 3 + 0] = l; win[b * 3 + 1] = c; win[b * 3 + 2] = e; }
+  write_coeffs(B, b, m, l, c, e, coef);
+}
+
+hipError_t cheb_coeffs(int B, int32_t k, int32_t m, const double *theta, const double *bounds,
+                       const int32_t *done, double *coef, double *win, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  cheb_kernel<<<(B + 63) / 64, 64, 0, st>>>(B, k, m, theta, bounds, done, coef, win);
+  return hipGetLastError();
+}
+
+__global__ void cheb_explicit_kernel(int B, int32_t m, const double *__restrict__ win,
+                                     double *__restrict__ coef) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  write_coeffs(B, b, m, win[b * 3 + 0], win[b * 3 + 1], win[b * 3 + 2], coef);
+}
+
+hipError_t cheb_coeffs_explicit(int B, int32_t m, const double *win, double *coef,
+                                hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  cheb_explicit_kernel<<<(B + 63) / 64, 64, 0, st>>>(B, m, win, coef);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- spectral upper bound
+// Lanczos bound of Zhou & Li (2011): theta_max(T_s) + beta_s, with Gershgorin's max row sum.
+__device__ inline int sturm_count(const double *a, const double *bb, int s, double x) {
+  // number of eigenvalues of the s x s tridiagonal (a, bb) below x
+  int cnt = 0;
+  double d = 1.0;
+  for (int i = 0; i < s; ++i) {
+    const double off = (i > 0) ? bb[i - 1] * bb[i - 1] : 0.0;
+    d = a[i] - x - ((i > 0) ? off / d : 0.0);
+    if (d == 0.0) d = -1e-300;
+    if (d < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(1024) bounds_kernel(
+    const OpDev *__restrict__ ops, int32_t steps, uint64_t seed, const int32_t *__restrict__ need,
+    double *__restrict__ work, int64_t nmax, double *__restrict__ out) {
+  __shared__ double sh[16];
+  __shared__ double al[128], be[128];
+  __shared__ int s_eff;
+  const int b = blockIdx.x;
+  if (need && !need[b]) return;
+  const OpDev op = ops[b];
+  const int64_t n = op.n;
+  double *v0 = work + (int64_t)b * 3 * nmax, *v1 = v0 + nmax, *w = v1 + nmax;
+  const int tid = threadIdx.x, NT = blockDim.x;
+  double nrm = 0.0;
+  for (int64_t p = tid; p < n; p += NT) {
+    const double2 g = gauss2(seed, (uint64_t)p, (uint32_t)b, 0x4C414E43u);
+    v1[p] = g.x;
+    v0[p] = 0.0;
+    nrm += g.x * g.x;
+  }
+  nrm = sqrt(block_sum(nrm, sh));
+  for (int64_t p = tid; p < n; p += NT) v1[p] /= nrm;
+  if (tid == 0) s_eff = steps;
+  double bold = 0.0, gmax = -INFINITY;
+  for (int j = 0; j < steps; ++j) {
+    __syncthreads();
+    double dot = 0.0;
+    for (int64_t p = tid; p < n; p += NT) {
+      double g;
+      const double r = op_row<KIND>(op, p, v1, j == 0 ? &g : nullptr) - bold * v0[p];
+      if (j == 0) gmax = fmax(gmax, g);
+      w[p] = r;
+      dot += r * v1[p];
+    }
+    const double a = block_sum(dot, sh);
+    double ss = 0.0;
+    for (int64_t p = tid; p < n; p += NT) {
+      const double r = w[p] - a * v1[p];
+      w[p] = r;
+      ss += r * r;
+    }
+    const double bt = sqrt(block_sum(ss, sh));
+    if (tid == 0) { al[j] = a; be[j] = bt; }
+    if (bt == 0.0) { if (tid == 0) s_eff = j + 1; break; }
+    for (int64_t p = tid; p < n; p += NT) { v0[p] = v1[p]; v1[p] = w[p] / bt; }
+    bold = bt;
+  }
+  gmax = block_max(gmax, sh);
+  __syncthreads();
+  if (tid < 2) {
+    const int s = s_eff;
+    // Gershgorin interval of T for the bisection brackets
+    double lo = INFINITY, hi = -INFINITY;
+    for (int i = 0; i < s; ++i) {
+      const double r = ((i > 0) ? fabs(be[i - 1]) : 0.0) + ((i < s - 1) ? fabs(be[i]) : 0.0);
+      lo = fmin(lo, al[i] - r);
+      hi = fmax(hi, al[i] + r);
+    }
+    const int target = (tid == 0) ? 1 : s;      // smallest / largest eigenvalue of T
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * fmax(fabs(lo), fabs(hi)); ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (sturm_count(al, be, s, mid) >= target) hi = mid; else lo = mid;
+    }
+    const double th = 0.5 * (lo + hi);
+    if (tid == 0) out[b * 4 + 2] = th;
+    else {
+      const double lz = th + fabs(be[s - 1]);
+      out[b * 4 + 0] = gmax;
+      out[b * 4 + 1] = lz;
+      out[b * 4 + 3] = fmin(gmax, lz);
+    }
+  }
+}
+
+hipError_t bounds(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t steps,
+                  uint64_t seed, const int32_t *need, double *work, double *out, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  if (steps < 1 || steps > 128) return hipErrorInvalidValue;
+  if (kind == SCSF_STENCIL5)
+    bounds_kernel<SCSF_STENCIL5><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out);
+  else if (kind == SCSF_STENCIL9)
+    bounds_kernel<SCSF_STENCIL9><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out);
+  else
+    bounds_kernel<SCSF_CSR><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- start block, copies, signs
+__global__ void gauss_kernel(int64_t n, int64_t ld, int64_t bs, int32_t k, double *__restrict__ X,
+                             uint64_t seed) {
+  const int b = blockIdx.z, c = blockIdx.y;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ld || c >= k) return;
+  double v = 0.0;
+  if (p < n) {
+    const uint64_t e = (uint64_t)c * n + p;
+    const double2 g = gauss2(seed, e >> 1, (uint32_t)b, 0x58424C4Bu);
+    v = (e & 1) ? g.y : g.x;
+  }
+  X[(int64_t)b * bs + (int64_t)c * ld + p] = v;
+}
+
+hipError_t gaussian_fill(int B, int64_t n, int64_t ld, int64_t bs, int32_t k, double *X,
+                         uint64_t seed, hipStream_t st) {
+  if (B <= 0 || k <= 0) return hipSuccess;
+  gauss_kernel<<<dim3((unsigned)ceil_div(ld, 256), k, B), 256, 0, st>>>(n, ld, bs, k, X, seed);
+  return hipGetLastError();
+}
+
+__global__ void copy_kernel(int64_t n, const double *__restrict__ src, int64_t lds,
+                            double *__restrict__ dst, int64_t ldd, int zero_pad) {
+  const int c = blockIdx.y;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) dst[(int64_t)c * ldd + p] = src[(int64_t)c * lds + p];
+  else if (zero_pad && p < ldd) dst[(int64_t)c * ldd + p] = 0.0;
+}
+
+hipError_t copy_block(int64_t n, int32_t ncols, const double *src, int64_t lds, double *dst,
+                      int64_t ldd, bool zero_pad, hipStream_t st) {
+  if (ncols <= 0 || n <= 0) return hipSuccess;
+  const int64_t rows = zero_pad ? ldd : n;
+  copy_kernel<<<dim3((unsigned)ceil_div(rows, 256), ncols), 256, 0, st>>>(n, src, lds, dst, ldd,
+                                                                          zero_pad ? 1 : 0);
+  return hipGetLastError();
+}
+
+// one workgroup per column: index of the largest |x| (lowest index on ties), then flip
+__global__ void __launch_bounds__(256) sign_kernel(int64_t n, double *__restrict__ X, int64_t ld) {
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  double *x = X + (int64_t)blockIdx.x * ld;
+  double best = -1.0;
+  int64_t bi = 0;
+  for (int64_t p = threadIdx.x; p < n; p += blockDim.x) {
+    const double a = fabs(x[p]);
+    if (a > best) { best = a; bi = p; }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double a = sv[threadIdx.x + o];
+      const int64_t ia = si[threadIdx.x + o];
+      if (a > sv[threadIdx.x] || (a == sv[threadIdx.x] && ia < si[threadIdx.x])) {
+        sv[threadIdx.x] = a;
+        si[threadIdx.x] = ia;
+      }
+    }
+    __syncthreads();
+  }
+  const bool flip = x[si[0]] < 0.0;
+  __syncthreads();
+  if (flip)
+    for (int64_t p = threadIdx.x; p < n; p += blockDim.x) x[p] = -x[p];
+}
+
+hipError_t canonical_sign(int64_t n, int32_t ncols, double *X, int64_t ld, hipStream_t st) {
+  if (ncols <= 0 || n <= 0) return hipSuccess;
+  sign_kernel<<<ncols, 256, 0, st>>>(n, X, ld);
+  return hipGetLastError();
+}
+
+}  // namespace scsf
+
+namespace scsf {
+
+__global__ void fill_int_kernel(int32_t *__restrict__ a, int32_t v, int32_t count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) a[i] = v;
+}
+
+hipError_t fill_int(int32_t *a, int32_t v, int32_t count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  fill_int_kernel<<<(count + 255) / 256, 256, 0, st>>>(a, v, count);
+  return hipGetLastError();
+}
+
+// dst[:, j] = src[:, perm[j]] for j < ncols (rows < n)
+__global__ void gather_kernel(int64_t n, const double *__restrict__ src, int64_t lds,
+                              const int32_t *__restrict__ perm, double *__restrict__ dst,
+                              int64_t ldd) {
+  const int j = blockIdx.y;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  dst[(int64_t)j * ldd + p] = src[(int64_t)perm[j] * lds + p];
+}
+
+hipError_t gather_columns(int64_t n, int32_t ncols, const double *src, int64_t lds,
+                          const int32_t *perm, double *dst, int64_t ldd, hipStream_t st) {
+  if (ncols <= 0 || n <= 0) return hipSuccess;
+  gather_kernel<<<dim3((unsigned)ceil_div(n, 256), ncols), 256, 0, st>>>(n, src, lds, perm, dst,
+                                                                         ldd);
+  return hipGetLastError();
+}
+
+}  // namespace scsf

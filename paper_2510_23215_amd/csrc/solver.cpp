@@ -1,0 +1,811 @@
+// Host side of libscsf: handle and workspace, the batched ChFSI engine (Algorithm 3), the step
+// primitives, the sort (Algorithm 2) and the chunked, warm-started sequence solver.
+//
+// The engine runs B independent problems of the same shape in lockstep: every kernel of an
+// outer iteration is one launch over all B problems (grid z = problem), and each problem's
+// active column range [lock[b], k) is read on the device, so problems at different stages of
+// convergence share the launches.  The host synchronises once per outer iteration to read the
+// lock counts.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "common.h"
+
+using namespace scsf;
+
+namespace {
+
+enum BufId {
+  B_X, B_Y1, B_Y2, B_W, B_G, B_M, B_PART, B_THETA, B_RES, B_INT, B_BND, B_COEF, B_UNIT, B_CHOL,
+  B_JAC, B_LZ, B_OPS, B_WIN, B_SORTF, B_SORTD, B_SORTO, B_COUNT
+};
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct scsf_handle {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  DevBuf bufs[B_COUNT];
+  void *pinned = nullptr;
+  size_t pinned_bytes = 0;
+  // filter-launch timing (scsf_profile_*): event pairs around each Chebyshev step launch
+  bool prof = false;
+  std::vector<hipEvent_t> ev;            // 2 per pending launch
+  std::vector<double> ev_bytes;          // algorithmic bytes of each pending launch
+  int ev_used = 0;
+  scsf_profile acc{};
+};
+
+namespace {
+
+#define HIPCHK(x)                               \
+  do {                                          \
+    hipError_t e_ = (x);                        \
+    if (e_ != hipSuccess) return SCSF_EHIP;     \
+  } while (0)
+#define STCHK(x)                                \
+  do {                                          \
+    int s_ = (x);                               \
+    if (s_ != SCSF_OK) return s_;               \
+  } while (0)
+
+template <typename T>
+int grow(scsf_handle *h, int id, size_t count, T **out) {
+  DevBuf &b = h->bufs[id];
+  const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  if (b.bytes < bytes) {
+    if (b.p) {
+      if (hipStreamSynchronize(h->stream) != hipSuccess) return SCSF_EHIP;
+      if (hipFree(b.p) != hipSuccess) return SCSF_EHIP;
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    const size_t nb = bytes + bytes / 8;
+    if (hipMalloc(&b.p, nb) != hipSuccess) {
+      b.p = nullptr;
+      return SCSF_ENOMEM;
+    }
+    b.bytes = nb;
+  }
+  *out = static_cast<T *>(b.p);
+  return SCSF_OK;
+}
+
+int grow_pinned(scsf_handle *h, size_t bytes) {
+  if (h->pinned_bytes >= bytes) return SCSF_OK;
+  if (h->pinned) {
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return SCSF_EHIP;
+    (void)hipHostFree(h->pinned);
+    h->pinned = nullptr;
+    h->pinned_bytes = 0;
+  }
+  if (hipHostMalloc(&h->pinned, bytes, hipHostMallocDefault) != hipSuccess) return SCSF_ENOMEM;
+  h->pinned_bytes = bytes;
+  return SCSF_OK;
+}
+
+int check_op(const scsf_operator *A) {
+  if (!A || A->n <= 0) return SCSF_EINVAL;
+  if (A->kind == SCSF_STENCIL5) {
+    if (A->nx <= 0 || (int64_t)A->nx * A->nx != A->n || !A->wx || !A->wy) return SCSF_EINVAL;
+  } else if (A->kind == SCSF_STENCIL9) {
+    if (A->nx <= 0 || (int64_t)A->nx * A->nx != A->n || !A->cell) return SCSF_EINVAL;
+  } else if (A->kind == SCSF_CSR) {
+    if (!A->row_ptr || !A->col_idx || !A->val || A->nnz < 0) return SCSF_EINVAL;
+  } else {
+    return SCSF_EINVAL;
+  }
+  if (A->n > ((int64_t)1 << 31) - 64) return SCSF_EINVAL;
+  return SCSF_OK;
+}
+
+OpDev to_dev(const scsf_operator &A) {
+  OpDev d;
+  d.kind = A.kind;
+  d.N = A.nx;
+  d.n = A.n;
+  d.wx = A.wx;
+  d.wy = A.wy;
+  d.v = A.v;
+  d.cell = A.cell;
+  d.row_ptr = A.row_ptr;
+  d.col_idx = A.col_idx;
+  d.val = A.val;
+  return d;
+}
+
+// Event pairs are recorded around each filter launch and drained at the next
+// synchronisation point (no extra synchronisation is added).
+int prof_begin(scsf_handle *h, double bytes) {
+  if (!h->prof) return -1;
+  if ((size_t)(2 * h->ev_used + 2) > h->ev.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      h->ev.push_back(e);
+    }
+  }
+  const int slot = h->ev_used++;
+  if ((size_t)slot >= h->ev_bytes.size()) h->ev_bytes.resize(slot + 1);
+  h->ev_bytes[slot] = bytes;
+  if (hipEventRecord(h->ev[2 * slot], h->stream) != hipSuccess) return -1;
+  return slot;
+}
+void prof_end(scsf_handle *h, int slot) {
+  if (slot >= 0) (void)hipEventRecord(h->ev[2 * slot + 1], h->stream);
+}
+void prof_drain(scsf_handle *h) {  // call only after the stream was synchronised
+  for (int i = 0; i < h->ev_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) == hipSuccess) {
+      h->acc.filter_launches += 1;
+      h->acc.filter_ms += ms;
+      h->acc.filter_bytes += h->ev_bytes[i];
+    }
+  }
+  h->ev_used = 0;
+}
+
+// ------------------------------------------------------------------------------- the engine
+struct Engine {
+  scsf_handle *h = nullptr;
+  hipStream_t st = nullptr;
+  int B = 0;
+  int64_t n = 0, ld = 0, bs = 0;
+  int32_t k = 0, L = 0, m = 0, kind = 0, ldm = 0, lz_steps = 20;
+  double tol = 1e-8;
+  uint64_t seed = 0;
+  int64_t part_stride = 0;
+  double *X = nullptr, *Y1 = nullptr, *Y2 = nullptr, *W = nullptr, *G = nullptr, *M = nullptr;
+  double *part = nullptr, *theta = nullptr, *res = nullptr, *bnd = nullptr, *coef = nullptr;
+  double *unit = nullptr, *chol = nullptr, *jac = nullptr, *lz = nullptr;
+  int32_t *lock = nullptr, *nconv = nullptr, *done = nullptr, *flag = nullptr, *need = nullptr;
+  OpDev *ops = nullptr;
+  // pinned host mirrors
+  int32_t *h_lock = nullptr, *h_nconv = nullptr, *h_done = nullptr, *h_flag = nullptr;
+  int32_t *h_need = nullptr, *h_perm = nullptr;
+  double *h_theta = nullptr, *h_res = nullptr, *h_bnd = nullptr, *h_unit = nullptr;
+  OpDev *h_ops = nullptr;
+
+  int setup(scsf_handle *hh, int B_, int64_t n_, int32_t k_, int32_t L_, int32_t m_, int32_t kind_,
+            double tol_, uint64_t seed_, int32_t lz_steps_) {
+    h = hh;
+    st = hh->stream;
+    B = B_;
+    n = n_;
+    k = k_;
+    L = L_;
+    m = m_;
+    kind = kind_;
+    tol = tol_;
+    seed = seed_;
+    lz_steps = lz_steps_;
+    ld = round_up(n, 64);
+    bs = ld * k;
+    ldm = (int32_t)round_up(k, 32);
+    part_stride = gemm_tn_partial_elems(n, ldm);
+    const size_t blk = (size_t)B * bs;
+    STCHK(grow(h, B_X, blk, &X));
+    STCHK(grow(h, B_Y1, blk, &Y1));
+    STCHK(grow(h, B_Y2, blk, &Y2));
+    STCHK(grow(h, B_W, blk, &W));
+    STCHK(grow(h, B_G, (size_t)B * ldm * ldm, &G));
+    STCHK(grow(h, B_M, (size_t)B * ldm * ldm, &M));
+    STCHK(grow(h, B_PART, (size_t)B * part_stride, &part));
+    STCHK(grow(h, B_THETA, (size_t)B * k, &theta));
+    STCHK(grow(h, B_RES, (size_t)B * k, &res));
+    int32_t *ints = nullptr;
+    STCHK(grow(h, B_INT, (size_t)B * 5, &ints));
+    lock = ints;
+    nconv = ints + B;
+    done = ints + 2 * B;
+    flag = ints + 3 * B;
+    need = ints + 4 * B;
+    STCHK(grow(h, B_BND, (size_t)B * 4, &bnd));
+    STCHK(grow(h, B_COEF, (size_t)std::max(m, 1) * B * 3, &coef));
+    STCHK(grow(h, B_UNIT, (size_t)B * 3, &unit));
+    STCHK(grow(h, B_CHOL, (size_t)B * kMaxK * (kMaxK + 1), &chol));
+    STCHK(grow(h, B_JAC, (size_t)B * 2 * kMaxK * (kMaxK + 1), &jac));
+    STCHK(grow(h, B_LZ, (size_t)B * 3 * n, &lz));
+    STCHK(grow(h, B_OPS, (size_t)B, &ops));
+    // pinned: 6 int arrays of B, perm B*k, theta/res B*k, bnd B*4, unit B*3, ops B
+    const size_t pin = (size_t)B * 6 * 4 + (size_t)B * k * 4 + (size_t)B * k * 16 +
+                       (size_t)B * 4 * 8 + (size_t)B * 3 * 8 + (size_t)B * sizeof(OpDev) + 1024;
+    STCHK(grow_pinned(h, pin));
+    char *pp = static_cast<char *>(h->pinned);
+    auto take = [&](size_t bytes) {
+      char *r = pp;
+      pp += (bytes + 63) / 64 * 64;
+      return r;
+    };
+    h_lock = (int32_t *)take(B * 4);
+    h_nconv = (int32_t *)take(B * 4);
+    h_done = (int32_t *)take(B * 4);
+    h_flag = (int32_t *)take(B * 4);
+    h_need = (int32_t *)take(B * 4);
+    h_perm = (int32_t *)take((size_t)B * k * 4);
+    h_theta = (double *)take((size_t)B * k * 8);
+    h_res = (double *)take((size_t)B * k * 8);
+    h_bnd = (double *)take((size_t)B * 4 * 8);
+    h_unit = (double *)take((size_t)B * 3 * 8);
+    h_ops = (OpDev *)take((size_t)B * sizeof(OpDev));
+    if ((size_t)(pp - static_cast<char *>(h->pinned)) > h->pinned_bytes) return SCSF_ENOMEM;
+    for (int b = 0; b < B; ++b) {
+      h_lock[b] = h_nconv[b] = h_done[b] = h_flag[b] = h_need[b] = 0;
+      h_unit[3 * b] = 1.0;
+      h_unit[3 * b + 1] = 0.0;
+      h_unit[3 * b + 2] = 0.0;
+    }
+    HIPCHK(hipMemcpyAsync(unit, h_unit, (size_t)B * 3 * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(fill_int(flag, 0, B, st));
+    return SCSF_OK;
+  }
+
+  // Uploads of the pinned mirrors complete before returning: the host edits the mirrors
+  // again right after, and an asynchronous copy would read the edited values.
+  int upload_state() {
+    HIPCHK(hipMemcpyAsync(lock, h_lock, (size_t)B * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(nconv, h_nconv, (size_t)B * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(done, h_done, (size_t)B * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(need, h_need, (size_t)B * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return SCSF_OK;
+  }
+  int upload_ops() {
+    HIPCHK(hipMemcpyAsync(ops, h_ops, (size_t)B * sizeof(OpDev), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return SCSF_OK;
+  }
+  int download_state() {
+    HIPCHK(hipMemcpyAsync(h_lock, lock, (size_t)B * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_nconv, nconv, (size_t)B * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_done, done, (size_t)B * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_flag, flag, (size_t)B * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    prof_drain(h);
+    return SCSF_OK;
+  }
+
+  // algorithmic bytes of one Chebyshev step over all unfinished problems: read Y_i (and
+  // Y_{i-1} after the first step), write Y_{i+1}, read the operator's coefficients once
+  double step_bytes(bool has_prev) const {
+    double cols = 0.0, nops = 0.0;
+    for (int b = 0; b < B; ++b)
+      if (!h_done[b]) { cols += (double)(k - h_lock[b]); nops += 1.0; }
+    const double coeff = (kind == SCSF_STENCIL5) ? 2.0 * n + (double)n
+                         : (kind == SCSF_STENCIL9) ? 3.0 * n : 0.0;
+    return 8.0 * ((has_prev ? 3.0 : 2.0) * (double)n * cols + coeff * nops);
+  }
+
+  // upper bounds of the problems with h_need[b] set
+  int compute_bounds() {
+    HIPCHK(bounds(ops, B, kind, n, lz_steps, seed ^ 0x5DEECE66DULL, need, lz, bnd, st));
+    return SCSF_OK;
+  }
+
+  // X active columns <- orthonormal basis (block Gram-Schmidt twice against the locked
+  // columns, then CholeskyQR2, with a third pass for problems that needed the shift)
+  int orth(double *Yf, bool cgs) {
+    if (cgs) {
+      for (int rep = 0; rep < 2; ++rep) {
+        HIPCHK(gemm_tn(B, n, ld, X, bs, COLS_LOCKED, Yf, bs, COLS_ACTIVE, k, lock, false, part,
+                       part_stride, G, ldm, nullptr, 0, st));
+        HIPCHK(gemm_nn(B, n, ld, X, bs, COLS_LOCKED, Yf, bs, COLS_ACTIVE, k, lock, G, ldm, -1.0,
+                       1.0, nullptr, 0, nullptr, 0, st));
+      }
+    }
+    for (int pass = 0; pass < 3; ++pass) {
+      const int32_t *gate = (pass == 2) ? flag : nullptr;
+      HIPCHK(gemm_tn(B, n, ld, Yf, bs, COLS_ACTIVE, Yf, bs, COLS_ACTIVE, k, lock, true, part,
+                     part_stride, G, ldm, gate, 4, st));
+      HIPCHK(chol_inv(B, n, k, lock, G, M, ldm, flag, gate, 4, chol, st));
+      HIPCHK(gemm_nn(B, n, ld, Yf, bs, COLS_ACTIVE, Yf, bs, COLS_ACTIVE, k, lock, M, ldm, 1.0, 0.0,
+                     gate, 4, flag, 3, st));
+    }
+    return SCSF_OK;
+  }
+
+  // Rayleigh-Ritz on the orthonormal active columns of Yf; Ritz vectors land in X, A X in W
+  int rayleigh_ritz(double *Yf) {
+    HIPCHK(spmm_step(ops, B, kind, n, 0, Yf, nullptr, W, ld, bs, COLS_ACTIVE, k, lock, unit, false,
+                     st));
+    HIPCHK(gemm_tn(B, n, ld, Yf, bs, COLS_ACTIVE, W, bs, COLS_ACTIVE, k, lock, true, part,
+                   part_stride, G, ldm, nullptr, 0, st));
+    HIPCHK(jacobi_eig(B, k, lock, G, M, ldm, theta, flag, jac, st));
+    HIPCHK(gemm_nn(B, n, ld, Yf, bs, COLS_ACTIVE, X, bs, COLS_ACTIVE, k, lock, M, ldm, 1.0, 0.0,
+                   nullptr, 0, nullptr, 0, st));
+    HIPCHK(gemm_nn(B, n, ld, W, bs, COLS_ACTIVE, W, bs, COLS_ACTIVE, k, lock, M, ldm, 1.0, 0.0,
+                   nullptr, 0, nullptr, 0, st));
+    return SCSF_OK;
+  }
+
+  // Cold start of the problems whose h_lock[b] == 0 while every other problem is parked
+  // (lock = k): Gaussian block, orthonormalisation and one Rayleigh-Ritz (no locking).
+  int cold_start(const std::vector<int> &slots) {
+    std::vector<int32_t> saved(h_lock, h_lock + B);
+    for (int b = 0; b < B; ++b) h_lock[b] = k;
+    for (int b : slots) {
+      h_lock[b] = 0;
+      HIPCHK(gaussian_fill(1, n, ld, bs, k, X + (int64_t)b * bs,
+                           seed * 0x9E3779B97F4A7C15ULL + (uint64_t)b * 0xD1B54A32D192ED03ULL + 1,
+                           st));
+    }
+    STCHK(upload_state());
+    HIPCHK(fill_int(flag, 0, B, st));
+    STCHK(orth(X, false));
+    STCHK(rayleigh_ritz(X));
+    for (int b = 0; b < B; ++b) h_lock[b] = saved[b];
+    for (int b : slots) h_lock[b] = 0;
+    STCHK(upload_state());
+    return SCSF_OK;
+  }
+
+  // One outer iteration of Algorithm 3 for every problem not done.
+  int iterate() {
+    HIPCHK(fill_int(flag, 0, B, st));
+    HIPCHK(cheb_coeffs(B, k, m, theta, bnd, done, coef, nullptr, st));
+    double *ring[3] = {X, Y1, Y2};
+    for (int s = 0; s < m; ++s) {
+      const int slot = prof_begin(h, h->prof ? step_bytes(s > 0) : 0.0);
+      HIPCHK(spmm_step(ops, B, kind, n, 0, ring[s % 3], ring[(s + 2) % 3], ring[(s + 1) % 3], ld,
+                       bs, COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 0, st));
+      prof_end(h, slot);
+    }
+    double *Yf = ring[m % 3];
+    STCHK(orth(Yf, true));
+    STCHK(rayleigh_ritz(Yf));
+    HIPCHK(residuals(B, n, ld, X, W, bs, k, lock, theta, res, st));
+    HIPCHK(lock_update(B, k, L, tol, lock, nconv, res, done, st));
+    return download_state();
+  }
+
+  // theta / res / bnd of problem b to the pinned mirrors (synchronises)
+  int fetch(int b) {
+    HIPCHK(hipMemcpyAsync(h_theta + (size_t)b * k, theta + (size_t)b * k, (size_t)k * 8,
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_res + (size_t)b * k, res + (size_t)b * k, (size_t)k * 8,
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_bnd + (size_t)b * 4, bnd + (size_t)b * 4, 32, hipMemcpyDeviceToHost,
+                          st));
+    HIPCHK(hipStreamSynchronize(st));
+    return SCSF_OK;
+  }
+
+  // Ascending first L pairs of problem b -> evals (device, L) and evecs (device, n x L, ld ldo),
+  // canonical sign.  Needs fetch(b) first.  Returns max relative residual of the pairs.
+  int extract(int b, double *evals, double *evecs, int64_t ldo, double *maxres) {
+    const double *th = h_theta + (size_t)b * k;
+    int32_t *perm = h_perm + (size_t)b * k;
+    std::iota(perm, perm + L, 0);
+    std::stable_sort(perm, perm + L, [&](int a, int c) { return th[a] < th[c]; });
+    double *vals = h_theta + (size_t)b * k;  // reorder in place after computing the maximum
+    double mr = 0.0;
+    for (int j = 0; j < L; ++j) mr = std::max(mr, h_res[(size_t)b * k + j]);
+    std::vector<double> sorted(L);
+    for (int j = 0; j < L; ++j) sorted[j] = th[perm[j]];
+    for (int j = 0; j < L; ++j) vals[j] = sorted[j];
+    int32_t *perm_d = nullptr;
+    STCHK(grow(h, B_SORTO, (size_t)B * k, &perm_d));
+    HIPCHK(hipMemcpyAsync(perm_d + (size_t)b * k, perm, (size_t)L * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(evals, vals, (size_t)L * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(gather_columns(n, L, X + (int64_t)b * bs, ld, perm_d + (size_t)b * k, evecs, ldo, st));
+    HIPCHK(canonical_sign(n, L, evecs, ldo, st));
+    HIPCHK(hipStreamSynchronize(st));                 // the copies above read pinned memory
+    if (maxres) *maxres = mr;
+    return SCSF_OK;
+  }
+};
+
+// status of a finished (or abandoned) solve from its flags
+int solve_status(int32_t flagv, bool converged) {
+  if (flagv & 2) return SCSF_ENUMERIC;
+  if (flagv & 1) return SCSF_EBREAKDOWN;
+  return converged ? SCSF_OK : SCSF_ENOTCONV;
+}
+
+int check_params(const scsf_params *p, int64_t n) {
+  if (!p) return SCSF_EINVAL;
+  if (p->L <= 0 || p->k <= p->L || p->k > kMaxK || p->k > n) return SCSF_EINVAL;
+  if (p->degree < 1 || p->degree > 64) return SCSF_EINVAL;
+  if (!(p->tol > 0.0)) return SCSF_EINVAL;
+  if (p->lanczos_steps < 0 || p->lanczos_steps > 128) return SCSF_EINVAL;
+  if (p->precision != SCSF_FP64) return SCSF_EINVAL;
+  return SCSF_OK;
+}
+
+}  // namespace
+
+// =============================================================================== C ABI
+extern "C" {
+
+const char *scsf_version(void) { return "libscsf 0.1 (gfx950, fp64 MFMA)"; }
+
+const char *scsf_status_string(int s) {
+  switch (s) {
+    case SCSF_OK: return "ok";
+    case SCSF_EINVAL: return "invalid argument";
+    case SCSF_ENOMEM: return "out of device memory";
+    case SCSF_ENOTCONV: return "not converged within max_iter";
+    case SCSF_EBREAKDOWN: return "Cholesky breakdown in orthonormalisation";
+    case SCSF_EHIP: return "HIP runtime error";
+    case SCSF_ENUMERIC: return "NaN or Inf in the iteration";
+    default: return "unknown status";
+  }
+}
+
+int scsf_create(scsf_handle **h, void *hip_stream) {
+  if (!h) return SCSF_EINVAL;
+  scsf_handle *x = new (std::nothrow) scsf_handle();
+  if (!x) return SCSF_ENOMEM;
+  x->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&x->device) != hipSuccess) {
+    delete x;
+    return SCSF_EHIP;
+  }
+  *h = x;
+  return SCSF_OK;
+}
+
+int scsf_profile_enable(scsf_handle *h, int on) {
+  if (!h) return SCSF_EINVAL;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return SCSF_EHIP;
+  prof_drain(h);
+  h->prof = on != 0;
+  return SCSF_OK;
+}
+
+int scsf_profile_read(scsf_handle *h, scsf_profile *out_host, int reset) {
+  if (!h || !out_host) return SCSF_EINVAL;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return SCSF_EHIP;
+  prof_drain(h);
+  *out_host = h->acc;
+  if (reset) h->acc = scsf_profile{};
+  return SCSF_OK;
+}
+
+int scsf_destroy(scsf_handle *h) {
+  if (!h) return SCSF_EINVAL;
+  for (auto e : h->ev) (void)hipEventDestroy(e);
+  (void)hipStreamSynchronize(h->stream);
+  for (auto &b : h->bufs)
+    if (b.p) (void)hipFree(b.p);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  delete h;
+  return SCSF_OK;
+}
+
+int scsf_set_stream(scsf_handle *h, void *hip_stream) {
+  if (!h) return SCSF_EINVAL;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return SCSF_EHIP;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  return SCSF_OK;
+}
+
+int scsf_spmm(scsf_handle *h, const scsf_operator *A, const double *X, int64_t ldx, int32_t ncols,
+              double *Y, int64_t ldy) {
+  if (!h) return SCSF_EINVAL;
+  STCHK(check_op(A));
+  if (!X || !Y || ncols < 0 || ldx < A->n || ldy < A->n) return SCSF_EINVAL;
+  if (ncols == 0) return SCSF_OK;
+  Engine e;
+  STCHK(e.setup(h, 1, A->n, 1, 0, 1, A->kind, 1.0, 0, 20));
+  e.h_ops[0] = to_dev(*A);
+  STCHK(e.upload_ops());
+  const double *src = X;
+  if (ldx != ldy) {
+    double *tmp = nullptr;
+    STCHK(grow(h, B_Y1, (size_t)ldy * ncols, &tmp));
+    HIPCHK(copy_block(A->n, ncols, X, ldx, tmp, ldy, false, h->stream));
+    src = tmp;
+  }
+  HIPCHK(spmm_step(e.ops, 1, A->kind, A->n, 0, src, nullptr, Y, ldy, 0, COLS_ALL, ncols, nullptr,
+                   e.unit, false, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return SCSF_OK;
+}
+
+int scsf_filter(scsf_handle *h, const scsf_operator *A, const double *X, int64_t ldx,
+                int32_t ncols, int32_t degree, double lambda, double c, double e, double *Y,
+                int64_t ldy) {
+  if (!h) return SCSF_EINVAL;
+  STCHK(check_op(A));
+  if (!X || !Y || ncols < 0 || ncols > kMaxK || ldx < A->n || ldy < A->n) return SCSF_EINVAL;
+  if (degree < 1 || degree > 64 || !(e > 0.0) || lambda == c) return SCSF_EINVAL;
+  if (ncols == 0) return SCSF_OK;
+  Engine en;
+  STCHK(en.setup(h, 1, A->n, ncols, 0, degree, A->kind, 1.0, 0, 20));
+  en.h_ops[0] = to_dev(*A);
+  STCHK(en.upload_ops());
+  double *win = nullptr;
+  STCHK(grow(h, B_WIN, 3, &win));
+  en.h_bnd[0] = lambda;
+  en.h_bnd[1] = c;
+  en.h_bnd[2] = e;
+  HIPCHK(hipMemcpyAsync(win, en.h_bnd, 3 * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(cheb_coeffs_explicit(1, degree, win, en.coef, h->stream));
+  HIPCHK(copy_block(A->n, ncols, X, ldx, en.X, en.ld, true, h->stream));
+  double *ring[3] = {en.X, en.Y1, en.Y2};
+  for (int s = 0; s < degree; ++s)
+    HIPCHK(spmm_step(en.ops, 1, A->kind, A->n, 0, ring[s % 3], ring[(s + 2) % 3],
+                     ring[(s + 1) % 3], en.ld, en.bs, COLS_ALL, ncols, nullptr,
+                     en.coef + (size_t)s * 3, s > 0, h->stream));
+  HIPCHK(copy_block(A->n, ncols, ring[degree % 3], en.ld, Y, ldy, false, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return SCSF_OK;
+}
+
+int scsf_orthonormalize(scsf_handle *h, int64_t n, double *X, int64_t ldx, int32_t ncols,
+                        const double *V, int64_t ldv, int32_t nlocked) {
+  if (!h || n <= 0 || !X || ncols <= 0 || nlocked < 0 || ldx < n) return SCSF_EINVAL;
+  if (nlocked > 0 && (!V || ldv < n)) return SCSF_EINVAL;
+  const int32_t k = ncols + nlocked;
+  if (k > kMaxK || k > n) return SCSF_EINVAL;
+  Engine e;
+  STCHK(e.setup(h, 1, n, k, 0, 1, SCSF_STENCIL5, 1.0, 0, 20));
+  if (nlocked > 0) HIPCHK(copy_block(n, nlocked, V, ldv, e.X, e.ld, true, h->stream));
+  HIPCHK(copy_block(n, ncols, X, ldx, e.X + (int64_t)nlocked * e.ld, e.ld, true, h->stream));
+  e.h_lock[0] = nlocked;
+  e.h_nconv[0] = nlocked;
+  STCHK(e.upload_state());
+  HIPCHK(fill_int(e.flag, 0, 1, h->stream));
+  STCHK(e.orth(e.X, nlocked > 0));
+  STCHK(e.download_state());
+  if (e.h_flag[0] & 2) return SCSF_ENUMERIC;
+  if (e.h_flag[0] & 1) return SCSF_EBREAKDOWN;
+  HIPCHK(copy_block(n, ncols, e.X + (int64_t)nlocked * e.ld, e.ld, X, ldx, false, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return SCSF_OK;
+}
+
+int scsf_rayleigh_ritz(scsf_handle *h, const scsf_operator *A, double *X, int64_t ldx,
+                       int32_t ncols, double *theta, double *rel_resid) {
+  if (!h) return SCSF_EINVAL;
+  STCHK(check_op(A));
+  if (!X || ncols <= 0 || ncols > kMaxK || ncols > A->n || ldx < A->n) return SCSF_EINVAL;
+  Engine e;
+  STCHK(e.setup(h, 1, A->n, ncols, 0, 1, A->kind, 1.0, 0, 20));
+  e.h_ops[0] = to_dev(*A);
+  STCHK(e.upload_ops());
+  STCHK(e.upload_state());
+  HIPCHK(fill_int(e.flag, 0, 1, h->stream));
+  HIPCHK(copy_block(A->n, ncols, X, ldx, e.X, e.ld, true, h->stream));
+  STCHK(e.rayleigh_ritz(e.X));
+  HIPCHK(residuals(1, A->n, e.ld, e.X, e.W, e.bs, ncols, e.lock, e.theta, e.res, h->stream));
+  HIPCHK(copy_block(A->n, ncols, e.X, e.ld, X, ldx, false, h->stream));
+  if (theta) HIPCHK(hipMemcpyAsync(theta, e.theta, (size_t)ncols * 8, hipMemcpyDeviceToDevice,
+                                   h->stream));
+  if (rel_resid) HIPCHK(hipMemcpyAsync(rel_resid, e.res, (size_t)ncols * 8,
+                                       hipMemcpyDeviceToDevice, h->stream));
+  STCHK(e.download_state());
+  if (e.h_flag[0] & 2) return SCSF_ENUMERIC;
+  return SCSF_OK;
+}
+
+int scsf_bounds(scsf_handle *h, const scsf_operator *A, int32_t steps, uint64_t seed,
+                double *out_host) {
+  if (!h || !out_host) return SCSF_EINVAL;
+  STCHK(check_op(A));
+  if (steps < 1 || steps > 128) return SCSF_EINVAL;
+  Engine e;
+  STCHK(e.setup(h, 1, A->n, 1, 0, 1, A->kind, 1.0, seed, steps));
+  e.h_ops[0] = to_dev(*A);
+  e.h_need[0] = 1;
+  STCHK(e.upload_ops());
+  STCHK(e.upload_state());
+  HIPCHK(bounds(e.ops, 1, A->kind, A->n, steps, seed, e.need, e.lz, e.bnd, h->stream));
+  HIPCHK(hipMemcpyAsync(e.h_bnd, e.bnd, 32, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  out_host[0] = e.h_bnd[0];
+  out_host[1] = e.h_bnd[1];
+  out_host[2] = e.h_bnd[2];
+  out_host[3] = e.h_bnd[3];
+  return SCSF_OK;
+}
+
+int scsf_features(scsf_handle *h, const double *fields, int32_t n_op, int32_t channels, int32_t p,
+                  int32_t p0, double *feats) {
+  if (!h || !fields || !feats || n_op <= 0 || channels <= 0 || p <= 0 || p0 <= 0 || p0 > p)
+    return SCSF_EINVAL;
+  if ((int64_t)p * p0 * 16 > 64 * 1024) return SCSF_EINVAL;
+  HIPCHK(dft_features(fields, n_op, channels, p, p0, feats, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return SCSF_OK;
+}
+
+int scsf_sort(scsf_handle *h, const double *fields, int32_t n_op, int32_t channels, int32_t p,
+              int32_t p0, int32_t start, int32_t *order_host) {
+  if (!h || !fields || !order_host || n_op <= 0 || channels <= 0 || p <= 0 || p0 <= 0 || p0 > p)
+    return SCSF_EINVAL;
+  if (start < 0 || start >= n_op || n_op > 32768) return SCSF_EINVAL;
+  if ((int64_t)p * p0 * 16 > 64 * 1024) return SCSF_EINVAL;
+  const int32_t flen = channels * p0 * p0;
+  double *F = nullptr, *D = nullptr;
+  int32_t *O = nullptr;
+  STCHK(grow(h, B_SORTF, (size_t)n_op * flen * 2, &F));
+  STCHK(grow(h, B_SORTD, (size_t)n_op * n_op, &D));
+  STCHK(grow(h, B_SORTO, (size_t)n_op, &O));
+  HIPCHK(dft_features(fields, n_op, channels, p, p0, F, h->stream));
+  HIPCHK(pair_distances(F, n_op, flen, D, h->stream));
+  HIPCHK(greedy_order(D, n_op, start, O, h->stream));
+  HIPCHK(hipMemcpyAsync(order_host, O, (size_t)n_op * 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return SCSF_OK;
+}
+
+int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
+               const double *X_prev, const double *theta_prev, double *evals, double *evecs,
+               double *X_next, double *theta_next, scsf_stats *stats_host) {
+  if (!h) return SCSF_EINVAL;
+  STCHK(check_op(A));
+  STCHK(check_params(prm, A->n));
+  if ((X_prev == nullptr) != (theta_prev == nullptr)) return SCSF_EINVAL;
+  if (!evals || !evecs) return SCSF_EINVAL;
+  const int max_iter = prm->max_iter > 0 ? prm->max_iter : 200;
+  const int lzs = prm->lanczos_steps > 0 ? prm->lanczos_steps : 20;
+  Engine e;
+  STCHK(e.setup(h, 1, A->n, prm->k, prm->L, prm->degree, A->kind, prm->tol, prm->seed, lzs));
+  e.h_ops[0] = to_dev(*A);
+  e.h_need[0] = 1;
+  STCHK(e.upload_ops());
+  STCHK(e.upload_state());
+  STCHK(e.compute_bounds());
+  if (X_prev) {
+    HIPCHK(copy_block(A->n, prm->k, X_prev, A->n, e.X, e.ld, true, h->stream));
+    HIPCHK(hipMemcpyAsync(e.theta, theta_prev, (size_t)prm->k * 8, hipMemcpyDeviceToDevice,
+                          h->stream));
+  } else {
+    STCHK(e.cold_start({0}));
+  }
+  int it = 0;
+  int64_t fcols = 0;
+  while (it < max_iter) {
+    fcols += (int64_t)prm->degree * (prm->k - e.h_nconv[0]);
+    STCHK(e.iterate());
+    ++it;
+    if (e.h_done[0] || (e.h_flag[0] & 3)) break;
+  }
+  const bool conv = e.h_done[0] != 0;
+  const int status = solve_status(e.h_flag[0], conv);
+  STCHK(e.fetch(0));
+  double mr = 0.0;
+  STCHK(e.extract(0, evals, evecs, A->n, &mr));
+  if (X_next) HIPCHK(copy_block(A->n, prm->k, e.X, e.ld, X_next, A->n, false, h->stream));
+  if (theta_next)
+    HIPCHK(hipMemcpyAsync(theta_next, e.theta, (size_t)prm->k * 8, hipMemcpyDeviceToDevice,
+                          h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (stats_host) {
+    stats_host->iterations = it;
+    stats_host->nconv = e.h_nconv[0];
+    stats_host->status = status;
+    stats_host->chol_shifts = (e.h_flag[0] & 4) ? 1 : 0;
+    stats_host->filter_cols = fcols;
+    stats_host->beta = e.h_bnd[3];
+    stats_host->max_rel_resid = mr;
+  }
+  return status;
+}
+
+int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
+                        const int32_t *order_host, int32_t chains, const scsf_params *prm,
+                        double *evals, double *evecs, scsf_stats *stats_host) {
+  if (!h || !ops_host || n_op <= 0 || !order_host || chains <= 0 || !evals || !evecs)
+    return SCSF_EINVAL;
+  const int64_t n = ops_host[0].n;
+  const int32_t kind = ops_host[0].kind;
+  for (int i = 0; i < n_op; ++i) {
+    STCHK(check_op(&ops_host[i]));
+    if (ops_host[i].n != n || ops_host[i].kind != kind) return SCSF_EINVAL;
+  }
+  STCHK(check_params(prm, n));
+  {
+    std::vector<char> seen(n_op, 0);
+    for (int i = 0; i < n_op; ++i) {
+      const int o = order_host[i];
+      if (o < 0 || o >= n_op || seen[o]) return SCSF_EINVAL;
+      seen[o] = 1;
+    }
+  }
+  chains = std::min(chains, n_op);
+  const int max_iter = prm->max_iter > 0 ? prm->max_iter : 200;
+  const int lzs = prm->lanczos_steps > 0 ? prm->lanczos_steps : 20;
+  const int32_t L = prm->L, k = prm->k, m = prm->degree;
+
+  // contiguous chunks of the order, sizes differing by at most one (App. C.5)
+  std::vector<int> cbeg(chains + 1);
+  for (int c = 0; c <= chains; ++c) cbeg[c] = (int)((int64_t)n_op * c / chains);
+
+  Engine e;
+  STCHK(e.setup(h, chains, n, k, L, m, kind, prm->tol, prm->seed, lzs));
+  std::vector<int> pos(chains), iters(chains, 0);
+  std::vector<int64_t> fcols(chains, 0);
+  std::vector<char> active(chains, 1), cold(chains, 1);
+  for (int b = 0; b < chains; ++b) {
+    pos[b] = cbeg[b];
+    e.h_ops[b] = to_dev(ops_host[order_host[pos[b]]]);
+    e.h_need[b] = 1;
+  }
+  STCHK(e.upload_ops());
+  STCHK(e.upload_state());
+  STCHK(e.compute_bounds());
+  {
+    std::vector<int> all(chains);
+    std::iota(all.begin(), all.end(), 0);
+    STCHK(e.cold_start(all));
+  }
+  for (int b = 0; b < chains; ++b) e.h_need[b] = 0;
+  STCHK(e.upload_state());
+
+  int worst = SCSF_OK;
+  int remaining = chains;
+  while (remaining > 0) {
+    for (int b = 0; b < chains; ++b)
+      if (active[b]) fcols[b] += (int64_t)m * (k - e.h_nconv[b]);
+    STCHK(e.iterate());
+    bool reload = false;
+    std::vector<int> recold;
+    for (int b = 0; b < chains; ++b) {
+      if (!active[b]) continue;
+      ++iters[b];
+      const bool fin = e.h_done[b] || (e.h_flag[b] & 3) || iters[b] >= max_iter;
+      if (!fin) continue;
+      const int op = order_host[pos[b]];
+      const int status = solve_status(e.h_flag[b], e.h_done[b] != 0);
+      STCHK(e.fetch(b));
+      double mr = 0.0;
+      STCHK(e.extract(b, evals + (size_t)op * L, evecs + (size_t)op * n * L, n, &mr));
+      if (stats_host) {
+        scsf_stats &s = stats_host[op];
+        s.iterations = iters[b];
+        s.nconv = e.h_nconv[b];
+        s.status = status;
+        s.chol_shifts = (e.h_flag[b] & 4) ? 1 : 0;
+        s.filter_cols = fcols[b];
+        s.beta = e.h_bnd[(size_t)b * 4 + 3];
+        s.max_rel_resid = mr;
+      }
+      if (status != SCSF_OK && (worst == SCSF_OK || status != SCSF_ENOTCONV)) worst = status;
+      // the pinned regions used by extract are read by the copies: finish them before reuse
+      HIPCHK(hipStreamSynchronize(h->stream));
+      ++pos[b];
+      iters[b] = 0;
+      fcols[b] = 0;
+      if (pos[b] >= cbeg[b + 1]) {
+        active[b] = 0;
+        --remaining;
+        e.h_done[b] = 1;
+        e.h_lock[b] = k;
+        continue;
+      }
+      // next operator of the chain, warm-started from this solve (all k Ritz pairs)
+      e.h_ops[b] = to_dev(ops_host[order_host[pos[b]]]);
+      e.h_need[b] = 1;
+      e.h_done[b] = 0;
+      e.h_nconv[b] = 0;
+      e.h_lock[b] = 0;
+      if (status == SCSF_ENUMERIC || status == SCSF_EBREAKDOWN) recold.push_back(b);
+      reload = true;
+    }
+    if (reload) {
+      STCHK(e.upload_ops());
+      STCHK(e.upload_state());
+      STCHK(e.compute_bounds());
+      if (!recold.empty()) STCHK(e.cold_start(recold));
+      for (int b = 0; b < chains; ++b) e.h_need[b] = 0;
+      STCHK(e.upload_state());
+      HIPCHK(hipStreamSynchronize(h->stream));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return worst;
+}
+
+}  // extern "C"

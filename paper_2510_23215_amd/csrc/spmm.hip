@@ -1,0 +1,122 @@
+// Operator application and the Chebyshev three-term step on a block of vectors (gfx950).
+//
+// One step of the scaled recurrence of Algorithm 1 (Section 2.2) is
+//   Y_{i+1} = a (A Y_i) + b Y_i + g Y_{i-1},
+// with a = 2 sigma_{i+1} / e, b = -2 sigma_{i+1} c / e, g = -sigma_i sigma_{i+1} (a = sigma_1/e,
+// b = -sigma_1 c / e, g = 0 for the first step).  The kernel streams the block once: each
+// thread owns one grid node and CPT consecutive columns, so the node's stencil coefficients
+// are loaded once and reused across the columns, and the loads of a wavefront are
+// contiguous in every column (column-major blocks).  Neighbour values along x come from the
+// same cache lines; the +-N neighbours are re-read from L2 by the adjacent row tiles.
+#include "stencil.h"
+
+namespace scsf {
+
+template <int KIND, int CPT>
+__global__ void __launch_bounds__(256) spmm_step_kernel(
+    const OpDev *__restrict__ ops, const double *__restrict__ X, const double *__restrict__ Z,
+    double *__restrict__ Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
+    const int32_t *__restrict__ lock, const double *__restrict__ coef, int has_z) {
+  const int b = blockIdx.z;
+  const OpDev op = ops[b];
+  const int64_t n = op.n;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t c0, cnt;
+  col_range(mode, k, lock, b, c0, cnt);
+  const int j0 = blockIdx.y * CPT;
+  if (p >= n || j0 >= cnt) return;
+  const double a = coef[3 * b + 0], bc = coef[3 * b + 1], g = coef[3 * b + 2];
+  const int64_t off = (int64_t)b * bs + (int64_t)(c0 + j0) * ld;
+  const double *x = X + off;
+  double *y = Y + off;
+  const double *z = has_z ? Z + off : nullptr;
+  const int jn = min(CPT, cnt - j0);
+
+  if constexpr (KIND == SCSF_STENCIL5) {
+    const int N = op.N;
+    const int iy = (int)(p / N), ix = (int)(p - (int64_t)iy * N);
+    const double cw = op.wx[(int64_t)iy * (N + 1) + ix];
+    const double ce = op.wx[(int64_t)iy * (N + 1) + ix + 1];
+    const double cs = op.wy[(int64_t)iy * N + ix];
+    const double cn = op.wy[(int64_t)(iy + 1) * N + ix];
+    const double cd = cw + ce + cs + cn + (op.v ? op.v[p] : 0.0);
+    const bool hw = ix > 0, he = ix < N - 1, hs = iy > 0, hn = iy < N - 1;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      if (j < jn) {
+        const double *xc = x + (int64_t)j * ld;
+        const double xv = xc[p];
+        double ax = cd * xv;
+        if (hw) ax -= cw * xc[p - 1];
+        if (he) ax -= ce * xc[p + 1];
+        if (hs) ax -= cs * xc[p - N];
+        if (hn) ax -= cn * xc[p + N];
+        double r = a * ax + bc * xv;
+        if (z) r += g * z[(int64_t)j * ld + p];
+        y[(int64_t)j * ld + p] = r;
+      }
+    }
+  } else if constexpr (KIND == SCSF_STENCIL9) {
+    const int N = op.N;
+    const int iy = (int)(p / N), ix = (int)(p - (int64_t)iy * N);
+    double c9[9];
+    stencil9_coeffs(op, iy, ix, c9);
+    bool ok[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int dy = t / 3 - 1, dx = t % 3 - 1;
+      ok[t] = (iy + dy >= 0) && (iy + dy < N) && (ix + dx >= 0) && (ix + dx < N);
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      if (j < jn) {
+        const double *xc = x + (int64_t)j * ld;
+        const double xv = xc[p];
+        double ax = 0.0;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const int dy = t / 3 - 1, dx = t % 3 - 1;
+          if (ok[t]) ax += c9[t] * xc[p + dy * N + dx];
+        }
+        double r = a * ax + bc * xv;
+        if (z) r += g * z[(int64_t)j * ld + p];
+        y[(int64_t)j * ld + p] = r;
+      }
+    }
+  } else {  // CSR
+    const int32_t r0 = op.row_ptr[p], r1 = op.row_ptr[p + 1];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      if (j < jn) {
+        const double *xc = x + (int64_t)j * ld;
+        double ax = 0.0;
+        for (int32_t q = r0; q < r1; ++q) ax += op.val[q] * xc[op.col_idx[q]];
+        double r = a * ax + bc * xc[p];
+        if (z) r += g * z[(int64_t)j * ld + p];
+        y[(int64_t)j * ld + p] = r;
+      }
+    }
+  }
+}
+
+hipError_t spmm_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t /*Nmax*/,
+                     const double *X, const double *Z, double *Y, int64_t ld, int64_t bs,
+                     int32_t mode, int32_t k, const int32_t *lock, const double *coef,
+                     bool has_z, hipStream_t st) {
+  constexpr int CPT = 4;
+  if (B <= 0 || nmax <= 0 || k <= 0) return hipSuccess;
+  dim3 block(256);
+  dim3 grid((unsigned)ceil_div(nmax, 256), (unsigned)ceil_div(k, CPT), (unsigned)B);
+  if (kind == SCSF_STENCIL5)
+    spmm_step_kernel<SCSF_STENCIL5, CPT><<<grid, block, 0, st>>>(ops, X, Z, Y, ld, bs, mode, k,
+                                                                 lock, coef, has_z ? 1 : 0);
+  else if (kind == SCSF_STENCIL9)
+    spmm_step_kernel<SCSF_STENCIL9, CPT><<<grid, block, 0, st>>>(ops, X, Z, Y, ld, bs, mode, k,
+                                                                 lock, coef, has_z ? 1 : 0);
+  else
+    spmm_step_kernel<SCSF_CSR, CPT><<<grid, block, 0, st>>>(ops, X, Z, Y, ld, bs, mode, k, lock,
+                                                            coef, has_z ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace scsf

@@ -1,0 +1,317 @@
+"""Thin Python binding of libscsf (the C ABI in include/scsf.h).
+
+Argument marshalling only: every step runs in the HIP library.  PyTorch provides device
+memory and the stream.  Blocks of vectors are n x k torch tensors in column-major layout
+(stride (1, ld)); `colmajor(n, k)` allocates one.  The library must have been built
+(`paper_2510_23215_amd.build.build()`); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_int64, c_uint64, c_void_p
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libscsf.so")
+
+SCSF_OK, SCSF_EINVAL, SCSF_ENOMEM, SCSF_ENOTCONV = 0, -1, -2, -3
+SCSF_EBREAKDOWN, SCSF_EHIP, SCSF_ENUMERIC = -4, -5, -6
+SCSF_STENCIL5, SCSF_STENCIL9, SCSF_CSR = 1, 2, 3
+SCSF_FP64, SCSF_MIXED = 0, 1
+
+
+class ScsfError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+class Operator(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("nx", c_int32), ("n", c_int64), ("wx", c_void_p),
+                ("wy", c_void_p), ("v", c_void_p), ("cell", c_void_p), ("row_ptr", c_void_p),
+                ("col_idx", c_void_p), ("val", c_void_p), ("nnz", c_int64)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("L", c_int32), ("k", c_int32), ("degree", c_int32), ("max_iter", c_int32),
+                ("lanczos_steps", c_int32), ("precision", c_int32), ("tol", c_double),
+                ("seed", c_uint64)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("filter_launches", c_int64), ("filter_ms", c_double), ("filter_bytes", c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", c_int32), ("nconv", c_int32), ("status", c_int32),
+                ("chol_shifts", c_int32), ("filter_cols", c_int64), ("beta", c_double),
+                ("max_rel_resid", c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2510_23215_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl, u64 = c_void_p, c_int32, c_int64, c_double, c_uint64
+        sig = {
+            "scsf_create": [POINTER(c_void_p), vp],
+            "scsf_destroy": [vp],
+            "scsf_set_stream": [vp, vp],
+            "scsf_spmm": [vp, POINTER(Operator), vp, i64, i32, vp, i64],
+            "scsf_filter": [vp, POINTER(Operator), vp, i64, i32, i32, dbl, dbl, dbl, vp, i64],
+            "scsf_orthonormalize": [vp, i64, vp, i64, i32, vp, i64, i32],
+            "scsf_rayleigh_ritz": [vp, POINTER(Operator), vp, i64, i32, vp, vp],
+            "scsf_bounds": [vp, POINTER(Operator), i32, u64, POINTER(c_double)],
+            "scsf_features": [vp, vp, i32, i32, i32, i32, vp],
+            "scsf_sort": [vp, vp, i32, i32, i32, i32, i32, POINTER(c_int32)],
+            "scsf_solve": [vp, POINTER(Operator), POINTER(Params), vp, vp, vp, vp, vp, vp,
+                           POINTER(Stats)],
+            "scsf_solve_sequence": [vp, POINTER(Operator), i32, POINTER(c_int32), i32,
+                                    POINTER(Params), vp, vp, POINTER(Stats)],
+        }
+        sig["scsf_profile_enable"] = [vp, i32]
+        sig["scsf_profile_read"] = [vp, POINTER(Profile), i32]
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = c_int32
+        L.scsf_status_string.argtypes = [c_int32]
+        L.scsf_status_string.restype = ctypes.c_char_p
+        L.scsf_version.argtypes = []
+        L.scsf_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().scsf_status_string(int(s)).decode()
+
+
+def _check(status: int, what: str, allow=(SCSF_OK,)):
+    if status not in allow:
+        raise ScsfError(status, what)
+    return status
+
+
+def colmajor(n: int, k: int, device="cuda", dtype=torch.float64) -> torch.Tensor:
+    """An n x k tensor with column-major strides (1, n)."""
+    return torch.empty((k, n), device=device, dtype=dtype).t()
+
+
+def as_colmajor(x: torch.Tensor) -> torch.Tensor:
+    if x.dim() == 1:
+        x = x[:, None]
+    if x.stride(0) == 1 and x.stride(1) >= x.shape[0]:
+        return x
+    return x.t().contiguous().t()
+
+
+def _ld(x: torch.Tensor) -> int:
+    return max(int(x.stride(1)), int(x.shape[0])) if x.dim() == 2 else int(x.shape[0])
+
+
+def _ptr(x):
+    return None if x is None else ctypes.c_void_p(x.data_ptr())
+
+
+class Handle:
+    """scsf_handle bound to a torch CUDA (HIP) stream (default: the current stream)."""
+
+    def __init__(self, stream: torch.cuda.Stream | None = None):
+        self._h = c_void_p()
+        stream = stream or torch.cuda.current_stream()
+        self.stream = stream
+        _check(lib().scsf_create(ctypes.byref(self._h), c_void_p(stream.cuda_stream)),
+               "scsf_create")
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().scsf_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceOperator:
+    """Device copy of an operator from `scsf_inputs` (Stencil5 / Stencil9) or a CSR matrix."""
+
+    def __init__(self, op=None, *, csr=None, device="cuda"):
+        self._keep = []
+        s = Operator()
+        if csr is not None:
+            indptr, indices, data = csr
+            n = len(indptr) - 1
+            rp = torch.as_tensor(np.asarray(indptr, np.int32), device=device)
+            ci = torch.as_tensor(np.asarray(indices, np.int32), device=device)
+            va = torch.as_tensor(np.asarray(data, np.float64), device=device)
+            self._keep += [rp, ci, va]
+            s.kind, s.nx, s.n = SCSF_CSR, 0, n
+            s.row_ptr, s.col_idx, s.val, s.nnz = rp.data_ptr(), ci.data_ptr(), va.data_ptr(), len(data)
+        elif hasattr(op, "wx"):
+            wx = torch.as_tensor(np.ascontiguousarray(op.wx, np.float64), device=device)
+            wy = torch.as_tensor(np.ascontiguousarray(op.wy, np.float64), device=device)
+            self._keep += [wx, wy]
+            s.kind, s.nx, s.n = SCSF_STENCIL5, op.N, op.N * op.N
+            s.wx, s.wy = wx.data_ptr(), wy.data_ptr()
+            if op.v is not None:
+                v = torch.as_tensor(np.ascontiguousarray(op.v, np.float64), device=device)
+                self._keep.append(v)
+                s.v = v.data_ptr()
+        else:
+            cell = torch.as_tensor(np.ascontiguousarray(op.cell, np.float64), device=device)
+            self._keep.append(cell)
+            s.kind, s.nx, s.n = SCSF_STENCIL9, op.N, op.N * op.N
+            s.cell = cell.data_ptr()
+        self.struct = s
+        self.n = int(s.n)
+
+    def ref(self):
+        return ctypes.byref(self.struct)
+
+
+# --------------------------------------------------------------------------- entry points
+def scsf_spmm(h: Handle, A: DeviceOperator, X: torch.Tensor, Y: torch.Tensor | None = None):
+    X = as_colmajor(X)
+    if Y is None:
+        Y = colmajor(X.shape[0], X.shape[1], device=X.device)
+    _check(lib().scsf_spmm(h.ptr, A.ref(), _ptr(X), _ld(X), X.shape[1], _ptr(Y), _ld(Y)),
+           "scsf_spmm")
+    return Y
+
+
+def scsf_filter(h: Handle, A: DeviceOperator, X: torch.Tensor, degree: int, lam: float, c: float,
+                e: float, Y: torch.Tensor | None = None):
+    X = as_colmajor(X)
+    if Y is None:
+        Y = colmajor(X.shape[0], X.shape[1], device=X.device)
+    _check(lib().scsf_filter(h.ptr, A.ref(), _ptr(X), _ld(X), X.shape[1], int(degree), float(lam),
+                             float(c), float(e), _ptr(Y), _ld(Y)), "scsf_filter")
+    return Y
+
+
+def scsf_orthonormalize(h: Handle, X: torch.Tensor, V: torch.Tensor | None = None):
+    """In place: X <- orthonormal basis of (I - V V^T) X.  X must be column-major."""
+    assert X.stride(0) == 1
+    nl = 0 if V is None else V.shape[1]
+    if V is not None:
+        V = as_colmajor(V)
+    _check(lib().scsf_orthonormalize(h.ptr, X.shape[0], _ptr(X), _ld(X), X.shape[1], _ptr(V),
+                                     _ld(V) if V is not None else 0, nl), "scsf_orthonormalize")
+    return X
+
+
+def scsf_rayleigh_ritz(h: Handle, A: DeviceOperator, X: torch.Tensor):
+    """In place: X <- Ritz vectors; returns (theta, relative residuals) as device tensors."""
+    assert X.stride(0) == 1
+    k = X.shape[1]
+    theta = torch.empty(k, device=X.device, dtype=torch.float64)
+    res = torch.empty(k, device=X.device, dtype=torch.float64)
+    _check(lib().scsf_rayleigh_ritz(h.ptr, A.ref(), _ptr(X), _ld(X), k, _ptr(theta), _ptr(res)),
+           "scsf_rayleigh_ritz")
+    return theta, res
+
+
+def scsf_bounds(h: Handle, A: DeviceOperator, steps: int = 20, seed: int = 0):
+    out = (c_double * 4)()
+    _check(lib().scsf_bounds(h.ptr, A.ref(), int(steps), c_uint64(seed), out), "scsf_bounds")
+    return {"gershgorin": out[0], "lanczos": out[1], "theta_min": out[2], "beta": out[3]}
+
+
+def scsf_features(h: Handle, fields: torch.Tensor, p0: int):
+    """fields: (n_op, C, p, p) float64 device tensor -> (n_op, C, p0, p0) complex128."""
+    fields = fields.contiguous()
+    n_op, C, p, _ = fields.shape
+    out = torch.empty((n_op, C, p0, p0, 2), device=fields.device, dtype=torch.float64)
+    _check(lib().scsf_features(h.ptr, _ptr(fields), n_op, C, p, p0, _ptr(out)), "scsf_features")
+    return torch.view_as_complex(out)
+
+
+def scsf_sort(h: Handle, fields: torch.Tensor, p0: int, start: int = 0) -> np.ndarray:
+    fields = fields.contiguous()
+    n_op, C, p, _ = fields.shape
+    order = (c_int32 * n_op)()
+    _check(lib().scsf_sort(h.ptr, _ptr(fields), n_op, C, p, p0, int(start), order), "scsf_sort")
+    return np.frombuffer(order, dtype=np.int32).copy()
+
+
+def make_params(L, k, degree=20, tol=1e-8, max_iter=200, lanczos_steps=20, seed=0,
+                precision=SCSF_FP64) -> Params:
+    return Params(L=L, k=k, degree=degree, max_iter=max_iter, lanczos_steps=lanczos_steps,
+                  precision=precision, tol=tol, seed=seed)
+
+
+def scsf_solve(h: Handle, A: DeviceOperator, prm: Params, X_prev=None, theta_prev=None,
+               allow_notconv=False):
+    """Returns (evals[L], evecs n x L, X_next n x k, theta_next[k], stats dict)."""
+    n, L, k = A.n, prm.L, prm.k
+    dev = torch.device("cuda")
+    evals = torch.empty(L, device=dev, dtype=torch.float64)
+    evecs = colmajor(n, L)
+    X_next = colmajor(n, k)
+    theta_next = torch.empty(k, device=dev, dtype=torch.float64)
+    if X_prev is not None:
+        X_prev = as_colmajor(X_prev)
+        assert _ld(X_prev) == n
+    st = Stats()
+    allow = (SCSF_OK, SCSF_ENOTCONV) if allow_notconv else (SCSF_OK,)
+    _check(lib().scsf_solve(h.ptr, A.ref(), ctypes.byref(prm), _ptr(X_prev), _ptr(theta_prev),
+                            _ptr(evals), _ptr(evecs), _ptr(X_next), _ptr(theta_next),
+                            ctypes.byref(st)), "scsf_solve", allow)
+    return evals, evecs, X_next, theta_next, st.as_dict()
+
+
+def scsf_solve_sequence(h: Handle, ops: list, order, chains: int, prm: Params,
+                        evals: torch.Tensor | None = None, evecs: torch.Tensor | None = None,
+                        allow_notconv=False):
+    """Solve every operator in `ops` (DeviceOperator list) in `order`, `chains` chunks.
+    Returns (evals n_op x L, evecs n_op x (n x L column-major) tensor, list of stats dicts)."""
+    n_op = len(ops)
+    n, L = ops[0].n, prm.L
+    arr = (Operator * n_op)(*[o.struct for o in ops])
+    order = np.asarray(order, dtype=np.int32)
+    ordc = (c_int32 * n_op)(*order.tolist())
+    if evals is None:
+        evals = torch.empty((n_op, L), device="cuda", dtype=torch.float64)
+    if evecs is None:
+        evecs = torch.empty((n_op, L, n), device="cuda", dtype=torch.float64)
+    stats = (Stats * n_op)()
+    allow = (SCSF_OK, SCSF_ENOTCONV) if allow_notconv else (SCSF_OK,)
+    _check(lib().scsf_solve_sequence(h.ptr, arr, n_op, ordc, int(chains), ctypes.byref(prm),
+                                     _ptr(evals), _ptr(evecs), stats), "scsf_solve_sequence",
+           allow)
+    return evals, evecs, [s.as_dict() for s in stats]
+
+
+def scsf_profile_enable(h: Handle, on: bool = True):
+    _check(lib().scsf_profile_enable(h.ptr, 1 if on else 0), "scsf_profile_enable")
+
+
+def scsf_profile_read(h: Handle, reset: bool = False) -> dict:
+    p = Profile()
+    _check(lib().scsf_profile_read(h.ptr, ctypes.byref(p), 1 if reset else 0), "scsf_profile_read")
+    return {"filter_launches": p.filter_launches, "filter_ms": p.filter_ms,
+            "filter_bytes": p.filter_bytes}
+
+
+def version() -> str:
+    return lib().scsf_version().decode()

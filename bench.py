@@ -83,7 +83,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--count", type=int, default=None, help="operators (default: all)")
-    ap.add_argument("--chains", type=int, default=8)
+    ap.add_argument("--chains", type=int, default=16)
+    ap.add_argument("--lanes", type=int, default=4)
     ap.add_argument("--degree", type=int, default=None)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -103,6 +104,7 @@ def main():
     degree = args.degree or cfg.degree
     n_op = len(ops)
     h = scsf.Handle()
+    scsf.scsf_set_lanes(h, args.lanes)
     fields = torch.tensor(np.stack([o.field for o in ops]), device="cuda")
     dops = [scsf.DeviceOperator(o) for o in ops]
     prm = scsf.make_params(cfg.L, cfg.k, degree, cfg.tol, seed=1)
@@ -160,6 +162,7 @@ def main():
                         f"(n={dops[0].n}), L={cfg.L}, k={cfg.k}, degree={degree}, p0={cfg.p0}, "
                         f"tol={cfg.tol:g}",
             "chains": args.chains,
+            "lanes": args.lanes,
             "mean_outer_iterations": float(np.mean(iters)),
         },
         "roofline": {

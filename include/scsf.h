@@ -112,6 +112,11 @@ int scsf_set_stream(scsf_handle *h, void *hip_stream);
 const char *scsf_status_string(int status);
 /* Library build/version string (host). */
 const char *scsf_version(void);
+/* Number of lockstep batches scsf_solve_sequence runs concurrently (1..8, default 4).  Batch 0
+ * uses the handle's stream; the others use streams the handle creates (default priority),
+ * ordered after the work already enqueued on the handle's stream, each driven by a host
+ * thread of its own. */
+int scsf_set_lanes(scsf_handle *h, int lanes);
 /* Turn filter-step timing on (on != 0) or off; synchronises the stream. */
 int scsf_profile_enable(scsf_handle *h, int on);
 /* Copy the accumulated filter timing to *out_host; reset != 0 clears it afterwards. */
@@ -179,8 +184,8 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
 
 /* A whole dataset (Fig. 2 c-d): ops_host[n_op] (host array of operator descriptors, all of
  * the same kind and n) are solved in the order order_host[n_op] split into `chains`
- * contiguous chunks (App. C.5 chunking); the chunks run concurrently in lockstep, each
- * chain warm-starting every solve from its previous one.  evals: n_op x L (row i = operator
+ * contiguous chunks (App. C.5 chunking); the chunks run concurrently (lockstep batches on
+ * up to scsf_set_lanes streams), each chain warm-starting every solve from its previous one.  evals: n_op x L (row i = operator
  * i), evecs: n_op x (n x L) (block i = operator i, ld n).  stats_host[n_op] may be NULL.
  * Returns SCSF_ENOTCONV if any solve did not converge. */
 int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,

@@ -86,9 +86,13 @@ hipError_t chol_inv(int B, int64_t n, int32_t k, const int32_t *lock, const doub
 
 // Per problem: symmetric eigendecomposition of the ACTIVE projected matrix G_b (ka x ka) by
 // parallel cyclic Jacobi.  Eigenvalues ascending into theta[b*k + lock[b] + j], eigenvectors
-// into Z_b (ldm x ldm).  scratch: B * 2 * kMaxK * (kMaxK+1) doubles.
+// into Z_b (ldm x ldm).  scratch: B * kMaxK * (kMaxK+1) doubles (matrices too large for LDS);
+// rec: B * jacobi_record_elems(k) doubles (recorded rotations); ranks: B * ldm ints;
+// nsweeps: B ints.  flag bit 8: not converged within the sweep limit.
 hipError_t jacobi_eig(int B, int32_t k, const int32_t *lock, double *G, double *Z, int32_t ldm,
-                      double *theta, int32_t *flag, double *scratch, hipStream_t st);
+                      double *theta, int32_t *flag, double *scratch, double *rec,
+                      int32_t *ranks, int32_t *nsweeps, hipStream_t st);
+int64_t jacobi_record_elems(int32_t k);
 
 // res[b*k + c] = ||W c - theta c X c|| / ||W c|| for the active columns.
 hipError_t residuals(int B, int64_t n, int64_t ld, const double *X, const double *W,

@@ -13,13 +13,20 @@ constexpr int kLdsDoubles = 19456;                  // 152 KB of matrix storage 
 __device__ inline int64_t upk(int i, int j) { return (int64_t)j * (j + 1) / 2 + i; }  // i <= j
 
 // flag bits: 1 = Cholesky breakdown, 2 = NaN/Inf, 4 = shifted factorisation used
+//
+// Thread layout: 512 threads as 16 (tx) x 32 (ty); loops over packed-triangle elements walk
+// rows with tx and columns with ty, so no index needs an integer division.  Each step of the
+// factorisation and of the inversion needs a single barrier: the step's trailing update uses
+// the not-yet-scaled pivot row divided by the pivot, and the row is scaled one step later,
+// when nobody reads it any more.
 template <bool LDS>
-__global__ void __launch_bounds__(256) chol_inv_kernel(
+__global__ void __launch_bounds__(512) chol_inv_kernel(
     int64_t n, int32_t k, const int32_t *__restrict__ lock, const double *__restrict__ G,
     double *__restrict__ M, int32_t ldm, int32_t *__restrict__ flag,
     const int32_t *__restrict__ gate, int32_t gate_mask, double *__restrict__ gscr) {
   __shared__ double lds[LDS ? kLdsDoubles : 1];
   __shared__ double dsc[kMaxK];
+  __shared__ double piv[kMaxK];
   __shared__ int s_fail;
   __shared__ double s_shift;
   const int b = blockIdx.x;
@@ -28,6 +35,7 @@ __global__ void __launch_bounds__(256) chol_inv_kernel(
   const int ka = k - l;
   if (ka <= 0) return;
   const int tid = threadIdx.x, NT = blockDim.x;
+  const int tx = tid & 15, ty = tid >> 4;              // 16 x 32
   double *S = LDS ? lds : gscr + (int64_t)b * kMaxK * (kMaxK + 1);
   double *T = S + (int64_t)ka * (ka + 1) / 2;
   const double *Gb = G + (int64_t)b * ldm * ldm;
@@ -40,36 +48,40 @@ __global__ void __launch_bounds__(256) chol_inv_kernel(
     for (int j = tid; j < ka; j += NT) {
       const double d = Gb[j + (int64_t)j * ldm] + sh;
       if (!isfinite(d)) atomicOr(&s_fail, 2);
-      dsc[j] = (d > 0.0) ? sqrt(d) : 1.0;
       if (!(d > 0.0)) atomicOr(&s_fail, 1);
+      dsc[j] = (d > 0.0) ? sqrt(d) : 1.0;
     }
     __syncthreads();
-    for (int64_t e = tid; e < (int64_t)ka * ka; e += NT) {
-      const int i = (int)(e % ka), j = (int)(e / ka);
-      if (i <= j) S[upk(i, j)] = (Gb[i + (int64_t)j * ldm] + (i == j ? sh : 0.0)) / (dsc[i] * dsc[j]);
-    }
+    for (int c = ty; c < ka; c += 32)
+      for (int i = tx; i <= c; i += 16)
+        S[upk(i, c)] = (Gb[i + (int64_t)c * ldm] + (i == c ? sh : 0.0)) / (dsc[i] * dsc[c]);
     __syncthreads();
-    // right-looking Cholesky, S <- R (upper), R^T R = scaled Gram
+    // right-looking Cholesky of the scaled Gram matrix; S <- R (upper), R^T R = S
     for (int j = 0; j < ka; ++j) {
-      if (tid == 0) {
-        const double piv = S[upk(j, j)];
-        if (!(piv > 0.0)) { atomicOr(&s_fail, isfinite(piv) ? 1 : 3); S[upk(j, j)] = 1.0; }
-        else S[upk(j, j)] = sqrt(piv);
+      const double p = S[upk(j, j)];
+      if (j > 0) {                                       // scale the previous pivot row
+        const double rp = sqrt(piv[j - 1]);
+        for (int c = j + tid; c < ka; c += NT) S[upk(j - 1, c)] /= rp;
+        if (tid == 0) S[upk(j - 1, j - 1)] = rp;
       }
-      __syncthreads();
-      const double rjj = S[upk(j, j)];
-      for (int c = j + 1 + tid; c < ka; c += NT) S[upk(j, c)] /= rjj;
-      __syncthreads();
-      const int m = ka - j - 1;
-      for (int64_t e = tid; e < (int64_t)m * m; e += NT) {
-        const int i = j + 1 + (int)(e % m), c = j + 1 + (int)(e / m);
-        if (i <= c) S[upk(i, c)] -= S[upk(j, i)] * S[upk(j, c)];
+      if (tid == 0) {
+        double pv = p;
+        if (!(pv > 0.0)) { atomicOr(&s_fail, isfinite(pv) ? 1 : 3); pv = 1.0; }
+        piv[j] = pv;
+      }
+      const double pv = (p > 0.0) ? p : 1.0;
+      const double inv = 1.0 / pv;
+      for (int c = j + 1 + ty; c < ka; c += 32) {
+        const double rc = S[upk(j, c)] * inv;
+        for (int i = j + 1 + tx; i <= c; i += 16) S[upk(i, c)] -= S[upk(j, i)] * rc;
       }
       __syncthreads();
     }
-    if (attempt == 0 && (s_fail & 1) && !(s_fail & 2)) {
+    if (tid == 0) S[upk(ka - 1, ka - 1)] = sqrt(piv[ka - 1]);
+    const int fnow = s_fail;
+    __syncthreads();                                     // every thread has read s_fail
+    if (attempt == 0 && (fnow & 1) && !(fnow & 2)) {
       // shifted CholeskyQR: s = 11 (n k + k (k+1)) u ||X||_F^2 (Fukaya et al. 2020)
-      __syncthreads();
       if (tid == 0) {
         double tr = 0.0;
         for (int j = 0; j < ka; ++j) tr += Gb[j + (int64_t)j * ldm];
@@ -81,29 +93,32 @@ __global__ void __launch_bounds__(256) chol_inv_kernel(
     }
     break;
   }
-  // T <- R^-1 (upper), column sweep from the last row up
-  const int64_t npk2 = (int64_t)ka * (ka + 1) / 2;
-  for (int64_t e = tid; e < npk2; e += NT) T[e] = 0.0;
+  // T <- R^-1 (upper) by a sweep from the last row up: row i of T is final once divided by
+  // R_ii; the rows above subtract R_ri times it.  Row i is divided one step later.
+  for (int c = ty; c < ka; c += 32)
+    for (int i = tx; i <= c; i += 16) T[upk(i, c)] = (i == c) ? 1.0 : 0.0;
   __syncthreads();
-  for (int j = tid; j < ka; j += NT) T[upk(j, j)] = 1.0;
   for (int i = ka - 1; i >= 0; --i) {
-    __syncthreads();
     const double rii = S[upk(i, i)];
-    for (int c = i + tid; c < ka; c += NT) T[upk(i, c)] /= rii;
-    __syncthreads();
-    if (i > 0) {
-      const int w = ka - i;
-      for (int64_t e = tid; e < (int64_t)i * w; e += NT) {
-        const int r = (int)(e % i), c = i + (int)(e / i);
-        T[upk(r, c)] -= S[upk(r, i)] * T[upk(i, c)];
-      }
+    if (i < ka - 1) {
+      const double rn = S[upk(i + 1, i + 1)];
+      for (int c = i + 1 + tid; c < ka; c += NT) T[upk(i + 1, c)] /= rn;
     }
+    const double inv = 1.0 / rii;
+    for (int c = i + ty; c < ka; c += 32) {
+      const double tic = T[upk(i, c)] * inv;
+      for (int r = tx; r < i; r += 16) T[upk(r, c)] -= S[upk(r, i)] * tic;
+    }
+    __syncthreads();
+  }
+  {
+    const double r0 = S[upk(0, 0)];
+    for (int c = tid; c < ka; c += NT) T[upk(0, c)] /= r0;
   }
   __syncthreads();
-  for (int64_t e = tid; e < (int64_t)ka * ka; e += NT) {
-    const int r = (int)(e % ka), c = (int)(e / ka);
-    Mb[r + (int64_t)c * ldm] = (r <= c) ? T[upk(r, c)] / dsc[r] : 0.0;
-  }
+  for (int c = ty; c < ka; c += 32)
+    for (int r = tx; r < ka; r += 16)
+      Mb[r + (int64_t)c * ldm] = (r <= c) ? T[upk(r, c)] / dsc[r] : 0.0;
   if (tid == 0 && s_fail) atomicOr(&flag[b], s_fail);
 }
 
@@ -113,140 +128,237 @@ hipError_t chol_inv(int B, int64_t n, int32_t k, const int32_t *lock, const doub
   if (B <= 0) return hipSuccess;
   // the packed R and R^-1 fit in LDS for every ka when k(k+1) <= kLdsDoubles
   if ((int64_t)k * (k + 1) <= kLdsDoubles)
-    chol_inv_kernel<true><<<B, 256, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask, scratch);
+    chol_inv_kernel<true><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask, scratch);
   else
-    chol_inv_kernel<false><<<B, 256, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask,
+    chol_inv_kernel<false><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask,
                                               scratch);
   return hipGetLastError();
 }
 
 // -------------------------------------------------------------------------------- Jacobi
+// Parallel cyclic Jacobi in two kernels.
+//   jacobi_values : one workgroup per problem keeps the symmetric matrix (upper triangle,
+//                   packed) in LDS.  Each round of the round-robin ordering rotates K/2
+//                   disjoint index pairs; every 2x2 block (pair a, pair b), a <= b, is read once,
+//                   transformed by J_a^T B J_b and written once, so a round touches each stored
+//                   entry once.  The rotations are recorded; after every sweep the largest
+//                   relative off-diagonal entry is checked directly.
+//   jacobi_vectors: the eigenvector matrix Z = product of the recorded rotations, built by
+//                   many workgroups at once (each row of Z evolves on its own).
 __device__ inline void rr_pair(int r, int s, int K, int &p, int &q) {
   // round-robin tournament: every pair of 0..K-1 meets once in rounds 0..K-2
   if (s == 0) { p = K - 1; q = r; }
   else { p = (r + s) % (K - 1); q = (r - s + (K - 1)) % (K - 1); }
 }
 
-template <bool G_LDS, bool Z_LDS>
-__global__ void __launch_bounds__(512) jacobi_kernel(
-    int32_t k, const int32_t *__restrict__ lock, const double *__restrict__ Gin,
-    double *__restrict__ Zout, int32_t ldm, double *__restrict__ theta, int32_t *__restrict__ flag,
+__device__ inline int pk(int i, int j) {              // packed upper triangle, any order
+  return (i <= j) ? (j * (j + 1) / 2 + i) : (i * (i + 1) / 2 + j);
+}
+
+constexpr int kJacobiMaxSweeps = 24;
+constexpr double kJacobiTol = 1e-15;                   // relative off-diagonal threshold
+
+int64_t jacobi_record_elems(int32_t k) {
+  const int64_t K = k + (k & 1);
+  return (int64_t)kJacobiMaxSweeps * (K - 1) * (K / 2) * 2 + (int64_t)kJacobiMaxSweeps * (K - 1);
+}
+
+template <bool LDS>
+__global__ void __launch_bounds__(512) jacobi_values_kernel(
+    int32_t k, const int32_t *__restrict__ lock, const double *__restrict__ Gin, int32_t ldm,
+    double *__restrict__ theta, int32_t *__restrict__ rank_out, double *__restrict__ rec,
+    int64_t rec_stride, int32_t *__restrict__ nsweeps, int32_t *__restrict__ flag,
     double *__restrict__ gscr) {
-  __shared__ double lds[(G_LDS || Z_LDS) ? kLdsDoubles : 1];
-  __shared__ int rp[kMaxK / 2 + 1], rq[kMaxK / 2 + 1], ract[kMaxK / 2 + 1];
+  __shared__ double lds[LDS ? kLdsDoubles : 1];
+  __shared__ int rp[kMaxK / 2 + 1], rq[kMaxK / 2 + 1];
   __shared__ double rc[kMaxK / 2 + 1], rs[kMaxK / 2 + 1];
-  __shared__ int s_nrot;
-  __shared__ int rank[kMaxK];
+  __shared__ int s_any[2];
+  __shared__ double sh[8];
   const int b = blockIdx.x;
   const int32_t l = lock ? lock[b] : 0;
   const int ka = k - l;
-  if (ka <= 0) return;
   const int tid = threadIdx.x, NT = blockDim.x;
-  const int sg = ka | 1;                               // odd stride against bank conflicts
-  double *Gs = G_LDS ? lds : gscr + (int64_t)b * 2 * kMaxK * (kMaxK + 1);
-  double *Zs = Z_LDS ? (G_LDS ? lds + (int64_t)ka * sg : lds)
-                     : gscr + (int64_t)b * 2 * kMaxK * (kMaxK + 1) + (int64_t)kMaxK * (kMaxK + 1);
+  if (ka <= 0) { if (tid == 0) nsweeps[b] = 0; return; }
+  const int tx = tid & 15, ty = tid >> 4;              // 16 x 32
+  const int K = ka + (ka & 1), half = K / 2;
+  double *S = LDS ? lds : gscr + (int64_t)b * kMaxK * (kMaxK + 1);
   const double *Gb = Gin + (int64_t)b * ldm * ldm;
-#define GG(i, j) Gs[(i) + (int64_t)(j) * sg]
-#define ZZ(i, j) Zs[(i) + (int64_t)(j) * sg]
-  for (int64_t e = tid; e < (int64_t)ka * ka; e += NT) {
-    const int i = (int)(e % ka), j = (int)(e / ka);
-    GG(i, j) = Gb[i + (int64_t)j * ldm];
-    ZZ(i, j) = (i == j) ? 1.0 : 0.0;
-  }
-  const int K = ka + (ka & 1);
-  const int half = K / 2;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    __syncthreads();                                  // every thread has read s_nrot
-    if (tid == 0) s_nrot = 0;
+  double *R = rec + (int64_t)b * rec_stride;           // (c, s) per (sweep, round, slot)
+  double *Ract = R + (int64_t)kJacobiMaxSweeps * (K - 1) * half * 2;
+  for (int c = ty; c < K; c += 32)
+    for (int i = tx; i <= c; i += 16)
+      S[pk(i, c)] = (i < ka && c < ka) ? Gb[i + (int64_t)c * ldm] : 0.0;  // zero dummy index
+  if (tid == 0) { s_any[0] = 0; s_any[1] = 0; }
+  __syncthreads();
+  int sweep = 0;
+  for (; sweep < kJacobiMaxSweeps; ++sweep) {
     for (int r = 0; r < K - 1; ++r) {
-      __syncthreads();
-      for (int s = tid; s < half; s += NT) {
+      // two barriers per round: (A) rotations ready, (B) block updates done.  The flag of
+      // the next round is reset before (A), after every thread read it before (B) last round.
+      const int par = r & 1;
+      for (int a = tid; a < half; a += NT) {
         int p, q;
-        rr_pair(r, s, K, p, q);
-        int act = 0;
+        rr_pair(r, a, K, p, q);
         double c = 1.0, sn = 0.0;
-        if (p < ka && q < ka) {
-          const double gpp = GG(p, p), gqq = GG(q, q), gpq = GG(p, q);
-          if (fabs(gpq) > 1e-15 * sqrt(fabs(gpp * gqq)) && fabs(gpq) > 1e-300) {
-            const double tau = (gqq - gpp) / (2.0 * gpq);
-            double t;
-            if (fabs(tau) > 1e150) t = 0.5 / tau;
-            else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            sn = c * t;
-            act = 1;
+        const double gpp = S[pk(p, p)], gqq = S[pk(q, q)], gpq = S[pk(p, q)];
+        if (fabs(gpq) > kJacobiTol * sqrt(fabs(gpp * gqq)) && fabs(gpq) > 1e-300) {
+          const double tau = (gqq - gpp) / (2.0 * gpq);
+          double t;
+          if (fabs(tau) > 1e150) t = 0.5 / tau;
+          else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          sn = c * t;
+          s_any[par] = 1;
+        }
+        rp[a] = p; rq[a] = q; rc[a] = c; rs[a] = sn;
+        double *o = R + (((int64_t)sweep * (K - 1) + r) * half + a) * 2;
+        o[0] = c;
+        o[1] = sn;
+      }
+      if (tid == 0) s_any[par ^ 1] = 0;
+      __syncthreads();                                   // (A)
+      const int any = s_any[par];
+      if (tid == 0) Ract[(int64_t)sweep * (K - 1) + r] = any ? 1.0 : 0.0;
+      if (any) {
+      for (int bb = ty; bb < half; bb += 32) {
+        const double cb = rc[bb], sb = rs[bb];
+        const int pb = rp[bb], qb = rq[bb];
+        for (int aa = tx; aa <= bb; aa += 16) {
+          const double ca = rc[aa], sa = rs[aa];
+          if (sa == 0.0 && sb == 0.0) continue;
+          const int pa = rp[aa], qa = rq[aa];
+          if (aa == bb) {                                // the pair's own 2x2 block
+            const int ipp = pk(pa, pa), iqq = pk(qa, qa), ipq = pk(pa, qa);
+            const double gpp = S[ipp], gqq = S[iqq], gpq = S[ipq];
+            const double t = sa / ca;
+            S[ipp] = gpp - t * gpq;
+            S[iqq] = gqq + t * gpq;
+            S[ipq] = 0.0;
+          } else {
+            const int i11 = pk(pa, pb), i12 = pk(pa, qb), i21 = pk(qa, pb), i22 = pk(qa, qb);
+            const double g11 = S[i11], g12 = S[i12], g21 = S[i21], g22 = S[i22];
+            const double r11 = ca * g11 - sa * g21, r12 = ca * g12 - sa * g22;
+            const double r21 = sa * g11 + ca * g21, r22 = sa * g12 + ca * g22;
+            S[i11] = cb * r11 - sb * r12;
+            S[i12] = sb * r11 + cb * r12;
+            S[i21] = cb * r21 - sb * r22;
+            S[i22] = sb * r21 + cb * r22;
           }
         }
-        rp[s] = p; rq[s] = q; rc[s] = c; rs[s] = sn; ract[s] = act;
-        if (act) atomicAdd(&s_nrot, 1);
       }
-      __syncthreads();
-      // rows p, q of J^T G
-      for (int64_t e = tid; e < (int64_t)half * ka; e += NT) {
-        const int s = (int)(e / ka), j = (int)(e % ka);
-        if (!ract[s]) continue;
-        const int p = rp[s], q = rq[s];
-        const double c = rc[s], sn = rs[s];
-        const double gp = GG(p, j), gq = GG(q, j);
-        GG(p, j) = c * gp - sn * gq;
-        GG(q, j) = sn * gp + c * gq;
       }
-      __syncthreads();
-      // columns p, q of (J^T G) J and of Z J
-      for (int64_t e = tid; e < (int64_t)half * ka; e += NT) {
-        const int s = (int)(e / ka), i = (int)(e % ka);
-        if (!ract[s]) continue;
-        const int p = rp[s], q = rq[s];
-        const double c = rc[s], sn = rs[s];
-        const double gp = GG(i, p), gq = GG(i, q);
-        GG(i, p) = c * gp - sn * gq;
-        GG(i, q) = sn * gp + c * gq;
-        const double zp = ZZ(i, p), zq = ZZ(i, q);
-        ZZ(i, p) = c * zp - sn * zq;
-        ZZ(i, q) = sn * zp + c * zq;
-      }
-      __syncthreads();
-      for (int s = tid; s < half; s += NT)
-        if (ract[s]) { GG(rp[s], rq[s]) = 0.0; GG(rq[s], rp[s]) = 0.0; }
+      __syncthreads();                                   // (B)
     }
+    // largest relative off-diagonal entry after this sweep
+    double off = 0.0;
+    for (int c = ty; c < ka; c += 32)
+      for (int i = tx; i < c; i += 16) {
+        const double den = sqrt(fabs(S[pk(i, i)] * S[pk(c, c)]));
+        const double v = fabs(S[pk(i, c)]);
+        off = fmax(off, (v > 1e-300) ? v / fmax(den, 1e-300) : 0.0);
+      }
+    for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_down(off, o, 64));
+    if ((tid & 63) == 0) sh[tid >> 6] = off;
     __syncthreads();
-    const int nrot = s_nrot;
-    if (nrot == 0) break;
+    double m = sh[0];
+    for (int w = 1; w < NT / 64; ++w) m = fmax(m, sh[w]);
+    __syncthreads();
+    if (!(m > 10.0 * kJacobiTol)) { ++sweep; break; }
   }
-  __syncthreads();
+  if (tid == 0) {
+    nsweeps[b] = sweep;
+    if (sweep >= kJacobiMaxSweeps) atomicOr(&flag[b], 8);
+  }
   // ascending order: rank_j = #{i : theta_i < theta_j or (== and i < j)}
   for (int j = tid; j < ka; j += NT) {
-    const double tj = GG(j, j);
+    const double tj = S[pk(j, j)];
     int rk = 0;
     for (int i = 0; i < ka; ++i) {
-      const double ti = GG(i, i);
+      const double ti = S[pk(i, i)];
       rk += (ti < tj) || (ti == tj && i < j);
     }
-    rank[j] = rk;
+    rank_out[(int64_t)b * ldm + j] = rk;
     theta[(int64_t)b * k + l + rk] = tj;
     if (!isfinite(tj)) atomicOr(&flag[b], 2);
   }
-  __syncthreads();
-  double *Zb = Zout + (int64_t)b * ldm * ldm;
-  for (int64_t e = tid; e < (int64_t)ka * ka; e += NT) {
-    const int i = (int)(e % ka), j = (int)(e / ka);
-    Zb[i + (int64_t)rank[j] * ldm] = ZZ(i, j);
+}
+
+// grid (ceil(kmax / 8), 1, B): 8 rows of Z per workgroup, 64 slots per row (one per lane).
+__global__ void __launch_bounds__(512) jacobi_vectors_kernel(
+    int32_t k, const int32_t *__restrict__ lock, const double *__restrict__ rec, int64_t rec_stride,
+    const int32_t *__restrict__ nsweeps, const int32_t *__restrict__ rank_in,
+    double *__restrict__ Zout, int32_t ldm) {
+  constexpr int RW = 8, CH = 8;                        // rows per workgroup, rounds per stage
+  __shared__ double z[RW][kMaxK + 1];
+  __shared__ double cs[CH][kMaxK / 2][2];
+  __shared__ double act[CH];
+  const int b = blockIdx.z;
+  const int32_t l = lock ? lock[b] : 0;
+  const int ka = k - l;
+  const int row0 = blockIdx.x * RW;
+  if (ka <= 0 || row0 >= ka) return;
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, lane = tid & 63;             // row w of this block, slot lane(+64)
+  const int K = ka + (ka & 1), half = K / 2;
+  const int rounds = nsweeps[b] * (K - 1);
+  const double *R = rec + (int64_t)b * rec_stride;
+  const double *Ract = R + (int64_t)kJacobiMaxSweeps * (K - 1) * half * 2;
+  for (int e = tid; e < RW * K; e += 512) {
+    const int rr = e / K, j = e % K;
+    z[rr][j] = (row0 + rr == j) ? 1.0 : 0.0;
   }
-#undef GG
-#undef ZZ
+  const int gi = row0 + w;                             // global row of this thread's z row
+  for (int g0 = 0; g0 < rounds; g0 += CH) {
+    const int nr = min(CH, rounds - g0);
+    __syncthreads();
+    for (int e = tid; e < nr * half * 2; e += 512) {
+      const int rr = e / (half * 2), q = e % (half * 2);
+      cs[rr][q >> 1][q & 1] = R[((int64_t)(g0 + rr) * half) * 2 + q];
+    }
+    if (tid < nr) act[tid] = Ract[g0 + tid];
+    __syncthreads();
+    for (int rr = 0; rr < nr; ++rr) {
+      if (act[rr] != 0.0 && gi < ka) {
+        const int r = (g0 + rr) % (K - 1);
+        for (int a = lane; a < half; a += 64) {
+          const double c = cs[rr][a][0], sn = cs[rr][a][1];
+          if (sn == 0.0) continue;
+          int p, q;
+          rr_pair(r, a, K, p, q);
+          const double zp = z[w][p], zq = z[w][q];
+          z[w][p] = c * zp - sn * zq;
+          z[w][q] = sn * zp + c * zq;
+        }
+      }
+      // rotations of one round touch disjoint columns of a row; the wave owning the row is
+      // the only writer, so the next round only needs the wave's own ordering
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  if (gi < ka) {
+    double *Zb = Zout + (int64_t)b * ldm * ldm;
+    const int32_t *rk = rank_in + (int64_t)b * ldm;
+    for (int j = lane; j < ka; j += 64) Zb[gi + (int64_t)rk[j] * ldm] = z[w][j];
+  }
 }
 
 hipError_t jacobi_eig(int B, int32_t k, const int32_t *lock, double *G, double *Z, int32_t ldm,
-                      double *theta, int32_t *flag, double *scratch, hipStream_t st) {
+                      double *theta, int32_t *flag, double *scratch, double *rec,
+                      int32_t *ranks, int32_t *nsweeps, hipStream_t st) {
   if (B <= 0) return hipSuccess;
-  const int sg = k | 1;
-  if ((int64_t)2 * k * sg <= kLdsDoubles)
-    jacobi_kernel<true, true><<<B, 512, 0, st>>>(k, lock, G, Z, ldm, theta, flag, scratch);
-  else if ((int64_t)k * sg <= kLdsDoubles)
-    jacobi_kernel<true, false><<<B, 512, 0, st>>>(k, lock, G, Z, ldm, theta, flag, scratch);
+  const int64_t rs = jacobi_record_elems(k);
+  const int K = k + (k & 1);
+  if ((int64_t)K * (K + 1) / 2 <= kLdsDoubles)
+    jacobi_values_kernel<true><<<B, 512, 0, st>>>(k, lock, G, ldm, theta, ranks, rec, rs, nsweeps,
+                                                  flag, scratch);
   else
-    jacobi_kernel<false, false><<<B, 512, 0, st>>>(k, lock, G, Z, ldm, theta, flag, scratch);
+    jacobi_values_kernel<false><<<B, 512, 0, st>>>(k, lock, G, ldm, theta, ranks, rec, rs,
+                                                   nsweeps, flag, scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  jacobi_vectors_kernel<<<dim3((unsigned)ceil_div(k, 8), 1, B), 512, 0, st>>>(
+      k, lock, rec, rs, nsweeps, ranks, Z, ldm);
   return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -20,7 +21,7 @@ namespace {
 
 enum BufId {
   B_X, B_Y1, B_Y2, B_W, B_G, B_M, B_PART, B_THETA, B_RES, B_INT, B_BND, B_COEF, B_UNIT, B_CHOL,
-  B_JAC, B_LZ, B_OPS, B_WIN, B_SORTF, B_SORTD, B_SORTO, B_COUNT
+  B_JAC, B_LZ, B_OPS, B_WIN, B_SORTF, B_SORTD, B_SORTO, B_REC, B_RANK, B_COUNT
 };
 
 struct DevBuf {
@@ -28,20 +29,26 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
-}  // namespace
-
-struct scsf_handle {
+// Device buffers, pinned host staging, a stream and filter timing of one concurrent lane.
+struct Workspace {
   hipStream_t stream = nullptr;
-  int device = 0;
+  bool own_stream = false;
   DevBuf bufs[B_COUNT];
   void *pinned = nullptr;
   size_t pinned_bytes = 0;
-  // filter-launch timing (scsf_profile_*): event pairs around each Chebyshev step launch
-  bool prof = false;
+  bool prof = false;                     // filter-launch timing (scsf_profile_*)
   std::vector<hipEvent_t> ev;            // 2 per pending launch
   std::vector<double> ev_bytes;          // algorithmic bytes of each pending launch
   int ev_used = 0;
   scsf_profile acc{};
+};
+
+}  // namespace
+
+struct scsf_handle {
+  int device = 0;
+  int lanes = 4;                         // concurrent chain groups in scsf_solve_sequence
+  std::vector<Workspace *> ws;           // ws[0] runs on the caller's stream
 };
 
 namespace {
@@ -58,7 +65,7 @@ namespace {
   } while (0)
 
 template <typename T>
-int grow(scsf_handle *h, int id, size_t count, T **out) {
+int grow(Workspace *h, int id, size_t count, T **out) {
   DevBuf &b = h->bufs[id];
   const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
   if (b.bytes < bytes) {
@@ -79,7 +86,7 @@ int grow(scsf_handle *h, int id, size_t count, T **out) {
   return SCSF_OK;
 }
 
-int grow_pinned(scsf_handle *h, size_t bytes) {
+int grow_pinned(Workspace *h, size_t bytes) {
   if (h->pinned_bytes >= bytes) return SCSF_OK;
   if (h->pinned) {
     if (hipStreamSynchronize(h->stream) != hipSuccess) return SCSF_EHIP;
@@ -124,7 +131,7 @@ OpDev to_dev(const scsf_operator &A) {
 
 // Event pairs are recorded around each filter launch and drained at the next
 // synchronisation point (no extra synchronisation is added).
-int prof_begin(scsf_handle *h, double bytes) {
+int prof_begin(Workspace *h, double bytes) {
   if (!h->prof) return -1;
   if ((size_t)(2 * h->ev_used + 2) > h->ev.size()) {
     for (int i = 0; i < 64; ++i) {
@@ -139,10 +146,10 @@ int prof_begin(scsf_handle *h, double bytes) {
   if (hipEventRecord(h->ev[2 * slot], h->stream) != hipSuccess) return -1;
   return slot;
 }
-void prof_end(scsf_handle *h, int slot) {
+void prof_end(Workspace *h, int slot) {
   if (slot >= 0) (void)hipEventRecord(h->ev[2 * slot + 1], h->stream);
 }
-void prof_drain(scsf_handle *h) {  // call only after the stream was synchronised
+void prof_drain(Workspace *h) {  // call only after the stream was synchronised
   for (int i = 0; i < h->ev_used; ++i) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) == hipSuccess) {
@@ -156,7 +163,7 @@ void prof_drain(scsf_handle *h) {  // call only after the stream was synchronise
 
 // ------------------------------------------------------------------------------- the engine
 struct Engine {
-  scsf_handle *h = nullptr;
+  Workspace *h = nullptr;
   hipStream_t st = nullptr;
   int B = 0;
   int64_t n = 0, ld = 0, bs = 0;
@@ -166,7 +173,8 @@ struct Engine {
   int64_t part_stride = 0;
   double *X = nullptr, *Y1 = nullptr, *Y2 = nullptr, *W = nullptr, *G = nullptr, *M = nullptr;
   double *part = nullptr, *theta = nullptr, *res = nullptr, *bnd = nullptr, *coef = nullptr;
-  double *unit = nullptr, *chol = nullptr, *jac = nullptr, *lz = nullptr;
+  double *unit = nullptr, *chol = nullptr, *jac = nullptr, *lz = nullptr, *rec = nullptr;
+  int32_t *ranks = nullptr, *nsweeps = nullptr;
   int32_t *lock = nullptr, *nconv = nullptr, *done = nullptr, *flag = nullptr, *need = nullptr;
   OpDev *ops = nullptr;
   // pinned host mirrors
@@ -175,7 +183,7 @@ struct Engine {
   double *h_theta = nullptr, *h_res = nullptr, *h_bnd = nullptr, *h_unit = nullptr;
   OpDev *h_ops = nullptr;
 
-  int setup(scsf_handle *hh, int B_, int64_t n_, int32_t k_, int32_t L_, int32_t m_, int32_t kind_,
+  int setup(Workspace *hh, int B_, int64_t n_, int32_t k_, int32_t L_, int32_t m_, int32_t kind_,
             double tol_, uint64_t seed_, int32_t lz_steps_) {
     h = hh;
     st = hh->stream;
@@ -213,7 +221,12 @@ struct Engine {
     STCHK(grow(h, B_COEF, (size_t)std::max(m, 1) * B * 3, &coef));
     STCHK(grow(h, B_UNIT, (size_t)B * 3, &unit));
     STCHK(grow(h, B_CHOL, (size_t)B * kMaxK * (kMaxK + 1), &chol));
-    STCHK(grow(h, B_JAC, (size_t)B * 2 * kMaxK * (kMaxK + 1), &jac));
+    STCHK(grow(h, B_JAC, (size_t)B * kMaxK * (kMaxK + 1), &jac));
+    STCHK(grow(h, B_REC, (size_t)B * jacobi_record_elems(k), &rec));
+    int32_t *rk = nullptr;
+    STCHK(grow(h, B_RANK, (size_t)B * ldm + B, &rk));
+    ranks = rk;
+    nsweeps = rk + (size_t)B * ldm;
     STCHK(grow(h, B_LZ, (size_t)B * 3 * n, &lz));
     STCHK(grow(h, B_OPS, (size_t)B, &ops));
     // pinned: 6 int arrays of B, perm B*k, theta/res B*k, bnd B*4, unit B*3, ops B
@@ -319,7 +332,7 @@ struct Engine {
                      st));
     HIPCHK(gemm_tn(B, n, ld, Yf, bs, COLS_ACTIVE, W, bs, COLS_ACTIVE, k, lock, true, part,
                    part_stride, G, ldm, nullptr, 0, st));
-    HIPCHK(jacobi_eig(B, k, lock, G, M, ldm, theta, flag, jac, st));
+    HIPCHK(jacobi_eig(B, k, lock, G, M, ldm, theta, flag, jac, rec, ranks, nsweeps, st));
     HIPCHK(gemm_nn(B, n, ld, Yf, bs, COLS_ACTIVE, X, bs, COLS_ACTIVE, k, lock, M, ldm, 1.0, 0.0,
                    nullptr, 0, nullptr, 0, st));
     HIPCHK(gemm_nn(B, n, ld, W, bs, COLS_ACTIVE, W, bs, COLS_ACTIVE, k, lock, M, ldm, 1.0, 0.0,
@@ -421,315 +434,26 @@ int check_params(const scsf_params *p, int64_t n) {
   return SCSF_OK;
 }
 
-}  // namespace
-
-// =============================================================================== C ABI
-extern "C" {
-
-const char *scsf_version(void) { return "libscsf 0.1 (gfx950, fp64 MFMA)"; }
-
-const char *scsf_status_string(int s) {
-  switch (s) {
-    case SCSF_OK: return "ok";
-    case SCSF_EINVAL: return "invalid argument";
-    case SCSF_ENOMEM: return "out of device memory";
-    case SCSF_ENOTCONV: return "not converged within max_iter";
-    case SCSF_EBREAKDOWN: return "Cholesky breakdown in orthonormalisation";
-    case SCSF_EHIP: return "HIP runtime error";
-    case SCSF_ENUMERIC: return "NaN or Inf in the iteration";
-    default: return "unknown status";
-  }
-}
-
-int scsf_create(scsf_handle **h, void *hip_stream) {
-  if (!h) return SCSF_EINVAL;
-  scsf_handle *x = new (std::nothrow) scsf_handle();
-  if (!x) return SCSF_ENOMEM;
-  x->stream = static_cast<hipStream_t>(hip_stream);
-  if (hipGetDevice(&x->device) != hipSuccess) {
-    delete x;
-    return SCSF_EHIP;
-  }
-  *h = x;
-  return SCSF_OK;
-}
-
-int scsf_profile_enable(scsf_handle *h, int on) {
-  if (!h) return SCSF_EINVAL;
-  if (hipStreamSynchronize(h->stream) != hipSuccess) return SCSF_EHIP;
-  prof_drain(h);
-  h->prof = on != 0;
-  return SCSF_OK;
-}
-
-int scsf_profile_read(scsf_handle *h, scsf_profile *out_host, int reset) {
-  if (!h || !out_host) return SCSF_EINVAL;
-  if (hipStreamSynchronize(h->stream) != hipSuccess) return SCSF_EHIP;
-  prof_drain(h);
-  *out_host = h->acc;
-  if (reset) h->acc = scsf_profile{};
-  return SCSF_OK;
-}
-
-int scsf_destroy(scsf_handle *h) {
-  if (!h) return SCSF_EINVAL;
-  for (auto e : h->ev) (void)hipEventDestroy(e);
-  (void)hipStreamSynchronize(h->stream);
-  for (auto &b : h->bufs)
-    if (b.p) (void)hipFree(b.p);
-  if (h->pinned) (void)hipHostFree(h->pinned);
-  delete h;
-  return SCSF_OK;
-}
-
-int scsf_set_stream(scsf_handle *h, void *hip_stream) {
-  if (!h) return SCSF_EINVAL;
-  if (hipStreamSynchronize(h->stream) != hipSuccess) return SCSF_EHIP;
-  h->stream = static_cast<hipStream_t>(hip_stream);
-  return SCSF_OK;
-}
-
-int scsf_spmm(scsf_handle *h, const scsf_operator *A, const double *X, int64_t ldx, int32_t ncols,
-              double *Y, int64_t ldy) {
-  if (!h) return SCSF_EINVAL;
-  STCHK(check_op(A));
-  if (!X || !Y || ncols < 0 || ldx < A->n || ldy < A->n) return SCSF_EINVAL;
-  if (ncols == 0) return SCSF_OK;
-  Engine e;
-  STCHK(e.setup(h, 1, A->n, 1, 0, 1, A->kind, 1.0, 0, 20));
-  e.h_ops[0] = to_dev(*A);
-  STCHK(e.upload_ops());
-  const double *src = X;
-  if (ldx != ldy) {
-    double *tmp = nullptr;
-    STCHK(grow(h, B_Y1, (size_t)ldy * ncols, &tmp));
-    HIPCHK(copy_block(A->n, ncols, X, ldx, tmp, ldy, false, h->stream));
-    src = tmp;
-  }
-  HIPCHK(spmm_step(e.ops, 1, A->kind, A->n, 0, src, nullptr, Y, ldy, 0, COLS_ALL, ncols, nullptr,
-                   e.unit, false, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  return SCSF_OK;
-}
-
-int scsf_filter(scsf_handle *h, const scsf_operator *A, const double *X, int64_t ldx,
-                int32_t ncols, int32_t degree, double lambda, double c, double e, double *Y,
-                int64_t ldy) {
-  if (!h) return SCSF_EINVAL;
-  STCHK(check_op(A));
-  if (!X || !Y || ncols < 0 || ncols > kMaxK || ldx < A->n || ldy < A->n) return SCSF_EINVAL;
-  if (degree < 1 || degree > 64 || !(e > 0.0) || lambda == c) return SCSF_EINVAL;
-  if (ncols == 0) return SCSF_OK;
-  Engine en;
-  STCHK(en.setup(h, 1, A->n, ncols, 0, degree, A->kind, 1.0, 0, 20));
-  en.h_ops[0] = to_dev(*A);
-  STCHK(en.upload_ops());
-  double *win = nullptr;
-  STCHK(grow(h, B_WIN, 3, &win));
-  en.h_bnd[0] = lambda;
-  en.h_bnd[1] = c;
-  en.h_bnd[2] = e;
-  HIPCHK(hipMemcpyAsync(win, en.h_bnd, 3 * sizeof(double), hipMemcpyHostToDevice, h->stream));
-  HIPCHK(cheb_coeffs_explicit(1, degree, win, en.coef, h->stream));
-  HIPCHK(copy_block(A->n, ncols, X, ldx, en.X, en.ld, true, h->stream));
-  double *ring[3] = {en.X, en.Y1, en.Y2};
-  for (int s = 0; s < degree; ++s)
-    HIPCHK(spmm_step(en.ops, 1, A->kind, A->n, 0, ring[s % 3], ring[(s + 2) % 3],
-                     ring[(s + 1) % 3], en.ld, en.bs, COLS_ALL, ncols, nullptr,
-                     en.coef + (size_t)s * 3, s > 0, h->stream));
-  HIPCHK(copy_block(A->n, ncols, ring[degree % 3], en.ld, Y, ldy, false, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  return SCSF_OK;
-}
-
-int scsf_orthonormalize(scsf_handle *h, int64_t n, double *X, int64_t ldx, int32_t ncols,
-                        const double *V, int64_t ldv, int32_t nlocked) {
-  if (!h || n <= 0 || !X || ncols <= 0 || nlocked < 0 || ldx < n) return SCSF_EINVAL;
-  if (nlocked > 0 && (!V || ldv < n)) return SCSF_EINVAL;
-  const int32_t k = ncols + nlocked;
-  if (k > kMaxK || k > n) return SCSF_EINVAL;
-  Engine e;
-  STCHK(e.setup(h, 1, n, k, 0, 1, SCSF_STENCIL5, 1.0, 0, 20));
-  if (nlocked > 0) HIPCHK(copy_block(n, nlocked, V, ldv, e.X, e.ld, true, h->stream));
-  HIPCHK(copy_block(n, ncols, X, ldx, e.X + (int64_t)nlocked * e.ld, e.ld, true, h->stream));
-  e.h_lock[0] = nlocked;
-  e.h_nconv[0] = nlocked;
-  STCHK(e.upload_state());
-  HIPCHK(fill_int(e.flag, 0, 1, h->stream));
-  STCHK(e.orth(e.X, nlocked > 0));
-  STCHK(e.download_state());
-  if (e.h_flag[0] & 2) return SCSF_ENUMERIC;
-  if (e.h_flag[0] & 1) return SCSF_EBREAKDOWN;
-  HIPCHK(copy_block(n, ncols, e.X + (int64_t)nlocked * e.ld, e.ld, X, ldx, false, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  return SCSF_OK;
-}
-
-int scsf_rayleigh_ritz(scsf_handle *h, const scsf_operator *A, double *X, int64_t ldx,
-                       int32_t ncols, double *theta, double *rel_resid) {
-  if (!h) return SCSF_EINVAL;
-  STCHK(check_op(A));
-  if (!X || ncols <= 0 || ncols > kMaxK || ncols > A->n || ldx < A->n) return SCSF_EINVAL;
-  Engine e;
-  STCHK(e.setup(h, 1, A->n, ncols, 0, 1, A->kind, 1.0, 0, 20));
-  e.h_ops[0] = to_dev(*A);
-  STCHK(e.upload_ops());
-  STCHK(e.upload_state());
-  HIPCHK(fill_int(e.flag, 0, 1, h->stream));
-  HIPCHK(copy_block(A->n, ncols, X, ldx, e.X, e.ld, true, h->stream));
-  STCHK(e.rayleigh_ritz(e.X));
-  HIPCHK(residuals(1, A->n, e.ld, e.X, e.W, e.bs, ncols, e.lock, e.theta, e.res, h->stream));
-  HIPCHK(copy_block(A->n, ncols, e.X, e.ld, X, ldx, false, h->stream));
-  if (theta) HIPCHK(hipMemcpyAsync(theta, e.theta, (size_t)ncols * 8, hipMemcpyDeviceToDevice,
-                                   h->stream));
-  if (rel_resid) HIPCHK(hipMemcpyAsync(rel_resid, e.res, (size_t)ncols * 8,
-                                       hipMemcpyDeviceToDevice, h->stream));
-  STCHK(e.download_state());
-  if (e.h_flag[0] & 2) return SCSF_ENUMERIC;
-  return SCSF_OK;
-}
-
-int scsf_bounds(scsf_handle *h, const scsf_operator *A, int32_t steps, uint64_t seed,
-                double *out_host) {
-  if (!h || !out_host) return SCSF_EINVAL;
-  STCHK(check_op(A));
-  if (steps < 1 || steps > 128) return SCSF_EINVAL;
-  Engine e;
-  STCHK(e.setup(h, 1, A->n, 1, 0, 1, A->kind, 1.0, seed, steps));
-  e.h_ops[0] = to_dev(*A);
-  e.h_need[0] = 1;
-  STCHK(e.upload_ops());
-  STCHK(e.upload_state());
-  HIPCHK(bounds(e.ops, 1, A->kind, A->n, steps, seed, e.need, e.lz, e.bnd, h->stream));
-  HIPCHK(hipMemcpyAsync(e.h_bnd, e.bnd, 32, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  out_host[0] = e.h_bnd[0];
-  out_host[1] = e.h_bnd[1];
-  out_host[2] = e.h_bnd[2];
-  out_host[3] = e.h_bnd[3];
-  return SCSF_OK;
-}
-
-int scsf_features(scsf_handle *h, const double *fields, int32_t n_op, int32_t channels, int32_t p,
-                  int32_t p0, double *feats) {
-  if (!h || !fields || !feats || n_op <= 0 || channels <= 0 || p <= 0 || p0 <= 0 || p0 > p)
-    return SCSF_EINVAL;
-  if ((int64_t)p * p0 * 16 > 64 * 1024) return SCSF_EINVAL;
-  HIPCHK(dft_features(fields, n_op, channels, p, p0, feats, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  return SCSF_OK;
-}
-
-int scsf_sort(scsf_handle *h, const double *fields, int32_t n_op, int32_t channels, int32_t p,
-              int32_t p0, int32_t start, int32_t *order_host) {
-  if (!h || !fields || !order_host || n_op <= 0 || channels <= 0 || p <= 0 || p0 <= 0 || p0 > p)
-    return SCSF_EINVAL;
-  if (start < 0 || start >= n_op || n_op > 32768) return SCSF_EINVAL;
-  if ((int64_t)p * p0 * 16 > 64 * 1024) return SCSF_EINVAL;
-  const int32_t flen = channels * p0 * p0;
-  double *F = nullptr, *D = nullptr;
-  int32_t *O = nullptr;
-  STCHK(grow(h, B_SORTF, (size_t)n_op * flen * 2, &F));
-  STCHK(grow(h, B_SORTD, (size_t)n_op * n_op, &D));
-  STCHK(grow(h, B_SORTO, (size_t)n_op, &O));
-  HIPCHK(dft_features(fields, n_op, channels, p, p0, F, h->stream));
-  HIPCHK(pair_distances(F, n_op, flen, D, h->stream));
-  HIPCHK(greedy_order(D, n_op, start, O, h->stream));
-  HIPCHK(hipMemcpyAsync(order_host, O, (size_t)n_op * 4, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  return SCSF_OK;
-}
-
-int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
-               const double *X_prev, const double *theta_prev, double *evals, double *evecs,
-               double *X_next, double *theta_next, scsf_stats *stats_host) {
-  if (!h) return SCSF_EINVAL;
-  STCHK(check_op(A));
-  STCHK(check_params(prm, A->n));
-  if ((X_prev == nullptr) != (theta_prev == nullptr)) return SCSF_EINVAL;
-  if (!evals || !evecs) return SCSF_EINVAL;
-  const int max_iter = prm->max_iter > 0 ? prm->max_iter : 200;
-  const int lzs = prm->lanczos_steps > 0 ? prm->lanczos_steps : 20;
-  Engine e;
-  STCHK(e.setup(h, 1, A->n, prm->k, prm->L, prm->degree, A->kind, prm->tol, prm->seed, lzs));
-  e.h_ops[0] = to_dev(*A);
-  e.h_need[0] = 1;
-  STCHK(e.upload_ops());
-  STCHK(e.upload_state());
-  STCHK(e.compute_bounds());
-  if (X_prev) {
-    HIPCHK(copy_block(A->n, prm->k, X_prev, A->n, e.X, e.ld, true, h->stream));
-    HIPCHK(hipMemcpyAsync(e.theta, theta_prev, (size_t)prm->k * 8, hipMemcpyDeviceToDevice,
-                          h->stream));
-  } else {
-    STCHK(e.cold_start({0}));
-  }
-  int it = 0;
-  int64_t fcols = 0;
-  while (it < max_iter) {
-    fcols += (int64_t)prm->degree * (prm->k - e.h_nconv[0]);
-    STCHK(e.iterate());
-    ++it;
-    if (e.h_done[0] || (e.h_flag[0] & 3)) break;
-  }
-  const bool conv = e.h_done[0] != 0;
-  const int status = solve_status(e.h_flag[0], conv);
-  STCHK(e.fetch(0));
-  double mr = 0.0;
-  STCHK(e.extract(0, evals, evecs, A->n, &mr));
-  if (X_next) HIPCHK(copy_block(A->n, prm->k, e.X, e.ld, X_next, A->n, false, h->stream));
-  if (theta_next)
-    HIPCHK(hipMemcpyAsync(theta_next, e.theta, (size_t)prm->k * 8, hipMemcpyDeviceToDevice,
-                          h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  if (stats_host) {
-    stats_host->iterations = it;
-    stats_host->nconv = e.h_nconv[0];
-    stats_host->status = status;
-    stats_host->chol_shifts = (e.h_flag[0] & 4) ? 1 : 0;
-    stats_host->filter_cols = fcols;
-    stats_host->beta = e.h_bnd[3];
-    stats_host->max_rel_resid = mr;
-  }
-  return status;
-}
-
-int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
-                        const int32_t *order_host, int32_t chains, const scsf_params *prm,
-                        double *evals, double *evecs, scsf_stats *stats_host) {
-  if (!h || !ops_host || n_op <= 0 || !order_host || chains <= 0 || !evals || !evecs)
-    return SCSF_EINVAL;
+// The chained solve of a set of chunks on one workspace (one lockstep batch, one stream):
+// chunk c covers order_host[cb[c] .. ce[c]).
+int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order_host,
+               const std::vector<int> &cb, const std::vector<int> &ce, const scsf_params *prm,
+               double *evals, double *evecs, scsf_stats *stats_host) {
+  const int chains = (int)cb.size();
+  if (chains == 0) return SCSF_OK;
   const int64_t n = ops_host[0].n;
   const int32_t kind = ops_host[0].kind;
-  for (int i = 0; i < n_op; ++i) {
-    STCHK(check_op(&ops_host[i]));
-    if (ops_host[i].n != n || ops_host[i].kind != kind) return SCSF_EINVAL;
-  }
-  STCHK(check_params(prm, n));
-  {
-    std::vector<char> seen(n_op, 0);
-    for (int i = 0; i < n_op; ++i) {
-      const int o = order_host[i];
-      if (o < 0 || o >= n_op || seen[o]) return SCSF_EINVAL;
-      seen[o] = 1;
-    }
-  }
-  chains = std::min(chains, n_op);
   const int max_iter = prm->max_iter > 0 ? prm->max_iter : 200;
   const int lzs = prm->lanczos_steps > 0 ? prm->lanczos_steps : 20;
   const int32_t L = prm->L, k = prm->k, m = prm->degree;
 
-  // contiguous chunks of the order, sizes differing by at most one (App. C.5)
-  std::vector<int> cbeg(chains + 1);
-  for (int c = 0; c <= chains; ++c) cbeg[c] = (int)((int64_t)n_op * c / chains);
-
   Engine e;
-  STCHK(e.setup(h, chains, n, k, L, m, kind, prm->tol, prm->seed, lzs));
+  STCHK(e.setup(w, chains, n, k, L, m, kind, prm->tol, prm->seed, lzs));
   std::vector<int> pos(chains), iters(chains, 0);
   std::vector<int64_t> fcols(chains, 0);
-  std::vector<char> active(chains, 1), cold(chains, 1);
+  std::vector<char> active(chains, 1);
   for (int b = 0; b < chains; ++b) {
-    pos[b] = cbeg[b];
+    pos[b] = cb[b];
     e.h_ops[b] = to_dev(ops_host[order_host[pos[b]]]);
     e.h_need[b] = 1;
   }
@@ -763,22 +487,20 @@ int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n
       double mr = 0.0;
       STCHK(e.extract(b, evals + (size_t)op * L, evecs + (size_t)op * n * L, n, &mr));
       if (stats_host) {
-        scsf_stats &s = stats_host[op];
-        s.iterations = iters[b];
-        s.nconv = e.h_nconv[b];
-        s.status = status;
-        s.chol_shifts = (e.h_flag[b] & 4) ? 1 : 0;
-        s.filter_cols = fcols[b];
-        s.beta = e.h_bnd[(size_t)b * 4 + 3];
-        s.max_rel_resid = mr;
+        scsf_stats &st = stats_host[op];
+        st.iterations = iters[b];
+        st.nconv = e.h_nconv[b];
+        st.status = status;
+        st.chol_shifts = (e.h_flag[b] & 4) ? 1 : 0;
+        st.filter_cols = fcols[b];
+        st.beta = e.h_bnd[(size_t)b * 4 + 3];
+        st.max_rel_resid = mr;
       }
       if (status != SCSF_OK && (worst == SCSF_OK || status != SCSF_ENOTCONV)) worst = status;
-      // the pinned regions used by extract are read by the copies: finish them before reuse
-      HIPCHK(hipStreamSynchronize(h->stream));
       ++pos[b];
       iters[b] = 0;
       fcols[b] = 0;
-      if (pos[b] >= cbeg[b + 1]) {
+      if (pos[b] >= ce[b]) {
         active[b] = 0;
         --remaining;
         e.h_done[b] = 1;
@@ -801,10 +523,399 @@ int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n
       if (!recold.empty()) STCHK(e.cold_start(recold));
       for (int b = 0; b < chains; ++b) e.h_need[b] = 0;
       STCHK(e.upload_state());
-      HIPCHK(hipStreamSynchronize(h->stream));
     }
   }
-  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipStreamSynchronize(w->stream));
+  return worst;
+}
+
+int add_lanes(scsf_handle *h, int count) {
+  while ((int)h->ws.size() < count) {
+    Workspace *w = new (std::nothrow) Workspace();
+    if (!w) return SCSF_ENOMEM;
+    if (hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete w;
+      return SCSF_EHIP;
+    }
+    w->own_stream = true;
+    w->prof = h->ws[0]->prof;
+    h->ws.push_back(w);
+  }
+  return SCSF_OK;
+}
+
+void free_workspace(Workspace *w) {
+  (void)hipStreamSynchronize(w->stream);
+  for (auto e : w->ev) (void)hipEventDestroy(e);
+  for (auto &b : w->bufs)
+    if (b.p) (void)hipFree(b.p);
+  if (w->pinned) (void)hipHostFree(w->pinned);
+  if (w->own_stream) (void)hipStreamDestroy(w->stream);
+  delete w;
+}
+
+}  // namespace
+
+// =============================================================================== C ABI
+extern "C" {
+
+const char *scsf_version(void) { return "libscsf 0.2 (gfx950, fp64 MFMA)"; }
+
+const char *scsf_status_string(int s) {
+  switch (s) {
+    case SCSF_OK: return "ok";
+    case SCSF_EINVAL: return "invalid argument";
+    case SCSF_ENOMEM: return "out of device memory";
+    case SCSF_ENOTCONV: return "not converged within max_iter";
+    case SCSF_EBREAKDOWN: return "Cholesky breakdown in orthonormalisation";
+    case SCSF_EHIP: return "HIP runtime error";
+    case SCSF_ENUMERIC: return "NaN or Inf in the iteration";
+    default: return "unknown status";
+  }
+}
+
+int scsf_create(scsf_handle **h, void *hip_stream) {
+  if (!h) return SCSF_EINVAL;
+  scsf_handle *x = new (std::nothrow) scsf_handle();
+  if (!x) return SCSF_ENOMEM;
+  Workspace *w = new (std::nothrow) Workspace();
+  if (!w) {
+    delete x;
+    return SCSF_ENOMEM;
+  }
+  w->stream = static_cast<hipStream_t>(hip_stream);
+  x->ws.push_back(w);
+  if (hipGetDevice(&x->device) != hipSuccess) {
+    delete w;
+    delete x;
+    return SCSF_EHIP;
+  }
+  *h = x;
+  return SCSF_OK;
+}
+
+int scsf_destroy(scsf_handle *h) {
+  if (!h) return SCSF_EINVAL;
+  for (auto *w : h->ws) free_workspace(w);
+  delete h;
+  return SCSF_OK;
+}
+
+int scsf_set_stream(scsf_handle *h, void *hip_stream) {
+  if (!h) return SCSF_EINVAL;
+  if (hipStreamSynchronize(h->ws[0]->stream) != hipSuccess) return SCSF_EHIP;
+  h->ws[0]->stream = static_cast<hipStream_t>(hip_stream);
+  return SCSF_OK;
+}
+
+int scsf_set_lanes(scsf_handle *h, int lanes) {
+  if (!h || lanes < 1 || lanes > 8) return SCSF_EINVAL;
+  h->lanes = lanes;
+  return SCSF_OK;
+}
+
+int scsf_profile_enable(scsf_handle *h, int on) {
+  if (!h) return SCSF_EINVAL;
+  for (auto *w : h->ws) {
+    if (hipStreamSynchronize(w->stream) != hipSuccess) return SCSF_EHIP;
+    prof_drain(w);
+    w->prof = on != 0;
+  }
+  return SCSF_OK;
+}
+
+int scsf_profile_read(scsf_handle *h, scsf_profile *out_host, int reset) {
+  if (!h || !out_host) return SCSF_EINVAL;
+  scsf_profile t{};
+  for (auto *w : h->ws) {
+    if (hipStreamSynchronize(w->stream) != hipSuccess) return SCSF_EHIP;
+    prof_drain(w);
+    t.filter_launches += w->acc.filter_launches;
+    t.filter_ms += w->acc.filter_ms;
+    t.filter_bytes += w->acc.filter_bytes;
+    if (reset) w->acc = scsf_profile{};
+  }
+  *out_host = t;
+  return SCSF_OK;
+}
+
+int scsf_spmm(scsf_handle *h, const scsf_operator *A, const double *X, int64_t ldx, int32_t ncols,
+              double *Y, int64_t ldy) {
+  if (!h) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+
+  STCHK(check_op(A));
+  if (!X || !Y || ncols < 0 || ldx < A->n || ldy < A->n) return SCSF_EINVAL;
+  if (ncols == 0) return SCSF_OK;
+  Engine e;
+  STCHK(e.setup(w0, 1, A->n, 1, 0, 1, A->kind, 1.0, 0, 20));
+  e.h_ops[0] = to_dev(*A);
+  STCHK(e.upload_ops());
+  const double *src = X;
+  if (ldx != ldy) {
+    double *tmp = nullptr;
+    STCHK(grow(w0, B_Y1, (size_t)ldy * ncols, &tmp));
+    HIPCHK(copy_block(A->n, ncols, X, ldx, tmp, ldy, false, w0->stream));
+    src = tmp;
+  }
+  HIPCHK(spmm_step(e.ops, 1, A->kind, A->n, 0, src, nullptr, Y, ldy, 0, COLS_ALL, ncols, nullptr,
+                   e.unit, false, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
+}
+
+int scsf_filter(scsf_handle *h, const scsf_operator *A, const double *X, int64_t ldx,
+                int32_t ncols, int32_t degree, double lambda, double c, double e, double *Y,
+                int64_t ldy) {
+  if (!h) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+
+  STCHK(check_op(A));
+  if (!X || !Y || ncols < 0 || ncols > kMaxK || ldx < A->n || ldy < A->n) return SCSF_EINVAL;
+  if (degree < 1 || degree > 64 || !(e > 0.0) || lambda == c) return SCSF_EINVAL;
+  if (ncols == 0) return SCSF_OK;
+  Engine en;
+  STCHK(en.setup(w0, 1, A->n, ncols, 0, degree, A->kind, 1.0, 0, 20));
+  en.h_ops[0] = to_dev(*A);
+  STCHK(en.upload_ops());
+  double *win = nullptr;
+  STCHK(grow(w0, B_WIN, 3, &win));
+  en.h_bnd[0] = lambda;
+  en.h_bnd[1] = c;
+  en.h_bnd[2] = e;
+  HIPCHK(hipMemcpyAsync(win, en.h_bnd, 3 * sizeof(double), hipMemcpyHostToDevice, w0->stream));
+  HIPCHK(cheb_coeffs_explicit(1, degree, win, en.coef, w0->stream));
+  HIPCHK(copy_block(A->n, ncols, X, ldx, en.X, en.ld, true, w0->stream));
+  double *ring[3] = {en.X, en.Y1, en.Y2};
+  for (int s = 0; s < degree; ++s)
+    HIPCHK(spmm_step(en.ops, 1, A->kind, A->n, 0, ring[s % 3], ring[(s + 2) % 3],
+                     ring[(s + 1) % 3], en.ld, en.bs, COLS_ALL, ncols, nullptr,
+                     en.coef + (size_t)s * 3, s > 0, w0->stream));
+  HIPCHK(copy_block(A->n, ncols, ring[degree % 3], en.ld, Y, ldy, false, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
+}
+
+int scsf_orthonormalize(scsf_handle *h, int64_t n, double *X, int64_t ldx, int32_t ncols,
+                        const double *V, int64_t ldv, int32_t nlocked) {
+  if (!h) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  if (!h || n <= 0 || !X || ncols <= 0 || nlocked < 0 || ldx < n) return SCSF_EINVAL;
+
+  if (nlocked > 0 && (!V || ldv < n)) return SCSF_EINVAL;
+  const int32_t k = ncols + nlocked;
+  if (k > kMaxK || k > n) return SCSF_EINVAL;
+  Engine e;
+  STCHK(e.setup(w0, 1, n, k, 0, 1, SCSF_STENCIL5, 1.0, 0, 20));
+  if (nlocked > 0) HIPCHK(copy_block(n, nlocked, V, ldv, e.X, e.ld, true, w0->stream));
+  HIPCHK(copy_block(n, ncols, X, ldx, e.X + (int64_t)nlocked * e.ld, e.ld, true, w0->stream));
+  e.h_lock[0] = nlocked;
+  e.h_nconv[0] = nlocked;
+  STCHK(e.upload_state());
+  HIPCHK(fill_int(e.flag, 0, 1, w0->stream));
+  STCHK(e.orth(e.X, nlocked > 0));
+  STCHK(e.download_state());
+  if (e.h_flag[0] & 2) return SCSF_ENUMERIC;
+  if (e.h_flag[0] & 1) return SCSF_EBREAKDOWN;
+  HIPCHK(copy_block(n, ncols, e.X + (int64_t)nlocked * e.ld, e.ld, X, ldx, false, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
+}
+
+int scsf_rayleigh_ritz(scsf_handle *h, const scsf_operator *A, double *X, int64_t ldx,
+                       int32_t ncols, double *theta, double *rel_resid) {
+  if (!h) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+
+  STCHK(check_op(A));
+  if (!X || ncols <= 0 || ncols > kMaxK || ncols > A->n || ldx < A->n) return SCSF_EINVAL;
+  Engine e;
+  STCHK(e.setup(w0, 1, A->n, ncols, 0, 1, A->kind, 1.0, 0, 20));
+  e.h_ops[0] = to_dev(*A);
+  STCHK(e.upload_ops());
+  STCHK(e.upload_state());
+  HIPCHK(fill_int(e.flag, 0, 1, w0->stream));
+  HIPCHK(copy_block(A->n, ncols, X, ldx, e.X, e.ld, true, w0->stream));
+  STCHK(e.rayleigh_ritz(e.X));
+  HIPCHK(residuals(1, A->n, e.ld, e.X, e.W, e.bs, ncols, e.lock, e.theta, e.res, w0->stream));
+  HIPCHK(copy_block(A->n, ncols, e.X, e.ld, X, ldx, false, w0->stream));
+  if (theta) HIPCHK(hipMemcpyAsync(theta, e.theta, (size_t)ncols * 8, hipMemcpyDeviceToDevice,
+                                   w0->stream));
+  if (rel_resid) HIPCHK(hipMemcpyAsync(rel_resid, e.res, (size_t)ncols * 8,
+                                       hipMemcpyDeviceToDevice, w0->stream));
+  STCHK(e.download_state());
+  if (e.h_flag[0] & 2) return SCSF_ENUMERIC;
+  return SCSF_OK;
+}
+
+int scsf_bounds(scsf_handle *h, const scsf_operator *A, int32_t steps, uint64_t seed,
+                double *out_host) {
+  if (!h) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  if (!h || !out_host) return SCSF_EINVAL;
+
+  STCHK(check_op(A));
+  if (steps < 1 || steps > 128) return SCSF_EINVAL;
+  Engine e;
+  STCHK(e.setup(w0, 1, A->n, 1, 0, 1, A->kind, 1.0, seed, steps));
+  e.h_ops[0] = to_dev(*A);
+  e.h_need[0] = 1;
+  STCHK(e.upload_ops());
+  STCHK(e.upload_state());
+  HIPCHK(bounds(e.ops, 1, A->kind, A->n, steps, seed, e.need, e.lz, e.bnd, w0->stream));
+  HIPCHK(hipMemcpyAsync(e.h_bnd, e.bnd, 32, hipMemcpyDeviceToHost, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  out_host[0] = e.h_bnd[0];
+  out_host[1] = e.h_bnd[1];
+  out_host[2] = e.h_bnd[2];
+  out_host[3] = e.h_bnd[3];
+  return SCSF_OK;
+}
+
+int scsf_features(scsf_handle *h, const double *fields, int32_t n_op, int32_t channels, int32_t p,
+                  int32_t p0, double *feats) {
+  if (!h) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  if (!h || !fields || !feats || n_op <= 0 || channels <= 0 || p <= 0 || p0 <= 0 || p0 > p)
+
+    return SCSF_EINVAL;
+  if ((int64_t)p * p0 * 16 > 64 * 1024) return SCSF_EINVAL;
+  HIPCHK(dft_features(fields, n_op, channels, p, p0, feats, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
+}
+
+int scsf_sort(scsf_handle *h, const double *fields, int32_t n_op, int32_t channels, int32_t p,
+              int32_t p0, int32_t start, int32_t *order_host) {
+  if (!h) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  if (!h || !fields || !order_host || n_op <= 0 || channels <= 0 || p <= 0 || p0 <= 0 || p0 > p)
+
+    return SCSF_EINVAL;
+  if (start < 0 || start >= n_op || n_op > 32768) return SCSF_EINVAL;
+  if ((int64_t)p * p0 * 16 > 64 * 1024) return SCSF_EINVAL;
+  const int32_t flen = channels * p0 * p0;
+  double *F = nullptr, *D = nullptr;
+  int32_t *O = nullptr;
+  STCHK(grow(w0, B_SORTF, (size_t)n_op * flen * 2, &F));
+  STCHK(grow(w0, B_SORTD, (size_t)n_op * n_op, &D));
+  STCHK(grow(w0, B_SORTO, (size_t)n_op, &O));
+  HIPCHK(dft_features(fields, n_op, channels, p, p0, F, w0->stream));
+  HIPCHK(pair_distances(F, n_op, flen, D, w0->stream));
+  HIPCHK(greedy_order(D, n_op, start, O, w0->stream));
+  HIPCHK(hipMemcpyAsync(order_host, O, (size_t)n_op * 4, hipMemcpyDeviceToHost, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
+}
+
+int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
+               const double *X_prev, const double *theta_prev, double *evals, double *evecs,
+               double *X_next, double *theta_next, scsf_stats *stats_host) {
+  if (!h) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+
+  STCHK(check_op(A));
+  STCHK(check_params(prm, A->n));
+  if ((X_prev == nullptr) != (theta_prev == nullptr)) return SCSF_EINVAL;
+  if (!evals || !evecs) return SCSF_EINVAL;
+  const int max_iter = prm->max_iter > 0 ? prm->max_iter : 200;
+  const int lzs = prm->lanczos_steps > 0 ? prm->lanczos_steps : 20;
+  Engine e;
+  STCHK(e.setup(w0, 1, A->n, prm->k, prm->L, prm->degree, A->kind, prm->tol, prm->seed, lzs));
+  e.h_ops[0] = to_dev(*A);
+  e.h_need[0] = 1;
+  STCHK(e.upload_ops());
+  STCHK(e.upload_state());
+  STCHK(e.compute_bounds());
+  if (X_prev) {
+    HIPCHK(copy_block(A->n, prm->k, X_prev, A->n, e.X, e.ld, true, w0->stream));
+    HIPCHK(hipMemcpyAsync(e.theta, theta_prev, (size_t)prm->k * 8, hipMemcpyDeviceToDevice,
+                          w0->stream));
+  } else {
+    STCHK(e.cold_start({0}));
+  }
+  int it = 0;
+  int64_t fcols = 0;
+  while (it < max_iter) {
+    fcols += (int64_t)prm->degree * (prm->k - e.h_nconv[0]);
+    STCHK(e.iterate());
+    ++it;
+    if (e.h_done[0] || (e.h_flag[0] & 3)) break;
+  }
+  const bool conv = e.h_done[0] != 0;
+  const int status = solve_status(e.h_flag[0], conv);
+  STCHK(e.fetch(0));
+  double mr = 0.0;
+  STCHK(e.extract(0, evals, evecs, A->n, &mr));
+  if (X_next) HIPCHK(copy_block(A->n, prm->k, e.X, e.ld, X_next, A->n, false, w0->stream));
+  if (theta_next)
+    HIPCHK(hipMemcpyAsync(theta_next, e.theta, (size_t)prm->k * 8, hipMemcpyDeviceToDevice,
+                          w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  if (stats_host) {
+    stats_host->iterations = it;
+    stats_host->nconv = e.h_nconv[0];
+    stats_host->status = status;
+    stats_host->chol_shifts = (e.h_flag[0] & 4) ? 1 : 0;
+    stats_host->filter_cols = fcols;
+    stats_host->beta = e.h_bnd[3];
+    stats_host->max_rel_resid = mr;
+  }
+  return status;
+}
+
+int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
+                        const int32_t *order_host, int32_t chains, const scsf_params *prm,
+                        double *evals, double *evecs, scsf_stats *stats_host) {
+  if (!h || !ops_host || n_op <= 0 || !order_host || chains <= 0 || !evals || !evecs)
+    return SCSF_EINVAL;
+  const int64_t n = ops_host[0].n;
+  const int32_t kind = ops_host[0].kind;
+  for (int i = 0; i < n_op; ++i) {
+    STCHK(check_op(&ops_host[i]));
+    if (ops_host[i].n != n || ops_host[i].kind != kind) return SCSF_EINVAL;
+  }
+  STCHK(check_params(prm, n));
+  {
+    std::vector<char> seen(n_op, 0);
+    for (int i = 0; i < n_op; ++i) {
+      const int o = order_host[i];
+      if (o < 0 || o >= n_op || seen[o]) return SCSF_EINVAL;
+      seen[o] = 1;
+    }
+  }
+  chains = std::min(chains, n_op);
+  // contiguous chunks of the order, sizes differing by at most one (App. C.5); the chunks are
+  // dealt round-robin to `lanes` lockstep batches that run concurrently on their own streams
+  std::vector<int> cbeg(chains + 1);
+  for (int c = 0; c <= chains; ++c) cbeg[c] = (int)((int64_t)n_op * c / chains);
+  const int lanes = std::min(h->lanes, chains);
+  STCHK(add_lanes(h, lanes));
+  hipEvent_t ready;
+  HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(ready, h->ws[0]->stream));
+  for (int g = 1; g < lanes; ++g) HIPCHK(hipStreamWaitEvent(h->ws[g]->stream, ready, 0));
+  std::vector<int> status(lanes, SCSF_OK);
+  auto lane_fn = [&](int g) {
+    if (hipSetDevice(h->device) != hipSuccess) { status[g] = SCSF_EHIP; return; }
+    std::vector<int> cb, ce;
+    for (int c = g; c < chains; c += lanes) {
+      cb.push_back(cbeg[c]);
+      ce.push_back(cbeg[c + 1]);
+    }
+    status[g] = run_chains(h->ws[g], ops_host, order_host, cb, ce, prm, evals, evecs, stats_host);
+  };
+  std::vector<std::thread> threads;
+  for (int g = 1; g < lanes; ++g) threads.emplace_back(lane_fn, g);
+  lane_fn(0);
+  for (auto &t : threads) t.join();
+  (void)hipEventDestroy(ready);
+  int worst = SCSF_OK;
+  for (int g = 0; g < lanes; ++g) {
+    const int s2 = status[g];
+    if (s2 == SCSF_OK) continue;
+    if (worst == SCSF_OK || (worst == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)) worst = s2;
+  }
   return worst;
 }
 

@@ -82,6 +82,7 @@ def lib():
                                     POINTER(Params), vp, vp, POINTER(Stats)],
         }
         sig["scsf_profile_enable"] = [vp, i32]
+        sig["scsf_set_lanes"] = [vp, i32]
         sig["scsf_profile_read"] = [vp, POINTER(Profile), i32]
         for name, args in sig.items():
             f = getattr(L, name)
@@ -300,6 +301,10 @@ def scsf_solve_sequence(h: Handle, ops: list, order, chains: int, prm: Params,
                                      _ptr(evals), _ptr(evecs), stats), "scsf_solve_sequence",
            allow)
     return evals, evecs, [s.as_dict() for s in stats]
+
+
+def scsf_set_lanes(h: Handle, lanes: int):
+    _check(lib().scsf_set_lanes(h.ptr, int(lanes)), "scsf_set_lanes")
 
 
 def scsf_profile_enable(h: Handle, on: bool = True):

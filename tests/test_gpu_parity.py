@@ -319,9 +319,11 @@ def test_solve_errors(h):
 
 
 # ------------------------------------------------------------------------------ sequences
-@pytest.mark.parametrize("chains", [1, 3])
-def test_sequence_config1_matches_oracle(h, chains):
-    say("sequence c1 chains", chains)
+@pytest.mark.parametrize("chains,lanes", [(1, 1), (3, 4), (5, 2)])
+def test_sequence_config1_matches_oracle(chains, lanes):
+    say("sequence c1 chains", chains, "lanes", lanes)
+    h = scsf.Handle()
+    scsf.scsf_set_lanes(h, lanes)
     cfg = si.CONFIGS[1]
     ops = si.operators(cfg)
     order = S.scsf_sort([o.field for o in ops], cfg.p0)

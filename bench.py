@@ -3,7 +3,7 @@
 One step = the whole path over one synthetic dataset: truncated-FFT sort of the coefficient
 fields (Algorithm 2) and the warm-started Chebyshev filtered subspace iteration over every
 operator in sorted order (Algorithm 3), split into `--chains` contiguous chunks that run
-concurrently (the chunk parallelism of App. C.5).  Inputs are resident in HBM before timing;
+concurrently (the chunk parallelism of App. D.6).  Inputs are resident in HBM before timing;
 the step ends with all eigenpairs resident in HBM.
 
 Workload (default): 200 generalized-Poisson operators -div(K grad u) on a 100 x 100 grid
@@ -83,11 +83,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--count", type=int, default=None, help="operators (default: all)")
-    ap.add_argument("--chains", type=int, default=16)
+    ap.add_argument("--chains", type=int, default=32)
     ap.add_argument("--lanes", type=int, default=4)
     ap.add_argument("--degree", type=int, default=None)
+    ap.add_argument("--schedule", choices=["static", "dynamic"], default="dynamic",
+                    help="static: contiguous chunks of the sorted order (App. D.6); dynamic: "
+                         "each chain takes the next unsolved operator of the sorted order")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="before timing, run a plain 1 GiB device-to-device copy kernel three "
+                         "times (reference for the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -107,10 +113,20 @@ def main():
     scsf.scsf_set_lanes(h, args.lanes)
     fields = torch.tensor(np.stack([o.field for o in ops]), device="cuda")
     dops = [scsf.DeviceOperator(o) for o in ops]
-    prm = scsf.make_params(cfg.L, cfg.k, degree, cfg.tol, seed=1)
+    prm = scsf.make_params(cfg.L, cfg.k, degree, cfg.tol, seed=1,
+                           schedule=scsf.SCSF_SCHED_DYNAMIC if args.schedule == "dynamic"
+                           else scsf.SCSF_SCHED_STATIC)
     evals = torch.empty((n_op, cfg.L), device="cuda", dtype=torch.float64)
     evecs = torch.empty((n_op, cfg.L, dops[0].n), device="cuda", dtype=torch.float64)
     torch.cuda.synchronize()
+    if args.calibrate_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] copy calibration: 3 x 1 GiB device copy done")
 
     def step():
         order = scsf.scsf_sort(h, fields, cfg.p0)
@@ -163,6 +179,7 @@ def main():
                         f"tol={cfg.tol:g}",
             "chains": args.chains,
             "lanes": args.lanes,
+            "schedule": args.schedule,
             "mean_outer_iterations": float(np.mean(iters)),
         },
         "roofline": {

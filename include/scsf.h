@@ -48,8 +48,14 @@ enum scsf_op_kind {
 
 enum scsf_precision { SCSF_FP64 = 0, SCSF_MIXED = 1 };
 
+/* How scsf_solve_sequence hands operators to its concurrent chains.
+ *   STATIC : the sorted order is cut into `chains` contiguous chunks (App. D.6 chunking);
+ *   DYNAMIC: every chain takes the next unsolved operator of the sorted order when it
+ *            finishes one, warm-starting from the operator it solved last (load balance). */
+enum scsf_schedule { SCSF_SCHED_STATIC = 0, SCSF_SCHED_DYNAMIC = 1 };
+
 /*
- * A discretised operator (Section 2.1; datasets of App. C.2).  Grid nodes are numbered
+ * A discretised operator (Section 2.1; datasets of App. D.2).  Grid nodes are numbered
  * row-major, p = iy*nx + ix, h = 1/(nx+1), zero Dirichlet values beyond the boundary.
  *   STENCIL5: wx[iy*(nx+1) + f] is the coefficient of the x-face between nodes (iy, f-1) and
  *             (iy, f) (f = 0 and f = nx are boundary faces); wy[f*nx + ix] the y-face between
@@ -71,15 +77,16 @@ typedef struct scsf_operator {
   int64_t nnz;
 } scsf_operator;
 
-/* Solver parameters (Algorithm 3; defaults of App. C.4: degree 20, k = L + 20% of L). */
+/* Solver parameters (Algorithm 3; defaults of App. D.4: degree 20, k = L + 20% of L). */
 typedef struct scsf_params {
   int32_t L;             /* wanted eigenpairs, 0 < L < k */
   int32_t k;             /* block width (L + guard vectors), k <= n, k <= 256 */
   int32_t degree;        /* Chebyshev degree m, 1..64 */
-  int32_t max_iter;      /* outer iterations before SCSF_ENOTCONV (0 -> 200) */
+  int32_t max_iter;      /* outer iterations before SCSF_ENOTCONV (0 -> 5000) */
   int32_t lanczos_steps; /* steps of the upper-bound Lanczos run (0 -> 20) */
   int32_t precision;     /* scsf_precision */
-  double tol;            /* lock when ||A v - theta v|| <= tol ||A v|| (App. C.6 metric) */
+  int32_t schedule;      /* scsf_solve_sequence: scsf_schedule */
+  double tol;            /* lock when ||A v - theta v|| <= tol ||A v|| (App. D.5 metric) */
   uint64_t seed;         /* seed of the random cold-start block and Lanczos start vector */
 } scsf_params;
 
@@ -184,7 +191,7 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
 
 /* A whole dataset (Fig. 2 c-d): ops_host[n_op] (host array of operator descriptors, all of
  * the same kind and n) are solved in the order order_host[n_op] split into `chains`
- * contiguous chunks (App. C.5 chunking); the chunks run concurrently (lockstep batches on
+ * contiguous chunks (App. D.6 chunking); the chunks run concurrently (lockstep batches on
  * up to scsf_set_lanes streams), each chain warm-starting every solve from its previous one.  evals: n_op x L (row i = operator
  * i), evecs: n_op x (n x L) (block i = operator i, ld n).  stats_host[n_op] may be NULL.
  * Returns SCSF_ENOTCONV if any solve did not converge. */

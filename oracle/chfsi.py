@@ -18,7 +18,7 @@ Readings (ambiguous or silent passages):
   e = (beta-alpha)/2;
 * a cold start first runs one QR + Rayleigh-Ritz on the random block to obtain Ritz values;
 * G is formed on the active columns only, and the rotated Ritz vectors replace V0;
-* convergence uses the relative residual ||A v - theta v|| / ||A v|| (App. C.6 error metric);
+* convergence uses the relative residual ||A v - theta v|| / ||A v|| (App. D.5 error metric);
   the longest converged ascending prefix of the active Ritz pairs is locked;
 * all k final Ritz pairs (locked and active) are handed to the next problem;
 * after `max_iter` outer iterations the best pairs so far are returned, flagged unconverged.

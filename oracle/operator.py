@@ -1,7 +1,7 @@
 """Assembly of the discretised operators as explicit sparse matrices (oracle).
 
 Section 2.1 turns an operator eigenvalue problem into a matrix one by finite differences; the
-datasets of App. C.2 use -div(K grad u) with Dirichlet boundary conditions and a central
+datasets of App. D.2 use -div(K grad u) with Dirichlet boundary conditions and a central
 difference scheme.  Here the matrix is built as a sum of rank-one face terms
     A = sum_f w_f (e_a - e_b)(e_a - e_b)^T   (interior face between nodes a and b)
       + sum_f w_f e_a e_a^T                   (boundary face next to node a)

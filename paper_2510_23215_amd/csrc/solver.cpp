@@ -7,6 +7,7 @@
 // convergence share the launches.  The host synchronises once per outer iteration to read the
 // lock counts.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -431,19 +432,24 @@ int check_params(const scsf_params *p, int64_t n) {
   if (!(p->tol > 0.0)) return SCSF_EINVAL;
   if (p->lanczos_steps < 0 || p->lanczos_steps > 128) return SCSF_EINVAL;
   if (p->precision != SCSF_FP64) return SCSF_EINVAL;
+  if (p->schedule != SCSF_SCHED_STATIC && p->schedule != SCSF_SCHED_DYNAMIC) return SCSF_EINVAL;
   return SCSF_OK;
 }
 
 // The chained solve of a set of chunks on one workspace (one lockstep batch, one stream):
 // chunk c covers order_host[cb[c] .. ce[c]).
+// With `next` (dynamic schedule) a chain that finishes an operator takes order position
+// next->fetch_add(1) instead of the next position of its own chunk; cb holds the chains' first
+// positions and ce is ignored.
 int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order_host,
-               const std::vector<int> &cb, const std::vector<int> &ce, const scsf_params *prm,
-               double *evals, double *evecs, scsf_stats *stats_host) {
+               int32_t n_op, const std::vector<int> &cb, const std::vector<int> &ce,
+               std::atomic<int> *next, const scsf_params *prm, double *evals, double *evecs,
+               scsf_stats *stats_host) {
   const int chains = (int)cb.size();
   if (chains == 0) return SCSF_OK;
   const int64_t n = ops_host[0].n;
   const int32_t kind = ops_host[0].kind;
-  const int max_iter = prm->max_iter > 0 ? prm->max_iter : 200;
+  const int max_iter = prm->max_iter > 0 ? prm->max_iter : 5000;
   const int lzs = prm->lanczos_steps > 0 ? prm->lanczos_steps : 20;
   const int32_t L = prm->L, k = prm->k, m = prm->degree;
 
@@ -497,10 +503,14 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
         st.max_rel_resid = mr;
       }
       if (status != SCSF_OK && (worst == SCSF_OK || status != SCSF_ENOTCONV)) worst = status;
-      ++pos[b];
+      if (next) {
+        pos[b] = next->fetch_add(1);
+      } else {
+        ++pos[b];
+      }
       iters[b] = 0;
       fcols[b] = 0;
-      if (pos[b] >= ce[b]) {
+      if (pos[b] >= (next ? n_op : ce[b])) {
         active[b] = 0;
         --remaining;
         e.h_done[b] = 1;
@@ -818,7 +828,7 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
   STCHK(check_params(prm, A->n));
   if ((X_prev == nullptr) != (theta_prev == nullptr)) return SCSF_EINVAL;
   if (!evals || !evecs) return SCSF_EINVAL;
-  const int max_iter = prm->max_iter > 0 ? prm->max_iter : 200;
+  const int max_iter = prm->max_iter > 0 ? prm->max_iter : 5000;
   const int lzs = prm->lanczos_steps > 0 ? prm->lanczos_steps : 20;
   Engine e;
   STCHK(e.setup(w0, 1, A->n, prm->k, prm->L, prm->degree, A->kind, prm->tol, prm->seed, lzs));
@@ -885,7 +895,7 @@ int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n
     }
   }
   chains = std::min(chains, n_op);
-  // contiguous chunks of the order, sizes differing by at most one (App. C.5); the chunks are
+  // contiguous chunks of the order, sizes differing by at most one (App. D.6); the chunks are
   // dealt round-robin to `lanes` lockstep batches that run concurrently on their own streams
   std::vector<int> cbeg(chains + 1);
   for (int c = 0; c <= chains; ++c) cbeg[c] = (int)((int64_t)n_op * c / chains);
@@ -896,14 +906,17 @@ int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n
   HIPCHK(hipEventRecord(ready, h->ws[0]->stream));
   for (int g = 1; g < lanes; ++g) HIPCHK(hipStreamWaitEvent(h->ws[g]->stream, ready, 0));
   std::vector<int> status(lanes, SCSF_OK);
+  const bool dyn = prm->schedule == SCSF_SCHED_DYNAMIC;
+  std::atomic<int> next(chains);                // dynamic: chain c starts at order position c
   auto lane_fn = [&](int g) {
     if (hipSetDevice(h->device) != hipSuccess) { status[g] = SCSF_EHIP; return; }
     std::vector<int> cb, ce;
     for (int c = g; c < chains; c += lanes) {
-      cb.push_back(cbeg[c]);
-      ce.push_back(cbeg[c + 1]);
+      cb.push_back(dyn ? c : cbeg[c]);
+      ce.push_back(dyn ? c + 1 : cbeg[c + 1]);
     }
-    status[g] = run_chains(h->ws[g], ops_host, order_host, cb, ce, prm, evals, evecs, stats_host);
+    status[g] = run_chains(h->ws[g], ops_host, order_host, n_op, cb, ce, dyn ? &next : nullptr,
+                           prm, evals, evecs, stats_host);
   };
   std::vector<std::thread> threads;
   for (int g = 1; g < lanes; ++g) threads.emplace_back(lane_fn, g);

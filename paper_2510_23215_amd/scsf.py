@@ -20,6 +20,7 @@ SCSF_OK, SCSF_EINVAL, SCSF_ENOMEM, SCSF_ENOTCONV = 0, -1, -2, -3
 SCSF_EBREAKDOWN, SCSF_EHIP, SCSF_ENUMERIC = -4, -5, -6
 SCSF_STENCIL5, SCSF_STENCIL9, SCSF_CSR = 1, 2, 3
 SCSF_FP64, SCSF_MIXED = 0, 1
+SCSF_SCHED_STATIC, SCSF_SCHED_DYNAMIC = 0, 1
 
 
 class ScsfError(RuntimeError):
@@ -36,8 +37,8 @@ class Operator(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("L", c_int32), ("k", c_int32), ("degree", c_int32), ("max_iter", c_int32),
-                ("lanczos_steps", c_int32), ("precision", c_int32), ("tol", c_double),
-                ("seed", c_uint64)]
+                ("lanczos_steps", c_int32), ("precision", c_int32), ("schedule", c_int32),
+                ("tol", c_double), ("seed", c_uint64)]
 
 
 class Profile(ctypes.Structure):
@@ -255,10 +256,10 @@ def scsf_sort(h: Handle, fields: torch.Tensor, p0: int, start: int = 0) -> np.nd
     return np.frombuffer(order, dtype=np.int32).copy()
 
 
-def make_params(L, k, degree=20, tol=1e-8, max_iter=200, lanczos_steps=20, seed=0,
-                precision=SCSF_FP64) -> Params:
+def make_params(L, k, degree=20, tol=1e-8, max_iter=0, lanczos_steps=20, seed=0,
+                precision=SCSF_FP64, schedule=SCSF_SCHED_STATIC) -> Params:
     return Params(L=L, k=k, degree=degree, max_iter=max_iter, lanczos_steps=lanczos_steps,
-                  precision=precision, tol=tol, seed=seed)
+                  precision=precision, schedule=schedule, tol=tol, seed=seed)
 
 
 def scsf_solve(h: Handle, A: DeviceOperator, prm: Params, X_prev=None, theta_prev=None,

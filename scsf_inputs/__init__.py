@@ -6,13 +6,13 @@ It only draws random coefficient fields and writes down the face coefficients of
 finite-difference operators they define:
 
 * generalized Poisson  -div(K grad u) = lambda u, K = exp(g), Dirichlet boundary
-  (paper App. C.2 "Dataset", item 1; Section 2.1 for the discretisation idea);
+  (paper App. D.2 "Dataset", item 1; Section 2.1 for the discretisation idea);
 * Schroedinger-type    -Laplace(u) + V u = lambda u, V = exp(g) rescaled to [0, 100];
 * anisotropic elliptic -div(K grad u) with a 2x2 SPD tensor field K (9-point Q1 stencil).
 
 g is a cosine series  g(x,y) = sum_{k1,k2<M} xi_{k1k2} (1+k1^2+k2^2)^-1 cos(pi k1 x) cos(pi k2 y),
 xi ~ N(0,1), so the coefficient variance is (1+k1^2+k2^2)^-2 -- a Gaussian random field
-(the paper generates its coefficient fields by GRF sampling, App. C.2).
+(the paper generates its coefficient fields by GRF sampling, App. D.2).
 
 Grid convention (row-major node order, as in the worked 2x2 example of Section 2.1):
 N x N interior nodes, h = 1/(N+1), node (iy, ix) sits at (x, y) = ((ix+1) h, (iy+1) h)
@@ -170,7 +170,7 @@ def gaussian_block(n: int, k: int, seed: int) -> np.ndarray:
 
 # ---------------------------------------------------------------------------------------------
 # The benchmark configurations (sizes of the paper's workloads: n from 10^3 to 2.6*10^4,
-# L up to a few hundred, degree 20, p0 = 20; App. C.4).
+# L up to a few hundred, degree 20, p0 = 20; App. D.4).
 # ---------------------------------------------------------------------------------------------
 
 @dataclasses.dataclass

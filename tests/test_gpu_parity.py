@@ -319,15 +319,15 @@ def test_solve_errors(h):
 
 
 # ------------------------------------------------------------------------------ sequences
-@pytest.mark.parametrize("chains,lanes", [(1, 1), (3, 4), (5, 2)])
-def test_sequence_config1_matches_oracle(chains, lanes):
-    say("sequence c1 chains", chains, "lanes", lanes)
+@pytest.mark.parametrize("chains,lanes,sched", [(1, 1, 0), (3, 4, 0), (5, 2, 0), (4, 2, 1)])
+def test_sequence_config1_matches_oracle(chains, lanes, sched):
+    say("sequence c1 chains", chains, "lanes", lanes, "schedule", sched)
     h = scsf.Handle()
     scsf.scsf_set_lanes(h, lanes)
     cfg = si.CONFIGS[1]
     ops = si.operators(cfg)
     order = S.scsf_sort([o.field for o in ops], cfg.p0)
-    prm = scsf.make_params(cfg.L, cfg.k, cfg.degree, cfg.tol, seed=1)
+    prm = scsf.make_params(cfg.L, cfg.k, cfg.degree, cfg.tol, seed=1, schedule=sched)
     evals, evecs, stats = scsf.scsf_solve_sequence(h, [scsf.DeviceOperator(o) for o in ops], order,
                                                    chains, prm)
     say([s["iterations"] for s in stats])

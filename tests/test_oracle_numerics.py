@@ -153,7 +153,7 @@ def test_chfsi_laplacian_closed_form_at_cluster_boundary():
 
 
 def test_identical_operator_warm_start_converges_at_once():
-    """App. D.8: re-solving the same operator (0% perturbation) needs almost no work."""
+    """App. E.7: re-solving the same operator (0% perturbation) needs almost no work."""
     A = O.assemble(si.operator(si.CONFIGS[1], 7))
     r = C.chfsi(A, 16, 24, 20, 1e-8, seed=3)
     r2 = C.chfsi(A, 16, 24, 20, 1e-8, X0=r.X_next, theta0=r.theta_next)

@@ -30,7 +30,7 @@ def test_worked_example_2x2():
 
 def test_kronecker_sum_of_1d_matrix():
     """K == 1 gives (T (x) I + I (x) T)/h^2 with T = tridiag(-1, 2, -1), the 1-D central
-    difference matrix of App. B taken with the sign of -d^2/dx^2."""
+    difference matrix of App. C taken with the sign of -d^2/dx^2."""
     N = 7
     h = 1.0 / (N + 1)
     T = 2 * np.eye(N) - np.eye(N, k=1) - np.eye(N, k=-1)

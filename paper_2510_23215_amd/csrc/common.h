@@ -53,6 +53,28 @@ hipError_t spmm_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_
                      int32_t mode, int32_t k, const int32_t *lock, const double *coef,
                      bool has_z, hipStream_t st);
 
+// FP32 variant of the step for the mixed-precision filter; with R non-null the step adds the
+// per-column source term src[b*k + c] * R[:, c] (R in the same layout as X).
+hipError_t spmm_step32(const OpDev *ops, int B, int32_t kind, int64_t nmax, const float *X,
+                       const float *Z, float *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
+                       const int32_t *lock, const double *coef, bool has_z, const float *R,
+                       const double *src, hipStream_t st);
+
+// Mixed-precision filter helpers (residual form of the recurrence, see misc.hip):
+//  mp_tables : src[(i*B + b)*k + c] = (2 sigma_{i+1}/e) p_i(theta_c) for steps i = 1..m-1 and
+//              gain[b*k + c] = p_m(theta_c), from the window written by cheb_coeffs (win).
+//  mp_prep   : R32 = fp32(W - theta X), E1 = fp32((sigma_1/e) (W - theta X)) (active columns).
+//  mp_final  : Y = X diag(gain) + fp64(Em) (active columns).
+hipError_t mp_tables(int B, int32_t k, int32_t m, const double *theta, const double *win,
+                     const int32_t *lock, const int32_t *done, double *src, double *gain,
+                     hipStream_t st);
+hipError_t mp_prep(int B, int64_t n, int64_t ld, int64_t bs, int32_t k, const int32_t *lock,
+                   const double *X, const double *W, const double *theta, const double *coef,
+                   float *R32, float *E1, hipStream_t st);
+hipError_t mp_final(int B, int64_t n, int64_t ld, int64_t bs, int32_t k, const int32_t *lock,
+                    const double *X, const float *Em, const double *gain, double *Y,
+                    hipStream_t st);
+
 // Partial tall-skinny products C_b = A_b^T B_b over row chunks; then reduce.
 //   A_b = A + b*bsA + a0*ld, B_b = Bm + b*bsB + b0*ld (column ranges from modes),
 //   C_b = C + b*ldc*ldc (ldc x ldc, column-major), entries outside the ranges untouched.

@@ -352,3 +352,93 @@ hipError_t gather_columns(int64_t n, int32_t ncols, const double *src, int64_t l
 }
 
 }  // namespace scsf
+
+// ------------------------------------------------------------------ mixed-precision filter
+// Residual form of the scaled recurrence.  With p_i the scaled Chebyshev polynomials of
+// Algorithm 1 and, for one column, x its Ritz vector, theta its Ritz value and r = A x - theta x,
+// the difference e_i = p_i(A) x - p_i(theta) x obeys
+//   e_0 = 0,  e_1 = (sigma_1/e) r,
+//   e_{i+1} = (2 sigma_{i+1}/e)(A - cI) e_i - sigma_i sigma_{i+1} e_{i-1} + (2 sigma_{i+1}/e) p_i(theta) r,
+// (p_{i+1}(A) - p_{i+1}(theta) expanded with p_i(A) x = e_i + p_i(theta) x), so that
+// p_m(A) x = p_m(theta) x + e_m exactly.  The e recurrence runs in FP32: its rounding error is
+// relative to ||e|| ~ ||r||, not to ||p_m(A) x||, so the iteration keeps converging in FP64.
+namespace scsf {
+
+__global__ void mp_tables_kernel(int B, int32_t k, int32_t m, const double *__restrict__ theta,
+                                 const double *__restrict__ win, const int32_t *__restrict__ lock,
+                                 const int32_t *__restrict__ done, double *__restrict__ src,
+                                 double *__restrict__ gain) {
+  const int b = blockIdx.x;
+  if (done && done[b]) return;
+  const int32_t l = lock ? lock[b] : 0;
+  const double c = win[b * 3 + 1], e = win[b * 3 + 2];
+  const double s1 = e / (win[b * 3 + 0] - c);
+  for (int col = l + threadIdx.x; col < k; col += blockDim.x) {
+    const double t = (theta[(int64_t)b * k + col] - c) / e;
+    double pm1 = 1.0, p = s1 * t, s = s1;
+    for (int i = 1; i < m; ++i) {
+      const double sn = 1.0 / (2.0 / s1 - s);
+      src[((int64_t)i * B + b) * k + col] = 2.0 * sn / e * p;
+      const double pn = 2.0 * sn * t * p - s * sn * pm1;
+      pm1 = p;
+      p = pn;
+      s = sn;
+    }
+    gain[(int64_t)b * k + col] = p;
+  }
+}
+
+hipError_t mp_tables(int B, int32_t k, int32_t m, const double *theta, const double *win,
+                     const int32_t *lock, const int32_t *done, double *src, double *gain,
+                     hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  mp_tables_kernel<<<B, 256, 0, st>>>(B, k, m, theta, win, lock, done, src, gain);
+  return hipGetLastError();
+}
+
+__global__ void mp_prep_kernel(int B, int64_t n, int64_t ld, int64_t bs, int32_t k,
+                               const int32_t *__restrict__ lock, const double *__restrict__ X,
+                               const double *__restrict__ W, const double *__restrict__ theta,
+                               const double *__restrict__ coef, float *__restrict__ R32,
+                               float *__restrict__ E1) {
+  const int b = blockIdx.z;
+  const int c = (lock ? lock[b] : 0) + blockIdx.y;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k || p >= n) return;
+  const int64_t o = (int64_t)b * bs + (int64_t)c * ld + p;
+  const double r = W[o] - theta[(int64_t)b * k + c] * X[o];
+  R32[o] = (float)r;
+  E1[o] = (float)(coef[3 * b + 0] * r);               // step-0 coefficient sigma_1 / e
+}
+
+hipError_t mp_prep(int B, int64_t n, int64_t ld, int64_t bs, int32_t k, const int32_t *lock,
+                   const double *X, const double *W, const double *theta, const double *coef,
+                   float *R32, float *E1, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  mp_prep_kernel<<<dim3((unsigned)ceil_div(n, 256), k, B), 256, 0, st>>>(B, n, ld, bs, k, lock, X,
+                                                                         W, theta, coef, R32, E1);
+  return hipGetLastError();
+}
+
+__global__ void mp_final_kernel(int64_t n, int64_t ld, int64_t bs, int32_t k,
+                                const int32_t *__restrict__ lock, const double *__restrict__ X,
+                                const float *__restrict__ Em, const double *__restrict__ gain,
+                                double *__restrict__ Y) {
+  const int b = blockIdx.z;
+  const int c = (lock ? lock[b] : 0) + blockIdx.y;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k || p >= n) return;
+  const int64_t o = (int64_t)b * bs + (int64_t)c * ld + p;
+  Y[o] = X[o] * gain[(int64_t)b * k + c] + (double)Em[o];
+}
+
+hipError_t mp_final(int B, int64_t n, int64_t ld, int64_t bs, int32_t k, const int32_t *lock,
+                    const double *X, const float *Em, const double *gain, double *Y,
+                    hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  mp_final_kernel<<<dim3((unsigned)ceil_div(n, 256), k, B), 256, 0, st>>>(n, ld, bs, k, lock, X, Em,
+                                                                          gain, Y);
+  return hipGetLastError();
+}
+
+}  // namespace scsf

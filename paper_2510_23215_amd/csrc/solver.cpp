@@ -22,7 +22,8 @@ namespace {
 
 enum BufId {
   B_X, B_Y1, B_Y2, B_W, B_G, B_M, B_PART, B_THETA, B_RES, B_INT, B_BND, B_COEF, B_UNIT, B_CHOL,
-  B_JAC, B_LZ, B_OPS, B_WIN, B_SORTF, B_SORTD, B_SORTO, B_REC, B_RANK, B_COUNT
+  B_JAC, B_LZ, B_OPS, B_WIN, B_SORTF, B_SORTD, B_SORTO, B_REC, B_RANK, B_E32, B_R32, B_SRC,
+  B_GAIN, B_WINB, B_COUNT
 };
 
 struct DevBuf {
@@ -176,6 +177,10 @@ struct Engine {
   double *part = nullptr, *theta = nullptr, *res = nullptr, *bnd = nullptr, *coef = nullptr;
   double *unit = nullptr, *chol = nullptr, *jac = nullptr, *lz = nullptr, *rec = nullptr;
   int32_t *ranks = nullptr, *nsweeps = nullptr;
+  // mixed precision (FP32 filter in residual form)
+  bool mixed = false, w_stale = true;
+  float *E32[3] = {nullptr, nullptr, nullptr}, *R32 = nullptr;
+  double *src = nullptr, *gain = nullptr, *winb = nullptr;
   int32_t *lock = nullptr, *nconv = nullptr, *done = nullptr, *flag = nullptr, *need = nullptr;
   OpDev *ops = nullptr;
   // pinned host mirrors
@@ -185,7 +190,9 @@ struct Engine {
   OpDev *h_ops = nullptr;
 
   int setup(Workspace *hh, int B_, int64_t n_, int32_t k_, int32_t L_, int32_t m_, int32_t kind_,
-            double tol_, uint64_t seed_, int32_t lz_steps_) {
+            double tol_, uint64_t seed_, int32_t lz_steps_, bool mixed_ = false) {
+    mixed = mixed_;
+    w_stale = true;
     h = hh;
     st = hh->stream;
     B = B_;
@@ -230,6 +237,17 @@ struct Engine {
     nsweeps = rk + (size_t)B * ldm;
     STCHK(grow(h, B_LZ, (size_t)B * 3 * n, &lz));
     STCHK(grow(h, B_OPS, (size_t)B, &ops));
+    if (mixed) {
+      float *e32 = nullptr;
+      STCHK(grow(h, B_E32, (size_t)3 * B * bs, &e32));
+      E32[0] = e32;
+      E32[1] = e32 + (size_t)B * bs;
+      E32[2] = e32 + (size_t)2 * B * bs;
+      STCHK(grow(h, B_R32, (size_t)B * bs, &R32));
+      STCHK(grow(h, B_SRC, (size_t)std::max(m, 1) * B * k, &src));
+      STCHK(grow(h, B_GAIN, (size_t)B * k, &gain));
+      STCHK(grow(h, B_WINB, (size_t)B * 3, &winb));
+    }
     // pinned: 6 int arrays of B, perm B*k, theta/res B*k, bnd B*4, unit B*3, ops B
     const size_t pin = (size_t)B * 6 * 4 + (size_t)B * k * 4 + (size_t)B * k * 16 +
                        (size_t)B * 4 * 8 + (size_t)B * 3 * 8 + (size_t)B * sizeof(OpDev) + 1024;
@@ -290,12 +308,14 @@ struct Engine {
 
   // algorithmic bytes of one Chebyshev step over all unfinished problems: read Y_i (and
   // Y_{i-1} after the first step), write Y_{i+1}, read the operator's coefficients once
-  double step_bytes(bool has_prev) const {
+  double step_bytes(bool has_prev, bool fp32 = false) const {
     double cols = 0.0, nops = 0.0;
     for (int b = 0; b < B; ++b)
       if (!h_done[b]) { cols += (double)(k - h_lock[b]); nops += 1.0; }
     const double coeff = (kind == SCSF_STENCIL5) ? 2.0 * n + (double)n
                          : (kind == SCSF_STENCIL9) ? 3.0 * n : 0.0;
+    if (fp32)  // e_i, e_{i-1}, r read, e_{i+1} written in FP32
+      return 4.0 * (has_prev ? 4.0 : 3.0) * (double)n * cols + 8.0 * coeff * nops;
     return 8.0 * ((has_prev ? 3.0 : 2.0) * (double)n * cols + coeff * nops);
   }
 
@@ -365,15 +385,36 @@ struct Engine {
   // One outer iteration of Algorithm 3 for every problem not done.
   int iterate() {
     HIPCHK(fill_int(flag, 0, B, st));
-    HIPCHK(cheb_coeffs(B, k, m, theta, bnd, done, coef, nullptr, st));
-    double *ring[3] = {X, Y1, Y2};
-    for (int s = 0; s < m; ++s) {
-      const int slot = prof_begin(h, h->prof ? step_bytes(s > 0) : 0.0);
-      HIPCHK(spmm_step(ops, B, kind, n, 0, ring[s % 3], ring[(s + 2) % 3], ring[(s + 1) % 3], ld,
-                       bs, COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 0, st));
-      prof_end(h, slot);
+    HIPCHK(cheb_coeffs(B, k, m, theta, bnd, done, coef, mixed ? winb : nullptr, st));
+    double *Yf = nullptr;
+    if (mixed) {
+      // Y = p_m(A) X = X p_m(Theta) + e_m with the correction e in FP32 (misc.hip)
+      if (w_stale) {
+        HIPCHK(spmm_step(ops, B, kind, n, 0, X, nullptr, W, ld, bs, COLS_ACTIVE, k, lock, unit,
+                         false, st));
+        w_stale = false;
+      }
+      HIPCHK(mp_tables(B, k, m, theta, winb, lock, done, src, gain, st));
+      HIPCHK(mp_prep(B, n, ld, bs, k, lock, X, W, theta, coef, R32, E32[1], st));
+      for (int s = 1; s < m; ++s) {
+        const int slot = prof_begin(h, h->prof ? step_bytes(s > 1, true) : 0.0);
+        HIPCHK(spmm_step32(ops, B, kind, n, E32[s % 3], E32[(s + 2) % 3], E32[(s + 1) % 3], ld, bs,
+                           COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 1, R32,
+                           src + (size_t)s * B * k, st));
+        prof_end(h, slot);
+      }
+      HIPCHK(mp_final(B, n, ld, bs, k, lock, X, E32[m % 3], gain, Y1, st));
+      Yf = Y1;
+    } else {
+      double *ring[3] = {X, Y1, Y2};
+      for (int s = 0; s < m; ++s) {
+        const int slot = prof_begin(h, h->prof ? step_bytes(s > 0) : 0.0);
+        HIPCHK(spmm_step(ops, B, kind, n, 0, ring[s % 3], ring[(s + 2) % 3], ring[(s + 1) % 3],
+                         ld, bs, COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 0, st));
+        prof_end(h, slot);
+      }
+      Yf = ring[m % 3];
     }
-    double *Yf = ring[m % 3];
     STCHK(orth(Yf, true));
     STCHK(rayleigh_ritz(Yf));
     HIPCHK(residuals(B, n, ld, X, W, bs, k, lock, theta, res, st));
@@ -431,7 +472,7 @@ int check_params(const scsf_params *p, int64_t n) {
   if (p->degree < 1 || p->degree > 64) return SCSF_EINVAL;
   if (!(p->tol > 0.0)) return SCSF_EINVAL;
   if (p->lanczos_steps < 0 || p->lanczos_steps > 128) return SCSF_EINVAL;
-  if (p->precision != SCSF_FP64) return SCSF_EINVAL;
+  if (p->precision != SCSF_FP64 && p->precision != SCSF_MIXED) return SCSF_EINVAL;
   if (p->schedule != SCSF_SCHED_STATIC && p->schedule != SCSF_SCHED_DYNAMIC) return SCSF_EINVAL;
   return SCSF_OK;
 }
@@ -454,7 +495,8 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
   const int32_t L = prm->L, k = prm->k, m = prm->degree;
 
   Engine e;
-  STCHK(e.setup(w, chains, n, k, L, m, kind, prm->tol, prm->seed, lzs));
+  STCHK(e.setup(w, chains, n, k, L, m, kind, prm->tol, prm->seed, lzs,
+                prm->precision == SCSF_MIXED));
   std::vector<int> pos(chains), iters(chains, 0);
   std::vector<int64_t> fcols(chains, 0);
   std::vector<char> active(chains, 1);
@@ -527,6 +569,7 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
       reload = true;
     }
     if (reload) {
+      e.w_stale = true;                 // A X of the newly loaded operators
       STCHK(e.upload_ops());
       STCHK(e.upload_state());
       STCHK(e.compute_bounds());
@@ -831,7 +874,8 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
   const int max_iter = prm->max_iter > 0 ? prm->max_iter : 5000;
   const int lzs = prm->lanczos_steps > 0 ? prm->lanczos_steps : 20;
   Engine e;
-  STCHK(e.setup(w0, 1, A->n, prm->k, prm->L, prm->degree, A->kind, prm->tol, prm->seed, lzs));
+  STCHK(e.setup(w0, 1, A->n, prm->k, prm->L, prm->degree, A->kind, prm->tol, prm->seed, lzs,
+                prm->precision == SCSF_MIXED));
   e.h_ops[0] = to_dev(*A);
   e.h_need[0] = 1;
   STCHK(e.upload_ops());

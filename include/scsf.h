@@ -96,6 +96,8 @@ typedef struct scsf_stats {
   int32_t nconv;         /* locked pairs at exit (>= L on success) */
   int32_t status;        /* status of this solve */
   int32_t chol_shifts;   /* Gram matrices that needed the shifted Cholesky fallback */
+  int32_t degree;        /* filter degree used (last iteration) */
+  int32_t hint;          /* window hint: 0 none, 2 used, 3 rejected by the Lanczos bounds */
   int64_t filter_cols;   /* sum over filter calls of degree * active columns */
   double beta;           /* upper spectral bound used by the filter */
   double max_rel_resid;  /* max relative residual of the returned pairs */
@@ -198,6 +200,55 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
 int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
                         const int32_t *order_host, int32_t chains, const scsf_params *prm,
                         double *evals, double *evecs, scsf_stats *stats_host);
+
+/* The learned-window form: as scsf_solve_sequence, with per-operator hints_host[n_op*3] =
+ * (predicted lambda_1, predicted lambda_{L+1}, predicted degree) in operator index order.
+ * A positive degree replaces prm->degree for that operator (1..64; within a lockstep batch
+ * degrees are raised by at most 2 to a common residue mod 3).  The predicted window replaces
+ * the Ritz-value window of the operator's first outer iteration if the Lanczos bounds accept it:
+ * lambda_1 <= theta_min(T_s) and lambda_1 < lambda_{L+1} < beta (stats.hint reports 2 / 3);
+ * otherwise the plain window is used.  hints_host may be NULL.  ritz (device, n_op x k, may be
+ * NULL) receives every operator's k final Ritz values, ascending (the labels of the window
+ * network). */
+int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
+                               const int32_t *order_host, int32_t chains,
+                               const scsf_params *prm, const double *hints_host, double *evals,
+                               double *evecs, double *ritz, scsf_stats *stats_host);
+
+/* ---------------------------------------------------------------------------------------
+ * Spectral-window network (the learned form of the window of Section 2.2; not in the paper).
+ * Input: the truncated-FFT features of Algorithm 2 with 3 channels and p0 = 16, fed as 6 real
+ * channels (Re, Im).  Layers: conv 3x3 6->16 stride 1 + ReLU, conv 3x3 16->32 stride 2 + ReLU,
+ * dense 2048->64 + ReLU, dense 64->3 (zero padding 1).  Parameters: one flat FP32 device array
+ * W1[16,6,3,3] b1[16] W2[32,16,3,3] b2[32] W3[64,2048] b3[64] W4[3,64] b4[3].
+ * Outputs: (log lambda_1, log lambda_{L+1}, degree / 64).
+ * ------------------------------------------------------------------------------------- */
+
+/* Number of FP32 parameters. */
+int scsf_window_param_count(void);
+/* He-normal weights (Philox keyed by seed), zero biases. */
+int scsf_window_init(scsf_handle *h, float *params, uint64_t seed);
+/* feats: n x 3 x 16 x 16 complex (re, im) from scsf_features -> x: n x 6 x 16 x 16 FP32. */
+int scsf_window_input(scsf_handle *h, const double *feats, int32_t n, int32_t channels,
+                      int32_t p0, float *x);
+/* out[n*3] = network(x); bf16 != 0 stores parameters and activations in BF16 (FP32 sums). */
+int scsf_window_forward(scsf_handle *h, const float *params, const float *x, int32_t n,
+                        int32_t bf16, float *out);
+/* FP32 loss mean((y - t)^2)/2 and its gradient (device, param_count floats). */
+int scsf_window_loss_grad(scsf_handle *h, const float *params, const float *x,
+                          const float *target, int32_t n, float *grad, double *loss_host);
+/* Full-batch Adam (lr, betas 0.9 / 0.999) for `epochs` steps from zero moments; params in place;
+ * loss_history_host[epochs] may be NULL. */
+int scsf_window_train(scsf_handle *h, float *params, const float *x, const float *target,
+                      int32_t n, int32_t epochs, float lr, double *loss_history_host);
+/* Training targets from solved operators: ritz (n x k ascending), beta[n] (the upper bounds
+ * used) -> target[n*3] = (log lambda_1, log lambda_{L+1}, mstar / 64) with
+ * mstar = clamp(ceil(acosh(1e4) / acosh|t(lambda_L)|), 8, 64) over the damped [lambda_{L+1}, beta]. */
+int scsf_window_labels(scsf_handle *h, const double *ritz, int32_t n, int32_t k, int32_t L,
+                       const double *beta, float *target);
+/* hints[n*3] (device, for scsf_solve_sequence_hinted) = (exp y0, exp y1, round(64 y2) clamped
+ * to [8, 64]). */
+int scsf_window_hints(scsf_handle *h, const float *out, int32_t n, double *hints);
 
 #ifdef __cplusplus
 }

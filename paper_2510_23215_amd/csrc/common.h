@@ -51,14 +51,16 @@ __host__ __device__ inline void col_range(int32_t mode, int32_t k, const int32_t
 hipError_t spmm_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t Nmax,
                      const double *X, const double *Z, double *Y, int64_t ld, int64_t bs,
                      int32_t mode, int32_t k, const int32_t *lock, const double *coef,
-                     bool has_z, hipStream_t st);
+                     bool has_z, hipStream_t st, const int32_t *mdeg = nullptr,
+                     int32_t step = 0);
 
 // FP32 variant of the step for the mixed-precision filter; with R non-null the step adds the
 // per-column source term src[b*k + c] * R[:, c] (R in the same layout as X).
 hipError_t spmm_step32(const OpDev *ops, int B, int32_t kind, int64_t nmax, const float *X,
                        const float *Z, float *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
                        const int32_t *lock, const double *coef, bool has_z, const float *R,
-                       const double *src, hipStream_t st);
+                       const double *src, hipStream_t st, const int32_t *mdeg = nullptr,
+                       int32_t step = 0);
 
 // Mixed-precision filter helpers (residual form of the recurrence, see misc.hip):
 //  mp_tables : src[(i*B + b)*k + c] = (2 sigma_{i+1}/e) p_i(theta_c) for steps i = 1..m-1 and
@@ -67,7 +69,7 @@ hipError_t spmm_step32(const OpDev *ops, int B, int32_t kind, int64_t nmax, cons
 //  mp_final  : Y = X diag(gain) + fp64(Em) (active columns).
 hipError_t mp_tables(int B, int32_t k, int32_t m, const double *theta, const double *win,
                      const int32_t *lock, const int32_t *done, double *src, double *gain,
-                     hipStream_t st);
+                     const int32_t *mdeg, hipStream_t st);
 hipError_t mp_prep(int B, int64_t n, int64_t ld, int64_t bs, int32_t k, const int32_t *lock,
                    const double *X, const double *W, const double *theta, const double *coef,
                    float *R32, float *E1, hipStream_t st);
@@ -129,9 +131,12 @@ hipError_t lock_update(int B, int32_t k, int32_t L, double tol, int32_t *lock, i
 
 // Chebyshev step coefficients for degree m: coef[(s*B + b)*3 + {0,1,2}] for s = 0..m-1 from
 // lambda = theta[b*k], alpha = theta[b*k + k-1] (or win[] when given), beta = bounds[b*4+3].
-// win (nullable) receives (lambda, c, e) per problem.
+// win (nullable) receives (lambda, c, e) per problem.  hint (nullable): per problem
+// (lambda_1, lambda_{L+1}, state); state 1 = apply once if the bounds accept it (-> 2 used,
+// 3 rejected).
 hipError_t cheb_coeffs(int B, int32_t k, int32_t m, const double *theta, const double *bounds,
-                       const int32_t *done, double *coef, double *win, hipStream_t st);
+                       const int32_t *done, double *coef, double *win, double *hint,
+                       hipStream_t st);
 // Same from explicit (lambda, c, e) per problem: win[b*3 + {0,1,2}].
 hipError_t cheb_coeffs_explicit(int B, int32_t m, const double *win, double *coef,
                                 hipStream_t st);

@@ -102,14 +102,25 @@ __device__ inline void write_coeffs(int B, int b, int32_t m, double lam, double 
 
 // Window of Section 2.2 with the reading: lambda = smallest Ritz value, alpha = largest Ritz
 // value of the block, beta = upper bound of the spectrum; c = (alpha+beta)/2, e = (beta-alpha)/2.
+// A pending hint (hint[b*3+2] == 1: predicted lambda_1, lambda_{L+1}) replaces lambda and alpha
+// once, if the Lanczos bounds accept it: lambda_1 <= theta_min(T_s) (a Ritz value bounds
+// lambda_1 from above) and lambda_1 < lambda_{L+1} < beta.  The hint state becomes 2 (used)
+// or 3 (rejected).
 __global__ void cheb_kernel(int B, int32_t k, int32_t m, const double *__restrict__ theta,
                             const double *__restrict__ bnd, const int32_t *__restrict__ done,
-                            double *__restrict__ coef, double *__restrict__ win) {
+                            double *__restrict__ coef, double *__restrict__ win,
+                            double *__restrict__ hint) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B || (done && done[b])) return;
-  const double lam = theta[(int64_t)b * k];
-  const double alpha = theta[(int64_t)b * k + k - 1];
+  double lam = theta[(int64_t)b * k];
+  double alpha = theta[(int64_t)b * k + k - 1];
   double beta = bnd[b * 4 + 3];
+  if (hint && hint[b * 3 + 2] == 1.0) {
+    const double l1 = hint[b * 3 + 0], lk = hint[b * 3 + 1];
+    const bool ok = isfinite(l1) && isfinite(lk) && l1 <= bnd[b * 4 + 2] && l1 < lk && lk < beta;
+    if (ok) { lam = l1; alpha = lk; }
+    hint[b * 3 + 2] = ok ? 2.0 : 3.0;
+  }
   const double span = fmax(fabs(alpha), fabs(lam));
   if (!(beta > alpha + 1e-12 * span)) beta = alpha + fmax(1e-3 * span, 1e-300);
   const double c = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
@@ -120,9 +131,10 @@ __global__ void cheb_kernel(int B, int32_t k, int32_t m, const double *__restric
 }
 
 hipError_t cheb_coeffs(int B, int32_t k, int32_t m, const double *theta, const double *bounds,
-                       const int32_t *done, double *coef, double *win, hipStream_t st) {
+                       const int32_t *done, double *coef, double *win, double *hint,
+                       hipStream_t st) {
   if (B <= 0) return hipSuccess;
-  cheb_kernel<<<(B + 63) / 64, 64, 0, st>>>(B, k, m, theta, bounds, done, coef, win);
+  cheb_kernel<<<(B + 63) / 64, 64, 0, st>>>(B, k, m, theta, bounds, done, coef, win, hint);
   return hipGetLastError();
 }
 
@@ -367,9 +379,10 @@ namespace scsf {
 __global__ void mp_tables_kernel(int B, int32_t k, int32_t m, const double *__restrict__ theta,
                                  const double *__restrict__ win, const int32_t *__restrict__ lock,
                                  const int32_t *__restrict__ done, double *__restrict__ src,
-                                 double *__restrict__ gain) {
+                                 double *__restrict__ gain, const int32_t *__restrict__ mdeg) {
   const int b = blockIdx.x;
   if (done && done[b]) return;
+  if (mdeg) m = mdeg[b];
   const int32_t l = lock ? lock[b] : 0;
   const double c = win[b * 3 + 1], e = win[b * 3 + 2];
   const double s1 = e / (win[b * 3 + 0] - c);
@@ -390,9 +403,9 @@ __global__ void mp_tables_kernel(int B, int32_t k, int32_t m, const double *__re
 
 hipError_t mp_tables(int B, int32_t k, int32_t m, const double *theta, const double *win,
                      const int32_t *lock, const int32_t *done, double *src, double *gain,
-                     hipStream_t st) {
+                     const int32_t *mdeg, hipStream_t st) {
   if (B <= 0) return hipSuccess;
-  mp_tables_kernel<<<B, 256, 0, st>>>(B, k, m, theta, win, lock, done, src, gain);
+  mp_tables_kernel<<<B, 256, 0, st>>>(B, k, m, theta, win, lock, done, src, gain, mdeg);
   return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 #include <thread>
 #include <vector>
 
+#include "cnn.h"
 #include "common.h"
 
 using namespace scsf;
@@ -23,7 +24,7 @@ namespace {
 enum BufId {
   B_X, B_Y1, B_Y2, B_W, B_G, B_M, B_PART, B_THETA, B_RES, B_INT, B_BND, B_COEF, B_UNIT, B_CHOL,
   B_JAC, B_LZ, B_OPS, B_WIN, B_SORTF, B_SORTD, B_SORTO, B_REC, B_RANK, B_E32, B_R32, B_SRC,
-  B_GAIN, B_WINB, B_COUNT
+  B_GAIN, B_WINB, B_HINT, B_MDEG, B_NETF, B_NETH, B_NETD, B_COUNT
 };
 
 struct DevBuf {
@@ -179,6 +180,11 @@ struct Engine {
   int32_t *ranks = nullptr, *nsweeps = nullptr;
   // mixed precision (FP32 filter in residual form)
   bool mixed = false, w_stale = true;
+  // per-problem filter degrees (hinted sequences) and window hints
+  bool var_deg = false;
+  int32_t *mdeg = nullptr, *h_mdeg = nullptr, *h_mraw = nullptr;
+  double *hint = nullptr, *h_hint = nullptr;
+  int32_t mcur = 0;                      // degree of the current iteration (max over problems)
   float *E32[3] = {nullptr, nullptr, nullptr}, *R32 = nullptr;
   double *src = nullptr, *gain = nullptr, *winb = nullptr;
   int32_t *lock = nullptr, *nconv = nullptr, *done = nullptr, *flag = nullptr, *need = nullptr;
@@ -190,9 +196,12 @@ struct Engine {
   OpDev *h_ops = nullptr;
 
   int setup(Workspace *hh, int B_, int64_t n_, int32_t k_, int32_t L_, int32_t m_, int32_t kind_,
-            double tol_, uint64_t seed_, int32_t lz_steps_, bool mixed_ = false) {
+            double tol_, uint64_t seed_, int32_t lz_steps_, bool mixed_ = false,
+            bool var_deg_ = false) {
     mixed = mixed_;
     w_stale = true;
+    var_deg = var_deg_;
+    if (var_deg) m_ = 64;                  // coefficient tables sized for the largest degree
     h = hh;
     st = hh->stream;
     B = B_;
@@ -237,6 +246,8 @@ struct Engine {
     nsweeps = rk + (size_t)B * ldm;
     STCHK(grow(h, B_LZ, (size_t)B * 3 * n, &lz));
     STCHK(grow(h, B_OPS, (size_t)B, &ops));
+    STCHK(grow(h, B_HINT, (size_t)B * 3, &hint));
+    STCHK(grow(h, B_MDEG, (size_t)B, &mdeg));
     if (mixed) {
       float *e32 = nullptr;
       STCHK(grow(h, B_E32, (size_t)3 * B * bs, &e32));
@@ -249,8 +260,8 @@ struct Engine {
       STCHK(grow(h, B_WINB, (size_t)B * 3, &winb));
     }
     // pinned: 6 int arrays of B, perm B*k, theta/res B*k, bnd B*4, unit B*3, ops B
-    const size_t pin = (size_t)B * 6 * 4 + (size_t)B * k * 4 + (size_t)B * k * 16 +
-                       (size_t)B * 4 * 8 + (size_t)B * 3 * 8 + (size_t)B * sizeof(OpDev) + 1024;
+    const size_t pin = (size_t)B * 8 * 4 + (size_t)B * k * 4 + (size_t)B * k * 16 +
+                       (size_t)B * 4 * 8 + (size_t)B * 6 * 8 + (size_t)B * sizeof(OpDev) + 2048;
     STCHK(grow_pinned(h, pin));
     char *pp = static_cast<char *>(h->pinned);
     auto take = [&](size_t bytes) {
@@ -269,15 +280,55 @@ struct Engine {
     h_bnd = (double *)take((size_t)B * 4 * 8);
     h_unit = (double *)take((size_t)B * 3 * 8);
     h_ops = (OpDev *)take((size_t)B * sizeof(OpDev));
+    h_mdeg = (int32_t *)take(B * 4);
+    h_mraw = (int32_t *)take(B * 4);
+    h_hint = (double *)take((size_t)B * 3 * 8);
     if ((size_t)(pp - static_cast<char *>(h->pinned)) > h->pinned_bytes) return SCSF_ENOMEM;
     for (int b = 0; b < B; ++b) {
       h_lock[b] = h_nconv[b] = h_done[b] = h_flag[b] = h_need[b] = 0;
+      h_mdeg[b] = h_mraw[b] = m_;
+      h_hint[3 * b] = h_hint[3 * b + 1] = h_hint[3 * b + 2] = 0.0;
       h_unit[3 * b] = 1.0;
       h_unit[3 * b + 1] = 0.0;
       h_unit[3 * b + 2] = 0.0;
     }
     HIPCHK(hipMemcpyAsync(unit, h_unit, (size_t)B * 3 * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(hint, h_hint, (size_t)B * 3 * 8, hipMemcpyHostToDevice, st));
+    // plan_degrees() uploads only when a degree differs from the mirror, so the device copy
+    // must match the mirror from the start (the buffer is reused across calls)
+    if (var_deg) HIPCHK(hipMemcpyAsync(mdeg, h_mdeg, (size_t)B * 4, hipMemcpyHostToDevice, st));
     HIPCHK(fill_int(flag, 0, B, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return SCSF_OK;
+  }
+
+  // Degrees of this iteration: the largest requested degree M over the unfinished problems;
+  // every problem's degree is raised by at most 2 to the same residue mod 3 as M, so all
+  // results end in the same buffer of the three-buffer ring.
+  int plan_degrees() {
+    int M = 1;
+    for (int b = 0; b < B; ++b)
+      if (!h_done[b]) M = std::max(M, h_mraw[b]);
+    bool changed = false;
+    for (int b = 0; b < B; ++b) {
+      int d = std::min(h_mraw[b], M);
+      while ((M - d) % 3 != 0) ++d;
+      if (d != h_mdeg[b]) { h_mdeg[b] = d; changed = true; }
+    }
+    mcur = M;
+    if (changed) {
+      HIPCHK(hipMemcpyAsync(mdeg, h_mdeg, (size_t)B * 4, hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    return SCSF_OK;
+  }
+  // Upload the hints of the listed slots only: the device marks a consumed hint (state 2/3),
+  // and the other slots' host copies would still say "pending".
+  int upload_hints(const std::vector<int> &slots) {
+    for (int b : slots)
+      HIPCHK(hipMemcpyAsync(hint + (size_t)b * 3, h_hint + (size_t)b * 3, 24,
+                            hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
     return SCSF_OK;
   }
 
@@ -308,10 +359,13 @@ struct Engine {
 
   // algorithmic bytes of one Chebyshev step over all unfinished problems: read Y_i (and
   // Y_{i-1} after the first step), write Y_{i+1}, read the operator's coefficients once
-  double step_bytes(bool has_prev, bool fp32 = false) const {
+  double step_bytes(bool has_prev, bool fp32 = false, int step = 0) const {
     double cols = 0.0, nops = 0.0;
     for (int b = 0; b < B; ++b)
-      if (!h_done[b]) { cols += (double)(k - h_lock[b]); nops += 1.0; }
+      if (!h_done[b] && (!var_deg || step < h_mdeg[b])) {
+        cols += (double)(k - h_lock[b]);
+        nops += 1.0;
+      }
     const double coeff = (kind == SCSF_STENCIL5) ? 2.0 * n + (double)n
                          : (kind == SCSF_STENCIL9) ? 3.0 * n : 0.0;
     if (fp32)  // e_i, e_{i-1}, r read, e_{i+1} written in FP32
@@ -383,9 +437,19 @@ struct Engine {
   }
 
   // One outer iteration of Algorithm 3 for every problem not done.
+  std::vector<int32_t> lock_before;
+  int32_t h_lock_prev(int b) const { return lock_before.empty() ? 0 : lock_before[b]; }
+
   int iterate() {
+    lock_before.assign(h_nconv, h_nconv + B);
+    int M = m;
+    if (var_deg) {
+      STCHK(plan_degrees());
+      M = mcur;
+    }
+    const int32_t *md = var_deg ? mdeg : nullptr;
     HIPCHK(fill_int(flag, 0, B, st));
-    HIPCHK(cheb_coeffs(B, k, m, theta, bnd, done, coef, mixed ? winb : nullptr, st));
+    HIPCHK(cheb_coeffs(B, k, M, theta, bnd, done, coef, mixed ? winb : nullptr, hint, st));
     double *Yf = nullptr;
     if (mixed) {
       // Y = p_m(A) X = X p_m(Theta) + e_m with the correction e in FP32 (misc.hip)
@@ -394,26 +458,27 @@ struct Engine {
                          false, st));
         w_stale = false;
       }
-      HIPCHK(mp_tables(B, k, m, theta, winb, lock, done, src, gain, st));
+      HIPCHK(mp_tables(B, k, M, theta, winb, lock, done, src, gain, md, st));
       HIPCHK(mp_prep(B, n, ld, bs, k, lock, X, W, theta, coef, R32, E32[1], st));
-      for (int s = 1; s < m; ++s) {
-        const int slot = prof_begin(h, h->prof ? step_bytes(s > 1, true) : 0.0);
+      for (int s = 1; s < M; ++s) {
+        const int slot = prof_begin(h, h->prof ? step_bytes(s > 1, true, s) : 0.0);
         HIPCHK(spmm_step32(ops, B, kind, n, E32[s % 3], E32[(s + 2) % 3], E32[(s + 1) % 3], ld, bs,
                            COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 1, R32,
-                           src + (size_t)s * B * k, st));
+                           src + (size_t)s * B * k, st, md, s));
         prof_end(h, slot);
       }
-      HIPCHK(mp_final(B, n, ld, bs, k, lock, X, E32[m % 3], gain, Y1, st));
+      HIPCHK(mp_final(B, n, ld, bs, k, lock, X, E32[M % 3], gain, Y1, st));
       Yf = Y1;
     } else {
       double *ring[3] = {X, Y1, Y2};
-      for (int s = 0; s < m; ++s) {
-        const int slot = prof_begin(h, h->prof ? step_bytes(s > 0) : 0.0);
+      for (int s = 0; s < M; ++s) {
+        const int slot = prof_begin(h, h->prof ? step_bytes(s > 0, false, s) : 0.0);
         HIPCHK(spmm_step(ops, B, kind, n, 0, ring[s % 3], ring[(s + 2) % 3], ring[(s + 1) % 3],
-                         ld, bs, COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 0, st));
+                         ld, bs, COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 0, st, md,
+                         s));
         prof_end(h, slot);
       }
-      Yf = ring[m % 3];
+      Yf = ring[M % 3];
     }
     STCHK(orth(Yf, true));
     STCHK(rayleigh_ritz(Yf));
@@ -429,6 +494,8 @@ struct Engine {
     HIPCHK(hipMemcpyAsync(h_res + (size_t)b * k, res + (size_t)b * k, (size_t)k * 8,
                           hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h_bnd + (size_t)b * 4, bnd + (size_t)b * 4, 32, hipMemcpyDeviceToHost,
+                          st));
+    HIPCHK(hipMemcpyAsync(h_hint + (size_t)b * 3, hint + (size_t)b * 3, 24, hipMemcpyDeviceToHost,
                           st));
     HIPCHK(hipStreamSynchronize(st));
     return SCSF_OK;
@@ -484,8 +551,8 @@ int check_params(const scsf_params *p, int64_t n) {
 // positions and ce is ignored.
 int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order_host,
                int32_t n_op, const std::vector<int> &cb, const std::vector<int> &ce,
-               std::atomic<int> *next, const scsf_params *prm, double *evals, double *evecs,
-               scsf_stats *stats_host) {
+               std::atomic<int> *next, const scsf_params *prm, const double *hints_host,
+               double *evals, double *evecs, double *ritz, scsf_stats *stats_host) {
   const int chains = (int)cb.size();
   if (chains == 0) return SCSF_OK;
   const int64_t n = ops_host[0].n;
@@ -496,15 +563,32 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
 
   Engine e;
   STCHK(e.setup(w, chains, n, k, L, m, kind, prm->tol, prm->seed, lzs,
-                prm->precision == SCSF_MIXED));
+                prm->precision == SCSF_MIXED, hints_host != nullptr));
   std::vector<int> pos(chains), iters(chains, 0);
   std::vector<int64_t> fcols(chains, 0);
   std::vector<char> active(chains, 1);
+  // degree and window hint of the operator at order position `at`, loaded into slot b
+  auto load_hint = [&](int b, int at) {
+    int d = m;
+    e.h_hint[3 * b + 2] = 0.0;
+    if (hints_host) {
+      const double *hh = hints_host + (size_t)order_host[at] * 3;
+      if (hh[2] >= 1.0) d = std::min(64, std::max(1, (int)std::lround(hh[2])));
+      e.h_hint[3 * b + 0] = hh[0];
+      e.h_hint[3 * b + 1] = hh[1];
+      e.h_hint[3 * b + 2] = (hh[0] > 0.0 && hh[1] > 0.0) ? 1.0 : 0.0;
+    }
+    e.h_mraw[b] = d;
+  };
+  std::vector<int> all_slots(chains);
+  std::iota(all_slots.begin(), all_slots.end(), 0);
   for (int b = 0; b < chains; ++b) {
     pos[b] = cb[b];
     e.h_ops[b] = to_dev(ops_host[order_host[pos[b]]]);
     e.h_need[b] = 1;
+    load_hint(b, pos[b]);
   }
+  STCHK(e.upload_hints(all_slots));
   STCHK(e.upload_ops());
   STCHK(e.upload_state());
   STCHK(e.compute_bounds());
@@ -519,11 +603,11 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
   int worst = SCSF_OK;
   int remaining = chains;
   while (remaining > 0) {
-    for (int b = 0; b < chains; ++b)
-      if (active[b]) fcols[b] += (int64_t)m * (k - e.h_nconv[b]);
     STCHK(e.iterate());
+    for (int b = 0; b < chains; ++b)
+      if (active[b]) fcols[b] += (int64_t)(e.var_deg ? e.h_mdeg[b] : m) * (k - e.h_lock_prev(b));
     bool reload = false;
-    std::vector<int> recold;
+    std::vector<int> recold, reloaded;
     for (int b = 0; b < chains; ++b) {
       if (!active[b]) continue;
       ++iters[b];
@@ -533,6 +617,11 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
       const int status = solve_status(e.h_flag[b], e.h_done[b] != 0);
       STCHK(e.fetch(b));
       double mr = 0.0;
+      if (ritz) {                       // all k Ritz values, ascending
+        std::vector<double> th(e.h_theta + (size_t)b * k, e.h_theta + (size_t)b * k + k);
+        std::sort(th.begin(), th.end());
+        HIPCHK(hipMemcpy(ritz + (size_t)op * k, th.data(), (size_t)k * 8, hipMemcpyHostToDevice));
+      }
       STCHK(e.extract(b, evals + (size_t)op * L, evecs + (size_t)op * n * L, n, &mr));
       if (stats_host) {
         scsf_stats &st = stats_host[op];
@@ -540,6 +629,8 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
         st.nconv = e.h_nconv[b];
         st.status = status;
         st.chol_shifts = (e.h_flag[b] & 4) ? 1 : 0;
+        st.degree = e.var_deg ? e.h_mdeg[b] : m;
+        st.hint = (int32_t)e.h_hint[(size_t)b * 3 + 2];
         st.filter_cols = fcols[b];
         st.beta = e.h_bnd[(size_t)b * 4 + 3];
         st.max_rel_resid = mr;
@@ -561,6 +652,8 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
       }
       // next operator of the chain, warm-started from this solve (all k Ritz pairs)
       e.h_ops[b] = to_dev(ops_host[order_host[pos[b]]]);
+      load_hint(b, pos[b]);
+      reloaded.push_back(b);
       e.h_need[b] = 1;
       e.h_done[b] = 0;
       e.h_nconv[b] = 0;
@@ -570,6 +663,7 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
     }
     if (reload) {
       e.w_stale = true;                 // A X of the newly loaded operators
+      STCHK(e.upload_hints(reloaded));
       STCHK(e.upload_ops());
       STCHK(e.upload_state());
       STCHK(e.compute_bounds());
@@ -911,6 +1005,8 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
     stats_host->nconv = e.h_nconv[0];
     stats_host->status = status;
     stats_host->chol_shifts = (e.h_flag[0] & 4) ? 1 : 0;
+    stats_host->degree = prm->degree;
+    stats_host->hint = 0;
     stats_host->filter_cols = fcols;
     stats_host->beta = e.h_bnd[3];
     stats_host->max_rel_resid = mr;
@@ -921,6 +1017,14 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
 int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
                         const int32_t *order_host, int32_t chains, const scsf_params *prm,
                         double *evals, double *evecs, scsf_stats *stats_host) {
+  return scsf_solve_sequence_hinted(h, ops_host, n_op, order_host, chains, prm, nullptr, evals,
+                                    evecs, nullptr, stats_host);
+}
+
+int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
+                               const int32_t *order_host, int32_t chains,
+                               const scsf_params *prm, const double *hints_host, double *evals,
+                               double *evecs, double *ritz, scsf_stats *stats_host) {
   if (!h || !ops_host || n_op <= 0 || !order_host || chains <= 0 || !evals || !evecs)
     return SCSF_EINVAL;
   const int64_t n = ops_host[0].n;
@@ -960,7 +1064,7 @@ int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n
       ce.push_back(dyn ? c + 1 : cbeg[c + 1]);
     }
     status[g] = run_chains(h->ws[g], ops_host, order_host, n_op, cb, ce, dyn ? &next : nullptr,
-                           prm, evals, evecs, stats_host);
+                           prm, hints_host, evals, evecs, ritz, stats_host);
   };
   std::vector<std::thread> threads;
   for (int g = 1; g < lanes; ++g) threads.emplace_back(lane_fn, g);
@@ -974,6 +1078,125 @@ int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n
     if (worst == SCSF_OK || (worst == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)) worst = s2;
   }
   return worst;
+}
+
+// ------------------------------------------------------------------ the learned window
+int scsf_window_param_count(void) { return (int)kNetParams; }
+
+namespace {
+struct NetBufs {
+  float *a1, *a2, *a3, *y, *d, *da3, *da2, *da1, *grad, *m, *v;
+  uint16_t *pbf, *xbf, *b1, *b2, *b3, *ybf;
+  double *loss;
+};
+int net_bufs(Workspace *w, int n, NetBufs &nb) {
+  const size_t per = 4096 + 2048 + 64 + 3 + 3 + 64 + 2048 + 4096;
+  float *f = nullptr;
+  STCHK(grow(w, B_NETF, (size_t)n * per + 3 * (size_t)kNetParams + 64, &f));
+  nb.a1 = f; f += (size_t)n * 4096;
+  nb.a2 = f; f += (size_t)n * 2048;
+  nb.a3 = f; f += (size_t)n * 64;
+  nb.y = f; f += (size_t)n * 3;
+  nb.d = f; f += (size_t)n * 3;
+  nb.da3 = f; f += (size_t)n * 64;
+  nb.da2 = f; f += (size_t)n * 2048;
+  nb.da1 = f; f += (size_t)n * 4096;
+  nb.grad = f; f += kNetParams;
+  nb.m = f; f += kNetParams;
+  nb.v = f;
+  uint16_t *hh = nullptr;
+  STCHK(grow(w, B_NETH, (size_t)kNetParams + (size_t)n * (1536 + 4096 + 2048 + 64 + 3) + 64, &hh));
+  nb.pbf = hh; hh += kNetParams;
+  nb.xbf = hh; hh += (size_t)n * 1536;
+  nb.b1 = hh; hh += (size_t)n * 4096;
+  nb.b2 = hh; hh += (size_t)n * 2048;
+  nb.b3 = hh; hh += (size_t)n * 64;
+  nb.ybf = hh;
+  STCHK(grow(w, B_NETD, 8, &nb.loss));
+  return SCSF_OK;
+}
+}  // namespace
+
+int scsf_window_init(scsf_handle *h, float *params, uint64_t seed) {
+  if (!h || !params) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  HIPCHK(cnn_init(params, seed, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
+}
+
+int scsf_window_input(scsf_handle *h, const double *feats, int32_t n, int32_t channels,
+                      int32_t p0, float *x) {
+  if (!h || !feats || !x || n <= 0 || channels != 3 || p0 != 16) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  HIPCHK(cnn_input(feats, n, channels, p0, x, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
+}
+
+int scsf_window_forward(scsf_handle *h, const float *params, const float *x, int32_t n,
+                        int32_t bf16, float *out) {
+  if (!h || !params || !x || !out || n <= 0) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  NetBufs nb;
+  STCHK(net_bufs(w0, n, nb));
+  if (bf16)
+    HIPCHK(cnn_forward_bf16(params, x, n, nb.pbf, nb.xbf, nb.b1, nb.b2, nb.b3, nb.ybf, out,
+                            w0->stream));
+  else
+    HIPCHK(cnn_forward(params, x, n, nb.a1, nb.a2, nb.a3, out, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
+}
+
+int scsf_window_loss_grad(scsf_handle *h, const float *params, const float *x,
+                          const float *target, int32_t n, float *grad, double *loss_host) {
+  if (!h || !params || !x || !target || !grad || n <= 0) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  NetBufs nb;
+  STCHK(net_bufs(w0, n, nb));
+  HIPCHK(cnn_loss_grad(params, x, target, n, nb.a1, nb.a2, nb.a3, nb.y, nb.d, nb.da3, nb.da2,
+                       nb.da1, grad, nb.loss, w0->stream));
+  if (loss_host)
+    HIPCHK(hipMemcpyAsync(loss_host, nb.loss, 8, hipMemcpyDeviceToHost, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
+}
+
+int scsf_window_train(scsf_handle *h, float *params, const float *x, const float *target,
+                      int32_t n, int32_t epochs, float lr, double *loss_history_host) {
+  if (!h || !params || !x || !target || n <= 0 || epochs <= 0 || !(lr > 0.f)) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  NetBufs nb;
+  STCHK(net_bufs(w0, n, nb));
+  HIPCHK(hipMemsetAsync(nb.m, 0, (size_t)2 * kNetParams * sizeof(float), w0->stream));
+  for (int ep = 1; ep <= epochs; ++ep) {
+    HIPCHK(cnn_loss_grad(params, x, target, n, nb.a1, nb.a2, nb.a3, nb.y, nb.d, nb.da3, nb.da2,
+                         nb.da1, nb.grad, nb.loss, w0->stream));
+    if (loss_history_host)
+      HIPCHK(hipMemcpyAsync(loss_history_host + (ep - 1), nb.loss, 8, hipMemcpyDeviceToHost,
+                            w0->stream));
+    HIPCHK(cnn_adam(params, nb.grad, nb.m, nb.v, ep, lr, w0->stream));
+  }
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
+}
+
+int scsf_window_labels(scsf_handle *h, const double *ritz, int32_t n, int32_t k, int32_t L,
+                       const double *beta, float *target) {
+  if (!h || !ritz || !beta || !target || n <= 0 || L <= 0 || L >= k) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  HIPCHK(cnn_labels(ritz, n, k, L, beta, target, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
+}
+
+int scsf_window_hints(scsf_handle *h, const float *out, int32_t n, double *hints) {
+  if (!h || !out || !hints || n <= 0) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  HIPCHK(cnn_hints(out, n, hints, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
 }
 
 }  // extern "C"

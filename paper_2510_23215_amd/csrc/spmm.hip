@@ -20,8 +20,10 @@ __global__ void __launch_bounds__(256) spmm_step_kernel(
     const OpDev *__restrict__ ops, const T *__restrict__ X, const T *__restrict__ Z,
     T *__restrict__ Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
     const int32_t *__restrict__ lock, const double *__restrict__ coef, int has_z,
-    const T *__restrict__ R, const double *__restrict__ src) {
+    const T *__restrict__ R, const double *__restrict__ src, const int32_t *__restrict__ mdeg,
+    int32_t step) {
   const int b = blockIdx.z;
+  if (mdeg && step >= mdeg[b]) return;                // this problem's filter has finished
   const OpDev op = ops[b];
   const int64_t n = op.n;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -118,7 +120,8 @@ template <typename T, bool SRC>
 static hipError_t launch_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, const T *X,
                               const T *Z, T *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
                               const int32_t *lock, const double *coef, bool has_z, const T *R,
-                              const double *src, hipStream_t st) {
+                              const double *src, const int32_t *mdeg, int32_t step,
+                              hipStream_t st) {
   constexpr int CPT = 4;
   if (B <= 0 || nmax <= 0 || k <= 0) return hipSuccess;
   dim3 block(256);
@@ -126,33 +129,33 @@ static hipError_t launch_step(const OpDev *ops, int B, int32_t kind, int64_t nma
   const int hz = has_z ? 1 : 0;
   if (kind == SCSF_STENCIL5)
     spmm_step_kernel<SCSF_STENCIL5, CPT, T, SRC><<<grid, block, 0, st>>>(
-        ops, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src);
+        ops, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src, mdeg, step);
   else if (kind == SCSF_STENCIL9)
     spmm_step_kernel<SCSF_STENCIL9, CPT, T, SRC><<<grid, block, 0, st>>>(
-        ops, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src);
+        ops, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src, mdeg, step);
   else
     spmm_step_kernel<SCSF_CSR, CPT, T, SRC><<<grid, block, 0, st>>>(
-        ops, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src);
+        ops, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src, mdeg, step);
   return hipGetLastError();
 }
 
 hipError_t spmm_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t /*Nmax*/,
                      const double *X, const double *Z, double *Y, int64_t ld, int64_t bs,
                      int32_t mode, int32_t k, const int32_t *lock, const double *coef,
-                     bool has_z, hipStream_t st) {
+                     bool has_z, hipStream_t st, const int32_t *mdeg, int32_t step) {
   return launch_step<double, false>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
-                                    has_z, nullptr, nullptr, st);
+                                    has_z, nullptr, nullptr, mdeg, step, st);
 }
 
 hipError_t spmm_step32(const OpDev *ops, int B, int32_t kind, int64_t nmax, const float *X,
                        const float *Z, float *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
                        const int32_t *lock, const double *coef, bool has_z, const float *R,
-                       const double *src, hipStream_t st) {
+                       const double *src, hipStream_t st, const int32_t *mdeg, int32_t step) {
   if (R)
     return launch_step<float, true>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
-                                    has_z, R, src, st);
+                                    has_z, R, src, mdeg, step, st);
   return launch_step<float, false>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
-                                   has_z, nullptr, nullptr, st);
+                                   has_z, nullptr, nullptr, mdeg, step, st);
 }
 
 }  // namespace scsf

@@ -47,8 +47,8 @@ class Profile(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", c_int32), ("nconv", c_int32), ("status", c_int32),
-                ("chol_shifts", c_int32), ("filter_cols", c_int64), ("beta", c_double),
-                ("max_rel_resid", c_double)]
+                ("chol_shifts", c_int32), ("degree", c_int32), ("hint", c_int32),
+                ("filter_cols", c_int64), ("beta", c_double), ("max_rel_resid", c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -82,6 +82,16 @@ def lib():
             "scsf_solve_sequence": [vp, POINTER(Operator), i32, POINTER(c_int32), i32,
                                     POINTER(Params), vp, vp, POINTER(Stats)],
         }
+        sig["scsf_solve_sequence_hinted"] = [vp, POINTER(Operator), i32, POINTER(c_int32), i32,
+                                             POINTER(Params), POINTER(c_double), vp, vp, vp,
+                                             POINTER(Stats)]
+        sig["scsf_window_init"] = [vp, vp, u64]
+        sig["scsf_window_input"] = [vp, vp, i32, i32, i32, vp]
+        sig["scsf_window_forward"] = [vp, vp, vp, i32, i32, vp]
+        sig["scsf_window_loss_grad"] = [vp, vp, vp, vp, i32, vp, POINTER(c_double)]
+        sig["scsf_window_train"] = [vp, vp, vp, vp, i32, i32, ctypes.c_float, POINTER(c_double)]
+        sig["scsf_window_labels"] = [vp, vp, i32, i32, i32, vp, vp]
+        sig["scsf_window_hints"] = [vp, vp, i32, vp]
         sig["scsf_profile_enable"] = [vp, i32]
         sig["scsf_set_lanes"] = [vp, i32]
         sig["scsf_profile_read"] = [vp, POINTER(Profile), i32]
@@ -91,6 +101,8 @@ def lib():
             f.restype = c_int32
         L.scsf_status_string.argtypes = [c_int32]
         L.scsf_status_string.restype = ctypes.c_char_p
+        L.scsf_window_param_count.argtypes = []
+        L.scsf_window_param_count.restype = c_int32
         L.scsf_version.argtypes = []
         L.scsf_version.restype = ctypes.c_char_p
         _lib = L
@@ -284,7 +296,7 @@ def scsf_solve(h: Handle, A: DeviceOperator, prm: Params, X_prev=None, theta_pre
 
 def scsf_solve_sequence(h: Handle, ops: list, order, chains: int, prm: Params,
                         evals: torch.Tensor | None = None, evecs: torch.Tensor | None = None,
-                        allow_notconv=False):
+                        allow_notconv=False, hints=None, ritz: torch.Tensor | None = None):
     """Solve every operator in `ops` (DeviceOperator list) in `order`, `chains` chunks.
     Returns (evals n_op x L, evecs n_op x (n x L column-major) tensor, list of stats dicts)."""
     n_op = len(ops)
@@ -298,9 +310,19 @@ def scsf_solve_sequence(h: Handle, ops: list, order, chains: int, prm: Params,
         evecs = torch.empty((n_op, L, n), device="cuda", dtype=torch.float64)
     stats = (Stats * n_op)()
     allow = (SCSF_OK, SCSF_ENOTCONV) if allow_notconv else (SCSF_OK,)
-    _check(lib().scsf_solve_sequence(h.ptr, arr, n_op, ordc, int(chains), ctypes.byref(prm),
-                                     _ptr(evals), _ptr(evecs), stats), "scsf_solve_sequence",
-           allow)
+    if hints is None and ritz is None:
+        _check(lib().scsf_solve_sequence(h.ptr, arr, n_op, ordc, int(chains), ctypes.byref(prm),
+                                         _ptr(evals), _ptr(evecs), stats), "scsf_solve_sequence",
+               allow)
+    else:
+        hp = None
+        if hints is not None:
+            hv = np.ascontiguousarray(np.asarray(hints, dtype=np.float64).reshape(n_op, 3))
+            hp = hv.ctypes.data_as(POINTER(c_double))
+        _check(lib().scsf_solve_sequence_hinted(h.ptr, arr, n_op, ordc, int(chains),
+                                                ctypes.byref(prm), hp, _ptr(evals), _ptr(evecs),
+                                                _ptr(ritz), stats),
+               "scsf_solve_sequence_hinted", allow)
     return evals, evecs, [s.as_dict() for s in stats]
 
 
@@ -317,6 +339,67 @@ def scsf_profile_read(h: Handle, reset: bool = False) -> dict:
     _check(lib().scsf_profile_read(h.ptr, ctypes.byref(p), 1 if reset else 0), "scsf_profile_read")
     return {"filter_launches": p.filter_launches, "filter_ms": p.filter_ms,
             "filter_bytes": p.filter_bytes}
+
+
+# ----------------------------------------------------------------- spectral-window network
+def window_param_count() -> int:
+    return int(lib().scsf_window_param_count())
+
+
+def scsf_window_init(h: Handle, seed: int = 0) -> torch.Tensor:
+    p = torch.empty(window_param_count(), device="cuda", dtype=torch.float32)
+    _check(lib().scsf_window_init(h.ptr, _ptr(p), c_uint64(seed)), "scsf_window_init")
+    return p
+
+
+def scsf_window_input(h: Handle, feats: torch.Tensor) -> torch.Tensor:
+    """feats: (n, 3, 16, 16) complex128 device tensor -> (n, 6, 16, 16) float32."""
+    n, C, p0, _ = feats.shape
+    fr = torch.view_as_real(feats.contiguous())
+    x = torch.empty((n, 2 * C, p0, p0), device=feats.device, dtype=torch.float32)
+    _check(lib().scsf_window_input(h.ptr, _ptr(fr), n, C, p0, _ptr(x)), "scsf_window_input")
+    return x
+
+
+def scsf_window_forward(h: Handle, params: torch.Tensor, x: torch.Tensor, bf16=False):
+    n = x.shape[0]
+    out = torch.empty((n, 3), device=x.device, dtype=torch.float32)
+    _check(lib().scsf_window_forward(h.ptr, _ptr(params), _ptr(x.contiguous()), n,
+                                     1 if bf16 else 0, _ptr(out)), "scsf_window_forward")
+    return out
+
+
+def scsf_window_loss_grad(h: Handle, params, x, target):
+    grad = torch.empty_like(params)
+    loss = c_double()
+    _check(lib().scsf_window_loss_grad(h.ptr, _ptr(params), _ptr(x.contiguous()),
+                                       _ptr(target.contiguous()), x.shape[0], _ptr(grad),
+                                       ctypes.byref(loss)), "scsf_window_loss_grad")
+    return loss.value, grad
+
+
+def scsf_window_train(h: Handle, params, x, target, epochs: int, lr: float):
+    hist = (c_double * epochs)()
+    _check(lib().scsf_window_train(h.ptr, _ptr(params), _ptr(x.contiguous()),
+                                   _ptr(target.contiguous()), x.shape[0], int(epochs),
+                                   ctypes.c_float(lr), hist), "scsf_window_train")
+    return np.frombuffer(hist, dtype=np.float64).copy()
+
+
+def scsf_window_labels(h: Handle, ritz: torch.Tensor, L: int, beta: torch.Tensor):
+    n, k = ritz.shape
+    t = torch.empty((n, 3), device=ritz.device, dtype=torch.float32)
+    _check(lib().scsf_window_labels(h.ptr, _ptr(ritz.contiguous()), n, k, L,
+                                    _ptr(beta.contiguous()), _ptr(t)), "scsf_window_labels")
+    return t
+
+
+def scsf_window_hints(h: Handle, out: torch.Tensor) -> torch.Tensor:
+    n = out.shape[0]
+    hints = torch.empty((n, 3), device=out.device, dtype=torch.float64)
+    _check(lib().scsf_window_hints(h.ptr, _ptr(out.contiguous()), n, _ptr(hints)),
+           "scsf_window_hints")
+    return hints
 
 
 def version() -> str:

@@ -39,4 +39,4 @@ def test_struct_layouts_match_header():
     from paper_2510_23215_amd import scsf
     assert ctypes.sizeof(scsf.Operator) == 4 + 4 + 8 + 7 * 8 + 8
     assert ctypes.sizeof(scsf.Params) == 7 * 4 + 4 + 8 + 8
-    assert ctypes.sizeof(scsf.Stats) == 4 * 4 + 8 + 8 + 8
+    assert ctypes.sizeof(scsf.Stats) == 6 * 4 + 8 + 8 + 8

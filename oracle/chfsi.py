@@ -20,17 +20,22 @@ Readings (ambiguous or silent passages):
 * G is formed on the active columns only, and the rotated Ritz vectors replace V0;
 * convergence uses the relative residual ||A v - theta v|| / ||A v|| (App. D.5 error metric);
   the longest converged ascending prefix of the active Ritz pairs is locked;
-* all k final Ritz pairs (locked and active) are handed to the next problem;
+* all k final Ritz pairs (locked and active) are handed to the next problem; between
+  operators on grids of different sides the vectors are moved by bilinear interpolation
+  (transfer.py) and the Ritz values are kept (the operators are scaled by 1/h^2, so the low
+  eigenvalues hardly depend on the side);
 * after `max_iter` outer iterations the best pairs so far are returned, flagged unconverged.
 """
 from __future__ import annotations
 
 import dataclasses
+import math
+
 import numpy as np
 
 from .chebyshev import filter_block
 from .eig import canonical_sign
-from . import lanczos
+from . import lanczos, transfer
 
 
 @dataclasses.dataclass
@@ -105,12 +110,23 @@ def scsf_sequence(mats, L: int, k: int, m: int, tol: float, order=None, warm: bo
     order = list(range(len(mats))) if order is None else list(order)
     out = {}
     prev = None
+    prev_n = None
     for i in order:
+        n = mats[i].shape[0]
         if warm and prev is not None:
-            r = chfsi(mats[i], L, k, m, tol, X0=prev.X_next, theta0=prev.theta_next,
+            X0 = prev.X_next
+            if n != prev_n:
+                # operators on square grids of different sides: the fields move by bilinear
+                # interpolation (zero Dirichlet boundary) before the warm start
+                N0, N1 = math.isqrt(prev_n), math.isqrt(n)
+                if N0 * N0 != prev_n or N1 * N1 != n:
+                    raise ValueError("warm start across sizes needs square grids")
+                X0 = transfer.interpolate_block(X0, N0, N1)
+            r = chfsi(mats[i], L, k, m, tol, X0=X0, theta0=prev.theta_next,
                       seed=seed, max_iter=max_iter)
         else:
             r = chfsi(mats[i], L, k, m, tol, seed=seed, max_iter=max_iter)
         out[i] = r
         prev = r
+        prev_n = n
     return out

@@ -178,6 +178,14 @@ int scsf_features(scsf_handle *h, const double *fields, int32_t n_op, int32_t ch
 int scsf_sort(scsf_handle *h, const double *fields, int32_t n_op, int32_t channels,
               int32_t p, int32_t p0, int32_t start, int32_t *order_host);
 
+/* The greedy nearest-neighbour order of Algorithm 2 on precomputed features: feats (device)
+ * holds n_op rows of flen complex numbers (re, im interleaved), e.g. scsf_features outputs of
+ * fields of different sides p concatenated (the 1/p^2 scaling makes them comparable).
+ * Squared Frobenius distances; ties go to the lowest index.  n_op <= 32768; needs n_op^2
+ * doubles of workspace. */
+int scsf_order_features(scsf_handle *h, const double *feats, int32_t n_op, int32_t flen,
+                        int32_t start, int32_t *order_host);
+
 /* ---------------------------------------------------------------------------------------
  * Solvers.
  * ------------------------------------------------------------------------------------- */
@@ -214,6 +222,42 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
                                const int32_t *order_host, int32_t chains,
                                const scsf_params *prm, const double *hints_host, double *evals,
                                double *evecs, double *ritz, scsf_stats *stats_host);
+
+/* ---------------------------------------------------------------------------------------
+ * Uneven batches (operators of different sizes and different L in one call).  Not in the
+ * paper: its chunked dataset runs (App. D.6) generalised to mixed sizes.
+ * ------------------------------------------------------------------------------------- */
+
+/* Default block width k for L wanted pairs: the smallest multiple of 8 that is >= L plus
+ * ceil(0.2 L) guard vectors (at most 256).  SCSF_EINVAL unless 0 < L < 256. */
+int scsf_block_width(int32_t L);
+
+/* Bilinear transfer of ncols nodal fields between interior grids of the unit square: column
+ * c of X (device, N0*N0 entries, node (iy, ix) at entry iy*N0 + ix, ld ldx >= N0^2) is read as
+ * a field with zero Dirichlet boundary and evaluated at the N1 x N1 nodes into column c of Y
+ * (device, ld ldy >= N1^2).  X and Y must not overlap (SCSF_EINVAL).  Used to warm-start a
+ * solve from the Ritz vectors of an operator on a grid of another side. */
+int scsf_interpolate(scsf_handle *h, int32_t N0, int32_t N1, int32_t ncols, const double *X,
+                     int64_t ldx, double *Y, int64_t ldy);
+
+/* A dataset of operators of different sizes and different numbers of wanted pairs.
+ * ops_host[n_op]: descriptors (any mix of sizes; kinds may differ).  L_host[n_op]: wanted
+ * pairs per operator (0 < L < 256).  k_host[n_op]: block widths, or NULL for
+ * scsf_block_width(L).  prm supplies degree, tol, max_iter, lanczos_steps, seed and schedule
+ * (prm->L and prm->k are ignored); only SCSF_FP64 is accepted.
+ * The operators are grouped by (kind, L, k), keeping order_host's order inside each group,
+ * and every group is split into chains (about chains * group size / n_op of them) that run as
+ * in scsf_solve_sequence.  Along a chain each solve warm-starts from the previous one; when
+ * the grid side changes the Ritz vectors are moved by scsf_interpolate's transfer (operators
+ * not on square grids restart cold).
+ * Outputs, packed in operator-index order: evals[sum L_i] with operator i at
+ * sum_{j<i} L_j, evecs[sum n_i L_i] with operator i's n_i x L_i block (ld n_i) at
+ * sum_{j<i} n_j L_j.  stats_host[n_op] may be NULL.  Returns SCSF_ENOTCONV if any solve did
+ * not converge. */
+int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
+                       const int32_t *L_host, const int32_t *k_host, const int32_t *order_host,
+                       int32_t chains, const scsf_params *prm, double *evals, double *evecs,
+                       scsf_stats *stats_host);
 
 /* ---------------------------------------------------------------------------------------
  * Spectral-window network (the learned form of the window of Section 2.2; not in the paper).

@@ -13,8 +13,8 @@ constexpr int kMaxK = 256;
 // Row chunk processed by one workgroup of the tall-skinny Gram kernel.
 constexpr int kGramChunk = 512;
 
-inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Device-side operator descriptor of one problem in a batch.
 struct OpDev {
@@ -82,10 +82,13 @@ hipError_t mp_final(int B, int64_t n, int64_t ld, int64_t bs, int32_t k, const i
 //   C_b = C + b*ldc*ldc (ldc x ldc, column-major), entries outside the ranges untouched.
 //   symmetric = true: A and B are the same block/range, only upper tiles computed and C is
 //   symmetrised.
+//   rows (nullable): rows[b] <= n rows of problem b take part (a batch of uneven sizes in
+//   blocks of leading dimension ld); null means n rows for every problem.
 hipError_t gemm_tn(int B, int64_t n, int64_t ld, const double *A, int64_t bsA, int32_t modeA,
                    const double *Bm, int64_t bsB, int32_t modeB, int32_t k, const int32_t *lock,
                    bool symmetric, double *partial, int64_t partial_stride, double *C, int32_t ldc,
-                   const int32_t *gate, int32_t gate_mask, hipStream_t st);
+                   const int32_t *gate, int32_t gate_mask, hipStream_t st,
+                   const int32_t *rows = nullptr);
 int64_t gemm_tn_partial_elems(int64_t n, int32_t ldc);
 
 // Out_b[:, cols(modeO)] = beta*Out + alpha * In_b[:, cols(modeI)] * M_b,
@@ -93,10 +96,12 @@ int64_t gemm_tn_partial_elems(int64_t n, int32_t ldc);
 // In and Out may be the same block when beta == 0 (in-place rotation).
 // gate (nullable): only problems with gate[b] & gate_mask run; skip (nullable): problems with
 // skip[b] & skip_mask are left untouched (a failed factorisation is never applied).
+// rows (nullable): only the first rows[b] rows of problem b are computed and written.
 hipError_t gemm_nn(int B, int64_t n, int64_t ld, const double *In, int64_t bsI, int32_t modeI,
                    double *Out, int64_t bsO, int32_t modeO, int32_t k, const int32_t *lock,
                    const double *M, int32_t ldm, double alpha, double beta, const int32_t *gate,
-                   int32_t gate_mask, const int32_t *skip, int32_t skip_mask, hipStream_t st);
+                   int32_t gate_mask, const int32_t *skip, int32_t skip_mask, hipStream_t st,
+                   const int32_t *rows = nullptr);
 
 // Per problem b (columns ACTIVE of width ka = k - lock[b]): scaled Cholesky of the Gram
 // matrix G_b (ldm x ldm) and the inverse factor M_b = D^-1 R^-1 with D = diag(sqrt(G_jj)),
@@ -118,10 +123,11 @@ hipError_t jacobi_eig(int B, int32_t k, const int32_t *lock, double *G, double *
                       int32_t *ranks, int32_t *nsweeps, hipStream_t st);
 int64_t jacobi_record_elems(int32_t k);
 
-// res[b*k + c] = ||W c - theta c X c|| / ||W c|| for the active columns.
+// res[b*k + c] = ||W c - theta c X c|| / ||W c|| for the active columns (over rows[b] rows
+// when rows is given).
 hipError_t residuals(int B, int64_t n, int64_t ld, const double *X, const double *W,
                      int64_t bs, int32_t k, const int32_t *lock, const double *theta, double *res,
-                     hipStream_t st);
+                     hipStream_t st, const int32_t *rows = nullptr);
 
 // Lock the longest converged ascending prefix of the active columns: nconv[b] grows by the
 // prefix with res <= tol.  lock[b] (first active column) follows nconv[b], and becomes k once
@@ -161,6 +167,10 @@ hipError_t copy_block(int64_t n, int32_t ncols, const double *src, int64_t lds, 
 hipError_t canonical_sign(int64_t n, int32_t ncols, double *X, int64_t ld, hipStream_t st);
 
 hipError_t fill_int(int32_t *a, int32_t v, int32_t count, hipStream_t st);
+// Bilinear transfer of ncols nodal fields from the N0 x N0 to the N1 x N1 interior grid of
+// the unit square (zero Dirichlet boundary); X and Y must not overlap.
+hipError_t interpolate_fields(int32_t N0, int32_t N1, int32_t ncols, const double *X,
+                              int64_t ldx, double *Y, int64_t ldy, hipStream_t st);
 hipError_t gather_columns(int64_t n, int32_t ncols, const double *src, int64_t lds,
                           const int32_t *perm, double *dst, int64_t ldd, hipStream_t st);
 

@@ -30,10 +30,13 @@ __global__ void __launch_bounds__(256) gemm_tn_kernel(
     int64_t n, int64_t ld, const double *__restrict__ A, int64_t bsA, int32_t modeA,
     const double *__restrict__ Bm, int64_t bsB, int32_t modeB, int32_t k,
     const int32_t *__restrict__ lock, int32_t sym, double *__restrict__ partial,
-    int64_t pstride, int32_t ldc, const int32_t *__restrict__ gate, int32_t gate_mask) {
+    int64_t pstride, int32_t ldc, const int32_t *__restrict__ gate, int32_t gate_mask,
+    const int32_t *__restrict__ rows) {
   __shared__ double red[3][64][16];
   const int b = blockIdx.z, s = blockIdx.y;
   if (gate && !(gate[b] & gate_mask)) return;
+  const int64_t nb = rows ? (int64_t)rows[b] : n;    // this problem's row count
+  if ((int64_t)s * kGramChunk >= nb) return;         // chunk beyond it: never reduced
   const int T = ldc / 32;
   const int ti = blockIdx.x % T, tj = blockIdx.x / T;
   if (sym == TN_GRAM && ti > tj) return;
@@ -45,7 +48,7 @@ __global__ void __launch_bounds__(256) gemm_tn_kernel(
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r4 = lane >> 4, c16 = lane & 15;
   const int64_t row_begin = (int64_t)s * kGramChunk;
-  const int64_t row_end = min(n, row_begin + kGramChunk);
+  const int64_t row_end = min(nb, row_begin + kGramChunk);
   const double *Ab = A + (int64_t)b * bsA;
   const double *Bb = Bm + (int64_t)b * bsB;
 
@@ -125,9 +128,11 @@ __global__ void gemm_tn_reduce_kernel(int32_t nchunks, int32_t modeA, int32_t mo
                                       const int32_t *__restrict__ lock, int32_t sym,
                                       const double *__restrict__ partial, int64_t pstride,
                                       double *__restrict__ C, int32_t ldc,
-                                      const int32_t *__restrict__ gate, int32_t gate_mask) {
+                                      const int32_t *__restrict__ gate, int32_t gate_mask,
+                                      const int32_t *__restrict__ rows) {
   const int b = blockIdx.z;
   if (gate && !(gate[b] & gate_mask)) return;
+  const int32_t nch = rows ? (int32_t)ceil_div((int64_t)rows[b], kGramChunk) : nchunks;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)ldc * ldc) return;
   int32_t a0, ka, b0, kb;
@@ -139,16 +144,16 @@ __global__ void gemm_tn_reduce_kernel(int32_t nchunks, int32_t modeA, int32_t mo
   double v = 0.0;
   if (sym == TN_GRAM) {
     const int lo = min(i, j), hi = max(i, j);
-    for (int s = 0; s < nchunks; ++s) v += P[(int64_t)s * pstride + lo + (int64_t)hi * ldc];
+    for (int s = 0; s < nch; ++s) v += P[(int64_t)s * pstride + lo + (int64_t)hi * ldc];
   } else if (sym == TN_SYMMETRISE) {
     double w = 0.0;
-    for (int s = 0; s < nchunks; ++s) {
+    for (int s = 0; s < nch; ++s) {
       v += P[(int64_t)s * pstride + i + (int64_t)j * ldc];
       w += P[(int64_t)s * pstride + j + (int64_t)i * ldc];
     }
     v = 0.5 * (v + w);
   } else {
-    for (int s = 0; s < nchunks; ++s) v += P[(int64_t)s * pstride + i + (int64_t)j * ldc];
+    for (int s = 0; s < nch; ++s) v += P[(int64_t)s * pstride + i + (int64_t)j * ldc];
   }
   C[(int64_t)b * ldc * ldc + i + (int64_t)j * ldc] = v;
 }
@@ -160,7 +165,7 @@ int64_t gemm_tn_partial_elems(int64_t n, int32_t ldc) {
 hipError_t gemm_tn(int B, int64_t n, int64_t ld, const double *A, int64_t bsA, int32_t modeA,
                    const double *Bm, int64_t bsB, int32_t modeB, int32_t k, const int32_t *lock,
                    bool symmetric, double *partial, int64_t partial_stride, double *C, int32_t ldc,
-                   const int32_t *gate, int32_t gate_mask, hipStream_t st) {
+                   const int32_t *gate, int32_t gate_mask, hipStream_t st, const int32_t *rows) {
   if (B <= 0 || n <= 0) return hipSuccess;
   const int32_t nchunks = (int32_t)ceil_div(n, kGramChunk);
   const int T = ldc / 32;
@@ -168,12 +173,13 @@ hipError_t gemm_tn(int B, int64_t n, int64_t ld, const double *A, int64_t bsA, i
                                 : TN_GENERAL;
   dim3 g1((unsigned)(T * T), (unsigned)nchunks, (unsigned)B);
   gemm_tn_kernel<<<g1, 256, 0, st>>>(n, ld, A, bsA, modeA, Bm, bsB, modeB, k, lock, sym, partial,
-                                     partial_stride / nchunks, ldc, gate, gate_mask);
+                                     partial_stride / nchunks, ldc, gate, gate_mask, rows);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   dim3 g2((unsigned)ceil_div((int64_t)ldc * ldc, 256), 1, (unsigned)B);
   gemm_tn_reduce_kernel<<<g2, 256, 0, st>>>(nchunks, modeA, modeB, k, lock, sym, partial,
-                                            partial_stride / nchunks, C, ldc, gate, gate_mask);
+                                            partial_stride / nchunks, C, ldc, gate, gate_mask,
+                                            rows);
   return hipGetLastError();
 }
 
@@ -184,7 +190,7 @@ __global__ void __launch_bounds__(256) gemm_nn_kernel(
     int64_t bsO, int32_t modeO, int32_t k, const int32_t *__restrict__ lock,
     const double *__restrict__ M, int32_t ldm, double alpha, double beta,
     const int32_t *__restrict__ gate, int32_t gate_mask, const int32_t *__restrict__ skip,
-    int32_t skip_mask) {
+    int32_t skip_mask, const int32_t *__restrict__ rows) {
   constexpr int KC = 32;                       // rows of M staged per pass
   constexpr int MS = NT * 16 + 2;              // padded LDS row stride
   __shared__ double Ms[KC * MS];
@@ -196,11 +202,13 @@ __global__ void __launch_bounds__(256) gemm_nn_kernel(
   col_range(modeO, k, lock, b, o0, ko);
   if (ko <= 0) return;
   if (ki <= 0 && beta == 1.0) return;          // nothing to add
+  const int64_t nb = rows ? (int64_t)rows[b] : n;
+  if ((int64_t)blockIdx.x * 64 >= nb) return;  // row tile beyond this problem's rows
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r4 = lane >> 4, c16 = lane & 15;
   const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
   const int64_t row = row0 + c16;
-  const bool row_ok = row < n;
+  const bool row_ok = row < nb;
   const double *Ib = In + (int64_t)b * bsI + (int64_t)i0 * ld;
   const double *Mb = M + (int64_t)b * ldm * ldm;
 
@@ -248,15 +256,18 @@ __global__ void __launch_bounds__(256) gemm_nn_kernel(
 hipError_t gemm_nn(int B, int64_t n, int64_t ld, const double *In, int64_t bsI, int32_t modeI,
                    double *Out, int64_t bsO, int32_t modeO, int32_t k, const int32_t *lock,
                    const double *M, int32_t ldm, double alpha, double beta, const int32_t *gate,
-                   int32_t gate_mask, const int32_t *skip, int32_t skip_mask, hipStream_t st) {
+                   int32_t gate_mask, const int32_t *skip, int32_t skip_mask, hipStream_t st,
+                   const int32_t *rows) {
   if (B <= 0 || n <= 0) return hipSuccess;
   dim3 grid((unsigned)ceil_div(n, 64), 1, (unsigned)B);
   if (k <= 128)
     gemm_nn_kernel<8><<<grid, 256, 0, st>>>(n, ld, In, bsI, modeI, Out, bsO, modeO, k, lock, M,
-                                            ldm, alpha, beta, gate, gate_mask, skip, skip_mask);
+                                            ldm, alpha, beta, gate, gate_mask, skip, skip_mask,
+        rows);
   else
     gemm_nn_kernel<16><<<grid, 256, 0, st>>>(n, ld, In, bsI, modeI, Out, bsO, modeO, k, lock, M,
-                                             ldm, alpha, beta, gate, gate_mask, skip, skip_mask);
+                                             ldm, alpha, beta, gate, gate_mask, skip, skip_mask,
+        rows);
   return hipGetLastError();
 }
 

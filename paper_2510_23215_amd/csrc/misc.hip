@@ -33,9 +33,10 @@ __device__ inline double block_max(double v, double *sh) {
 __global__ void __launch_bounds__(256) residual_kernel(
     int64_t n, int64_t ld, const double *__restrict__ X, const double *__restrict__ W, int64_t bs,
     int32_t k, const int32_t *__restrict__ lock, const double *__restrict__ theta,
-    double *__restrict__ res) {
+    double *__restrict__ res, const int32_t *__restrict__ rows) {
   __shared__ double sh[16];
   const int b = blockIdx.z;
+  if (rows) n = rows[b];
   const int32_t l = lock ? lock[b] : 0;
   const int c = l + blockIdx.x;
   if (c >= k) return;
@@ -55,9 +56,9 @@ __global__ void __launch_bounds__(256) residual_kernel(
 
 hipError_t residuals(int B, int64_t n, int64_t ld, const double *X, const double *W,
                      int64_t bs, int32_t k, const int32_t *lock, const double *theta, double *res,
-                     hipStream_t st) {
+                     hipStream_t st, const int32_t *rows) {
   if (B <= 0) return hipSuccess;
-  residual_kernel<<<dim3(k, 1, B), 256, 0, st>>>(n, ld, X, W, bs, k, lock, theta, res);
+  residual_kernel<<<dim3(k, 1, B), 256, 0, st>>>(n, ld, X, W, bs, k, lock, theta, res, rows);
   return hipGetLastError();
 }
 
@@ -451,6 +452,38 @@ hipError_t mp_final(int B, int64_t n, int64_t ld, int64_t bs, int32_t k, const i
   if (B <= 0) return hipSuccess;
   mp_final_kernel<<<dim3((unsigned)ceil_div(n, 256), k, B), 256, 0, st>>>(n, ld, bs, k, lock, X, Em,
                                                                           gain, Y);
+  return hipGetLastError();
+}
+
+// Warm start across grid sides: column c of X is a nodal field on the N0 x N0 interior grid
+// of the unit square (node (iy, ix) at ((ix+1)/(N0+1), (iy+1)/(N0+1)), entry iy*N0 + ix, zero
+// on the boundary); Y column c is its bilinear interpolant at the N1 x N1 nodes.  The source
+// position of output node i is (i+1)(N0+1)/(N1+1) - 1 in units of the source spacing.
+// grid (ceil(N1^2 / 256), ncols): one thread per output node and column.
+__global__ void __launch_bounds__(256) interp_kernel(int32_t N0, int32_t N1,
+                                                     const double *__restrict__ X, int64_t ldx,
+                                                     double *__restrict__ Y, int64_t ldy) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)N1 * N1) return;
+  const int oy = (int)(p / N1), ox = (int)(p - (int64_t)oy * N1);
+  const double *x = X + (int64_t)blockIdx.y * ldx;
+  const double sy = (double)((int64_t)(oy + 1) * (N0 + 1)) / (double)(N1 + 1) - 1.0;
+  const double sx = (double)((int64_t)(ox + 1) * (N0 + 1)) / (double)(N1 + 1) - 1.0;
+  const int jy = (int)floor(sy), jx = (int)floor(sx);
+  const double fy = sy - jy, fx = sx - jx;
+  auto at = [&](int iy, int ix) -> double {
+    return (iy >= 0 && iy < N0 && ix >= 0 && ix < N0) ? x[(int64_t)iy * N0 + ix] : 0.0;
+  };
+  const double lo = (1.0 - fx) * at(jy, jx) + fx * at(jy, jx + 1);
+  const double hi = (1.0 - fx) * at(jy + 1, jx) + fx * at(jy + 1, jx + 1);
+  Y[(int64_t)blockIdx.y * ldy + p] = (1.0 - fy) * lo + fy * hi;
+}
+
+hipError_t interpolate_fields(int32_t N0, int32_t N1, int32_t ncols, const double *X,
+                              int64_t ldx, double *Y, int64_t ldy, hipStream_t st) {
+  if (ncols <= 0 || N1 <= 0) return hipSuccess;
+  interp_kernel<<<dim3((unsigned)ceil_div((int64_t)N1 * N1, 256), (unsigned)ncols), 256, 0, st>>>(
+      N0, N1, X, ldx, Y, ldy);
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 // convergence share the launches.  The host synchronises once per outer iteration to read the
 // lock counts.
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -24,7 +25,7 @@ namespace {
 enum BufId {
   B_X, B_Y1, B_Y2, B_W, B_G, B_M, B_PART, B_THETA, B_RES, B_INT, B_BND, B_COEF, B_UNIT, B_CHOL,
   B_JAC, B_LZ, B_OPS, B_WIN, B_SORTF, B_SORTD, B_SORTO, B_REC, B_RANK, B_E32, B_R32, B_SRC,
-  B_GAIN, B_WINB, B_HINT, B_MDEG, B_NETF, B_NETH, B_NETD, B_COUNT
+  B_GAIN, B_WINB, B_HINT, B_MDEG, B_NETF, B_NETH, B_NETD, B_ROWS, B_COUNT
 };
 
 struct DevBuf {
@@ -189,6 +190,7 @@ struct Engine {
   double *src = nullptr, *gain = nullptr, *winb = nullptr;
   int32_t *lock = nullptr, *nconv = nullptr, *done = nullptr, *flag = nullptr, *need = nullptr;
   OpDev *ops = nullptr;
+  int32_t *rows = nullptr, *h_rows = nullptr;   // per-problem row count (uneven batches)
   // pinned host mirrors
   int32_t *h_lock = nullptr, *h_nconv = nullptr, *h_done = nullptr, *h_flag = nullptr;
   int32_t *h_need = nullptr, *h_perm = nullptr;
@@ -248,6 +250,7 @@ struct Engine {
     STCHK(grow(h, B_OPS, (size_t)B, &ops));
     STCHK(grow(h, B_HINT, (size_t)B * 3, &hint));
     STCHK(grow(h, B_MDEG, (size_t)B, &mdeg));
+    STCHK(grow(h, B_ROWS, (size_t)B, &rows));
     if (mixed) {
       float *e32 = nullptr;
       STCHK(grow(h, B_E32, (size_t)3 * B * bs, &e32));
@@ -260,7 +263,7 @@ struct Engine {
       STCHK(grow(h, B_WINB, (size_t)B * 3, &winb));
     }
     // pinned: 6 int arrays of B, perm B*k, theta/res B*k, bnd B*4, unit B*3, ops B
-    const size_t pin = (size_t)B * 8 * 4 + (size_t)B * k * 4 + (size_t)B * k * 16 +
+    const size_t pin = (size_t)B * 9 * 4 + (size_t)B * k * 4 + (size_t)B * k * 16 +
                        (size_t)B * 4 * 8 + (size_t)B * 6 * 8 + (size_t)B * sizeof(OpDev) + 2048;
     STCHK(grow_pinned(h, pin));
     char *pp = static_cast<char *>(h->pinned);
@@ -282,11 +285,13 @@ struct Engine {
     h_ops = (OpDev *)take((size_t)B * sizeof(OpDev));
     h_mdeg = (int32_t *)take(B * 4);
     h_mraw = (int32_t *)take(B * 4);
+    h_rows = (int32_t *)take(B * 4);
     h_hint = (double *)take((size_t)B * 3 * 8);
     if ((size_t)(pp - static_cast<char *>(h->pinned)) > h->pinned_bytes) return SCSF_ENOMEM;
     for (int b = 0; b < B; ++b) {
       h_lock[b] = h_nconv[b] = h_done[b] = h_flag[b] = h_need[b] = 0;
       h_mdeg[b] = h_mraw[b] = m_;
+      h_rows[b] = (int32_t)n;
       h_hint[3 * b] = h_hint[3 * b + 1] = h_hint[3 * b + 2] = 0.0;
       h_unit[3 * b] = 1.0;
       h_unit[3 * b + 1] = 0.0;
@@ -297,6 +302,7 @@ struct Engine {
     // plan_degrees() uploads only when a degree differs from the mirror, so the device copy
     // must match the mirror from the start (the buffer is reused across calls)
     if (var_deg) HIPCHK(hipMemcpyAsync(mdeg, h_mdeg, (size_t)B * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(rows, h_rows, (size_t)B * 4, hipMemcpyHostToDevice, st));
     HIPCHK(fill_int(flag, 0, B, st));
     HIPCHK(hipStreamSynchronize(st));
     return SCSF_OK;
@@ -343,7 +349,9 @@ struct Engine {
     return SCSF_OK;
   }
   int upload_ops() {
+    for (int b = 0; b < B; ++b) h_rows[b] = (int32_t)h_ops[b].n;
     HIPCHK(hipMemcpyAsync(ops, h_ops, (size_t)B * sizeof(OpDev), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(rows, h_rows, (size_t)B * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
     return SCSF_OK;
   }
@@ -359,18 +367,22 @@ struct Engine {
 
   // algorithmic bytes of one Chebyshev step over all unfinished problems: read Y_i (and
   // Y_{i-1} after the first step), write Y_{i+1}, read the operator's coefficients once
+  // Algorithmic HBM bytes of one filter step: each active column of the input block (and of
+  // the previous block after the first step) read once, the output written once, and the
+  // operator coefficients read once per problem (5-point: the two face arrays plus the
+  // potential when present; 9-point: one cell tensor).  Rows are per problem.
   double step_bytes(bool has_prev, bool fp32 = false, int step = 0) const {
-    double cols = 0.0, nops = 0.0;
+    double vec = 0.0, coeff = 0.0;
     for (int b = 0; b < B; ++b)
       if (!h_done[b] && (!var_deg || step < h_mdeg[b])) {
-        cols += (double)(k - h_lock[b]);
-        nops += 1.0;
+        const double nb = (double)h_rows[b];
+        vec += nb * (double)(k - h_lock[b]);
+        coeff += (kind == SCSF_STENCIL5) ? (h_ops[b].v ? 3.0 : 2.0) * nb
+                 : (kind == SCSF_STENCIL9) ? 3.0 * nb : 0.0;
       }
-    const double coeff = (kind == SCSF_STENCIL5) ? 2.0 * n + (double)n
-                         : (kind == SCSF_STENCIL9) ? 3.0 * n : 0.0;
     if (fp32)  // e_i, e_{i-1}, r read, e_{i+1} written in FP32
-      return 4.0 * (has_prev ? 4.0 : 3.0) * (double)n * cols + 8.0 * coeff * nops;
-    return 8.0 * ((has_prev ? 3.0 : 2.0) * (double)n * cols + coeff * nops);
+      return 4.0 * (has_prev ? 4.0 : 3.0) * vec + 8.0 * coeff;
+    return 8.0 * ((has_prev ? 3.0 : 2.0) * vec + coeff);
   }
 
   // upper bounds of the problems with h_need[b] set
@@ -385,18 +397,18 @@ struct Engine {
     if (cgs) {
       for (int rep = 0; rep < 2; ++rep) {
         HIPCHK(gemm_tn(B, n, ld, X, bs, COLS_LOCKED, Yf, bs, COLS_ACTIVE, k, lock, false, part,
-                       part_stride, G, ldm, nullptr, 0, st));
+                       part_stride, G, ldm, nullptr, 0, st, rows));
         HIPCHK(gemm_nn(B, n, ld, X, bs, COLS_LOCKED, Yf, bs, COLS_ACTIVE, k, lock, G, ldm, -1.0,
-                       1.0, nullptr, 0, nullptr, 0, st));
+                       1.0, nullptr, 0, nullptr, 0, st, rows));
       }
     }
     for (int pass = 0; pass < 3; ++pass) {
       const int32_t *gate = (pass == 2) ? flag : nullptr;
       HIPCHK(gemm_tn(B, n, ld, Yf, bs, COLS_ACTIVE, Yf, bs, COLS_ACTIVE, k, lock, true, part,
-                     part_stride, G, ldm, gate, 4, st));
+                     part_stride, G, ldm, gate, 4, st, rows));
       HIPCHK(chol_inv(B, n, k, lock, G, M, ldm, flag, gate, 4, chol, st));
       HIPCHK(gemm_nn(B, n, ld, Yf, bs, COLS_ACTIVE, Yf, bs, COLS_ACTIVE, k, lock, M, ldm, 1.0, 0.0,
-                     gate, 4, flag, 3, st));
+                     gate, 4, flag, 3, st, rows));
     }
     return SCSF_OK;
   }
@@ -406,12 +418,12 @@ struct Engine {
     HIPCHK(spmm_step(ops, B, kind, n, 0, Yf, nullptr, W, ld, bs, COLS_ACTIVE, k, lock, unit, false,
                      st));
     HIPCHK(gemm_tn(B, n, ld, Yf, bs, COLS_ACTIVE, W, bs, COLS_ACTIVE, k, lock, true, part,
-                   part_stride, G, ldm, nullptr, 0, st));
+                   part_stride, G, ldm, nullptr, 0, st, rows));
     HIPCHK(jacobi_eig(B, k, lock, G, M, ldm, theta, flag, jac, rec, ranks, nsweeps, st));
     HIPCHK(gemm_nn(B, n, ld, Yf, bs, COLS_ACTIVE, X, bs, COLS_ACTIVE, k, lock, M, ldm, 1.0, 0.0,
-                   nullptr, 0, nullptr, 0, st));
+                   nullptr, 0, nullptr, 0, st, rows));
     HIPCHK(gemm_nn(B, n, ld, W, bs, COLS_ACTIVE, W, bs, COLS_ACTIVE, k, lock, M, ldm, 1.0, 0.0,
-                   nullptr, 0, nullptr, 0, st));
+                   nullptr, 0, nullptr, 0, st, rows));
     return SCSF_OK;
   }
 
@@ -422,7 +434,7 @@ struct Engine {
     for (int b = 0; b < B; ++b) h_lock[b] = k;
     for (int b : slots) {
       h_lock[b] = 0;
-      HIPCHK(gaussian_fill(1, n, ld, bs, k, X + (int64_t)b * bs,
+      HIPCHK(gaussian_fill(1, h_rows[b], ld, bs, k, X + (int64_t)b * bs,
                            seed * 0x9E3779B97F4A7C15ULL + (uint64_t)b * 0xD1B54A32D192ED03ULL + 1,
                            st));
     }
@@ -482,7 +494,7 @@ struct Engine {
     }
     STCHK(orth(Yf, true));
     STCHK(rayleigh_ritz(Yf));
-    HIPCHK(residuals(B, n, ld, X, W, bs, k, lock, theta, res, st));
+    HIPCHK(residuals(B, n, ld, X, W, bs, k, lock, theta, res, st, rows));
     HIPCHK(lock_update(B, k, L, tol, lock, nconv, res, done, st));
     return download_state();
   }
@@ -518,8 +530,9 @@ struct Engine {
     STCHK(grow(h, B_SORTO, (size_t)B * k, &perm_d));
     HIPCHK(hipMemcpyAsync(perm_d + (size_t)b * k, perm, (size_t)L * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(evals, vals, (size_t)L * 8, hipMemcpyHostToDevice, st));
-    HIPCHK(gather_columns(n, L, X + (int64_t)b * bs, ld, perm_d + (size_t)b * k, evecs, ldo, st));
-    HIPCHK(canonical_sign(n, L, evecs, ldo, st));
+    HIPCHK(gather_columns(h_rows[b], L, X + (int64_t)b * bs, ld, perm_d + (size_t)b * k, evecs,
+                          ldo, st));
+    HIPCHK(canonical_sign(h_rows[b], L, evecs, ldo, st));
     HIPCHK(hipStreamSynchronize(st));                 // the copies above read pinned memory
     if (maxres) *maxres = mr;
     return SCSF_OK;
@@ -549,17 +562,32 @@ int check_params(const scsf_params *p, int64_t n) {
 // With `next` (dynamic schedule) a chain that finishes an operator takes order position
 // next->fetch_add(1) instead of the next position of its own chunk; cb holds the chains' first
 // positions and ce is ignored.
+// One group of an uneven batch: operators sharing (kind, L, k), with sizes up to nmax, whose
+// outputs sit at per-operator offsets of packed arrays.
+struct Group {
+  int32_t L = 0, k = 0;
+  int64_t nmax = 0;
+  const int64_t *eoff = nullptr, *voff = nullptr;   // evals / evecs offsets by operator index
+};
+
+// Grid stencils on square grids: the Ritz vectors can move between sides by interpolation.
+bool on_square_grid(const OpDev &o) {
+  return (o.kind == SCSF_STENCIL5 || o.kind == SCSF_STENCIL9) && (int64_t)o.N * o.N == o.n;
+}
+
 int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order_host,
                int32_t n_op, const std::vector<int> &cb, const std::vector<int> &ce,
                std::atomic<int> *next, const scsf_params *prm, const double *hints_host,
-               double *evals, double *evecs, double *ritz, scsf_stats *stats_host) {
+               double *evals, double *evecs, double *ritz, scsf_stats *stats_host,
+               const Group *grp = nullptr) {
   const int chains = (int)cb.size();
   if (chains == 0) return SCSF_OK;
-  const int64_t n = ops_host[0].n;
-  const int32_t kind = ops_host[0].kind;
+  const int64_t n = grp ? grp->nmax : ops_host[0].n;
+  const int32_t kind = ops_host[order_host[0]].kind;
   const int max_iter = prm->max_iter > 0 ? prm->max_iter : 5000;
   const int lzs = prm->lanczos_steps > 0 ? prm->lanczos_steps : 20;
-  const int32_t L = prm->L, k = prm->k, m = prm->degree;
+  const int32_t L = grp ? grp->L : prm->L, k = grp ? grp->k : prm->k, m = prm->degree;
+  const int64_t *eoff = grp ? grp->eoff : nullptr, *voff = grp ? grp->voff : nullptr;
 
   Engine e;
   STCHK(e.setup(w, chains, n, k, L, m, kind, prm->tol, prm->seed, lzs,
@@ -608,6 +636,7 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
       if (active[b]) fcols[b] += (int64_t)(e.var_deg ? e.h_mdeg[b] : m) * (k - e.h_lock_prev(b));
     bool reload = false;
     std::vector<int> recold, reloaded;
+    std::vector<std::array<int, 3>> resize;   // (slot, old side, new side)
     for (int b = 0; b < chains; ++b) {
       if (!active[b]) continue;
       ++iters[b];
@@ -622,7 +651,9 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
         std::sort(th.begin(), th.end());
         HIPCHK(hipMemcpy(ritz + (size_t)op * k, th.data(), (size_t)k * 8, hipMemcpyHostToDevice));
       }
-      STCHK(e.extract(b, evals + (size_t)op * L, evecs + (size_t)op * n * L, n, &mr));
+      const int64_t nop = ops_host[op].n;
+      STCHK(e.extract(b, evals + (eoff ? eoff[op] : (int64_t)op * L),
+                      evecs + (voff ? voff[op] : (int64_t)op * n * L), nop, &mr));
       if (stats_host) {
         scsf_stats &st = stats_host[op];
         st.iterations = iters[b];
@@ -650,21 +681,36 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
         e.h_lock[b] = k;
         continue;
       }
-      // next operator of the chain, warm-started from this solve (all k Ritz pairs)
+      // next operator of the chain, warm-started from this solve (all k Ritz pairs); a
+      // different size moves the vectors by bilinear interpolation (square grids) or, where
+      // that is not possible, restarts cold
+      const OpDev prev = e.h_ops[b];
       e.h_ops[b] = to_dev(ops_host[order_host[pos[b]]]);
+      const bool bad = status == SCSF_ENUMERIC || status == SCSF_EBREAKDOWN;
+      if (e.h_ops[b].n != prev.n && !bad) {
+        if (on_square_grid(prev) && on_square_grid(e.h_ops[b]))
+          resize.push_back({b, prev.N, e.h_ops[b].N});
+        else
+          recold.push_back(b);
+      }
       load_hint(b, pos[b]);
       reloaded.push_back(b);
       e.h_need[b] = 1;
       e.h_done[b] = 0;
       e.h_nconv[b] = 0;
       e.h_lock[b] = 0;
-      if (status == SCSF_ENUMERIC || status == SCSF_EBREAKDOWN) recold.push_back(b);
+      if (bad) recold.push_back(b);
       reload = true;
     }
     if (reload) {
       e.w_stale = true;                 // A X of the newly loaded operators
       STCHK(e.upload_hints(reloaded));
       STCHK(e.upload_ops());
+      for (const auto &r : resize) {
+        const int64_t o = (int64_t)r[0] * e.bs;
+        HIPCHK(interpolate_fields(r[1], r[2], k, e.X + o, e.ld, e.Y1 + o, e.ld, e.st));
+        HIPCHK(copy_block((int64_t)r[2] * r[2], k, e.Y1 + o, e.ld, e.X + o, e.ld, false, e.st));
+      }
       STCHK(e.upload_state());
       STCHK(e.compute_bounds());
       if (!recold.empty()) STCHK(e.cold_start(recold));
@@ -1078,6 +1124,168 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
     if (worst == SCSF_OK || (worst == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)) worst = s2;
   }
   return worst;
+}
+
+// ------------------------------------------------------------ uneven batches (mixed sizes)
+// Default block width for L wanted pairs: the smallest multiple of 8 with at least 20% guard
+// vectors (Section 4 sizes the inherited subspace as a fraction of L).
+static int32_t default_width(int32_t L) {
+  const int32_t g = (L + 4) / 5;                       // ceil(0.2 L)
+  return std::min<int32_t>(kMaxK, (int32_t)round_up(L + std::max(g, 1), 8));
+}
+
+int scsf_block_width(int32_t L) {
+  if (L <= 0 || L >= kMaxK) return SCSF_EINVAL;
+  return default_width(L);
+}
+
+int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
+                       const int32_t *L_host, const int32_t *k_host, const int32_t *order_host,
+                       int32_t chains, const scsf_params *prm, double *evals, double *evecs,
+                       scsf_stats *stats_host) {
+  if (!h || !ops_host || n_op <= 0 || !L_host || !order_host || chains <= 0 || !evals ||
+      !evecs || !prm)
+    return SCSF_EINVAL;
+  if (prm->precision != SCSF_FP64) return SCSF_EINVAL;
+  std::vector<int32_t> kk(n_op);
+  for (int i = 0; i < n_op; ++i) {
+    STCHK(check_op(&ops_host[i]));
+    if (L_host[i] <= 0 || L_host[i] >= kMaxK) return SCSF_EINVAL;
+    kk[i] = k_host ? k_host[i] : default_width(L_host[i]);
+    scsf_params p = *prm;
+    p.L = L_host[i];
+    p.k = kk[i];
+    STCHK(check_params(&p, ops_host[i].n));
+  }
+  {
+    std::vector<char> seen(n_op, 0);
+    for (int i = 0; i < n_op; ++i) {
+      const int o = order_host[i];
+      if (o < 0 || o >= n_op || seen[o]) return SCSF_EINVAL;
+      seen[o] = 1;
+    }
+  }
+  // packed outputs in operator-index order
+  std::vector<int64_t> eoff(n_op), voff(n_op);
+  {
+    int64_t e = 0, v = 0;
+    for (int i = 0; i < n_op; ++i) {
+      eoff[i] = e;
+      voff[i] = v;
+      e += L_host[i];
+      v += ops_host[i].n * L_host[i];
+    }
+  }
+  // groups of equal (kind, L, k), in order of first appearance; each keeps the given order
+  struct G {
+    int32_t kind, L, k;
+    int64_t nmax = 0;
+    std::vector<int32_t> order;
+    int chains = 1;
+  };
+  std::vector<G> groups;
+  for (int i = 0; i < n_op; ++i) {
+    const int o = order_host[i];
+    G *g = nullptr;
+    for (auto &x : groups)
+      if (x.kind == ops_host[o].kind && x.L == L_host[o] && x.k == kk[o]) g = &x;
+    if (!g) {
+      groups.push_back(G{ops_host[o].kind, L_host[o], kk[o]});
+      g = &groups.back();
+    }
+    g->order.push_back(o);
+    g->nmax = std::max<int64_t>(g->nmax, ops_host[o].n);
+  }
+  // chains shared out in proportion to the group sizes
+  int maxc = 1;
+  for (auto &g : groups) {
+    g.chains = (int)std::lround((double)chains * (double)g.order.size() / (double)n_op);
+    g.chains = std::max(1, std::min<int>(g.chains, (int)g.order.size()));
+    maxc = std::max(maxc, g.chains);
+  }
+  const int lanes = std::min(h->lanes, maxc);
+  STCHK(add_lanes(h, lanes));
+  hipEvent_t ready;
+  HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(ready, h->ws[0]->stream));
+  for (int l = 1; l < lanes; ++l) HIPCHK(hipStreamWaitEvent(h->ws[l]->stream, ready, 0));
+  const bool dyn = prm->schedule == SCSF_SCHED_DYNAMIC;
+  std::vector<std::atomic<int>> next(groups.size());
+  for (size_t gi = 0; gi < groups.size(); ++gi) next[gi] = groups[gi].chains;
+  std::vector<int> status(lanes, SCSF_OK);
+  // every lane works through the groups in turn; a lane that finishes its chains of one group
+  // moves on to the next without waiting for the others
+  auto lane_fn = [&](int l) {
+    if (hipSetDevice(h->device) != hipSuccess) { status[l] = SCSF_EHIP; return; }
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      const G &g = groups[gi];
+      const int nord = (int)g.order.size();
+      std::vector<int> cb, ce;
+      for (int c = l; c < g.chains; c += lanes) {
+        cb.push_back(dyn ? c : (int)((int64_t)nord * c / g.chains));
+        ce.push_back(dyn ? c + 1 : (int)((int64_t)nord * (c + 1) / g.chains));
+      }
+      if (cb.empty()) continue;
+      Group grp;
+      grp.L = g.L;
+      grp.k = g.k;
+      grp.nmax = g.nmax;
+      grp.eoff = eoff.data();
+      grp.voff = voff.data();
+      const int s2 = run_chains(h->ws[l], ops_host, g.order.data(), nord, cb, ce,
+                                dyn ? &next[gi] : nullptr, prm, nullptr, evals, evecs, nullptr,
+                                stats_host, &grp);
+      if (s2 != SCSF_OK && (status[l] == SCSF_OK ||
+                            (status[l] == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)))
+        status[l] = s2;
+      if (s2 != SCSF_OK && s2 != SCSF_ENOTCONV) return;
+    }
+  };
+  std::vector<std::thread> threads;
+  for (int l = 1; l < lanes; ++l) threads.emplace_back(lane_fn, l);
+  lane_fn(0);
+  for (auto &t : threads) t.join();
+  (void)hipEventDestroy(ready);
+  int worst = SCSF_OK;
+  for (int l = 0; l < lanes; ++l) {
+    const int s2 = status[l];
+    if (s2 == SCSF_OK) continue;
+    if (worst == SCSF_OK || (worst == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)) worst = s2;
+  }
+  return worst;
+}
+
+int scsf_interpolate(scsf_handle *h, int32_t N0, int32_t N1, int32_t ncols, const double *X,
+                     int64_t ldx, double *Y, int64_t ldy) {
+  if (!h || N0 <= 0 || N1 <= 0 || ncols < 0 || ncols > 65535) return SCSF_EINVAL;
+  if (ncols == 0) return SCSF_OK;
+  if (!X || !Y || ldx < (int64_t)N0 * N0 || ldy < (int64_t)N1 * N1) return SCSF_EINVAL;
+  // no overlap between the source and destination ranges
+  const char *x0 = reinterpret_cast<const char *>(X);
+  const char *x1 = reinterpret_cast<const char *>(X + (int64_t)(ncols - 1) * ldx + (int64_t)N0 * N0);
+  const char *y0 = reinterpret_cast<const char *>(Y);
+  const char *y1 = reinterpret_cast<const char *>(Y + (int64_t)(ncols - 1) * ldy + (int64_t)N1 * N1);
+  if (x0 < y1 && y0 < x1) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  HIPCHK(interpolate_fields(N0, N1, ncols, X, ldx, Y, ldy, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
+}
+
+int scsf_order_features(scsf_handle *h, const double *feats, int32_t n_op, int32_t flen,
+                        int32_t start, int32_t *order_host) {
+  if (!h || !feats || !order_host || n_op <= 0 || flen <= 0) return SCSF_EINVAL;
+  if (start < 0 || start >= n_op || n_op > 32768) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  double *D = nullptr;
+  int32_t *O = nullptr;
+  STCHK(grow(w0, B_SORTD, (size_t)n_op * n_op, &D));
+  STCHK(grow(w0, B_SORTO, (size_t)n_op, &O));
+  HIPCHK(pair_distances(feats, n_op, flen, D, w0->stream));
+  HIPCHK(greedy_order(D, n_op, start, O, w0->stream));
+  HIPCHK(hipMemcpyAsync(order_host, O, (size_t)n_op * 4, hipMemcpyDeviceToHost, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
 }
 
 // ------------------------------------------------------------------ the learned window

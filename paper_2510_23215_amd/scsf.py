@@ -95,6 +95,12 @@ def lib():
         sig["scsf_profile_enable"] = [vp, i32]
         sig["scsf_set_lanes"] = [vp, i32]
         sig["scsf_profile_read"] = [vp, POINTER(Profile), i32]
+        sig["scsf_order_features"] = [vp, vp, i32, i32, i32, POINTER(c_int32)]
+        sig["scsf_interpolate"] = [vp, i32, i32, i32, vp, i64, vp, i64]
+        sig["scsf_block_width"] = [i32]
+        sig["scsf_solve_batched"] = [vp, POINTER(Operator), i32, POINTER(c_int32),
+                                     POINTER(c_int32), POINTER(c_int32), i32, POINTER(Params),
+                                     vp, vp, POINTER(Stats)]
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
@@ -266,6 +272,63 @@ def scsf_sort(h: Handle, fields: torch.Tensor, p0: int, start: int = 0) -> np.nd
     order = (c_int32 * n_op)()
     _check(lib().scsf_sort(h.ptr, _ptr(fields), n_op, C, p, p0, int(start), order), "scsf_sort")
     return np.frombuffer(order, dtype=np.int32).copy()
+
+
+def scsf_order_features(h: Handle, feats: torch.Tensor, start: int = 0) -> np.ndarray:
+    """Greedy order of Algorithm 2 on precomputed features: feats (n_op, ...) complex128."""
+    feats = torch.view_as_real(feats.contiguous()).contiguous()
+    n_op = feats.shape[0]
+    flen = feats[0].numel() // 2
+    order = (c_int32 * n_op)()
+    _check(lib().scsf_order_features(h.ptr, _ptr(feats), n_op, flen, int(start), order),
+           "scsf_order_features")
+    return np.frombuffer(order, dtype=np.int32).copy()
+
+
+def scsf_interpolate(h: Handle, X: torch.Tensor, N0: int, N1: int) -> torch.Tensor:
+    """X: (ncols, N0*N0) float64 device tensor (one field per row) -> (ncols, N1*N1)."""
+    X = X.contiguous()
+    ncols = X.shape[0]
+    Y = torch.empty((ncols, N1 * N1), device=X.device, dtype=torch.float64)
+    _check(lib().scsf_interpolate(h.ptr, int(N0), int(N1), ncols, _ptr(X), N0 * N0, _ptr(Y),
+                                  N1 * N1), "scsf_interpolate")
+    return Y
+
+
+def scsf_block_width(L: int) -> int:
+    k = int(lib().scsf_block_width(int(L)))
+    if k < 0:
+        raise ScsfError(k, "scsf_block_width")
+    return k
+
+
+def scsf_solve_batched(h: Handle, ops: list, Ls, order, chains: int, prm: Params, ks=None,
+                       allow_notconv=False):
+    """Operators of different sizes and L in one call.  Returns (evals, evecs, stats): evals[i]
+    a length-L_i view, evecs[i] an (L_i, n_i) view (row j = eigenvector j), both into the
+    packed device arrays, and the per-operator stats dicts."""
+    n_op = len(ops)
+    arr = (Operator * n_op)(*[o.struct for o in ops])
+    Ls = [int(x) for x in Ls]
+    Lc = (c_int32 * n_op)(*Ls)
+    kc = None if ks is None else (c_int32 * n_op)(*[int(x) for x in ks])
+    ordc = (c_int32 * n_op)(*np.asarray(order, dtype=np.int32).tolist())
+    ne = sum(Ls)
+    nv = sum(o.n * L for o, L in zip(ops, Ls))
+    ev = torch.empty(ne, device="cuda", dtype=torch.float64)
+    vec = torch.empty(nv, device="cuda", dtype=torch.float64)
+    stats = (Stats * n_op)()
+    allow = (SCSF_OK, SCSF_ENOTCONV) if allow_notconv else (SCSF_OK,)
+    _check(lib().scsf_solve_batched(h.ptr, arr, n_op, Lc, kc, ordc, int(chains), ctypes.byref(prm),
+                                    _ptr(ev), _ptr(vec), stats), "scsf_solve_batched", allow)
+    evals, evecs = [], []
+    e = v = 0
+    for o, L in zip(ops, Ls):
+        evals.append(ev[e:e + L])
+        evecs.append(vec[v:v + o.n * L].view(L, o.n))
+        e += L
+        v += o.n * L
+    return evals, evecs, [st.as_dict() for st in stats]
 
 
 def make_params(L, k, degree=20, tol=1e-8, max_iter=0, lanczos_steps=20, seed=0,

@@ -1,0 +1,174 @@
+"""Uneven batches on the GPU: operators of different sizes and different L in one call, the
+grid transfer for warm starts across sizes, and the feature order over mixed sizes, against
+the CPU oracle.  Needs an MI355X."""
+import numpy as np
+import pytest
+
+import scsf_inputs as si
+from oracle import operator as O, eig as E, sort as S, transfer as T
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2510_23215_amd import scsf  # noqa: E402
+
+from test_gpu_parity import say, host, check_pairs, check_order_stepwise  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def h():
+    return scsf.Handle()
+
+
+# ------------------------------------------------------------------------------ transfer
+@pytest.mark.parametrize("N0,N1,ncols", [(13, 21, 3), (21, 13, 2), (48, 53, 5), (128, 48, 2),
+                                         (57, 57, 1), (1, 6, 1), (6, 1, 1)])
+def test_interpolate_matches_oracle(h, N0, N1, ncols):
+    say("interpolate", N0, N1, ncols)
+    rng = np.random.default_rng(N0 * 1000 + N1)
+    X = rng.standard_normal((N0 * N0, ncols))
+    Y = host(scsf.scsf_interpolate(h, torch.tensor(X.T.copy(), device="cuda"), N0, N1)).T
+    ref = T.interpolate_block(X, N0, N1)
+    # rounding of the source position (~ N0 eps relative) times a slope <= 2 max|X| per cell
+    tol = 4 * max(N0, 1) * np.finfo(float).eps * 2 * np.max(np.abs(X))
+    assert np.max(np.abs(Y - ref)) <= tol
+    if N0 == N1:
+        np.testing.assert_array_equal(Y, X)
+
+
+def test_interpolate_rejects_overlap_and_bad_sizes(h):
+    X = torch.zeros((2, 100), dtype=torch.float64, device="cuda")
+    lib = scsf.lib()
+    # Y aliasing X
+    st = lib.scsf_interpolate(h.ptr, 10, 10, 2, scsf._ptr(X), 100, scsf._ptr(X), 100)
+    assert st == scsf.SCSF_EINVAL
+    with pytest.raises(scsf.ScsfError):
+        scsf.scsf_interpolate(h, X, 0, 5)
+
+
+# ------------------------------------------------------------------------------ order
+def test_order_features_over_mixed_sizes(h):
+    """Features of fields of different sides (1/p^2 scaling) ordered together."""
+    say("order features mixed sizes")
+    sides = [24, 31, 24, 40, 33, 31, 24, 40, 29, 35, 24, 33]
+    f = [si.divk_operator(N, 8, 700 + i).field for i, N in enumerate(sides)]
+    p0 = 6
+    feats = torch.cat([scsf.scsf_features(h, torch.tensor(x[None], device="cuda"), p0) for x in f])
+    order = scsf.scsf_order_features(h, feats, start=0)
+    ref = np.stack([S.truncated_features(x, p0) for x in f])
+    np.testing.assert_allclose(host(feats), ref, rtol=0, atol=1e-13 * np.max(np.abs(ref)))
+    check_order_stepwise(ref, order)
+
+
+# ------------------------------------------------------------------------------ solves
+def small_uneven(count=14, seed=0):
+    """Mixed families, sides 14..29, L in {4, 8, 12}: small enough for dense references."""
+    rng = np.random.default_rng(seed)
+    ops, Ls = [], []
+    for i in range(count):
+        N = int(rng.integers(14, 30))
+        ops.append(si.divk_operator(N, 8, 300 + i) if i % 2 == 0
+                   else si.potential_operator(N, 8, 300 + i))
+        Ls.append(int(rng.choice([4, 8, 12])))
+    return ops, Ls
+
+
+def family_order(h, ops, p0):
+    """Algorithm 2 within each family (div-K first, then -Laplace + V), concatenated."""
+    order = []
+    for fam in ("divk", "potential"):
+        idx = [i for i, o in enumerate(ops) if o.family == fam]
+        if not idx:
+            continue
+        feats = torch.cat([scsf.scsf_features(h, torch.tensor(ops[i].field[None], device="cuda"),
+                                              p0) for i in idx])
+        sub = scsf.scsf_order_features(h, feats, start=0)
+        order += [idx[j] for j in sub]
+    return order
+
+
+@pytest.mark.parametrize("chains,lanes,sched", [(1, 1, 0), (4, 2, 0), (6, 3, 1), (14, 4, 1)])
+def test_batched_small_matches_oracle(chains, lanes, sched):
+    say("batched small chains", chains, "lanes", lanes, "schedule", sched)
+    h = scsf.Handle()
+    scsf.scsf_set_lanes(h, lanes)
+    ops, Ls = small_uneven()
+    order = family_order(h, ops, 6)
+    prm = scsf.make_params(0, 0, 20, 1e-8, seed=2, schedule=sched)
+    evals, evecs, stats = scsf.scsf_solve_batched(h, [scsf.DeviceOperator(o) for o in ops], Ls,
+                                                  order, chains, prm)
+    say([s["iterations"] for s in stats])
+    for i, o in enumerate(ops):
+        A = O.assemble(o)
+        w, V = E.smallest_eigenpairs(A, Ls[i] + 6, method="dense")
+        assert stats[i]["status"] == 0
+        check_pairs(A, evals[i], evecs[i].t(), Ls[i], 1e-8, w, V)
+
+
+def test_batched_explicit_widths_and_single_operator(h):
+    ops, Ls = small_uneven(3, 5)
+    ks = [L + 6 for L in Ls]
+    prm = scsf.make_params(0, 0, 16, 1e-8, seed=4)
+    evals, evecs, stats = scsf.scsf_solve_batched(h, [scsf.DeviceOperator(o) for o in ops], Ls,
+                                                  [2, 0, 1], 2, prm, ks=ks)
+    for i, o in enumerate(ops):
+        A = O.assemble(o)
+        w, V = E.smallest_eigenpairs(A, Ls[i] + 6, method="dense")
+        check_pairs(A, evals[i], evecs[i].t(), Ls[i], 1e-8, w, V)
+    e1, v1, s1 = scsf.scsf_solve_batched(h, [scsf.DeviceOperator(ops[0])], [Ls[0]], [0], 1, prm)
+    np.testing.assert_allclose(host(e1[0]), host(evals[0]), rtol=1e-10)
+
+
+def test_block_width_rule():
+    for L, k in [(1, 8), (4, 8), (8, 16), (32, 40), (64, 80), (100, 120), (128, 160), (200, 240)]:
+        assert scsf.scsf_block_width(L) == k
+        assert k >= L + int(np.ceil(0.2 * L))
+    with pytest.raises(scsf.ScsfError):
+        scsf.scsf_block_width(0)
+
+
+def test_batched_errors(h):
+    ops, Ls = small_uneven(2, 7)
+    d = [scsf.DeviceOperator(o) for o in ops]
+    prm = scsf.make_params(0, 0, 20, 1e-8)
+    with pytest.raises(scsf.ScsfError):                       # L >= k
+        scsf.scsf_solve_batched(h, d, Ls, [0, 1], 1, prm, ks=[Ls[0], Ls[1] + 4])
+    with pytest.raises(scsf.ScsfError):                       # not a permutation
+        scsf.scsf_solve_batched(h, d, Ls, [0, 0], 1, prm)
+    with pytest.raises(scsf.ScsfError):                       # mixed precision is uniform-only
+        scsf.scsf_solve_batched(h, d, Ls, [0, 1], 1,
+                                scsf.make_params(0, 0, 20, 1e-8, precision=scsf.SCSF_MIXED))
+    with pytest.raises(scsf.ScsfError):                       # L out of range
+        scsf.scsf_solve_batched(h, d, [0, 4], [0, 1], 1, prm)
+
+
+def test_batched_uneven_full_sizes_sampled(h):
+    """The uneven workload at its real shapes (sides 48..128, L in {32, 64, 128}, both
+    families) in the launch shape of the benchmark (dynamic schedule, 4 lanes), on a prefix of
+    the operators: every pair's residual, and sampled operators against shift-invert."""
+    say("batched uneven full sizes")
+    cfg = si.CONFIGS[3]
+    count = 24
+    ops = si.operators(cfg, count)
+    Ls = [si.mixed_L(cfg, i) for i in range(count)]
+    order = family_order(h, ops, cfg.p0)
+    prm = scsf.make_params(0, 0, cfg.degree, cfg.tol, seed=1, schedule=scsf.SCSF_SCHED_DYNAMIC)
+    scsf.scsf_set_lanes(h, 4)
+    evals, evecs, stats = scsf.scsf_solve_batched(h, [scsf.DeviceOperator(o) for o in ops], Ls,
+                                                  order, 8, prm)
+    say([(o.N, L, s["iterations"]) for o, L, s in zip(ops, Ls, stats)])
+    for i, o in enumerate(ops):
+        assert stats[i]["status"] == 0
+        A = O.assemble(o)
+        X = host(evecs[i]).T
+        lam = host(evals[i])
+        W = A @ X
+        rel = np.linalg.norm(W - X * lam, axis=0) / np.linalg.norm(W, axis=0)
+        assert rel.max() <= cfg.tol * (1 + 1e-6)
+        assert np.all(np.diff(lam) >= 0)
+    for i in sorted({order[0], order[count // 2], max(range(count), key=lambda j: ops[j].N)}):
+        A = O.assemble(ops[i])
+        w, V = E.smallest_eigenpairs(A, Ls[i] + 10)
+        check_pairs(A, evals[i], evecs[i].t(), Ls[i], cfg.tol, w, V)

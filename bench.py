@@ -43,28 +43,48 @@ def workload(cfg_index: int, count: int | None):
     return cfg, ops
 
 
-def cpu_baseline(cfg, ops, budget_s: float):
+def family_order_host(ops, p0):
+    """Algorithm 2 within each operator family, concatenated (oracle; CPU baseline only)."""
+    from oracle import sort as S
+    order = []
+    for fam in ("divk", "potential", "aniso"):
+        idx = [i for i, o in enumerate(ops) if o.family == fam]
+        if idx:
+            sub = S.scsf_sort([ops[i].field for i in idx], p0)
+            order += [idx[j] for j in sub]
+    return order
+
+
+def cpu_baseline(cfg, ops, budget_s: float, Ls=None, ks=None):
     """The oracle (plain NumPy/SciPy SCSF) on a bounded prefix of the sorted sequence."""
+    import math
     import numpy as np
-    from oracle import operator as O, sort as S, chfsi as C
+    from oracle import operator as O, sort as S, chfsi as C, transfer as T
     try:
         from threadpoolctl import threadpool_info
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
         threads = 1
     t0 = time.time()
-    order = S.scsf_sort([o.field for o in ops], cfg.p0)
-    prev, done, pairs = None, 0, 0
+    if Ls is None:
+        order = S.scsf_sort([o.field for o in ops], cfg.p0)
+        Ls, ks = [cfg.L] * len(ops), [cfg.k] * len(ops)
+    else:
+        order = family_order_host(ops, cfg.p0)
+    prev, prev_key, done, pairs = None, None, 0, 0
     for i in order:
         A = O.assemble(ops[i])
-        if prev is None:
-            r = C.chfsi(A, cfg.L, cfg.k, cfg.degree, cfg.tol, seed=1)
+        key = (ops[i].family, Ls[i], ks[i])
+        if prev is None or key != prev_key:
+            r = C.chfsi(A, Ls[i], ks[i], cfg.degree, cfg.tol, seed=1)
         else:
-            r = C.chfsi(A, cfg.L, cfg.k, cfg.degree, cfg.tol, X0=prev.X_next,
-                        theta0=prev.theta_next)
-        prev = r
+            X0 = prev.X_next
+            if X0.shape[0] != A.shape[0]:
+                X0 = T.interpolate_block(X0, math.isqrt(X0.shape[0]), ops[i].N)
+            r = C.chfsi(A, Ls[i], ks[i], cfg.degree, cfg.tol, X0=X0, theta0=prev.theta_next)
+        prev, prev_key = r, key
         done += 1
-        pairs += cfg.L
+        pairs += Ls[i]
         log(f"[bench] cpu oracle: operator {done} ({r.iterations} iterations) "
             f"{time.time() - t0:.1f}s")
         if time.time() - t0 > budget_s:
@@ -111,17 +131,31 @@ def main():
     cfg, ops = workload(args.config, args.count)
     degree = args.degree or cfg.degree
     n_op = len(ops)
+    uneven = cfg.family == "mixed"
+    import scsf_inputs as si
+    Ls = [si.mixed_L(cfg, i) for i in range(n_op)] if uneven else [cfg.L] * n_op
     h = scsf.Handle()
     scsf.scsf_set_lanes(h, args.lanes)
-    fields = torch.tensor(np.stack([o.field for o in ops]), device="cuda")
     dops = [scsf.DeviceOperator(o) for o in ops]
+    if uneven:
+        # fields grouped by family and side: features per side, one greedy order per family
+        groups = {}
+        for i, o in enumerate(ops):
+            groups.setdefault((o.family, o.N), []).append(i)
+        gfields = {key: torch.tensor(np.stack([ops[i].field for i in idx]), device="cuda")
+                   for key, idx in groups.items()}
+        fams = sorted({key[0] for key in groups})
+    else:
+        fields = torch.tensor(np.stack([o.field for o in ops]), device="cuda")
     precision = args.precision or ("mixed" if cfg.precision == "mixed" else "fp64")
     prm = scsf.make_params(cfg.L, cfg.k, degree, cfg.tol, seed=1,
                            schedule=scsf.SCSF_SCHED_DYNAMIC if args.schedule == "dynamic"
                            else scsf.SCSF_SCHED_STATIC,
                            precision=scsf.SCSF_MIXED if precision == "mixed" else scsf.SCSF_FP64)
-    evals = torch.empty((n_op, cfg.L), device="cuda", dtype=torch.float64)
-    evecs = torch.empty((n_op, cfg.L, dops[0].n), device="cuda", dtype=torch.float64)
+    if not uneven:
+        evals = torch.empty((n_op, cfg.L), device="cuda", dtype=torch.float64)
+        evecs = torch.empty((n_op, cfg.L, dops[0].n), device="cuda", dtype=torch.float64)
+    ks = [scsf.scsf_block_width(L) for L in Ls] if uneven else [cfg.k] * n_op
     torch.cuda.synchronize()
     if args.calibrate_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -133,6 +167,15 @@ def main():
         log("[bench] copy calibration: 3 x 1 GiB device copy done")
 
     def step():
+        if uneven:
+            order = []
+            for fam in fams:
+                keys = [key for key in groups if key[0] == fam]
+                idx = [i for key in keys for i in groups[key]]
+                feats = torch.cat([scsf.scsf_features(h, gfields[key], cfg.p0) for key in keys])
+                order += [idx[j] for j in scsf.scsf_order_features(h, feats)]
+            _, _, stats = scsf.scsf_solve_batched(h, dops, Ls, order, args.chains, prm, ks=ks)
+            return stats
         order = scsf.scsf_sort(h, fields, cfg.p0)
         _, _, stats = scsf.scsf_solve_sequence(h, dops, order, args.chains, prm, evals, evecs)
         return stats
@@ -158,7 +201,7 @@ def main():
     prof = scsf.scsf_profile_read(h, reset=True)
     scsf.scsf_profile_enable(h, False)
 
-    pairs = args.steps * n_op * cfg.L
+    pairs = args.steps * sum(Ls)
     value = pairs / dt
     avg_ms = prof["filter_ms"] / max(prof["filter_launches"], 1)
     avg_bytes = prof["filter_bytes"] / max(prof["filter_launches"], 1)
@@ -179,9 +222,13 @@ def main():
         "dtype": "f64" if precision == "fp64" else "f32 filter + f64",
         "data": "synthetic (seeded GRF coefficient fields)",
         "config": {
-            "workload": f"{cfg.name}: {n_op} operators ({cfg.family}), {ops[0].N}x{ops[0].N} grid "
-                        f"(n={dops[0].n}), L={cfg.L}, k={cfg.k}, degree={degree}, p0={cfg.p0}, "
-                        f"tol={cfg.tol:g}",
+            "workload": (f"{cfg.name}: {n_op} operators ({cfg.family}), {ops[0].N}x{ops[0].N} "
+                         f"grid (n={dops[0].n}), L={cfg.L}, k={cfg.k}, degree={degree}, "
+                         f"p0={cfg.p0}, tol={cfg.tol:g}") if not uneven else
+                        (f"{cfg.name}: {n_op} operators (half -div(K grad u), half -Laplace u + "
+                         f"V u), sides {min(o.N for o in ops)}..{max(o.N for o in ops)}, "
+                         f"L in {{32, 64, 128}} (sum {sum(Ls)}), k = scsf_block_width(L), "
+                         f"degree={degree}, p0={cfg.p0}, tol={cfg.tol:g}"),
             "chains": args.chains,
             "lanes": args.lanes,
             "schedule": args.schedule,
@@ -203,7 +250,8 @@ def main():
         },
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, ops, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(cfg, ops, args.cpu_budget,
+                                           Ls if uneven else None, ks if uneven else None)
     print(json.dumps(out))
 
 

@@ -27,6 +27,7 @@ __global__ void __launch_bounds__(512) chol_inv_kernel(
   __shared__ double lds[LDS ? kLdsDoubles : 1];
   __shared__ double dsc[kMaxK];
   __shared__ double piv[kMaxK];
+  __shared__ double colv[kMaxK];
   __shared__ int s_fail;
   __shared__ double s_shift;
   const int b = blockIdx.x;
@@ -37,7 +38,6 @@ __global__ void __launch_bounds__(512) chol_inv_kernel(
   const int tid = threadIdx.x, NT = blockDim.x;
   const int tx = tid & 15, ty = tid >> 4;              // 16 x 32
   double *S = LDS ? lds : gscr + (int64_t)b * kMaxK * (kMaxK + 1);
-  double *T = S + (int64_t)ka * (ka + 1) / 2;
   const double *Gb = G + (int64_t)b * ldm * ldm;
   double *Mb = M + (int64_t)b * ldm * ldm;
 
@@ -93,32 +93,28 @@ __global__ void __launch_bounds__(512) chol_inv_kernel(
     }
     break;
   }
-  // T <- R^-1 (upper) by a sweep from the last row up: row i of T is final once divided by
-  // R_ii; the rows above subtract R_ri times it.  Row i is divided one step later.
-  for (int c = ty; c < ka; c += 32)
-    for (int i = tx; i <= c; i += 16) T[upk(i, c)] = (i == c) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int i = ka - 1; i >= 0; --i) {
-    const double rii = S[upk(i, i)];
-    if (i < ka - 1) {
-      const double rn = S[upk(i + 1, i + 1)];
-      for (int c = i + 1 + tid; c < ka; c += NT) T[upk(i + 1, c)] /= rn;
-    }
-    const double inv = 1.0 / rii;
-    for (int c = i + ty; c < ka; c += 32) {
-      const double tic = T[upk(i, c)] * inv;
-      for (int r = tx; r < i; r += 16) T[upk(r, c)] -= S[upk(r, i)] * tic;
+  // S <- R^-1 in place, column by column: with T = R^-1 already on the columns < j,
+  // T[0:j, j] = -T[0:j, 0:j] R[0:j, j] / R_jj and T_jj = 1 / R_jj (both read the original
+  // column j, which is overwritten only after the barrier).  Four lanes share each row's
+  // dot product.
+  for (int j = 0; j < ka; ++j) {
+    const double tjj = 1.0 / S[upk(j, j)];
+    const int g = tid & 3;
+    for (int r = tid >> 2; r < j; r += NT >> 2) {
+      double acc = 0.0;
+      for (int c = r + g; c < j; c += 4) acc += S[upk(r, c)] * S[upk(c, j)];
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      if (g == 0) colv[r] = acc;
     }
     __syncthreads();
+    for (int r = tid; r < j; r += NT) S[upk(r, j)] = -colv[r] * tjj;
+    if (tid == 0) S[upk(j, j)] = tjj;
+    __syncthreads();
   }
-  {
-    const double r0 = S[upk(0, 0)];
-    for (int c = tid; c < ka; c += NT) T[upk(0, c)] /= r0;
-  }
-  __syncthreads();
   for (int c = ty; c < ka; c += 32)
     for (int r = tx; r < ka; r += 16)
-      Mb[r + (int64_t)c * ldm] = (r <= c) ? T[upk(r, c)] / dsc[r] : 0.0;
+      Mb[r + (int64_t)c * ldm] = (r <= c) ? S[upk(r, c)] / dsc[r] : 0.0;
   if (tid == 0 && s_fail) atomicOr(&flag[b], s_fail);
 }
 
@@ -126,8 +122,8 @@ hipError_t chol_inv(int B, int64_t n, int32_t k, const int32_t *lock, const doub
                     int32_t ldm, int32_t *flag, const int32_t *gate, int32_t gate_mask,
                     double *scratch, hipStream_t st) {
   if (B <= 0) return hipSuccess;
-  // the packed R and R^-1 fit in LDS for every ka when k(k+1) <= kLdsDoubles
-  if ((int64_t)k * (k + 1) <= kLdsDoubles)
+  // the packed R (inverted in place) fits in LDS for every ka when k(k+1)/2 <= kLdsDoubles
+  if ((int64_t)k * (k + 1) / 2 <= kLdsDoubles)
     chol_inv_kernel<true><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask, scratch);
   else
     chol_inv_kernel<false><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask,

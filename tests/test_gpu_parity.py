@@ -97,7 +97,9 @@ def test_filter_on_sine_modes_closed_form(h):
 
 
 # ------------------------------------------------------------------------------ orthonormalisation
-@pytest.mark.parametrize("n,k,nl", [(1024, 24, 0), (1369, 40, 9), (10000, 120, 0), (4900, 70, 50)])
+# k = 160 and 196 (the largest width whose packed factor fits in LDS) and 240 (global scratch)
+@pytest.mark.parametrize("n,k,nl", [(1024, 24, 0), (1369, 40, 9), (10000, 120, 0), (4900, 70, 50),
+                                    (16384, 160, 0), (9000, 176, 20), (12000, 200, 40)])
 def test_orthonormalize(h, n, k, nl):
     say("orth", n, k, nl)
     rng = np.random.default_rng(n + k)

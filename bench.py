@@ -23,6 +23,11 @@ import os
 import sys
 import time
 
+# HIP maps every stream to one of GPU_MAX_HW_QUEUES hardware queues (4 by default); the
+# concurrent lanes of the chained solver plus the default stream need one queue each, or two
+# lanes share a queue and run one after the other.  Set before HIP initialises.
+os.environ["GPU_MAX_HW_QUEUES"] = "8"
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -104,13 +109,16 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--count", type=int, default=None, help="operators (default: all)")
     ap.add_argument("--chains", type=int, default=32)
-    ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--lanes", type=int, default=5)
     ap.add_argument("--degree", type=int, default=None)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
                     help="default: the configuration's (fp64; mixed for config 4)")
     ap.add_argument("--schedule", choices=["static", "dynamic"], default="dynamic",
                     help="static: contiguous chunks of the sorted order (App. D.6); dynamic: "
                          "each chain takes the next unsolved operator of the sorted order")
+    ap.add_argument("--graphs", choices=["on", "off"], default="on",
+                    help="replay each outer iteration as HIP graphs (on) or launch its kernels "
+                         "one by one (off)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -136,6 +144,7 @@ def main():
     Ls = [si.mixed_L(cfg, i) for i in range(n_op)] if uneven else [cfg.L] * n_op
     h = scsf.Handle()
     scsf.scsf_set_lanes(h, args.lanes)
+    scsf.scsf_set_graphs(h, args.graphs == "on")
     dops = [scsf.DeviceOperator(o) for o in ops]
     if uneven:
         # fields grouped by family and side: features per side, one greedy order per family
@@ -232,6 +241,7 @@ def main():
             "chains": args.chains,
             "lanes": args.lanes,
             "schedule": args.schedule,
+            "graphs": args.graphs,
             "precision": precision,
             "mean_outer_iterations": float(np.mean(iters)),
         },

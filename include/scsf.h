@@ -121,11 +121,16 @@ int scsf_set_stream(scsf_handle *h, void *hip_stream);
 const char *scsf_status_string(int status);
 /* Library build/version string (host). */
 const char *scsf_version(void);
-/* Number of lockstep batches scsf_solve_sequence runs concurrently (1..8, default 4).  Batch 0
- * uses the handle's stream; the others use streams the handle creates (default priority),
- * ordered after the work already enqueued on the handle's stream, each driven by a host
- * thread of its own. */
+/* Number of lockstep batches the chained solvers (scsf_solve_sequence*, scsf_solve_batched)
+ * run concurrently (1..8, default 4).  Each batch runs on a stream the handle creates (default
+ * priority), ordered after the work already enqueued on the handle's stream, and is driven by
+ * a host thread of its own; the call returns when every batch has finished. */
 int scsf_set_lanes(scsf_handle *h, int lanes);
+/* Chained solvers: on != 0 (default) replays each outer iteration of Algorithm 3 as three HIP
+ * graphs captured once per filter degree (window and coefficients; the filter's m steps;
+ * orthonormalisation, Rayleigh-Ritz, residuals and locking); on == 0 launches the same
+ * kernels one by one.  Results are identical either way. */
+int scsf_set_graphs(scsf_handle *h, int on);
 /* Turn filter-step timing on (on != 0) or off; synchronises the stream. */
 int scsf_profile_enable(scsf_handle *h, int on);
 /* Copy the accumulated filter timing to *out_host; reset != 0 clears it afterwards. */

@@ -42,7 +42,8 @@ struct Workspace {
   size_t pinned_bytes = 0;
   bool prof = false;                     // filter-launch timing (scsf_profile_*)
   std::vector<hipEvent_t> ev;            // 2 per pending launch
-  std::vector<double> ev_bytes;          // algorithmic bytes of each pending launch
+  std::vector<double> ev_bytes;          // algorithmic bytes of each pending timed span
+  std::vector<int> ev_count;             // filter launches inside each pending timed span
   int ev_used = 0;
   scsf_profile acc{};
 };
@@ -52,7 +53,9 @@ struct Workspace {
 struct scsf_handle {
   int device = 0;
   int lanes = 4;                         // concurrent chain groups in scsf_solve_sequence
-  std::vector<Workspace *> ws;           // ws[0] runs on the caller's stream
+  bool graphs = true;                    // outer iterations of chained solves as HIP graphs
+  std::vector<Workspace *> ws;           // ws[0] runs on the caller's stream; ws[1..] are the
+                                         // lanes of chained solves (private streams)
 };
 
 namespace {
@@ -135,7 +138,7 @@ OpDev to_dev(const scsf_operator &A) {
 
 // Event pairs are recorded around each filter launch and drained at the next
 // synchronisation point (no extra synchronisation is added).
-int prof_begin(Workspace *h, double bytes) {
+int prof_begin(Workspace *h, double bytes, int launches = 1) {
   if (!h->prof) return -1;
   if ((size_t)(2 * h->ev_used + 2) > h->ev.size()) {
     for (int i = 0; i < 64; ++i) {
@@ -145,8 +148,12 @@ int prof_begin(Workspace *h, double bytes) {
     }
   }
   const int slot = h->ev_used++;
-  if ((size_t)slot >= h->ev_bytes.size()) h->ev_bytes.resize(slot + 1);
+  if ((size_t)slot >= h->ev_bytes.size()) {
+    h->ev_bytes.resize(slot + 1);
+    h->ev_count.resize(slot + 1);
+  }
   h->ev_bytes[slot] = bytes;
+  h->ev_count[slot] = launches;
   if (hipEventRecord(h->ev[2 * slot], h->stream) != hipSuccess) return -1;
   return slot;
 }
@@ -157,7 +164,7 @@ void prof_drain(Workspace *h) {  // call only after the stream was synchronised
   for (int i = 0; i < h->ev_used; ++i) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) == hipSuccess) {
-      h->acc.filter_launches += 1;
+      h->acc.filter_launches += h->ev_count[i];
       h->acc.filter_ms += ms;
       h->acc.filter_bytes += h->ev_bytes[i];
     }
@@ -448,10 +455,123 @@ struct Engine {
     return SCSF_OK;
   }
 
-  // One outer iteration of Algorithm 3 for every problem not done.
   std::vector<int32_t> lock_before;
   int32_t h_lock_prev(int b) const { return lock_before.empty() ? 0 : lock_before[b]; }
 
+  // The three parts of one outer iteration: window + coefficients, the degree-M filter, and
+  // orthonormalisation + Rayleigh-Ritz + residuals + locking.  All of them only launch
+  // kernels on `st`, so each can be captured into a graph and replayed.
+  int enqueue_pre(int M) {
+    HIPCHK(fill_int(flag, 0, B, st));
+    HIPCHK(cheb_coeffs(B, k, M, theta, bnd, done, coef, mixed ? winb : nullptr, hint, st));
+    return SCSF_OK;
+  }
+  int enqueue_filter(int M, bool timed) {
+    const int32_t *md = var_deg ? mdeg : nullptr;
+    if (mixed) {
+      // Y = p_m(A) X = X p_m(Theta) + e_m with the correction e in FP32 (misc.hip)
+      HIPCHK(mp_tables(B, k, M, theta, winb, lock, done, src, gain, md, st));
+      HIPCHK(mp_prep(B, n, ld, bs, k, lock, X, W, theta, coef, R32, E32[1], st));
+      for (int s = 1; s < M; ++s) {
+        const int slot = timed ? prof_begin(h, step_bytes(s > 1, true, s)) : -1;
+        HIPCHK(spmm_step32(ops, B, kind, n, E32[s % 3], E32[(s + 2) % 3], E32[(s + 1) % 3], ld, bs,
+                           COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 1, R32,
+                           src + (size_t)s * B * k, st, md, s));
+        prof_end(h, slot);
+      }
+      HIPCHK(mp_final(B, n, ld, bs, k, lock, X, E32[M % 3], gain, Y1, st));
+    } else {
+      double *ring[3] = {X, Y1, Y2};
+      for (int s = 0; s < M; ++s) {
+        const int slot = timed ? prof_begin(h, step_bytes(s > 0, false, s)) : -1;
+        HIPCHK(spmm_step(ops, B, kind, n, 0, ring[s % 3], ring[(s + 2) % 3], ring[(s + 1) % 3],
+                         ld, bs, COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 0, st, md,
+                         s));
+        prof_end(h, slot);
+      }
+    }
+    return SCSF_OK;
+  }
+  double *filtered(int M) {
+    double *ring[3] = {X, Y1, Y2};
+    return mixed ? Y1 : ring[M % 3];
+  }
+  int enqueue_post(int M) {
+    double *Yf = filtered(M);
+    STCHK(orth(Yf, true));
+    STCHK(rayleigh_ritz(Yf));
+    HIPCHK(residuals(B, n, ld, X, W, bs, k, lock, theta, res, st, rows));
+    HIPCHK(lock_update(B, k, L, tol, lock, nconv, res, done, st));
+    return SCSF_OK;
+  }
+
+  // Graphs of the three parts, one set per filter degree (the only launch parameter that
+  // changes between iterations; every kernel reads its per-problem state from device memory).
+  struct GraphSet {
+    int M = 0;
+    hipGraphExec_t pre = nullptr, filt = nullptr, post = nullptr;
+  };
+  bool use_graph = false;
+  std::vector<GraphSet> gcache;
+  static constexpr int kMaxGraphSets = 16;
+
+  template <typename F>
+  int capture(F &&body, hipGraphExec_t *out) {
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const int rc = body();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc != SCSF_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    HIPCHK(e);
+    const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(ei);
+    return SCSF_OK;
+  }
+  void drop_graphs() {
+    for (auto &gs : gcache) {
+      if (gs.pre) (void)hipGraphExecDestroy(gs.pre);
+      if (gs.filt) (void)hipGraphExecDestroy(gs.filt);
+      if (gs.post) (void)hipGraphExecDestroy(gs.post);
+    }
+    gcache.clear();
+  }
+  int graphs_for(int M, GraphSet **out) {
+    for (auto &gs : gcache)
+      if (gs.M == M) { *out = &gs; return SCSF_OK; }
+    if ((int)gcache.size() >= kMaxGraphSets) {
+      HIPCHK(hipStreamSynchronize(st));
+      drop_graphs();
+    }
+    GraphSet gs;
+    gs.M = M;
+    int rc = capture([&] { return enqueue_pre(M); }, &gs.pre);
+    if (rc == SCSF_OK) rc = capture([&] { return enqueue_filter(M, false); }, &gs.filt);
+    if (rc == SCSF_OK) rc = capture([&] { return enqueue_post(M); }, &gs.post);
+    if (rc != SCSF_OK) {
+      if (gs.pre) (void)hipGraphExecDestroy(gs.pre);
+      if (gs.filt) (void)hipGraphExecDestroy(gs.filt);
+      return rc;
+    }
+    gcache.push_back(gs);
+    *out = &gcache.back();
+    return SCSF_OK;
+  }
+
+  Engine() = default;
+  Engine(const Engine &) = delete;
+  Engine &operator=(const Engine &) = delete;
+  ~Engine() {
+    if (!gcache.empty()) {
+      (void)hipStreamSynchronize(st);
+      drop_graphs();
+    }
+  }
+
+  // One outer iteration of Algorithm 3 for every problem not done.
   int iterate() {
     lock_before.assign(h_nconv, h_nconv + B);
     int M = m;
@@ -459,43 +579,30 @@ struct Engine {
       STCHK(plan_degrees());
       M = mcur;
     }
-    const int32_t *md = var_deg ? mdeg : nullptr;
-    HIPCHK(fill_int(flag, 0, B, st));
-    HIPCHK(cheb_coeffs(B, k, M, theta, bnd, done, coef, mixed ? winb : nullptr, hint, st));
-    double *Yf = nullptr;
-    if (mixed) {
-      // Y = p_m(A) X = X p_m(Theta) + e_m with the correction e in FP32 (misc.hip)
-      if (w_stale) {
-        HIPCHK(spmm_step(ops, B, kind, n, 0, X, nullptr, W, ld, bs, COLS_ACTIVE, k, lock, unit,
-                         false, st));
-        w_stale = false;
-      }
-      HIPCHK(mp_tables(B, k, M, theta, winb, lock, done, src, gain, md, st));
-      HIPCHK(mp_prep(B, n, ld, bs, k, lock, X, W, theta, coef, R32, E32[1], st));
-      for (int s = 1; s < M; ++s) {
-        const int slot = prof_begin(h, h->prof ? step_bytes(s > 1, true, s) : 0.0);
-        HIPCHK(spmm_step32(ops, B, kind, n, E32[s % 3], E32[(s + 2) % 3], E32[(s + 1) % 3], ld, bs,
-                           COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 1, R32,
-                           src + (size_t)s * B * k, st, md, s));
-        prof_end(h, slot);
-      }
-      HIPCHK(mp_final(B, n, ld, bs, k, lock, X, E32[M % 3], gain, Y1, st));
-      Yf = Y1;
-    } else {
-      double *ring[3] = {X, Y1, Y2};
-      for (int s = 0; s < M; ++s) {
-        const int slot = prof_begin(h, h->prof ? step_bytes(s > 0, false, s) : 0.0);
-        HIPCHK(spmm_step(ops, B, kind, n, 0, ring[s % 3], ring[(s + 2) % 3], ring[(s + 1) % 3],
-                         ld, bs, COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 0, st, md,
-                         s));
-        prof_end(h, slot);
-      }
-      Yf = ring[M % 3];
+    if (mixed && w_stale) {           // A X of newly loaded operators (residual form)
+      HIPCHK(spmm_step(ops, B, kind, n, 0, X, nullptr, W, ld, bs, COLS_ACTIVE, k, lock, unit,
+                       false, st));
+      w_stale = false;
     }
-    STCHK(orth(Yf, true));
-    STCHK(rayleigh_ritz(Yf));
-    HIPCHK(residuals(B, n, ld, X, W, bs, k, lock, theta, res, st, rows));
-    HIPCHK(lock_update(B, k, L, tol, lock, nconv, res, done, st));
+    if (!use_graph) {
+      STCHK(enqueue_pre(M));
+      STCHK(enqueue_filter(M, h->prof));
+      STCHK(enqueue_post(M));
+    } else {
+      GraphSet *gs = nullptr;
+      STCHK(graphs_for(M, &gs));
+      HIPCHK(hipGraphLaunch(gs->pre, st));
+      int slot = -1;
+      if (h->prof) {                  // one timed span over the filter graph's M launches
+        double bytes = 0.0;
+        for (int s = mixed ? 1 : 0; s < M; ++s)
+          bytes += mixed ? step_bytes(s > 1, true, s) : step_bytes(s > 0, false, s);
+        slot = prof_begin(h, bytes, mixed ? M - 1 : M);
+      }
+      HIPCHK(hipGraphLaunch(gs->filt, st));
+      prof_end(h, slot);
+      HIPCHK(hipGraphLaunch(gs->post, st));
+    }
     return download_state();
   }
 
@@ -579,7 +686,7 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
                int32_t n_op, const std::vector<int> &cb, const std::vector<int> &ce,
                std::atomic<int> *next, const scsf_params *prm, const double *hints_host,
                double *evals, double *evecs, double *ritz, scsf_stats *stats_host,
-               const Group *grp = nullptr) {
+               const Group *grp = nullptr, bool graphs = false) {
   const int chains = (int)cb.size();
   if (chains == 0) return SCSF_OK;
   const int64_t n = grp ? grp->nmax : ops_host[0].n;
@@ -592,6 +699,7 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
   Engine e;
   STCHK(e.setup(w, chains, n, k, L, m, kind, prm->tol, prm->seed, lzs,
                 prm->precision == SCSF_MIXED, hints_host != nullptr));
+  e.use_graph = graphs && w->own_stream;     // capture needs a stream of our own
   std::vector<int> pos(chains), iters(chains, 0);
   std::vector<int64_t> fcols(chains, 0);
   std::vector<char> active(chains, 1);
@@ -798,6 +906,12 @@ int scsf_set_stream(scsf_handle *h, void *hip_stream) {
   if (!h) return SCSF_EINVAL;
   if (hipStreamSynchronize(h->ws[0]->stream) != hipSuccess) return SCSF_EHIP;
   h->ws[0]->stream = static_cast<hipStream_t>(hip_stream);
+  return SCSF_OK;
+}
+
+int scsf_set_graphs(scsf_handle *h, int on) {
+  if (!h) return SCSF_EINVAL;
+  h->graphs = on != 0;
   return SCSF_OK;
 }
 
@@ -1094,11 +1208,11 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
   std::vector<int> cbeg(chains + 1);
   for (int c = 0; c <= chains; ++c) cbeg[c] = (int)((int64_t)n_op * c / chains);
   const int lanes = std::min(h->lanes, chains);
-  STCHK(add_lanes(h, lanes));
-  hipEvent_t ready;
+  STCHK(add_lanes(h, lanes + 1));
+  hipEvent_t ready;                              // the lanes start after the caller's work
   HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
   HIPCHK(hipEventRecord(ready, h->ws[0]->stream));
-  for (int g = 1; g < lanes; ++g) HIPCHK(hipStreamWaitEvent(h->ws[g]->stream, ready, 0));
+  for (int g = 1; g <= lanes; ++g) HIPCHK(hipStreamWaitEvent(h->ws[g]->stream, ready, 0));
   std::vector<int> status(lanes, SCSF_OK);
   const bool dyn = prm->schedule == SCSF_SCHED_DYNAMIC;
   std::atomic<int> next(chains);                // dynamic: chain c starts at order position c
@@ -1109,8 +1223,9 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
       cb.push_back(dyn ? c : cbeg[c]);
       ce.push_back(dyn ? c + 1 : cbeg[c + 1]);
     }
-    status[g] = run_chains(h->ws[g], ops_host, order_host, n_op, cb, ce, dyn ? &next : nullptr,
-                           prm, hints_host, evals, evecs, ritz, stats_host);
+    status[g] = run_chains(h->ws[g + 1], ops_host, order_host, n_op, cb, ce,
+                           dyn ? &next : nullptr, prm, hints_host, evals, evecs, ritz, stats_host,
+                           nullptr, h->graphs);
   };
   std::vector<std::thread> threads;
   for (int g = 1; g < lanes; ++g) threads.emplace_back(lane_fn, g);
@@ -1204,11 +1319,11 @@ int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_
     maxc = std::max(maxc, g.chains);
   }
   const int lanes = std::min(h->lanes, maxc);
-  STCHK(add_lanes(h, lanes));
-  hipEvent_t ready;
+  STCHK(add_lanes(h, lanes + 1));
+  hipEvent_t ready;                              // the lanes start after the caller's work
   HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
   HIPCHK(hipEventRecord(ready, h->ws[0]->stream));
-  for (int l = 1; l < lanes; ++l) HIPCHK(hipStreamWaitEvent(h->ws[l]->stream, ready, 0));
+  for (int l = 1; l <= lanes; ++l) HIPCHK(hipStreamWaitEvent(h->ws[l]->stream, ready, 0));
   const bool dyn = prm->schedule == SCSF_SCHED_DYNAMIC;
   std::vector<std::atomic<int>> next(groups.size());
   for (size_t gi = 0; gi < groups.size(); ++gi) next[gi] = groups[gi].chains;
@@ -1232,9 +1347,9 @@ int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_
       grp.nmax = g.nmax;
       grp.eoff = eoff.data();
       grp.voff = voff.data();
-      const int s2 = run_chains(h->ws[l], ops_host, g.order.data(), nord, cb, ce,
+      const int s2 = run_chains(h->ws[l + 1], ops_host, g.order.data(), nord, cb, ce,
                                 dyn ? &next[gi] : nullptr, prm, nullptr, evals, evecs, nullptr,
-                                stats_host, &grp);
+                                stats_host, &grp, h->graphs);
       if (s2 != SCSF_OK && (status[l] == SCSF_OK ||
                             (status[l] == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)))
         status[l] = s2;

@@ -94,6 +94,7 @@ def lib():
         sig["scsf_window_hints"] = [vp, vp, i32, vp]
         sig["scsf_profile_enable"] = [vp, i32]
         sig["scsf_set_lanes"] = [vp, i32]
+        sig["scsf_set_graphs"] = [vp, i32]
         sig["scsf_profile_read"] = [vp, POINTER(Profile), i32]
         sig["scsf_order_features"] = [vp, vp, i32, i32, i32, POINTER(c_int32)]
         sig["scsf_interpolate"] = [vp, i32, i32, i32, vp, i64, vp, i64]
@@ -391,6 +392,10 @@ def scsf_solve_sequence(h: Handle, ops: list, order, chains: int, prm: Params,
 
 def scsf_set_lanes(h: Handle, lanes: int):
     _check(lib().scsf_set_lanes(h.ptr, int(lanes)), "scsf_set_lanes")
+
+
+def scsf_set_graphs(h: Handle, on: bool = True):
+    _check(lib().scsf_set_graphs(h.ptr, 1 if on else 0), "scsf_set_graphs")
 
 
 def scsf_profile_enable(h: Handle, on: bool = True):

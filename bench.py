@@ -119,6 +119,15 @@ def main():
     ap.add_argument("--graphs", choices=["on", "off"], default="on",
                     help="replay each outer iteration as HIP graphs (on) or launch its kernels "
                          "one by one (off)")
+    ap.add_argument("--autotune", choices=["on", "off"], default="on",
+                    help="tune filter tiles (and, for the uneven workload, block widths) on the "
+                         "dataset once before the warmup; the timed steps use the result")
+    ap.add_argument("--form", choices=["learned", "plain"], default=None,
+                    help="learned-window workload only: learned (train on the first solves, "
+                         "predict windows and degrees for the rest; default) or plain")
+    ap.add_argument("--train", type=int, default=500,
+                    help="learned form: operators solved plainly to train the network")
+    ap.add_argument("--epochs", type=int, default=600)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -140,6 +149,8 @@ def main():
     degree = args.degree or cfg.degree
     n_op = len(ops)
     uneven = cfg.family == "mixed"
+    windowed = cfg.family == "aniso"             # the learned-window workload
+    form = (args.form or "learned") if windowed else "plain"
     import scsf_inputs as si
     Ls = [si.mixed_L(cfg, i) for i in range(n_op)] if uneven else [cfg.L] * n_op
     h = scsf.Handle()
@@ -156,7 +167,8 @@ def main():
         fams = sorted({key[0] for key in groups})
     else:
         fields = torch.tensor(np.stack([o.field for o in ops]), device="cuda")
-    precision = args.precision or ("mixed" if cfg.precision == "mixed" else "fp64")
+    precision = args.precision or ("mixed" if cfg.precision == "mixed" or form == "learned"
+                                   else "fp64")
     prm = scsf.make_params(cfg.L, cfg.k, degree, cfg.tol, seed=1,
                            schedule=scsf.SCSF_SCHED_DYNAMIC if args.schedule == "dynamic"
                            else scsf.SCSF_SCHED_STATIC,
@@ -164,7 +176,6 @@ def main():
     if not uneven:
         evals = torch.empty((n_op, cfg.L), device="cuda", dtype=torch.float64)
         evecs = torch.empty((n_op, cfg.L, dops[0].n), device="cuda", dtype=torch.float64)
-    ks = [scsf.scsf_block_width(L) for L in Ls] if uneven else [cfg.k] * n_op
     torch.cuda.synchronize()
     if args.calibrate_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -175,7 +186,11 @@ def main():
         del src, dst
         log("[bench] copy calibration: 3 x 1 GiB device copy done")
 
-    def step():
+    prm64 = scsf.make_params(cfg.L, cfg.k, degree, cfg.tol, seed=1,
+                             schedule=scsf.SCSF_SCHED_DYNAMIC if args.schedule == "dynamic"
+                             else scsf.SCSF_SCHED_STATIC, precision=scsf.SCSF_FP64)
+
+    def make_order():
         if uneven:
             order = []
             for fam in fams:
@@ -183,11 +198,53 @@ def main():
                 idx = [i for key in keys for i in groups[key]]
                 feats = torch.cat([scsf.scsf_features(h, gfields[key], cfg.p0) for key in keys])
                 order += [idx[j] for j in scsf.scsf_order_features(h, feats)]
-            _, _, stats = scsf.scsf_solve_batched(h, dops, Ls, order, args.chains, prm, ks=ks)
-            return stats
+            return order
+        return scsf.scsf_sort(h, fields, cfg.p0)
+
+    n_train = min(args.train, n_op // 2) if windowed else 0
+    train_info = {}
+
+    def step_learned():
+        """Sort; plain solves of the first n_train operators of the order (their Ritz values
+        and bounds give the labels); FP32 training; BF16 inference for the rest, whose solves
+        take the predicted window and degree."""
         order = scsf.scsf_sort(h, fields, cfg.p0)
+        head, tail = [int(i) for i in order[:n_train]], [int(i) for i in order[n_train:]]
+        ritz = torch.empty((n_train, cfg.k), device="cuda", dtype=torch.float64)
+        _, _, st1 = scsf.scsf_solve_sequence(h, [dops[i] for i in head], np.arange(n_train),
+                                             args.chains, prm, ritz=ritz)
+        beta = torch.tensor([s["beta"] for s in st1], device="cuda", dtype=torch.float64)
+        target = scsf.scsf_window_labels(h, ritz, cfg.L, beta)
+        x = scsf.scsf_window_input(h, scsf.scsf_features(h, fields, 16))
+        params = scsf.scsf_window_init(h, 5)
+        hist = scsf.scsf_window_train(h, params, x[torch.tensor(head, device="cuda")], target,
+                                      args.epochs, 1e-3)
+        out = scsf.scsf_window_forward(h, params, x[torch.tensor(tail, device="cuda")], bf16=True)
+        hints = scsf.scsf_window_hints(h, out).cpu().numpy()
+        _, _, st2 = scsf.scsf_solve_sequence(h, [dops[i] for i in tail], np.arange(len(tail)),
+                                             args.chains, prm, hints=hints)
+        train_info.update(loss_first=float(hist[0]), loss_last=float(hist[-1]),
+                          hints_used=int(sum(s["hint"] == 2 for s in st2)),
+                          mean_degree=float(np.mean([s["degree"] for s in st2])))
+        return st1 + st2
+
+    def step():
+        if form == "learned":
+            return step_learned()
+        order = make_order()
+        if uneven:
+            _, _, stats = scsf.scsf_solve_batched(h, dops, Ls, order, args.chains, prm)
+            return stats
         _, _, stats = scsf.scsf_solve_sequence(h, dops, order, args.chains, prm, evals, evecs)
         return stats
+
+    tune_s = 0.0
+    if args.autotune == "on":
+        t = time.time()
+        scsf.scsf_autotune(h, dops, Ls, make_order(), prm64, probe=4)
+        tune_s = time.time() - t
+        log(f"[bench] autotune {tune_s:.2f}s")
+    ks = [scsf.scsf_tuned_width(h, L) for L in Ls] if uneven else [cfg.k] * n_op
 
     for w in range(args.warmup):
         t = time.time()
@@ -210,6 +267,18 @@ def main():
     prof = scsf.scsf_profile_read(h, reset=True)
     scsf.scsf_profile_enable(h, False)
 
+    comparison = None
+    if windowed and form == "learned":
+        # the plain FP64 method (window from Ritz values, degree 20) on the same operators
+        t = time.perf_counter()
+        order = scsf.scsf_sort(h, fields, cfg.p0)
+        _, _, stp = scsf.scsf_solve_sequence(h, dops, order, args.chains, prm64)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        comparison = {"plain_fp64_value": n_op * cfg.L / tp, "plain_fp64_ms": tp * 1e3,
+                      "plain_fp64_mean_iterations": float(np.mean([s["iterations"] for s in stp]))}
+        log(f"[bench] plain fp64 comparison: {n_op * cfg.L / tp:.0f} eigenpairs/s")
+
     pairs = args.steps * sum(Ls)
     value = pairs / dt
     avg_ms = prof["filter_ms"] / max(prof["filter_launches"], 1)
@@ -217,7 +286,8 @@ def main():
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
 
     out = {
-        "metric": "eigenpairs/sec at residual 1e-8 (SCSF GPU, %s)" % (
+        "metric": "eigenpairs/sec at residual 1e-8 (SCSF GPU, %s%s)" % (
+            "learned window, " if form == "learned" else "",
             "FP64" if precision == "fp64" else "FP32 filter / FP64 rest"),
         "value": value,
         "unit": "eigenpairs/s",
@@ -236,12 +306,18 @@ def main():
                          f"p0={cfg.p0}, tol={cfg.tol:g}") if not uneven else
                         (f"{cfg.name}: {n_op} operators (half -div(K grad u), half -Laplace u + "
                          f"V u), sides {min(o.N for o in ops)}..{max(o.N for o in ops)}, "
-                         f"L in {{32, 64, 128}} (sum {sum(Ls)}), k = scsf_block_width(L), "
+                         f"L in {{32, 64, 128}} (sum {sum(Ls)}), k autotuned per L, "
                          f"degree={degree}, p0={cfg.p0}, tol={cfg.tol:g}"),
             "chains": args.chains,
             "lanes": args.lanes,
             "schedule": args.schedule,
             "graphs": args.graphs,
+            "autotune_s": tune_s,
+            "form": form,
+            "block_widths": ({str(L): scsf.scsf_tuned_width(h, L) for L in sorted(set(Ls))}
+                             if uneven else {str(cfg.L): cfg.k}),
+            "spmm_columns_per_thread": scsf.scsf_tuned_tile(h, max(d.n for d in dops),
+                                                            max(ks)),
             "precision": precision,
             "mean_outer_iterations": float(np.mean(iters)),
         },
@@ -259,6 +335,10 @@ def main():
             "algorithmic_bytes_per_launch": avg_bytes,
         },
     }
+    if comparison:
+        comparison["ratio"] = value / comparison["plain_fp64_value"]
+        out["config"]["learned"] = dict(train_info, trained_on=n_train, epochs=args.epochs)
+        out["comparison"] = comparison
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, ops, args.cpu_budget,
                                            Ls if uneven else None, ks if uneven else None)

@@ -237,6 +237,26 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
  * ceil(0.2 L) guard vectors (at most 256).  SCSF_EINVAL unless 0 < L < 256. */
 int scsf_block_width(int32_t L);
 
+/* Autotuner (project-specific; the paper fixes its block widths by hand, Section 4).  For
+ * every distinct L of the dataset (ops_host / L_host / order_host as in scsf_solve_batched):
+ *  - tiles: the filter step is timed with 2, 4 and 8 block columns per thread on 8 copies of
+ *    the largest operator of each size bucket (n <= 4096, <= 16384, larger) for each width
+ *    bucket (k <= 48, <= 96, <= 160, larger) it meets, and the fastest is kept;
+ *  - widths: the first `probe` operators of the L group (in order_host order) are solved as
+ *    one warm-started chain with block widths 1.2 L, 1.35 L and 1.5 L (rounded up to a
+ *    multiple of 8, at most 256 and at most the smallest n), and the width with the least
+ *    time wins (a width whose probe does not converge never wins).
+ * The results stay in the handle: scsf_solve_batched with k_host == NULL uses the tuned
+ * width, and every chained solve uses the tuned tile for its (n, k).  prm as in
+ * scsf_solve_batched; 1 <= probe <= 64.  Runs synchronously; allocates its probe outputs. */
+int scsf_autotune(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
+                  const int32_t *L_host, const int32_t *order_host, const scsf_params *prm,
+                  int32_t probe);
+/* The tuned block width for L (scsf_block_width(L) when L was never tuned). */
+int scsf_tuned_width(scsf_handle *h, int32_t L);
+/* The tuned filter-step tile (block columns per thread: 2, 4 or 8) for size n and width k. */
+int scsf_tuned_tile(scsf_handle *h, int64_t n, int32_t k);
+
 /* Bilinear transfer of ncols nodal fields between interior grids of the unit square: column
  * c of X (device, N0*N0 entries, node (iy, ix) at entry iy*N0 + ix, ld ldx >= N0^2) is read as
  * a field with zero Dirichlet boundary and evaluated at the N1 x N1 nodes into column c of Y
@@ -247,8 +267,8 @@ int scsf_interpolate(scsf_handle *h, int32_t N0, int32_t N1, int32_t ncols, cons
 
 /* A dataset of operators of different sizes and different numbers of wanted pairs.
  * ops_host[n_op]: descriptors (any mix of sizes; kinds may differ).  L_host[n_op]: wanted
- * pairs per operator (0 < L < 256).  k_host[n_op]: block widths, or NULL for
- * scsf_block_width(L).  prm supplies degree, tol, max_iter, lanczos_steps, seed and schedule
+ * pairs per operator (0 < L < 256).  k_host[n_op]: block widths, or NULL for the
+ * autotuned width of each L (scsf_tuned_width).  prm supplies degree, tol, max_iter, lanczos_steps, seed and schedule
  * (prm->L and prm->k are ignored); only SCSF_FP64 is accepted.
  * The operators are grouped by (kind, L, k), keeping order_host's order inside each group,
  * and every group is split into chains (about chains * group size / n_op of them) that run as

@@ -52,7 +52,7 @@ hipError_t spmm_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_
                      const double *X, const double *Z, double *Y, int64_t ld, int64_t bs,
                      int32_t mode, int32_t k, const int32_t *lock, const double *coef,
                      bool has_z, hipStream_t st, const int32_t *mdeg = nullptr,
-                     int32_t step = 0);
+                     int32_t step = 0, int cpt = 4);
 
 // FP32 variant of the step for the mixed-precision filter; with R non-null the step adds the
 // per-column source term src[b*k + c] * R[:, c] (R in the same layout as X).
@@ -60,7 +60,7 @@ hipError_t spmm_step32(const OpDev *ops, int B, int32_t kind, int64_t nmax, cons
                        const float *Z, float *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
                        const int32_t *lock, const double *coef, bool has_z, const float *R,
                        const double *src, hipStream_t st, const int32_t *mdeg = nullptr,
-                       int32_t step = 0);
+                       int32_t step = 0, int cpt = 4);
 
 // Mixed-precision filter helpers (residual form of the recurrence, see misc.hip):
 //  mp_tables : src[(i*B + b)*k + c] = (2 sigma_{i+1}/e) p_i(theta_c) for steps i = 1..m-1 and

@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <array>
 #include <atomic>
+#include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -54,6 +56,9 @@ struct scsf_handle {
   int device = 0;
   int lanes = 4;                         // concurrent chain groups in scsf_solve_sequence
   bool graphs = true;                    // outer iterations of chained solves as HIP graphs
+  // autotuned settings: SpMM columns per thread per (k bucket, n bucket), block width per L
+  int32_t cpt[4][3] = {{4, 4, 4}, {4, 4, 4}, {4, 4, 4}, {4, 4, 4}};
+  std::vector<std::pair<int32_t, int32_t>> widths;
   std::vector<Workspace *> ws;           // ws[0] runs on the caller's stream; ws[1..] are the
                                          // lanes of chained solves (private streams)
 };
@@ -198,6 +203,7 @@ struct Engine {
   int32_t *lock = nullptr, *nconv = nullptr, *done = nullptr, *flag = nullptr, *need = nullptr;
   OpDev *ops = nullptr;
   int32_t *rows = nullptr, *h_rows = nullptr;   // per-problem row count (uneven batches)
+  int cpt = 4;                                  // SpMM columns per thread (autotuned tile)
   // pinned host mirrors
   int32_t *h_lock = nullptr, *h_nconv = nullptr, *h_done = nullptr, *h_flag = nullptr;
   int32_t *h_need = nullptr, *h_perm = nullptr;
@@ -423,7 +429,7 @@ struct Engine {
   // Rayleigh-Ritz on the orthonormal active columns of Yf; Ritz vectors land in X, A X in W
   int rayleigh_ritz(double *Yf) {
     HIPCHK(spmm_step(ops, B, kind, n, 0, Yf, nullptr, W, ld, bs, COLS_ACTIVE, k, lock, unit, false,
-                     st));
+                     st, nullptr, 0, cpt));
     HIPCHK(gemm_tn(B, n, ld, Yf, bs, COLS_ACTIVE, W, bs, COLS_ACTIVE, k, lock, true, part,
                    part_stride, G, ldm, nullptr, 0, st, rows));
     HIPCHK(jacobi_eig(B, k, lock, G, M, ldm, theta, flag, jac, rec, ranks, nsweeps, st));
@@ -476,7 +482,7 @@ struct Engine {
         const int slot = timed ? prof_begin(h, step_bytes(s > 1, true, s)) : -1;
         HIPCHK(spmm_step32(ops, B, kind, n, E32[s % 3], E32[(s + 2) % 3], E32[(s + 1) % 3], ld, bs,
                            COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 1, R32,
-                           src + (size_t)s * B * k, st, md, s));
+                           src + (size_t)s * B * k, st, md, s, cpt));
         prof_end(h, slot);
       }
       HIPCHK(mp_final(B, n, ld, bs, k, lock, X, E32[M % 3], gain, Y1, st));
@@ -486,7 +492,7 @@ struct Engine {
         const int slot = timed ? prof_begin(h, step_bytes(s > 0, false, s)) : -1;
         HIPCHK(spmm_step(ops, B, kind, n, 0, ring[s % 3], ring[(s + 2) % 3], ring[(s + 1) % 3],
                          ld, bs, COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 0, st, md,
-                         s));
+                         s, cpt));
         prof_end(h, slot);
       }
     }
@@ -581,7 +587,7 @@ struct Engine {
     }
     if (mixed && w_stale) {           // A X of newly loaded operators (residual form)
       HIPCHK(spmm_step(ops, B, kind, n, 0, X, nullptr, W, ld, bs, COLS_ACTIVE, k, lock, unit,
-                       false, st));
+                       false, st, nullptr, 0, cpt));
       w_stale = false;
     }
     if (!use_graph) {
@@ -686,7 +692,7 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
                int32_t n_op, const std::vector<int> &cb, const std::vector<int> &ce,
                std::atomic<int> *next, const scsf_params *prm, const double *hints_host,
                double *evals, double *evecs, double *ritz, scsf_stats *stats_host,
-               const Group *grp = nullptr, bool graphs = false) {
+               const Group *grp = nullptr, bool graphs = false, int cpt = 4) {
   const int chains = (int)cb.size();
   if (chains == 0) return SCSF_OK;
   const int64_t n = grp ? grp->nmax : ops_host[0].n;
@@ -700,6 +706,7 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
   STCHK(e.setup(w, chains, n, k, L, m, kind, prm->tol, prm->seed, lzs,
                 prm->precision == SCSF_MIXED, hints_host != nullptr));
   e.use_graph = graphs && w->own_stream;     // capture needs a stream of our own
+  e.cpt = cpt;
   std::vector<int> pos(chains), iters(chains, 0);
   std::vector<int64_t> fcols(chains, 0);
   std::vector<char> active(chains, 1);
@@ -853,6 +860,25 @@ void free_workspace(Workspace *w) {
   if (w->pinned) (void)hipHostFree(w->pinned);
   if (w->own_stream) (void)hipStreamDestroy(w->stream);
   delete w;
+}
+
+// Default block width for L wanted pairs: the smallest multiple of 8 with at least 20% guard
+// vectors (Section 4 sizes the inherited subspace as a fraction of L).
+static int32_t default_width(int32_t L) {
+  const int32_t g = (L + 4) / 5;                       // ceil(0.2 L)
+  return std::min<int32_t>(kMaxK, (int32_t)round_up(L + std::max(g, 1), 8));
+}
+
+// Autotuned settings held by the handle.
+static int kbucket(int32_t k) { return k <= 48 ? 0 : k <= 96 ? 1 : k <= 160 ? 2 : 3; }
+static int nbucket(int64_t n) { return n <= 4096 ? 0 : n <= 16384 ? 1 : 2; }
+static int tuned_cpt(const scsf_handle *h, int64_t n, int32_t k) {
+  return h->cpt[kbucket(k)][nbucket(n)];
+}
+static int32_t tuned_width(const scsf_handle *h, int32_t L) {
+  for (const auto &p : h->widths)
+    if (p.first == L) return p.second;
+  return default_width(L);
 }
 
 }  // namespace
@@ -1225,7 +1251,7 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
     }
     status[g] = run_chains(h->ws[g + 1], ops_host, order_host, n_op, cb, ce,
                            dyn ? &next : nullptr, prm, hints_host, evals, evecs, ritz, stats_host,
-                           nullptr, h->graphs);
+                           nullptr, h->graphs, tuned_cpt(h, n, prm->k));
   };
   std::vector<std::thread> threads;
   for (int g = 1; g < lanes; ++g) threads.emplace_back(lane_fn, g);
@@ -1242,13 +1268,6 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
 }
 
 // ------------------------------------------------------------ uneven batches (mixed sizes)
-// Default block width for L wanted pairs: the smallest multiple of 8 with at least 20% guard
-// vectors (Section 4 sizes the inherited subspace as a fraction of L).
-static int32_t default_width(int32_t L) {
-  const int32_t g = (L + 4) / 5;                       // ceil(0.2 L)
-  return std::min<int32_t>(kMaxK, (int32_t)round_up(L + std::max(g, 1), 8));
-}
-
 int scsf_block_width(int32_t L) {
   if (L <= 0 || L >= kMaxK) return SCSF_EINVAL;
   return default_width(L);
@@ -1266,7 +1285,7 @@ int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_
   for (int i = 0; i < n_op; ++i) {
     STCHK(check_op(&ops_host[i]));
     if (L_host[i] <= 0 || L_host[i] >= kMaxK) return SCSF_EINVAL;
-    kk[i] = k_host ? k_host[i] : default_width(L_host[i]);
+    kk[i] = k_host ? k_host[i] : tuned_width(h, L_host[i]);
     scsf_params p = *prm;
     p.L = L_host[i];
     p.k = kk[i];
@@ -1349,7 +1368,7 @@ int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_
       grp.voff = voff.data();
       const int s2 = run_chains(h->ws[l + 1], ops_host, g.order.data(), nord, cb, ce,
                                 dyn ? &next[gi] : nullptr, prm, nullptr, evals, evecs, nullptr,
-                                stats_host, &grp, h->graphs);
+                                stats_host, &grp, h->graphs, tuned_cpt(h, g.nmax, g.k));
       if (s2 != SCSF_OK && (status[l] == SCSF_OK ||
                             (status[l] == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)))
         status[l] = s2;
@@ -1368,6 +1387,185 @@ int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_
     if (worst == SCSF_OK || (worst == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)) worst = s2;
   }
   return worst;
+}
+
+// ---- autotuner
+// SpMM tile: time the filter step on B copies of a representative operator for each
+// columns-per-thread choice and keep the fastest.
+static int tune_tile(Workspace *w, const scsf_operator &rep, int32_t k, int32_t *best) {
+  constexpr int B = 8, reps = 10;
+  Engine e;
+  STCHK(e.setup(w, B, rep.n, k, 1, 1, rep.kind, 1.0, 7, 20));
+  for (int b = 0; b < B; ++b) e.h_ops[b] = to_dev(rep);
+  STCHK(e.upload_ops());
+  HIPCHK(gaussian_fill(B, rep.n, e.ld, e.bs, k, e.X, 0x7A11ULL, e.st));
+  HIPCHK(gaussian_fill(B, rep.n, e.ld, e.bs, k, e.Y2, 0x7A12ULL, e.st));
+  hipEvent_t t0, t1;
+  HIPCHK(hipEventCreate(&t0));
+  if (hipEventCreate(&t1) != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return SCSF_EHIP;
+  }
+  float best_ms = 1e30f;
+  int rc = SCSF_OK;
+  *best = 4;
+  for (int c : {2, 4, 8}) {
+    auto step = [&] {
+      return spmm_step(e.ops, B, e.kind, e.n, 0, e.X, e.Y2, e.Y1, e.ld, e.bs, COLS_ALL, k,
+                       nullptr, e.unit, true, e.st, nullptr, 0, c);
+    };
+    if (step() != hipSuccess) { rc = SCSF_EHIP; break; }
+    if (hipEventRecord(t0, e.st) != hipSuccess) { rc = SCSF_EHIP; break; }
+    for (int r = 0; r < reps; ++r)
+      if (step() != hipSuccess) rc = SCSF_EHIP;
+    if (rc != SCSF_OK || hipEventRecord(t1, e.st) != hipSuccess ||
+        hipEventSynchronize(t1) != hipSuccess) { rc = SCSF_EHIP; break; }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t0, t1) != hipSuccess) { rc = SCSF_EHIP; break; }
+    if (ms < best_ms) { best_ms = ms; *best = c; }
+  }
+  (void)hipStreamSynchronize(e.st);
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  return rc;
+}
+
+// Block width for L: a warm-started probe chain over the group's first operators for each
+// candidate width; the width with the least time per eigenpair wins.
+static int tune_width(scsf_handle *h, Workspace *w, const scsf_operator *ops_host, int32_t n_op,
+                      const std::vector<int32_t> &probe, int32_t L, const scsf_params *prm,
+                      int32_t *best) {
+  int64_t nmin = INT64_MAX, nmax = 0, ne = 0, nv = 0;
+  std::vector<int64_t> eoff(n_op, 0), voff(n_op, 0);
+  for (int o : probe) {
+    nmin = std::min<int64_t>(nmin, ops_host[o].n);
+    nmax = std::max<int64_t>(nmax, ops_host[o].n);
+    eoff[o] = ne;
+    voff[o] = nv;
+    ne += L;
+    nv += ops_host[o].n * L;
+  }
+  std::vector<int32_t> cand;
+  for (double f : {1.2, 1.35, 1.5}) {
+    const int32_t kc = (int32_t)round_up((int64_t)std::ceil(f * L), 8);
+    if (kc > L && kc <= kMaxK && kc <= nmin &&
+        std::find(cand.begin(), cand.end(), kc) == cand.end())
+      cand.push_back(kc);
+  }
+  *best = default_width(L);
+  if (cand.empty()) return SCSF_OK;
+  double *ev = nullptr, *vv = nullptr;
+  if (hipMalloc(&ev, (size_t)ne * 8) != hipSuccess) return SCSF_ENOMEM;
+  if (hipMalloc(&vv, (size_t)nv * 8) != hipSuccess) {
+    (void)hipFree(ev);
+    return SCSF_ENOMEM;
+  }
+  double best_t = 1e300;
+  int rc = SCSF_OK;
+  for (int32_t kc : cand) {
+    scsf_params p = *prm;
+    p.L = L;
+    p.k = kc;
+    Group grp;
+    grp.L = L;
+    grp.k = kc;
+    grp.nmax = nmax;
+    grp.eoff = eoff.data();
+    grp.voff = voff.data();
+    std::vector<int> cb{0}, ce{(int)probe.size()};
+    const auto t0 = std::chrono::steady_clock::now();
+    const int s2 = run_chains(w, ops_host, probe.data(), (int32_t)probe.size(), cb, ce, nullptr,
+                              &p, nullptr, ev, vv, nullptr, nullptr, &grp, h->graphs,
+                              tuned_cpt(h, nmax, kc));
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (s2 == SCSF_ENOTCONV) continue;             // a width that cannot converge never wins
+    if (s2 != SCSF_OK) { rc = s2; break; }
+    if (dt < best_t) { best_t = dt; *best = kc; }
+  }
+  (void)hipFree(ev);
+  (void)hipFree(vv);
+  return rc;
+}
+
+int scsf_autotune(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
+                  const int32_t *L_host, const int32_t *order_host, const scsf_params *prm,
+                  int32_t probe) {
+  if (!h || !ops_host || n_op <= 0 || !L_host || !order_host || !prm || probe < 1 || probe > 64)
+    return SCSF_EINVAL;
+  if (prm->precision != SCSF_FP64) return SCSF_EINVAL;
+  for (int i = 0; i < n_op; ++i) {
+    STCHK(check_op(&ops_host[i]));
+    if (L_host[i] <= 0 || L_host[i] >= kMaxK) return SCSF_EINVAL;
+    scsf_params p = *prm;
+    p.L = L_host[i];
+    p.k = std::min<int64_t>(default_width(L_host[i]), ops_host[i].n);
+    if (p.k <= p.L) return SCSF_EINVAL;
+    STCHK(check_params(&p, ops_host[i].n));
+  }
+  {
+    std::vector<char> seen(n_op, 0);
+    for (int i = 0; i < n_op; ++i) {
+      const int o = order_host[i];
+      if (o < 0 || o >= n_op || seen[o]) return SCSF_EINVAL;
+      seen[o] = 1;
+    }
+  }
+  STCHK(add_lanes(h, 2));
+  Workspace *w = h->ws[1];
+  HIPCHK(hipStreamSynchronize(h->ws[0]->stream));
+  bool tuned[4][3] = {};
+  std::vector<int32_t> Ls;
+  for (int i = 0; i < n_op; ++i) {
+    const int32_t L = L_host[order_host[i]];
+    if (std::find(Ls.begin(), Ls.end(), L) == Ls.end()) Ls.push_back(L);
+  }
+  for (int32_t L : Ls) {
+    // operators with this L and the kind of the first of them, in the given order
+    std::vector<int32_t> grp;
+    int32_t kind = 0;
+    for (int i = 0; i < n_op; ++i) {
+      const int o = order_host[i];
+      if (L_host[o] != L) continue;
+      if (grp.empty()) kind = ops_host[o].kind;
+      if (ops_host[o].kind == kind) grp.push_back(o);
+    }
+    // tiles for every (width candidate, size bucket) this group meets
+    for (double f : {1.2, 1.35, 1.5}) {
+      const int32_t kc = (int32_t)round_up((int64_t)std::ceil(f * L), 8);
+      if (kc > kMaxK) continue;
+      for (int nb = 0; nb < 3; ++nb) {
+        if (tuned[kbucket(kc)][nb]) continue;
+        int rep = -1;
+        for (int o : grp)
+          if (nbucket(ops_host[o].n) == nb && ops_host[o].n >= kc &&
+              (rep < 0 || ops_host[o].n > ops_host[rep].n))
+            rep = o;
+        if (rep < 0) continue;
+        int32_t c = 4;
+        STCHK(tune_tile(w, ops_host[rep], kc, &c));
+        h->cpt[kbucket(kc)][nb] = c;
+        tuned[kbucket(kc)][nb] = true;
+      }
+    }
+    std::vector<int32_t> pr(grp.begin(), grp.begin() + std::min<size_t>(grp.size(), probe));
+    int32_t kbest = default_width(L);
+    STCHK(tune_width(h, w, ops_host, n_op, pr, L, prm, &kbest));
+    bool found = false;
+    for (auto &p : h->widths)
+      if (p.first == L) { p.second = kbest; found = true; }
+    if (!found) h->widths.emplace_back(L, kbest);
+  }
+  return SCSF_OK;
+}
+
+int scsf_tuned_width(scsf_handle *h, int32_t L) {
+  if (!h || L <= 0 || L >= kMaxK) return SCSF_EINVAL;
+  return tuned_width(h, L);
+}
+
+int scsf_tuned_tile(scsf_handle *h, int64_t n, int32_t k) {
+  if (!h || n <= 0 || k <= 0 || k > kMaxK) return SCSF_EINVAL;
+  return tuned_cpt(h, n, k);
 }
 
 int scsf_interpolate(scsf_handle *h, int32_t N0, int32_t N1, int32_t ncols, const double *X,

@@ -116,17 +116,13 @@ __global__ void __launch_bounds__(256) spmm_step_kernel(
   }
 }
 
-template <typename T, bool SRC>
-static hipError_t launch_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, const T *X,
-                              const T *Z, T *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
-                              const int32_t *lock, const double *coef, bool has_z, const T *R,
-                              const double *src, const int32_t *mdeg, int32_t step,
-                              hipStream_t st) {
-  constexpr int CPT = 4;
-  if (B <= 0 || nmax <= 0 || k <= 0) return hipSuccess;
+template <int CPT, typename T, bool SRC>
+static void launch_kind(const OpDev *ops, int B, int32_t kind, int64_t nmax, const T *X,
+                        const T *Z, T *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
+                        const int32_t *lock, const double *coef, int hz, const T *R,
+                        const double *src, const int32_t *mdeg, int32_t step, hipStream_t st) {
   dim3 block(256);
   dim3 grid((unsigned)ceil_div(nmax, 256), (unsigned)ceil_div(k, CPT), (unsigned)B);
-  const int hz = has_z ? 1 : 0;
   if (kind == SCSF_STENCIL5)
     spmm_step_kernel<SCSF_STENCIL5, CPT, T, SRC><<<grid, block, 0, st>>>(
         ops, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src, mdeg, step);
@@ -136,26 +132,47 @@ static hipError_t launch_step(const OpDev *ops, int B, int32_t kind, int64_t nma
   else
     spmm_step_kernel<SCSF_CSR, CPT, T, SRC><<<grid, block, 0, st>>>(
         ops, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src, mdeg, step);
+}
+
+// cpt: columns per thread (2, 4 or 8), the tile the autotuner chooses per (n, k).
+template <typename T, bool SRC>
+static hipError_t launch_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, const T *X,
+                              const T *Z, T *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
+                              const int32_t *lock, const double *coef, bool has_z, const T *R,
+                              const double *src, const int32_t *mdeg, int32_t step, int cpt,
+                              hipStream_t st) {
+  if (B <= 0 || nmax <= 0 || k <= 0) return hipSuccess;
+  const int hz = has_z ? 1 : 0;
+  if (cpt == 2)
+    launch_kind<2, T, SRC>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src,
+                           mdeg, step, st);
+  else if (cpt == 8)
+    launch_kind<8, T, SRC>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src,
+                           mdeg, step, st);
+  else
+    launch_kind<4, T, SRC>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src,
+                           mdeg, step, st);
   return hipGetLastError();
 }
 
 hipError_t spmm_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t /*Nmax*/,
                      const double *X, const double *Z, double *Y, int64_t ld, int64_t bs,
                      int32_t mode, int32_t k, const int32_t *lock, const double *coef,
-                     bool has_z, hipStream_t st, const int32_t *mdeg, int32_t step) {
+                     bool has_z, hipStream_t st, const int32_t *mdeg, int32_t step, int cpt) {
   return launch_step<double, false>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
-                                    has_z, nullptr, nullptr, mdeg, step, st);
+                                    has_z, nullptr, nullptr, mdeg, step, cpt, st);
 }
 
 hipError_t spmm_step32(const OpDev *ops, int B, int32_t kind, int64_t nmax, const float *X,
                        const float *Z, float *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
                        const int32_t *lock, const double *coef, bool has_z, const float *R,
-                       const double *src, hipStream_t st, const int32_t *mdeg, int32_t step) {
+                       const double *src, hipStream_t st, const int32_t *mdeg, int32_t step,
+                       int cpt) {
   if (R)
     return launch_step<float, true>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
-                                    has_z, R, src, mdeg, step, st);
+                                    has_z, R, src, mdeg, step, cpt, st);
   return launch_step<float, false>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
-                                   has_z, nullptr, nullptr, mdeg, step, st);
+                                   has_z, nullptr, nullptr, mdeg, step, cpt, st);
 }
 
 }  // namespace scsf

@@ -99,6 +99,10 @@ def lib():
         sig["scsf_order_features"] = [vp, vp, i32, i32, i32, POINTER(c_int32)]
         sig["scsf_interpolate"] = [vp, i32, i32, i32, vp, i64, vp, i64]
         sig["scsf_block_width"] = [i32]
+        sig["scsf_autotune"] = [vp, POINTER(Operator), i32, POINTER(c_int32), POINTER(c_int32),
+                                POINTER(Params), i32]
+        sig["scsf_tuned_width"] = [vp, i32]
+        sig["scsf_tuned_tile"] = [vp, i64, i32]
         sig["scsf_solve_batched"] = [vp, POINTER(Operator), i32, POINTER(c_int32),
                                      POINTER(c_int32), POINTER(c_int32), i32, POINTER(Params),
                                      vp, vp, POINTER(Stats)]
@@ -301,6 +305,30 @@ def scsf_block_width(L: int) -> int:
     if k < 0:
         raise ScsfError(k, "scsf_block_width")
     return k
+
+
+def scsf_autotune(h: Handle, ops: list, Ls, order, prm: Params, probe: int = 4):
+    """Tune filter tiles and block widths on this dataset; the handle keeps the results."""
+    n_op = len(ops)
+    arr = (Operator * n_op)(*[o.struct for o in ops])
+    Lc = (c_int32 * n_op)(*[int(x) for x in Ls])
+    ordc = (c_int32 * n_op)(*np.asarray(order, dtype=np.int32).tolist())
+    _check(lib().scsf_autotune(h.ptr, arr, n_op, Lc, ordc, ctypes.byref(prm), int(probe)),
+           "scsf_autotune")
+
+
+def scsf_tuned_width(h: Handle, L: int) -> int:
+    k = int(lib().scsf_tuned_width(h.ptr, int(L)))
+    if k < 0:
+        raise ScsfError(k, "scsf_tuned_width")
+    return k
+
+
+def scsf_tuned_tile(h: Handle, n: int, k: int) -> int:
+    c = int(lib().scsf_tuned_tile(h.ptr, int(n), int(k)))
+    if c < 0:
+        raise ScsfError(c, "scsf_tuned_tile")
+    return c
 
 
 def scsf_solve_batched(h: Handle, ops: list, Ls, order, chains: int, prm: Params, ks=None,

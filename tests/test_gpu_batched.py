@@ -172,3 +172,31 @@ def test_batched_uneven_full_sizes_sampled(h):
         A = O.assemble(ops[i])
         w, V = E.smallest_eigenpairs(A, Ls[i] + 10)
         check_pairs(A, evals[i], evecs[i].t(), Ls[i], cfg.tol, w, V)
+
+
+# ------------------------------------------------------------------------------ autotuner
+def test_autotune_picks_valid_settings_and_solves():
+    say("autotune")
+    h = scsf.Handle()
+    ops, Ls = small_uneven(12, 11)
+    dops = [scsf.DeviceOperator(o) for o in ops]
+    order = family_order(h, ops, 6)
+    prm = scsf.make_params(0, 0, 20, 1e-8, seed=5)
+    before = {L: scsf.scsf_tuned_width(h, L) for L in set(Ls)}
+    assert all(before[L] == scsf.scsf_block_width(L) for L in before)
+    scsf.scsf_autotune(h, dops, Ls, order, prm, probe=3)
+    for L in set(Ls):
+        k = scsf.scsf_tuned_width(h, L)
+        assert k % 8 == 0 and k >= L + int(np.ceil(0.2 * L)) and k <= 256
+        assert k <= min(o.n for o, LL in zip(ops, Ls) if LL == L)
+        say("L", L, "width", k)
+    for n in (900, 5000, 20000):
+        for k in (16, 40, 80, 160, 240):
+            assert scsf.scsf_tuned_tile(h, n, k) in (2, 4, 8)
+    evals, evecs, stats = scsf.scsf_solve_batched(h, dops, Ls, order, 4, prm)
+    for i, o in enumerate(ops):
+        A = O.assemble(o)
+        w, V = E.smallest_eigenpairs(A, Ls[i] + 6, method="dense")
+        check_pairs(A, evals[i], evecs[i].t(), Ls[i], 1e-8, w, V)
+    with pytest.raises(scsf.ScsfError):
+        scsf.scsf_autotune(h, dops, Ls, order, prm, probe=0)

@@ -119,6 +119,8 @@ def main():
     ap.add_argument("--graphs", choices=["on", "off"], default="on",
                     help="replay each outer iteration as HIP graphs (on) or launch its kernels "
                          "one by one (off)")
+    ap.add_argument("--eig", choices=["jacobi", "tridiag"], default="jacobi",
+                    help="Rayleigh-Ritz eigensolver")
     ap.add_argument("--autotune", choices=["on", "off"], default="on",
                     help="tune filter tiles (and, for the uneven workload, block widths) on the "
                          "dataset once before the warmup; the timed steps use the result")
@@ -156,6 +158,8 @@ def main():
     h = scsf.Handle()
     scsf.scsf_set_lanes(h, args.lanes)
     scsf.scsf_set_graphs(h, args.graphs == "on")
+    scsf.scsf_set_eigensolver(h, scsf.SCSF_EIG_TRIDIAG if args.eig == "tridiag"
+                              else scsf.SCSF_EIG_JACOBI)
     dops = [scsf.DeviceOperator(o) for o in ops]
     if uneven:
         # fields grouped by family and side: features per side, one greedy order per family
@@ -312,6 +316,7 @@ def main():
             "lanes": args.lanes,
             "schedule": args.schedule,
             "graphs": args.graphs,
+            "eigensolver": args.eig,
             "autotune_s": tune_s,
             "form": form,
             "block_widths": ({str(L): scsf.scsf_tuned_width(h, L) for L in sorted(set(Ls))}

@@ -53,6 +53,8 @@ enum scsf_precision { SCSF_FP64 = 0, SCSF_MIXED = 1 };
  *   DYNAMIC: every chain takes the next unsolved operator of the sorted order when it
  *            finishes one, warm-starting from the operator it solved last (load balance). */
 enum scsf_schedule { SCSF_SCHED_STATIC = 0, SCSF_SCHED_DYNAMIC = 1 };
+/* Eigensolver of the Rayleigh-Ritz step (scsf_set_eigensolver). */
+enum scsf_eigensolver { SCSF_EIG_JACOBI = 0, SCSF_EIG_TRIDIAG = 1 };
 
 /*
  * A discretised operator (Section 2.1; datasets of App. D.2).  Grid nodes are numbered
@@ -131,6 +133,14 @@ int scsf_set_lanes(scsf_handle *h, int lanes);
  * orthonormalisation, Rayleigh-Ritz, residuals and locking); on == 0 launches the same
  * kernels one by one.  Results are identical either way. */
 int scsf_set_graphs(scsf_handle *h, int on);
+/* The eigensolver of the Rayleigh-Ritz step (the reduced problem G W = W Theta of
+ * Algorithm 3): SCSF_EIG_JACOBI (default: parallel cyclic Jacobi, sweeping until the largest
+ * relative off-diagonal entry is at most tol / 100, within [1e-14, 1e-10]; the warm-started
+ * projected matrices are nearly diagonal, so one or two sweeps usually suffice) or
+ * SCSF_EIG_TRIDIAG (Householder tridiagonalisation, Sturm bisection and inverse iteration: a
+ * fixed amount of work).  Both return the eigenvalues ascending with orthonormal
+ * eigenvectors. */
+int scsf_set_eigensolver(scsf_handle *h, int which);
 /* Turn filter-step timing on (on != 0) or off; synchronises the stream. */
 int scsf_profile_enable(scsf_handle *h, int on);
 /* Copy the accumulated filter timing to *out_host; reset != 0 clears it afterwards. */

@@ -118,10 +118,22 @@ hipError_t chol_inv(int B, int64_t n, int32_t k, const int32_t *lock, const doub
 // into Z_b (ldm x ldm).  scratch: B * kMaxK * (kMaxK+1) doubles (matrices too large for LDS);
 // rec: B * jacobi_record_elems(k) doubles (recorded rotations); ranks: B * ldm ints;
 // nsweeps: B ints.  flag bit 8: not converged within the sweep limit.
+// stop: the sweeps end once the largest relative off-diagonal entry |g_pq| / sqrt|g_pp g_qq|
+// is at most `stop` (checked before the first sweep and after each one).
 hipError_t jacobi_eig(int B, int32_t k, const int32_t *lock, double *G, double *Z, int32_t ldm,
                       double *theta, int32_t *flag, double *scratch, double *rec,
-                      int32_t *ranks, int32_t *nsweeps, hipStream_t st);
+                      int32_t *ranks, int32_t *nsweeps, hipStream_t st, double stop = 1e-14);
 int64_t jacobi_record_elems(int32_t k);
+
+// The same decomposition without sweeps: Householder tridiagonalisation in LDS, Sturm
+// bisection for the eigenvalues (ascending into theta[b*k + lock[b] + j]) and inverse
+// iteration for the eigenvectors, back-transformed into Z_b (ldm x ldm, column j = the
+// eigenvector of the j-th smallest eigenvalue).  scratch as for jacobi_eig (widths whose packed
+// matrix exceeds LDS); work: B * tridiag_work_elems(k) doubles.  flag bit 2: NaN/Inf.
+hipError_t tridiag_eig(int B, int32_t k, const int32_t *lock, const double *G, double *Z,
+                       int32_t ldm, double *theta, int32_t *flag, double *scratch, double *work,
+                       hipStream_t st);
+int64_t tridiag_work_elems(int32_t k);
 
 // res[b*k + c] = ||W c - theta c X c|| / ||W c|| for the active columns (over rows[b] rows
 // when rows is given).

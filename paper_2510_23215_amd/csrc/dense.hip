@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(512) jacobi_values_kernel(
     int32_t k, const int32_t *__restrict__ lock, const double *__restrict__ Gin, int32_t ldm,
     double *__restrict__ theta, int32_t *__restrict__ rank_out, double *__restrict__ rec,
     int64_t rec_stride, int32_t *__restrict__ nsweeps, int32_t *__restrict__ flag,
-    double *__restrict__ gscr) {
+    double *__restrict__ gscr, double stop) {
   __shared__ double lds[LDS ? kLdsDoubles : 1];
   __shared__ int rp[kMaxK / 2 + 1], rq[kMaxK / 2 + 1];
   __shared__ double rc[kMaxK / 2 + 1], rs[kMaxK / 2 + 1];
@@ -186,8 +186,26 @@ __global__ void __launch_bounds__(512) jacobi_values_kernel(
       S[pk(i, c)] = (i < ka && c < ka) ? Gb[i + (int64_t)c * ldm] : 0.0;  // zero dummy index
   if (tid == 0) { s_any[0] = 0; s_any[1] = 0; }
   __syncthreads();
+  // largest relative off-diagonal entry (all threads get the value)
+  auto max_off = [&]() {
+    double off = 0.0;
+    for (int c = ty; c < ka; c += 32)
+      for (int i = tx; i < c; i += 16) {
+        const double den = sqrt(fabs(S[pk(i, i)] * S[pk(c, c)]));
+        const double v = fabs(S[pk(i, c)]);
+        off = fmax(off, (v > 1e-300) ? v / fmax(den, 1e-300) : 0.0);
+      }
+    for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_down(off, o, 64));
+    if ((tid & 63) == 0) sh[tid >> 6] = off;
+    __syncthreads();
+    double m = sh[0];
+    for (int w = 1; w < NT / 64; ++w) m = fmax(m, sh[w]);
+    __syncthreads();
+    return m;
+  };
   int sweep = 0;
-  for (; sweep < kJacobiMaxSweeps; ++sweep) {
+  bool converged = !(max_off() > stop);              // already diagonal to the requested level
+  for (; sweep < kJacobiMaxSweeps && !converged; ++sweep) {
     for (int r = 0; r < K - 1; ++r) {
       // two barriers per round: (A) rotations ready, (B) block updates done.  The flag of
       // the next round is reset before (A), after every thread read it before (B) last round.
@@ -245,25 +263,15 @@ __global__ void __launch_bounds__(512) jacobi_values_kernel(
       }
       __syncthreads();                                   // (B)
     }
-    // largest relative off-diagonal entry after this sweep
-    double off = 0.0;
-    for (int c = ty; c < ka; c += 32)
-      for (int i = tx; i < c; i += 16) {
-        const double den = sqrt(fabs(S[pk(i, i)] * S[pk(c, c)]));
-        const double v = fabs(S[pk(i, c)]);
-        off = fmax(off, (v > 1e-300) ? v / fmax(den, 1e-300) : 0.0);
-      }
-    for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_down(off, o, 64));
-    if ((tid & 63) == 0) sh[tid >> 6] = off;
-    __syncthreads();
-    double m = sh[0];
-    for (int w = 1; w < NT / 64; ++w) m = fmax(m, sh[w]);
-    __syncthreads();
-    if (!(m > 10.0 * kJacobiTol)) { ++sweep; break; }
+    if (!(max_off() > stop)) {
+      converged = true;
+      ++sweep;
+      break;
+    }
   }
   if (tid == 0) {
     nsweeps[b] = sweep;
-    if (sweep >= kJacobiMaxSweeps) atomicOr(&flag[b], 8);
+    if (!converged) atomicOr(&flag[b], 8);
   }
   // ascending order: rank_j = #{i : theta_i < theta_j or (== and i < j)}
   for (int j = tid; j < ka; j += NT) {
@@ -341,16 +349,16 @@ __global__ void __launch_bounds__(512) jacobi_vectors_kernel(
 
 hipError_t jacobi_eig(int B, int32_t k, const int32_t *lock, double *G, double *Z, int32_t ldm,
                       double *theta, int32_t *flag, double *scratch, double *rec,
-                      int32_t *ranks, int32_t *nsweeps, hipStream_t st) {
+                      int32_t *ranks, int32_t *nsweeps, hipStream_t st, double stop) {
   if (B <= 0) return hipSuccess;
   const int64_t rs = jacobi_record_elems(k);
   const int K = k + (k & 1);
   if ((int64_t)K * (K + 1) / 2 <= kLdsDoubles)
     jacobi_values_kernel<true><<<B, 512, 0, st>>>(k, lock, G, ldm, theta, ranks, rec, rs, nsweeps,
-                                                  flag, scratch);
+                                                  flag, scratch, stop);
   else
     jacobi_values_kernel<false><<<B, 512, 0, st>>>(k, lock, G, ldm, theta, ranks, rec, rs,
-                                                   nsweeps, flag, scratch);
+                                                   nsweeps, flag, scratch, stop);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   jacobi_vectors_kernel<<<dim3((unsigned)ceil_div(k, 8), 1, B), 512, 0, st>>>(

@@ -27,7 +27,7 @@ namespace {
 enum BufId {
   B_X, B_Y1, B_Y2, B_W, B_G, B_M, B_PART, B_THETA, B_RES, B_INT, B_BND, B_COEF, B_UNIT, B_CHOL,
   B_JAC, B_LZ, B_OPS, B_WIN, B_SORTF, B_SORTD, B_SORTO, B_REC, B_RANK, B_E32, B_R32, B_SRC,
-  B_GAIN, B_WINB, B_HINT, B_MDEG, B_NETF, B_NETH, B_NETD, B_ROWS, B_COUNT
+  B_GAIN, B_WINB, B_HINT, B_MDEG, B_NETF, B_NETH, B_NETD, B_ROWS, B_EIG, B_COUNT
 };
 
 struct DevBuf {
@@ -56,6 +56,7 @@ struct scsf_handle {
   int device = 0;
   int lanes = 4;                         // concurrent chain groups in scsf_solve_sequence
   bool graphs = true;                    // outer iterations of chained solves as HIP graphs
+  int eig = SCSF_EIG_JACOBI;             // Rayleigh-Ritz eigensolver
   // autotuned settings: SpMM columns per thread per (k bucket, n bucket), block width per L
   int32_t cpt[4][3] = {{4, 4, 4}, {4, 4, 4}, {4, 4, 4}, {4, 4, 4}};
   std::vector<std::pair<int32_t, int32_t>> widths;
@@ -204,6 +205,8 @@ struct Engine {
   OpDev *ops = nullptr;
   int32_t *rows = nullptr, *h_rows = nullptr;   // per-problem row count (uneven batches)
   int cpt = 4;                                  // SpMM columns per thread (autotuned tile)
+  int eig = SCSF_EIG_JACOBI;                    // Rayleigh-Ritz eigensolver
+  double *eigw = nullptr;                       // its work area
   // pinned host mirrors
   int32_t *h_lock = nullptr, *h_nconv = nullptr, *h_done = nullptr, *h_flag = nullptr;
   int32_t *h_need = nullptr, *h_perm = nullptr;
@@ -255,6 +258,7 @@ struct Engine {
     STCHK(grow(h, B_CHOL, (size_t)B * kMaxK * (kMaxK + 1), &chol));
     STCHK(grow(h, B_JAC, (size_t)B * kMaxK * (kMaxK + 1), &jac));
     STCHK(grow(h, B_REC, (size_t)B * jacobi_record_elems(k), &rec));
+    STCHK(grow(h, B_EIG, (size_t)B * tridiag_work_elems(k), &eigw));
     int32_t *rk = nullptr;
     STCHK(grow(h, B_RANK, (size_t)B * ldm + B, &rk));
     ranks = rk;
@@ -427,12 +431,20 @@ struct Engine {
   }
 
   // Rayleigh-Ritz on the orthonormal active columns of Yf; Ritz vectors land in X, A X in W
+  // Jacobi accuracy for the convergence target: an off-diagonal entry delta sqrt|g_pp g_qq|
+  // left in G moves a Ritz vector's relative residual by about delta sqrt(theta_i / theta_j),
+  // so delta = tol / 100 keeps it well below tol (bounded to [1e-14, 1e-10]).
+  double jacobi_stop() const { return std::min(1e-10, std::max(1e-14, 0.01 * tol)); }
   int rayleigh_ritz(double *Yf) {
     HIPCHK(spmm_step(ops, B, kind, n, 0, Yf, nullptr, W, ld, bs, COLS_ACTIVE, k, lock, unit, false,
                      st, nullptr, 0, cpt));
     HIPCHK(gemm_tn(B, n, ld, Yf, bs, COLS_ACTIVE, W, bs, COLS_ACTIVE, k, lock, true, part,
                    part_stride, G, ldm, nullptr, 0, st, rows));
-    HIPCHK(jacobi_eig(B, k, lock, G, M, ldm, theta, flag, jac, rec, ranks, nsweeps, st));
+    if (eig == SCSF_EIG_JACOBI)
+      HIPCHK(jacobi_eig(B, k, lock, G, M, ldm, theta, flag, jac, rec, ranks, nsweeps, st,
+                        jacobi_stop()));
+    else
+      HIPCHK(tridiag_eig(B, k, lock, G, M, ldm, theta, flag, jac, eigw, st));
     HIPCHK(gemm_nn(B, n, ld, Yf, bs, COLS_ACTIVE, X, bs, COLS_ACTIVE, k, lock, M, ldm, 1.0, 0.0,
                    nullptr, 0, nullptr, 0, st, rows));
     HIPCHK(gemm_nn(B, n, ld, W, bs, COLS_ACTIVE, W, bs, COLS_ACTIVE, k, lock, M, ldm, 1.0, 0.0,
@@ -692,7 +704,8 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
                int32_t n_op, const std::vector<int> &cb, const std::vector<int> &ce,
                std::atomic<int> *next, const scsf_params *prm, const double *hints_host,
                double *evals, double *evecs, double *ritz, scsf_stats *stats_host,
-               const Group *grp = nullptr, bool graphs = false, int cpt = 4) {
+               const Group *grp = nullptr, bool graphs = false, int cpt = 4,
+               int eig = SCSF_EIG_JACOBI) {
   const int chains = (int)cb.size();
   if (chains == 0) return SCSF_OK;
   const int64_t n = grp ? grp->nmax : ops_host[0].n;
@@ -707,6 +720,7 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
                 prm->precision == SCSF_MIXED, hints_host != nullptr));
   e.use_graph = graphs && w->own_stream;     // capture needs a stream of our own
   e.cpt = cpt;
+  e.eig = eig;
   std::vector<int> pos(chains), iters(chains, 0);
   std::vector<int64_t> fcols(chains, 0);
   std::vector<char> active(chains, 1);
@@ -935,6 +949,12 @@ int scsf_set_stream(scsf_handle *h, void *hip_stream) {
   return SCSF_OK;
 }
 
+int scsf_set_eigensolver(scsf_handle *h, int which) {
+  if (!h || (which != SCSF_EIG_JACOBI && which != SCSF_EIG_TRIDIAG)) return SCSF_EINVAL;
+  h->eig = which;
+  return SCSF_OK;
+}
+
 int scsf_set_graphs(scsf_handle *h, int on) {
   if (!h) return SCSF_EINVAL;
   h->graphs = on != 0;
@@ -1063,7 +1083,9 @@ int scsf_rayleigh_ritz(scsf_handle *h, const scsf_operator *A, double *X, int64_
   STCHK(check_op(A));
   if (!X || ncols <= 0 || ncols > kMaxK || ncols > A->n || ldx < A->n) return SCSF_EINVAL;
   Engine e;
-  STCHK(e.setup(w0, 1, A->n, ncols, 0, 1, A->kind, 1.0, 0, 20));
+  // no locking here; the tolerance only sets the eigensolver's accuracy (full, 1e-14)
+  STCHK(e.setup(w0, 1, A->n, ncols, 0, 1, A->kind, 1e-12, 0, 20));
+  e.eig = h->eig;
   e.h_ops[0] = to_dev(*A);
   STCHK(e.upload_ops());
   STCHK(e.upload_state());
@@ -1154,6 +1176,7 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
   const int max_iter = prm->max_iter > 0 ? prm->max_iter : 5000;
   const int lzs = prm->lanczos_steps > 0 ? prm->lanczos_steps : 20;
   Engine e;
+  e.eig = h->eig;
   STCHK(e.setup(w0, 1, A->n, prm->k, prm->L, prm->degree, A->kind, prm->tol, prm->seed, lzs,
                 prm->precision == SCSF_MIXED));
   e.h_ops[0] = to_dev(*A);
@@ -1251,7 +1274,7 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
     }
     status[g] = run_chains(h->ws[g + 1], ops_host, order_host, n_op, cb, ce,
                            dyn ? &next : nullptr, prm, hints_host, evals, evecs, ritz, stats_host,
-                           nullptr, h->graphs, tuned_cpt(h, n, prm->k));
+                           nullptr, h->graphs, tuned_cpt(h, n, prm->k), h->eig);
   };
   std::vector<std::thread> threads;
   for (int g = 1; g < lanes; ++g) threads.emplace_back(lane_fn, g);
@@ -1368,7 +1391,7 @@ int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_
       grp.voff = voff.data();
       const int s2 = run_chains(h->ws[l + 1], ops_host, g.order.data(), nord, cb, ce,
                                 dyn ? &next[gi] : nullptr, prm, nullptr, evals, evecs, nullptr,
-                                stats_host, &grp, h->graphs, tuned_cpt(h, g.nmax, g.k));
+                                stats_host, &grp, h->graphs, tuned_cpt(h, g.nmax, g.k), h->eig);
       if (s2 != SCSF_OK && (status[l] == SCSF_OK ||
                             (status[l] == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)))
         status[l] = s2;
@@ -1476,7 +1499,7 @@ static int tune_width(scsf_handle *h, Workspace *w, const scsf_operator *ops_hos
     const auto t0 = std::chrono::steady_clock::now();
     const int s2 = run_chains(w, ops_host, probe.data(), (int32_t)probe.size(), cb, ce, nullptr,
                               &p, nullptr, ev, vv, nullptr, nullptr, &grp, h->graphs,
-                              tuned_cpt(h, nmax, kc));
+                              tuned_cpt(h, nmax, kc), h->eig);
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (s2 == SCSF_ENOTCONV) continue;             // a width that cannot converge never wins
     if (s2 != SCSF_OK) { rc = s2; break; }

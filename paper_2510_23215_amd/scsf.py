@@ -21,6 +21,7 @@ SCSF_EBREAKDOWN, SCSF_EHIP, SCSF_ENUMERIC = -4, -5, -6
 SCSF_STENCIL5, SCSF_STENCIL9, SCSF_CSR = 1, 2, 3
 SCSF_FP64, SCSF_MIXED = 0, 1
 SCSF_SCHED_STATIC, SCSF_SCHED_DYNAMIC = 0, 1
+SCSF_EIG_JACOBI, SCSF_EIG_TRIDIAG = 0, 1
 
 
 class ScsfError(RuntimeError):
@@ -95,6 +96,7 @@ def lib():
         sig["scsf_profile_enable"] = [vp, i32]
         sig["scsf_set_lanes"] = [vp, i32]
         sig["scsf_set_graphs"] = [vp, i32]
+        sig["scsf_set_eigensolver"] = [vp, i32]
         sig["scsf_profile_read"] = [vp, POINTER(Profile), i32]
         sig["scsf_order_features"] = [vp, vp, i32, i32, i32, POINTER(c_int32)]
         sig["scsf_interpolate"] = [vp, i32, i32, i32, vp, i64, vp, i64]
@@ -424,6 +426,10 @@ def scsf_set_lanes(h: Handle, lanes: int):
 
 def scsf_set_graphs(h: Handle, on: bool = True):
     _check(lib().scsf_set_graphs(h.ptr, 1 if on else 0), "scsf_set_graphs")
+
+
+def scsf_set_eigensolver(h: Handle, which: int):
+    _check(lib().scsf_set_eigensolver(h.ptr, int(which)), "scsf_set_eigensolver")
 
 
 def scsf_profile_enable(h: Handle, on: bool = True):

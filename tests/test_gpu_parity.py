@@ -131,10 +131,25 @@ def test_orthonormalize_rank_deficient_uses_shift_or_reports(h):
 
 
 # ------------------------------------------------------------------------------ Rayleigh-Ritz
-@pytest.mark.parametrize("name,k", [("divk32", 24), ("divk37_ragged", 45), ("aniso24", 33)])
-def test_rayleigh_ritz_matches_oracle(h, name, k):
+@pytest.fixture(params=[scsf.SCSF_EIG_TRIDIAG, scsf.SCSF_EIG_JACOBI], ids=["tridiag", "jacobi"])
+def he(request):
+    """A handle per Rayleigh-Ritz eigensolver."""
+    hh = scsf.Handle()
+    scsf.scsf_set_eigensolver(hh, request.param)
+    return hh
+
+
+OPS_RR = dict(OPS5, divk100=lambda: si.divk_operator(100, 8, 9),
+              potential128=lambda: si.potential_operator(128, 8, 4))
+
+
+@pytest.mark.parametrize("name,k", [("divk32", 24), ("divk37_ragged", 45), ("aniso24", 33),
+                                    ("divk100", 160), ("potential128", 195),
+                                    ("potential128", 240)])
+def test_rayleigh_ritz_matches_oracle(he, name, k):
+    h = he
     say("rr", name, k)
-    op = OPS5[name]()
+    op = OPS_RR[name]()
     A = O.assemble(op)
     rng = np.random.default_rng(3)
     Q = np.linalg.qr(rng.standard_normal((A.shape[0], k)))[0]
@@ -148,9 +163,30 @@ def test_rayleigh_ritz_matches_oracle(h, name, k):
     for a, b in E.clusters(w, 1e-6):
         s = E.subspace_sines(ref[:, a:b], Xr[:, a:b])
         assert s.max() < 1e-9, (a, b, s.max())
+    assert np.max(np.abs(Xr.T @ Xr - np.eye(k))) < 1e-13
     W = A @ Xr
     rr = np.linalg.norm(W - Xr * host(th), axis=0) / np.linalg.norm(W, axis=0)
     np.testing.assert_allclose(host(res), rr, rtol=1e-8, atol=1e-14)
+
+
+def test_rayleigh_ritz_degenerate_clusters(he):
+    """Exact eigenvectors of the Dirichlet Laplacian (doubly degenerate eigenvalues), mixed by a
+    random rotation: the projected matrix has exactly repeated eigenvalues."""
+    h = he
+    say("rr degenerate")
+    op = si.laplace_operator(12)
+    A = O.assemble(op).toarray()
+    w, V = np.linalg.eigh(A)
+    k = 40
+    R = np.linalg.qr(np.random.default_rng(5).standard_normal((k, k)))[0]
+    Xd = to_dev(V[:, :k] @ R)
+    th, res = scsf.scsf_rayleigh_ritz(h, scsf.DeviceOperator(op), Xd)
+    np.testing.assert_allclose(host(th), w[:k], rtol=1e-12)
+    Xr = host(Xd)
+    assert np.max(np.abs(Xr.T @ Xr - np.eye(k))) < 1e-13
+    assert host(res).max() < 1e-12
+    for a, b in E.clusters(w[:k], 1e-6):
+        assert E.subspace_sines(V[:, a:b], Xr[:, a:b]).max() < 1e-10
 
 
 # ------------------------------------------------------------------------------ bounds

@@ -48,19 +48,24 @@ __host__ __device__ inline void col_range(int32_t mode, int32_t k, const int32_t
 // Y[:, c] = a*(A X[:, c]) + bcoef*X[:, c] + g*Z[:, c] for the columns selected by (mode, k,
 // lock), per problem coefficients coef[3*b + {0,1,2}] (device).  Z may be null when g == 0
 // for every problem (flag has_z = false).  Blocks of problem b start at base + b*bs.
+// Nmax: the largest grid side of the stencil problems in the batch (sizes the LDS staging;
+// 0 for CSR).  tile: 1, 2 or 4 columns per thread of the LDS-staged form (autotuned).
+// pot: some 5-point problem of the batch may carry a potential (op.v); false selects the form
+// without the per-node check and is only valid when no problem ever has one.
 hipError_t spmm_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t Nmax,
                      const double *X, const double *Z, double *Y, int64_t ld, int64_t bs,
                      int32_t mode, int32_t k, const int32_t *lock, const double *coef,
                      bool has_z, hipStream_t st, const int32_t *mdeg = nullptr,
-                     int32_t step = 0, int cpt = 4);
+                     int32_t step = 0, int tile = 2, bool pot = true);
 
 // FP32 variant of the step for the mixed-precision filter; with R non-null the step adds the
 // per-column source term src[b*k + c] * R[:, c] (R in the same layout as X).
-hipError_t spmm_step32(const OpDev *ops, int B, int32_t kind, int64_t nmax, const float *X,
-                       const float *Z, float *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
-                       const int32_t *lock, const double *coef, bool has_z, const float *R,
-                       const double *src, hipStream_t st, const int32_t *mdeg = nullptr,
-                       int32_t step = 0, int cpt = 4);
+hipError_t spmm_step32(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t Nmax,
+                       const float *X, const float *Z, float *Y, int64_t ld, int64_t bs,
+                       int32_t mode, int32_t k, const int32_t *lock, const double *coef,
+                       bool has_z, const float *R, const double *src, hipStream_t st,
+                       const int32_t *mdeg = nullptr, int32_t step = 0, int tile = 2,
+                       bool pot = true);
 
 // Mixed-precision filter helpers (residual form of the recurrence, see misc.hip):
 //  mp_tables : src[(i*B + b)*k + c] = (2 sigma_{i+1}/e) p_i(theta_c) for steps i = 1..m-1 and

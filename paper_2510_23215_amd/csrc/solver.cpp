@@ -58,7 +58,7 @@ struct scsf_handle {
   bool graphs = true;                    // outer iterations of chained solves as HIP graphs
   int eig = SCSF_EIG_JACOBI;             // Rayleigh-Ritz eigensolver
   // autotuned settings: SpMM columns per thread per (k bucket, n bucket), block width per L
-  int32_t cpt[4][3] = {{4, 4, 4}, {4, 4, 4}, {4, 4, 4}, {4, 4, 4}};
+  int32_t cpt[4][3] = {{2, 2, 2}, {2, 2, 2}, {2, 2, 2}, {2, 2, 2}};
   std::vector<std::pair<int32_t, int32_t>> widths;
   std::vector<Workspace *> ws;           // ws[0] runs on the caller's stream; ws[1..] are the
                                          // lanes of chained solves (private streams)
@@ -204,7 +204,9 @@ struct Engine {
   int32_t *lock = nullptr, *nconv = nullptr, *done = nullptr, *flag = nullptr, *need = nullptr;
   OpDev *ops = nullptr;
   int32_t *rows = nullptr, *h_rows = nullptr;   // per-problem row count (uneven batches)
-  int cpt = 4;                                  // SpMM columns per thread (autotuned tile)
+  int cpt = 2;                                  // filter-step tile (autotuned)
+  int32_t Nmax = 0;                             // largest grid side the engine is sized for
+  bool pot = true;                              // some operator it runs may have a potential
   int eig = SCSF_EIG_JACOBI;                    // Rayleigh-Ritz eigensolver
   double *eigw = nullptr;                       // its work area
   // pinned host mirrors
@@ -233,6 +235,11 @@ struct Engine {
     lz_steps = lz_steps_;
     ld = round_up(n, 64);
     bs = ld * k;
+    Nmax = 0;
+    if (kind != SCSF_CSR) {               // square grids: side = sqrt(n), fixed for the engine
+      Nmax = (int32_t)std::llround(std::sqrt((double)n));
+      while ((int64_t)Nmax * Nmax < n) ++Nmax;
+    }
     ldm = (int32_t)round_up(k, 32);
     part_stride = gemm_tn_partial_elems(n, ldm);
     const size_t blk = (size_t)B * bs;
@@ -436,8 +443,8 @@ struct Engine {
   // so delta = tol / 100 keeps it well below tol (bounded to [1e-14, 1e-10]).
   double jacobi_stop() const { return std::min(1e-10, std::max(1e-14, 0.01 * tol)); }
   int rayleigh_ritz(double *Yf) {
-    HIPCHK(spmm_step(ops, B, kind, n, 0, Yf, nullptr, W, ld, bs, COLS_ACTIVE, k, lock, unit, false,
-                     st, nullptr, 0, cpt));
+    HIPCHK(spmm_step(ops, B, kind, n, Nmax, Yf, nullptr, W, ld, bs, COLS_ACTIVE, k, lock, unit, false,
+                     st, nullptr, 0, cpt, pot));
     HIPCHK(gemm_tn(B, n, ld, Yf, bs, COLS_ACTIVE, W, bs, COLS_ACTIVE, k, lock, true, part,
                    part_stride, G, ldm, nullptr, 0, st, rows));
     if (eig == SCSF_EIG_JACOBI)
@@ -492,9 +499,9 @@ struct Engine {
       HIPCHK(mp_prep(B, n, ld, bs, k, lock, X, W, theta, coef, R32, E32[1], st));
       for (int s = 1; s < M; ++s) {
         const int slot = timed ? prof_begin(h, step_bytes(s > 1, true, s)) : -1;
-        HIPCHK(spmm_step32(ops, B, kind, n, E32[s % 3], E32[(s + 2) % 3], E32[(s + 1) % 3], ld, bs,
+        HIPCHK(spmm_step32(ops, B, kind, n, Nmax, E32[s % 3], E32[(s + 2) % 3], E32[(s + 1) % 3], ld, bs,
                            COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 1, R32,
-                           src + (size_t)s * B * k, st, md, s, cpt));
+                           src + (size_t)s * B * k, st, md, s, cpt, pot));
         prof_end(h, slot);
       }
       HIPCHK(mp_final(B, n, ld, bs, k, lock, X, E32[M % 3], gain, Y1, st));
@@ -502,9 +509,9 @@ struct Engine {
       double *ring[3] = {X, Y1, Y2};
       for (int s = 0; s < M; ++s) {
         const int slot = timed ? prof_begin(h, step_bytes(s > 0, false, s)) : -1;
-        HIPCHK(spmm_step(ops, B, kind, n, 0, ring[s % 3], ring[(s + 2) % 3], ring[(s + 1) % 3],
+        HIPCHK(spmm_step(ops, B, kind, n, Nmax, ring[s % 3], ring[(s + 2) % 3], ring[(s + 1) % 3],
                          ld, bs, COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 0, st, md,
-                         s, cpt));
+                         s, cpt, pot));
         prof_end(h, slot);
       }
     }
@@ -598,8 +605,8 @@ struct Engine {
       M = mcur;
     }
     if (mixed && w_stale) {           // A X of newly loaded operators (residual form)
-      HIPCHK(spmm_step(ops, B, kind, n, 0, X, nullptr, W, ld, bs, COLS_ACTIVE, k, lock, unit,
-                       false, st, nullptr, 0, cpt));
+      HIPCHK(spmm_step(ops, B, kind, n, Nmax, X, nullptr, W, ld, bs, COLS_ACTIVE, k, lock, unit,
+                       false, st, nullptr, 0, cpt, pot));
       w_stale = false;
     }
     if (!use_graph) {
@@ -721,6 +728,8 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
   e.use_graph = graphs && w->own_stream;     // capture needs a stream of our own
   e.cpt = cpt;
   e.eig = eig;
+  e.pot = false;                             // fixed for the engine: graphs keep the choice
+  for (int i = 0; i < n_op; ++i) e.pot = e.pot || ops_host[order_host[i]].v != nullptr;
   std::vector<int> pos(chains), iters(chains, 0);
   std::vector<int64_t> fcols(chains, 0);
   std::vector<char> active(chains, 1);
@@ -1011,7 +1020,7 @@ int scsf_spmm(scsf_handle *h, const scsf_operator *A, const double *X, int64_t l
     HIPCHK(copy_block(A->n, ncols, X, ldx, tmp, ldy, false, w0->stream));
     src = tmp;
   }
-  HIPCHK(spmm_step(e.ops, 1, A->kind, A->n, 0, src, nullptr, Y, ldy, 0, COLS_ALL, ncols, nullptr,
+  HIPCHK(spmm_step(e.ops, 1, A->kind, A->n, e.Nmax, src, nullptr, Y, ldy, 0, COLS_ALL, ncols, nullptr,
                    e.unit, false, w0->stream));
   HIPCHK(hipStreamSynchronize(w0->stream));
   return SCSF_OK;
@@ -1041,7 +1050,7 @@ int scsf_filter(scsf_handle *h, const scsf_operator *A, const double *X, int64_t
   HIPCHK(copy_block(A->n, ncols, X, ldx, en.X, en.ld, true, w0->stream));
   double *ring[3] = {en.X, en.Y1, en.Y2};
   for (int s = 0; s < degree; ++s)
-    HIPCHK(spmm_step(en.ops, 1, A->kind, A->n, 0, ring[s % 3], ring[(s + 2) % 3],
+    HIPCHK(spmm_step(en.ops, 1, A->kind, A->n, en.Nmax, ring[s % 3], ring[(s + 2) % 3],
                      ring[(s + 1) % 3], en.ld, en.bs, COLS_ALL, ncols, nullptr,
                      en.coef + (size_t)s * 3, s > 0, w0->stream));
   HIPCHK(copy_block(A->n, ncols, ring[degree % 3], en.ld, Y, ldy, false, w0->stream));
@@ -1416,7 +1425,10 @@ int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_
 // SpMM tile: time the filter step on B copies of a representative operator for each
 // columns-per-thread choice and keep the fastest.
 static int tune_tile(Workspace *w, const scsf_operator &rep, int32_t k, int32_t *best) {
-  constexpr int B = 8, reps = 10;
+  constexpr int reps = 10;
+  // enough copies for a working set of about 768 MB (the 256 MB MALL must not hold it)
+  const double blk = 3.0 * 8.0 * (double)round_up(rep.n, 64) * k;
+  const int B = (int)std::min<double>(64.0, std::max(8.0, std::ceil(768e6 / blk)));
   Engine e;
   STCHK(e.setup(w, B, rep.n, k, 1, 1, rep.kind, 1.0, 7, 20));
   for (int b = 0; b < B; ++b) e.h_ops[b] = to_dev(rep);
@@ -1431,11 +1443,11 @@ static int tune_tile(Workspace *w, const scsf_operator &rep, int32_t k, int32_t 
   }
   float best_ms = 1e30f;
   int rc = SCSF_OK;
-  *best = 4;
-  for (int c : {2, 4, 8}) {
+  *best = 2;
+  for (int c : {1, 2, 4}) {
     auto step = [&] {
-      return spmm_step(e.ops, B, e.kind, e.n, 0, e.X, e.Y2, e.Y1, e.ld, e.bs, COLS_ALL, k,
-                       nullptr, e.unit, true, e.st, nullptr, 0, c);
+      return spmm_step(e.ops, B, e.kind, e.n, e.Nmax, e.X, e.Y2, e.Y1, e.ld, e.bs, COLS_ALL, k,
+                       nullptr, e.unit, true, e.st, nullptr, 0, c, rep.v != nullptr);
     };
     if (step() != hipSuccess) { rc = SCSF_EHIP; break; }
     if (hipEventRecord(t0, e.st) != hipSuccess) { rc = SCSF_EHIP; break; }

@@ -22,14 +22,23 @@ __global__ void __launch_bounds__(256) spmm_step_kernel(
     const int32_t *__restrict__ lock, const double *__restrict__ coef, int has_z,
     const T *__restrict__ R, const double *__restrict__ src, const int32_t *__restrict__ mdeg,
     int32_t step) {
-  const int b = blockIdx.z;
+  // XCD-aware order: the hardware deals workgroups to the 8 XCDs round-robin by linear id, and
+  // each XCD has its own L2.  Remapping the linear id gives every XCD one contiguous range of
+  // row tiles (of one problem and column group), so the +-N neighbour rows a tile reads were
+  // just fetched by its neighbour tile on the same XCD.
+  const uint32_t gx = gridDim.x, gy = gridDim.y, total = gx * gy * gridDim.z;
+  uint32_t lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const uint32_t per = total / 8;
+  if (lin < 8 * per) lin = (lin % 8) * per + lin / 8;
+  const uint32_t tile = lin % gx, rest = lin / gx;
+  const int b = (int)(rest / gy);
   if (mdeg && step >= mdeg[b]) return;                // this problem's filter has finished
   const OpDev op = ops[b];
   const int64_t n = op.n;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t p = (int64_t)tile * blockDim.x + threadIdx.x;
   int32_t c0, cnt;
   col_range(mode, k, lock, b, c0, cnt);
-  const int j0 = blockIdx.y * CPT;
+  const int j0 = (int)(rest % gy) * CPT;
   if (p >= n || j0 >= cnt) return;
   const T a = (T)coef[3 * b + 0], bc = (T)coef[3 * b + 1], g = (T)coef[3 * b + 2];
   const int64_t off = (int64_t)b * bs + (int64_t)(c0 + j0) * ld;
@@ -116,11 +125,143 @@ __global__ void __launch_bounds__(256) spmm_step_kernel(
   }
 }
 
+// LDS-staged step for the grid stencils: a workgroup takes TILE = 256 NPT consecutive nodes and
+// CPT columns.  It stages each column's nodes [p0 - H, p0 + TILE + H) (H = N, or N + 1 for the
+// 9-point stencil) into LDS with coalesced loads, then every thread computes NPT nodes
+// (p0 + t 256 + tid, so the Z reads and Y writes of a wavefront stay contiguous) from LDS.
+// Each element of X is read from HBM about once (the 2H halo nodes come from L2), and the
+// memory instructions per node and column drop fourfold against the register form above.
+// One node's step for JN columns staged in LDS (JN = CPT on full column groups, so every
+// loop below unrolls without per-column checks).
+// KIND: SCSF_STENCIL5 (no problem of the batch has a potential: no per-node branch),
+// kStencil5V (5-point, potential where op.v is set) or SCSF_STENCIL9.
+constexpr int kStencil5V = 105;
+
+template <int KIND, int JN, typename T, bool SRC, bool HZ>
+__device__ inline void lds_node(const OpDev &op, const T *sx, int span, int e, int64_t p,
+                                int N, T a, T bc, T g, const T *srcj,
+                                const T *__restrict__ Z, const T *__restrict__ R,
+                                T *__restrict__ Y, int64_t off, int64_t ld) {
+  const int iy = (int)(p / N), ix = (int)(p - (int64_t)iy * N);
+  if constexpr (KIND == SCSF_STENCIL5 || KIND == kStencil5V) {
+    const double cw64 = op.wx[(int64_t)iy * (N + 1) + ix];
+    const double ce64 = op.wx[(int64_t)iy * (N + 1) + ix + 1];
+    const double cs64 = op.wy[(int64_t)iy * N + ix];
+    const double cn64 = op.wy[(int64_t)(iy + 1) * N + ix];
+    double vp = 0.0;
+    if constexpr (KIND == kStencil5V) vp = op.v ? op.v[p] : 0.0;
+    const T cd = (T)(cw64 + ce64 + cs64 + cn64 + vp);
+    const T mw = ix > 0 ? (T)cw64 : (T)0, me = ix < N - 1 ? (T)ce64 : (T)0;
+    const T ms = iy > 0 ? (T)cs64 : (T)0, mn = iy < N - 1 ? (T)cn64 : (T)0;
+#pragma unroll
+    for (int j = 0; j < JN; ++j) {
+      const T *sj = sx + j * span;
+      const T xv = sj[e];
+      const T ax = cd * xv - mw * sj[e - 1] - me * sj[e + 1] - ms * sj[e - N] - mn * sj[e + N];
+      const int64_t o = off + (int64_t)j * ld + p;
+      T r = a * ax + bc * xv;
+      if constexpr (HZ) r += g * Z[o];
+      if constexpr (SRC) r += srcj[j] * R[o];
+      Y[o] = r;
+    }
+  } else {
+    double c64[9];
+    stencil9_coeffs(op, iy, ix, c64);
+    T c9[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const int dy = q / 3 - 1, dx = q % 3 - 1;
+      const bool ok = (iy + dy >= 0) && (iy + dy < N) && (ix + dx >= 0) && (ix + dx < N);
+      c9[q] = ok ? (T)c64[q] : (T)0;
+    }
+#pragma unroll
+    for (int j = 0; j < JN; ++j) {
+      const T *sj = sx + j * span;
+      T ax = 0;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) ax += c9[q] * sj[e + (q / 3 - 1) * N + (q % 3 - 1)];
+      const int64_t o = off + (int64_t)j * ld + p;
+      T r = a * ax + bc * sj[e];
+      if constexpr (HZ) r += g * Z[o];
+      if constexpr (SRC) r += srcj[j] * R[o];
+      Y[o] = r;
+    }
+  }
+}
+
+// LDS-staged step for the grid stencils: a workgroup takes TILE = 256 NPT consecutive nodes and
+// CPT columns.  It stages each column's nodes [p0 - H, p0 + TILE + H) (H = N, or N + 1 for the
+// 9-point stencil) into LDS with coalesced loads, then every thread computes NPT nodes
+// (p0 + t 256 + tid, so the Z reads and Y writes of a wavefront stay contiguous) from LDS.
+// Each element of X is read from HBM about once (the 2H halo nodes come from L2), and the
+// memory instructions per node and column drop fourfold against the register form above.
+template <int KIND, int CPT, int NPT, typename T, bool SRC, bool HZ>
+__global__ void __launch_bounds__(256) spmm_lds_kernel(
+    const OpDev *__restrict__ ops, const T *__restrict__ X, const T *__restrict__ Z,
+    T *__restrict__ Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
+    const int32_t *__restrict__ lock, const double *__restrict__ coef,
+    const T *__restrict__ R, const double *__restrict__ src, const int32_t *__restrict__ mdeg,
+    int32_t step) {
+  constexpr int TILE = 256 * NPT;
+  extern __shared__ unsigned char smem_raw[];
+  T *sx = reinterpret_cast<T *>(smem_raw);
+  const int b = blockIdx.z;
+  if (mdeg && step >= mdeg[b]) return;
+  const OpDev op = ops[b];
+  const int N = op.N;
+  const int64_t n = op.n;
+  const int64_t p0 = (int64_t)blockIdx.x * TILE;
+  if (p0 >= n) return;
+  int32_t c0, cnt;
+  col_range(mode, k, lock, b, c0, cnt);
+  const int j0 = blockIdx.y * CPT;
+  if (j0 >= cnt) return;
+  const int jn = min(CPT, cnt - j0);
+  const int H = (KIND == SCSF_STENCIL9) ? N + 1 : N;
+  const int span = TILE + 2 * H;
+  const int tid = threadIdx.x;
+  const int64_t off = (int64_t)b * bs + (int64_t)(c0 + j0) * ld;
+  const T *xb = X + off;
+  // the columns' loads interleaved, so every thread keeps CPT of them in flight
+  for (int e = tid; e < span; e += 256) {
+    const int64_t q = p0 - H + e;
+    const bool in = q >= 0 && q < n;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j)
+      if (j < jn) sx[j * span + e] = in ? xb[(int64_t)j * ld + q] : (T)0;
+  }
+  __syncthreads();
+  const T a = (T)coef[3 * b + 0], bc = (T)coef[3 * b + 1], g = (T)coef[3 * b + 2];
+  T srcj[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j)
+    srcj[j] = (SRC && j < jn) ? (T)src[(int64_t)b * k + c0 + j0 + j] : (T)0;
+#pragma unroll
+  for (int t = 0; t < NPT; ++t) {
+    const int64_t p = p0 + t * 256 + tid;
+    if (p >= n) break;
+    const int e = H + t * 256 + tid;
+    if (jn == CPT) {
+      lds_node<KIND, CPT, T, SRC, HZ>(op, sx, span, e, p, N, a, bc, g, srcj, Z, R, Y, off, ld);
+    } else {
+      // the last, partial column group of a problem (indices stay compile-time constants)
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) {
+        if (j < jn) {
+          const T one[1] = {srcj[j]};
+          lds_node<KIND, 1, T, SRC, HZ>(op, sx + j * span, span, e, p, N, a, bc, g, one, Z, R, Y,
+                                        off + (int64_t)j * ld, ld);
+        }
+      }
+    }
+  }
+}
+
 template <int CPT, typename T, bool SRC>
-static void launch_kind(const OpDev *ops, int B, int32_t kind, int64_t nmax, const T *X,
-                        const T *Z, T *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
-                        const int32_t *lock, const double *coef, int hz, const T *R,
-                        const double *src, const int32_t *mdeg, int32_t step, hipStream_t st) {
+static void launch_reg(const OpDev *ops, int B, int32_t kind, int64_t nmax, const T *X,
+                       const T *Z, T *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
+                       const int32_t *lock, const double *coef, int hz, const T *R,
+                       const double *src, const int32_t *mdeg, int32_t step, hipStream_t st) {
   dim3 block(256);
   dim3 grid((unsigned)ceil_div(nmax, 256), (unsigned)ceil_div(k, CPT), (unsigned)B);
   if (kind == SCSF_STENCIL5)
@@ -134,45 +275,82 @@ static void launch_kind(const OpDev *ops, int B, int32_t kind, int64_t nmax, con
         ops, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src, mdeg, step);
 }
 
-// cpt: columns per thread (2, 4 or 8), the tile the autotuner chooses per (n, k).
+constexpr size_t kStageBytes = 65536;                 // dynamic LDS of one staged workgroup
+
+template <int CPT, typename T, bool SRC>
+static bool launch_lds(const OpDev *ops, int B, int32_t kind, bool pot, int64_t nmax, int32_t Nmax,
+                       const T *X, const T *Z, T *Y, int64_t ld, int64_t bs, int32_t mode,
+                       int32_t k, const int32_t *lock, const double *coef, int hz, const T *R,
+                       const double *src, const int32_t *mdeg, int32_t step, hipStream_t st) {
+  constexpr int NPT = 8 / CPT, TILE = 256 * NPT;
+  const int64_t H = (kind == SCSF_STENCIL9) ? (int64_t)Nmax + 1 : Nmax;
+  const size_t shm = (size_t)CPT * (TILE + 2 * H) * sizeof(T);
+  if (shm > kStageBytes) return false;
+  dim3 grid((unsigned)ceil_div(nmax, TILE), (unsigned)ceil_div(k, CPT), (unsigned)B);
+  auto go = [&](auto kern) {
+    kern<<<grid, 256, shm, st>>>(ops, X, Z, Y, ld, bs, mode, k, lock, coef, R, src, mdeg, step);
+  };
+  if (kind == SCSF_STENCIL5 && !pot) {
+    if (hz) go(spmm_lds_kernel<SCSF_STENCIL5, CPT, NPT, T, SRC, true>);
+    else go(spmm_lds_kernel<SCSF_STENCIL5, CPT, NPT, T, SRC, false>);
+  } else if (kind == SCSF_STENCIL5) {
+    if (hz) go(spmm_lds_kernel<kStencil5V, CPT, NPT, T, SRC, true>);
+    else go(spmm_lds_kernel<kStencil5V, CPT, NPT, T, SRC, false>);
+  } else {
+    if (hz) go(spmm_lds_kernel<SCSF_STENCIL9, CPT, NPT, T, SRC, true>);
+    else go(spmm_lds_kernel<SCSF_STENCIL9, CPT, NPT, T, SRC, false>);
+  }
+  return true;
+}
+
+// tile: columns per thread of the LDS-staged step (1, 2 or 4, with 8 / tile nodes per thread),
+// the choice the autotuner makes per (n, k).  CSR operators, and grids whose staged rows would
+// not fit in 64 KB of LDS, take the register form with 4 columns per thread.
 template <typename T, bool SRC>
-static hipError_t launch_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, const T *X,
-                              const T *Z, T *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
-                              const int32_t *lock, const double *coef, bool has_z, const T *R,
-                              const double *src, const int32_t *mdeg, int32_t step, int cpt,
-                              hipStream_t st) {
+static hipError_t launch_step(const OpDev *ops, int B, int32_t kind, int64_t nmax,
+                              int32_t Nmax, const T *X, const T *Z, T *Y, int64_t ld, int64_t bs,
+                              int32_t mode, int32_t k, const int32_t *lock, const double *coef,
+                              bool has_z, const T *R, const double *src, const int32_t *mdeg,
+                              int32_t step, int tile, bool pot, hipStream_t st) {
   if (B <= 0 || nmax <= 0 || k <= 0) return hipSuccess;
   const int hz = has_z ? 1 : 0;
-  if (cpt == 2)
-    launch_kind<2, T, SRC>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src,
-                           mdeg, step, st);
-  else if (cpt == 8)
-    launch_kind<8, T, SRC>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src,
-                           mdeg, step, st);
-  else
-    launch_kind<4, T, SRC>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src,
-                           mdeg, step, st);
+  bool done = false;
+  if (kind != SCSF_CSR && Nmax > 0) {
+    if (tile == 1)
+      done = launch_lds<1, T, SRC>(ops, B, kind, pot, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
+                                   hz, R, src, mdeg, step, st);
+    else if (tile == 4)
+      done = launch_lds<4, T, SRC>(ops, B, kind, pot, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
+                                   hz, R, src, mdeg, step, st);
+    else
+      done = launch_lds<2, T, SRC>(ops, B, kind, pot, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
+                                   hz, R, src, mdeg, step, st);
+  }
+  if (!done)
+    launch_reg<4, T, SRC>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src,
+                          mdeg, step, st);
   return hipGetLastError();
 }
 
-hipError_t spmm_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t /*Nmax*/,
+hipError_t spmm_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t Nmax,
                      const double *X, const double *Z, double *Y, int64_t ld, int64_t bs,
                      int32_t mode, int32_t k, const int32_t *lock, const double *coef,
-                     bool has_z, hipStream_t st, const int32_t *mdeg, int32_t step, int cpt) {
-  return launch_step<double, false>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
-                                    has_z, nullptr, nullptr, mdeg, step, cpt, st);
+                     bool has_z, hipStream_t st, const int32_t *mdeg, int32_t step, int tile,
+                     bool pot) {
+  return launch_step<double, false>(ops, B, kind, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock,
+                                    coef, has_z, nullptr, nullptr, mdeg, step, tile, pot, st);
 }
 
-hipError_t spmm_step32(const OpDev *ops, int B, int32_t kind, int64_t nmax, const float *X,
-                       const float *Z, float *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
-                       const int32_t *lock, const double *coef, bool has_z, const float *R,
-                       const double *src, hipStream_t st, const int32_t *mdeg, int32_t step,
-                       int cpt) {
+hipError_t spmm_step32(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t Nmax,
+                       const float *X, const float *Z, float *Y, int64_t ld, int64_t bs,
+                       int32_t mode, int32_t k, const int32_t *lock, const double *coef,
+                       bool has_z, const float *R, const double *src, hipStream_t st,
+                       const int32_t *mdeg, int32_t step, int tile, bool pot) {
   if (R)
-    return launch_step<float, true>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
-                                    has_z, R, src, mdeg, step, cpt, st);
-  return launch_step<float, false>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
-                                   has_z, nullptr, nullptr, mdeg, step, cpt, st);
+    return launch_step<float, true>(ops, B, kind, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock,
+                                    coef, has_z, R, src, mdeg, step, tile, pot, st);
+  return launch_step<float, false>(ops, B, kind, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
+                                   has_z, nullptr, nullptr, mdeg, step, tile, pot, st);
 }
 
 }  // namespace scsf

@@ -48,6 +48,28 @@ def workload(cfg_index: int, count: int | None):
     return cfg, ops
 
 
+def measured_traffic(cfg_name: str):
+    """HBM bytes per filter launch from the committed counter record of this workload, while
+    the filter step's source is unchanged since the counters were taken (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"spmm_traffic_{cfg_name}.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            key, _, val = line.partition(" ")
+            rec[key] = val.strip()
+    src = os.path.join(ROOT, rec.get("source", ""))
+    if not os.path.isfile(src):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if digest != rec.get("source_sha256_16"):
+        return None
+    return float(rec["bytes_per_launch"])
+
+
 def family_order_host(ops, p0):
     """Algorithm 2 within each operator family, concatenated (oracle; CPU baseline only)."""
     from oracle import sort as S
@@ -334,7 +356,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": (measured_traffic(cfg.name) if (cfg.index == 2 and form == "plain"
+                                                         and precision == "fp64") else None),
             "avg_launch_ms": avg_ms,
             "launches": prof["filter_launches"],
             "algorithmic_bytes_per_launch": avg_bytes,

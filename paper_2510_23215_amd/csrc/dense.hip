@@ -37,7 +37,9 @@ __global__ void __launch_bounds__(512) chol_inv_kernel(
   if (ka <= 0) return;
   const int tid = threadIdx.x, NT = blockDim.x;
   const int tx = tid & 15, ty = tid >> 4;              // 16 x 32
-  double *S = LDS ? lds : gscr + (int64_t)b * kMaxK * (kMaxK + 1);
+  // the packed factor of this problem's active width in LDS when it fits, else global scratch
+  const bool in_lds = LDS && (int64_t)ka * (ka + 1) / 2 <= kLdsDoubles;
+  double *S = in_lds ? lds : gscr + (int64_t)b * kMaxK * (kMaxK + 1);
   const double *Gb = G + (int64_t)b * ldm * ldm;
   double *Mb = M + (int64_t)b * ldm * ldm;
 
@@ -122,12 +124,9 @@ hipError_t chol_inv(int B, int64_t n, int32_t k, const int32_t *lock, const doub
                     int32_t ldm, int32_t *flag, const int32_t *gate, int32_t gate_mask,
                     double *scratch, hipStream_t st) {
   if (B <= 0) return hipSuccess;
-  // the packed R (inverted in place) fits in LDS for every ka when k(k+1)/2 <= kLdsDoubles
-  if ((int64_t)k * (k + 1) / 2 <= kLdsDoubles)
-    chol_inv_kernel<true><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask, scratch);
-  else
-    chol_inv_kernel<false><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask,
-                                              scratch);
+  // each workgroup keeps its packed R (inverted in place) in LDS when its active width fits
+  // (ka(ka+1)/2 <= kLdsDoubles), so wide blocks move into LDS as their pairs lock
+  chol_inv_kernel<true><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask, scratch);
   return hipGetLastError();
 }
 
@@ -177,7 +176,8 @@ __global__ void __launch_bounds__(512) jacobi_values_kernel(
   if (ka <= 0) { if (tid == 0) nsweeps[b] = 0; return; }
   const int tx = tid & 15, ty = tid >> 4;              // 16 x 32
   const int K = ka + (ka & 1), half = K / 2;
-  double *S = LDS ? lds : gscr + (int64_t)b * kMaxK * (kMaxK + 1);
+  const bool in_lds = LDS && (int64_t)K * (K + 1) / 2 <= kLdsDoubles;
+  double *S = in_lds ? lds : gscr + (int64_t)b * kMaxK * (kMaxK + 1);
   const double *Gb = Gin + (int64_t)b * ldm * ldm;
   double *R = rec + (int64_t)b * rec_stride;           // (c, s) per (sweep, round, slot)
   double *Ract = R + (int64_t)kJacobiMaxSweeps * (K - 1) * half * 2;
@@ -352,13 +352,9 @@ hipError_t jacobi_eig(int B, int32_t k, const int32_t *lock, double *G, double *
                       int32_t *ranks, int32_t *nsweeps, hipStream_t st, double stop) {
   if (B <= 0) return hipSuccess;
   const int64_t rs = jacobi_record_elems(k);
-  const int K = k + (k & 1);
-  if ((int64_t)K * (K + 1) / 2 <= kLdsDoubles)
-    jacobi_values_kernel<true><<<B, 512, 0, st>>>(k, lock, G, ldm, theta, ranks, rec, rs, nsweeps,
-                                                  flag, scratch, stop);
-  else
-    jacobi_values_kernel<false><<<B, 512, 0, st>>>(k, lock, G, ldm, theta, ranks, rec, rs,
-                                                   nsweeps, flag, scratch, stop);
+  // per problem: the packed matrix in LDS when its active width fits, else global scratch
+  jacobi_values_kernel<true><<<B, 512, 0, st>>>(k, lock, G, ldm, theta, ranks, rec, rs, nsweeps,
+                                                flag, scratch, stop);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   jacobi_vectors_kernel<<<dim3((unsigned)ceil_div(k, 8), 1, B), 512, 0, st>>>(

@@ -58,7 +58,8 @@ __global__ void __launch_bounds__(512) tridiag_eig_kernel(
   if (ka <= 0) return;
   const int tid = threadIdx.x, NT = blockDim.x, lane = tid & 63, wv = tid >> 6, NW = NT >> 6;
   const int tx = tid & 15, ty = tid >> 4;            // 16 x 32
-  double *S = LDS ? lds : gscr + (int64_t)b * kMaxK * (kMaxK + 1);
+  const bool in_lds = LDS && (int64_t)ka * (ka + 1) / 2 <= kTriLds;
+  double *S = in_lds ? lds : gscr + (int64_t)b * kMaxK * (kMaxK + 1);
   const double *Gb = Gin + (int64_t)b * ldm * ldm;
   double *Wk = work + (int64_t)b * wstride;
   double *refl = Wk, *tau = Wk + (int64_t)k * k;
@@ -330,10 +331,8 @@ hipError_t tridiag_eig(int B, int32_t k, const int32_t *lock, const double *G, d
                        hipStream_t st) {
   if (B <= 0 || k <= 0) return hipSuccess;
   const int64_t ws = tridiag_work_elems(k);
-  if ((int64_t)k * (k + 1) / 2 <= kTriLds)
-    tridiag_eig_kernel<true><<<B, 512, 0, st>>>(k, lock, G, ldm, theta, flag, scratch, work, ws);
-  else
-    tridiag_eig_kernel<false><<<B, 512, 0, st>>>(k, lock, G, ldm, theta, flag, scratch, work, ws);
+  // per problem: the packed matrix in LDS when its active width fits, else global scratch
+  tridiag_eig_kernel<true><<<B, 512, 0, st>>>(k, lock, G, ldm, theta, flag, scratch, work, ws);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   tridiag_back_kernel<<<dim3((unsigned)ceil_div(k, 4), 1, (unsigned)B), 256, 0, st>>>(

@@ -350,7 +350,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "spmm_step_kernel (Chebyshev three-term step, 5-point stencil, %s)" % (
+            "kernel": "spmm_lds_kernel (Chebyshev three-term step, %s stencil, %s)" % (
+                "9-point Q1" if windowed else "5-point",
                 "FP64" if precision == "fp64" else "FP32 residual form"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -151,7 +151,7 @@ __device__ inline int pk(int i, int j) {              // packed upper triangle, 
 }
 
 constexpr int kJacobiMaxSweeps = 24;
-constexpr double kJacobiTol = 1e-15;                   // relative off-diagonal threshold
+constexpr double kJacobiTol = 1e-15;                   // smallest relative rotation threshold
 
 int64_t jacobi_record_elems(int32_t k) {
   const int64_t K = k + (k & 1);
@@ -203,6 +203,9 @@ __global__ void __launch_bounds__(512) jacobi_values_kernel(
     __syncthreads();
     return m;
   };
+  // entries below a tenth of the stopping level are left alone: the sweep ends at `stop`
+  // anyway, and a 2x2 block whose two rotations are both skipped costs no LDS traffic
+  const double rthr = fmax(kJacobiTol, 0.1 * stop);
   int sweep = 0;
   bool converged = !(max_off() > stop);              // already diagonal to the requested level
   for (; sweep < kJacobiMaxSweeps && !converged; ++sweep) {
@@ -215,7 +218,7 @@ __global__ void __launch_bounds__(512) jacobi_values_kernel(
         rr_pair(r, a, K, p, q);
         double c = 1.0, sn = 0.0;
         const double gpp = S[pk(p, p)], gqq = S[pk(q, q)], gpq = S[pk(p, q)];
-        if (fabs(gpq) > kJacobiTol * sqrt(fabs(gpp * gqq)) && fabs(gpq) > 1e-300) {
+        if (fabs(gpq) > rthr * sqrt(fabs(gpp * gqq)) && fabs(gpq) > 1e-300) {
           const double tau = (gqq - gpp) / (2.0 * gpq);
           double t;
           if (fabs(tau) > 1e150) t = 0.5 / tau;

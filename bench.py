@@ -23,11 +23,6 @@ import os
 import sys
 import time
 
-# HIP maps every stream to one of GPU_MAX_HW_QUEUES hardware queues (4 by default); the
-# concurrent lanes of the chained solver plus the default stream need one queue each, or two
-# lanes share a queue and run one after the other.  Set before HIP initialises.
-os.environ["GPU_MAX_HW_QUEUES"] = "8"
-
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -48,9 +43,10 @@ def workload(cfg_index: int, count: int | None):
     return cfg, ops
 
 
-def measured_traffic(cfg_name: str):
+def measured_traffic(cfg_name: str, launch: dict):
     """HBM bytes per filter launch from the committed counter record of this workload, while
-    the filter step's source is unchanged since the counters were taken (else None)."""
+    the filter step's source and the launch configuration (chains, lanes, schedule, graphs)
+    are those the counters were taken with (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"spmm_traffic_{cfg_name}.txt")
     if not os.path.exists(path):
@@ -66,6 +62,8 @@ def measured_traffic(cfg_name: str):
         return None
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     if digest != rec.get("source_sha256_16"):
+        return None
+    if any(str(v) != rec.get(key) for key, v in launch.items()):
         return None
     return float(rec["bytes_per_launch"])
 
@@ -130,8 +128,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--count", type=int, default=None, help="operators (default: all)")
-    ap.add_argument("--chains", type=int, default=32)
-    ap.add_argument("--lanes", type=int, default=5)
+    ap.add_argument("--chains", type=int, default=128)
+    ap.add_argument("--lanes", type=int, default=8)
     ap.add_argument("--degree", type=int, default=None)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
                     help="default: the configuration's (fp64; mixed for config 4)")
@@ -152,12 +150,18 @@ def main():
     ap.add_argument("--train", type=int, default=500,
                     help="learned form: operators solved plainly to train the network")
     ap.add_argument("--epochs", type=int, default=600)
+    ap.add_argument("--tile", type=int, choices=[1, 2, 4], default=None,
+                    help="pin the filter-step tile instead of the autotuned one")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="before timing, run a plain 1 GiB device-to-device copy kernel three "
                          "times (reference for the HBM byte counters)")
     args = ap.parse_args()
+    # HIP maps every stream to one of GPU_MAX_HW_QUEUES hardware queues (4 by default); the
+    # concurrent lanes of the chained solver plus the default stream need one queue each, or
+    # two lanes share a queue and run one after the other.  Set before HIP initialises.
+    os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(8, args.lanes + 2)))
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU chunking is not "
@@ -270,7 +274,10 @@ def main():
         scsf.scsf_autotune(h, dops, Ls, make_order(), prm64, probe=4)
         tune_s = time.time() - t
         log(f"[bench] autotune {tune_s:.2f}s")
+    if args.tile:
+        scsf.scsf_set_tile(h, args.tile)
     ks = [scsf.scsf_tuned_width(h, L) for L in Ls] if uneven else [cfg.k] * n_op
+    tile_used = scsf.scsf_tuned_tile(h, max(d.n for d in dops), max(ks))
 
     for w in range(args.warmup):
         t = time.time()
@@ -343,8 +350,7 @@ def main():
             "form": form,
             "block_widths": ({str(L): scsf.scsf_tuned_width(h, L) for L in sorted(set(Ls))}
                              if uneven else {str(cfg.L): cfg.k}),
-            "spmm_columns_per_thread": scsf.scsf_tuned_tile(h, max(d.n for d in dops),
-                                                            max(ks)),
+            "spmm_columns_per_thread": tile_used,
             "precision": precision,
             "mean_outer_iterations": float(np.mean(iters)),
         },
@@ -357,8 +363,12 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": (measured_traffic(cfg.name) if (cfg.index == 2 and form == "plain"
-                                                         and precision == "fp64") else None),
+            "traffic": (measured_traffic(cfg.name, {"chains": args.chains, "lanes": args.lanes,
+                                                    "schedule": args.schedule,
+                                                    "graphs": args.graphs,
+                                                    "tile": tile_used})
+                        if (cfg.index == 2 and form == "plain" and precision == "fp64")
+                        else None),
             "avg_launch_ms": avg_ms,
             "launches": prof["filter_launches"],
             "algorithmic_bytes_per_launch": avg_bytes,

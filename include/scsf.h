@@ -124,7 +124,8 @@ const char *scsf_status_string(int status);
 /* Library build/version string (host). */
 const char *scsf_version(void);
 /* Number of lockstep batches the chained solvers (scsf_solve_sequence*, scsf_solve_batched)
- * run concurrently (1..8, default 4).  Each batch runs on a stream the handle creates (default
+ * run concurrently (1..16, default 4; each needs a hardware queue of its own, see
+ * GPU_MAX_HW_QUEUES).  Each batch runs on a stream the handle creates (default
  * priority), ordered after the work already enqueued on the handle's stream, and is driven by
  * a host thread of its own; the call returns when every batch has finished. */
 int scsf_set_lanes(scsf_handle *h, int lanes);
@@ -267,6 +268,9 @@ int scsf_autotune(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
 int scsf_tuned_width(scsf_handle *h, int32_t L);
 /* The tuned filter-step tile (block columns per thread: 1, 2 or 4; default 2) for size n and
  * width k. */
+/* Set the filter-step tile (1, 2 or 4) for every size and width, overriding the autotuner
+ * (for reproducible measurements). */
+int scsf_set_tile(scsf_handle *h, int32_t tile);
 int scsf_tuned_tile(scsf_handle *h, int64_t n, int32_t k);
 
 /* Bilinear transfer of ncols nodal fields between interior grids of the unit square: column

@@ -105,6 +105,7 @@ def lib():
                                 POINTER(Params), i32]
         sig["scsf_tuned_width"] = [vp, i32]
         sig["scsf_tuned_tile"] = [vp, i64, i32]
+        sig["scsf_set_tile"] = [vp, i32]
         sig["scsf_solve_batched"] = [vp, POINTER(Operator), i32, POINTER(c_int32),
                                      POINTER(c_int32), POINTER(c_int32), i32, POINTER(Params),
                                      vp, vp, POINTER(Stats)]
@@ -331,6 +332,10 @@ def scsf_tuned_tile(h: Handle, n: int, k: int) -> int:
     if c < 0:
         raise ScsfError(c, "scsf_tuned_tile")
     return c
+
+
+def scsf_set_tile(h: Handle, tile: int):
+    _check(lib().scsf_set_tile(h.ptr, int(tile)), "scsf_set_tile")
 
 
 def scsf_solve_batched(h: Handle, ops: list, Ls, order, chains: int, prm: Params, ks=None,

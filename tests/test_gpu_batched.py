@@ -200,3 +200,12 @@ def test_autotune_picks_valid_settings_and_solves():
         check_pairs(A, evals[i], evecs[i].t(), Ls[i], 1e-8, w, V)
     with pytest.raises(scsf.ScsfError):
         scsf.scsf_autotune(h, dops, Ls, order, prm, probe=0)
+    scsf.scsf_set_tile(h, 4)
+    assert scsf.scsf_tuned_tile(h, 5000, 40) == 4 and scsf.scsf_tuned_tile(h, 20000, 240) == 4
+    with pytest.raises(scsf.ScsfError):
+        scsf.scsf_set_tile(h, 3)
+    evals, evecs, stats = scsf.scsf_solve_batched(h, dops, Ls, order, 4, prm)
+    for i, o in enumerate(ops):
+        A = O.assemble(o)
+        w, V = E.smallest_eigenpairs(A, Ls[i] + 6, method="dense")
+        check_pairs(A, evals[i], evecs[i].t(), Ls[i], 1e-8, w, V)

@@ -11,7 +11,7 @@ namespace scsf {
 // Largest block width the small dense kernels handle (Gram, Cholesky, Jacobi).
 constexpr int kMaxK = 256;
 // Row chunk processed by one workgroup of the tall-skinny Gram kernel.
-constexpr int kGramChunk = 512;
+constexpr int kGramChunk = 2048;
 
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

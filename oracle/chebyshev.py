@@ -59,3 +59,24 @@ def filter_block(A, Y0: np.ndarray, m: int, lam: float, c: float, e: float) -> n
 def filter_gain(mu, m: int, lam: float, c: float, e: float):
     """Scalar factor the filter applies to an eigenvector of eigenvalue mu."""
     return cheb(m, (np.asarray(mu, dtype=np.float64) - c) / e) / cheb(m, np.array([(lam - c) / e]))[0]
+
+
+def adaptive_degrees(theta, res, tol: float, c: float, e: float, m_max: int, m_min: int = 1):
+    """Per-vector filter degree of the optimized filter the paper cites for Algorithm 1
+    (per-column degrees) and leaves out of Algorithm 3: each non-converged vector gets the
+    degree its residual and Ritz value call for.
+
+    A Ritz value theta below the damped interval [c - e, c + e] (t = (theta - c)/e < -1) is
+    amplified by |C_m(t)| ~ |rho|^m / 2 against the interval, |rho| = |t| + sqrt(t^2 - 1), so
+    a residual res falls to tol after m = ceil(ln(res / tol) / ln|rho|) steps.  The degree is
+    clamped to [m_min, m_max]; a Ritz value inside the interval (|t| <= 1) gets m_max.
+    """
+    theta = np.asarray(theta, dtype=np.float64)
+    res = np.asarray(res, dtype=np.float64)
+    t = (theta - c) / e
+    out = np.full(theta.shape, m_max, dtype=np.int64)
+    grow = np.abs(t) > 1.0
+    rho = np.abs(t[grow]) + np.sqrt(t[grow] ** 2 - 1.0)
+    need = np.log(np.maximum(res[grow], tol) / tol) / np.log(rho)
+    out[grow] = np.ceil(need - 1e-12).astype(np.int64)
+    return np.clip(out, m_min, m_max)

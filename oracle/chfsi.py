@@ -33,7 +33,7 @@ import math
 
 import numpy as np
 
-from .chebyshev import filter_block
+from .chebyshev import adaptive_degrees, filter_block
 from .eig import canonical_sign
 from . import lanczos, transfer
 
@@ -55,7 +55,11 @@ def _gaussian(n: int, k: int, seed: int) -> np.ndarray:
 
 
 def chfsi(A, L: int, k: int, m: int, tol: float, X0=None, theta0=None, beta=None,
-          seed: int = 0, max_iter: int = 200, lanczos_steps: int = 20) -> Result:
+          seed: int = 0, max_iter: int = 200, lanczos_steps: int = 20,
+          adaptive: bool = False) -> Result:
+    """adaptive: after the first outer iteration every active vector is filtered with the
+    degree its residual calls for (chebyshev.adaptive_degrees), between m and min(2m, 64):
+    vectors near convergence keep m, slow ones get up to twice as many steps."""
     n = A.shape[0]
     if not (0 < L < k <= n):
         raise ValueError("need 0 < L < k <= n")
@@ -74,13 +78,23 @@ def chfsi(A, L: int, k: int, m: int, tol: float, X0=None, theta0=None, beta=None
     thl = np.zeros(0)
     matvecs = 0
     it = 0
+    res_act = None                       # residuals of the active Ritz pairs (last iteration)
     while it < max_iter and thl.size < L:
         it += 1
         lam = thl[0] if thl.size else theta[0]
         alpha = theta[-1]
         c, e = 0.5 * (alpha + beta), 0.5 * (beta - alpha)
-        Y = filter_block(A, X, m, lam, c, e)
-        matvecs += m * X.shape[1]
+        if adaptive and res_act is not None:
+            deg = adaptive_degrees(theta, res_act, tol, c, e, m_max=max(m, min(2 * m, 64)),
+                                   m_min=m)
+            Y = np.empty_like(X)
+            for d in np.unique(deg):
+                cols = np.nonzero(deg == d)[0]
+                Y[:, cols] = filter_block(A, X[:, cols], int(d), lam, c, e)
+            matvecs += int(deg.sum())
+        else:
+            Y = filter_block(A, X, m, lam, c, e)
+            matvecs += m * X.shape[1]
         Q, _ = np.linalg.qr(np.hstack([Vl, Y]))
         Qa = Q[:, Vl.shape[1]:]
         AQ = A @ Qa
@@ -95,6 +109,7 @@ def chfsi(A, L: int, k: int, m: int, tol: float, X0=None, theta0=None, beta=None
         Vl = np.hstack([Vl, X[:, :j]])
         thl = np.concatenate([thl, theta[:j]])
         X, theta = X[:, j:], theta[j:]
+        res_act = res[j:]
 
     allV = np.hstack([Vl, X])
     allth = np.concatenate([thl, theta])
@@ -105,7 +120,7 @@ def chfsi(A, L: int, k: int, m: int, tol: float, X0=None, theta0=None, beta=None
 
 
 def scsf_sequence(mats, L: int, k: int, m: int, tol: float, order=None, warm: bool = True,
-                  seed: int = 0, max_iter: int = 200):
+                  seed: int = 0, max_iter: int = 200, adaptive: bool = False):
     """Solve the matrices in `order`, each warm-started from the previous one (Algorithm 3)."""
     order = list(range(len(mats))) if order is None else list(order)
     out = {}
@@ -123,9 +138,9 @@ def scsf_sequence(mats, L: int, k: int, m: int, tol: float, order=None, warm: bo
                     raise ValueError("warm start across sizes needs square grids")
                 X0 = transfer.interpolate_block(X0, N0, N1)
             r = chfsi(mats[i], L, k, m, tol, X0=X0, theta0=prev.theta_next,
-                      seed=seed, max_iter=max_iter)
+                      seed=seed, max_iter=max_iter, adaptive=adaptive)
         else:
-            r = chfsi(mats[i], L, k, m, tol, seed=seed, max_iter=max_iter)
+            r = chfsi(mats[i], L, k, m, tol, seed=seed, max_iter=max_iter, adaptive=adaptive)
         out[i] = r
         prev = r
         prev_n = n

@@ -80,8 +80,9 @@ def family_order_host(ops, p0):
     return order
 
 
-def cpu_baseline(cfg, ops, budget_s: float, Ls=None, ks=None):
-    """The oracle (plain NumPy/SciPy SCSF) on a bounded prefix of the sorted sequence."""
+def cpu_baseline(cfg, ops, budget_s: float, Ls=None, ks=None, degree=None, adaptive=False):
+    """The oracle (plain NumPy/SciPy SCSF) on a bounded prefix of the sorted sequence, with the
+    filter degree (and per-vector degrees) of the timed run."""
     import math
     import numpy as np
     from oracle import operator as O, sort as S, chfsi as C, transfer as T
@@ -90,6 +91,7 @@ def cpu_baseline(cfg, ops, budget_s: float, Ls=None, ks=None):
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
         threads = 1
+    degree = degree or cfg.degree
     t0 = time.time()
     if Ls is None:
         order = S.scsf_sort([o.field for o in ops], cfg.p0)
@@ -101,12 +103,13 @@ def cpu_baseline(cfg, ops, budget_s: float, Ls=None, ks=None):
         A = O.assemble(ops[i])
         key = (ops[i].family, Ls[i], ks[i])
         if prev is None or key != prev_key:
-            r = C.chfsi(A, Ls[i], ks[i], cfg.degree, cfg.tol, seed=1)
+            r = C.chfsi(A, Ls[i], ks[i], degree, cfg.tol, seed=1, adaptive=adaptive)
         else:
             X0 = prev.X_next
             if X0.shape[0] != A.shape[0]:
                 X0 = T.interpolate_block(X0, math.isqrt(X0.shape[0]), ops[i].N)
-            r = C.chfsi(A, Ls[i], ks[i], cfg.degree, cfg.tol, X0=X0, theta0=prev.theta_next)
+            r = C.chfsi(A, Ls[i], ks[i], degree, cfg.tol, X0=X0, theta0=prev.theta_next,
+                        adaptive=adaptive)
         prev, prev_key = r, key
         done += 1
         pairs += Ls[i]
@@ -152,6 +155,9 @@ def main():
     ap.add_argument("--epochs", type=int, default=600)
     ap.add_argument("--tile", type=int, choices=[1, 2, 4], default=None,
                     help="pin the filter-step tile instead of the autotuned one")
+    ap.add_argument("--adaptive", choices=["on", "off"], default="off",
+                    help="per-vector filter degrees in [degree, min(2 degree, 64)] (FP64 "
+                         "solves without degree hints)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -199,10 +205,17 @@ def main():
         fields = torch.tensor(np.stack([o.field for o in ops]), device="cuda")
     precision = args.precision or ("mixed" if cfg.precision == "mixed" or form == "learned"
                                    else "fp64")
+    adaptive = args.adaptive == "on"
+    if adaptive and (precision != "fp64" or form == "learned"):
+        print(json.dumps({"error": "--adaptive needs FP64 solves without degree hints "
+                                   "(--precision fp64, and --form plain on the learned-window "
+                                   "workload)"}))
+        sys.exit(2)
     prm = scsf.make_params(cfg.L, cfg.k, degree, cfg.tol, seed=1,
                            schedule=scsf.SCSF_SCHED_DYNAMIC if args.schedule == "dynamic"
                            else scsf.SCSF_SCHED_STATIC,
-                           precision=scsf.SCSF_MIXED if precision == "mixed" else scsf.SCSF_FP64)
+                           precision=scsf.SCSF_MIXED if precision == "mixed" else scsf.SCSF_FP64,
+                           adaptive=int(adaptive))
     if not uneven:
         evals = torch.empty((n_op, cfg.L), device="cuda", dtype=torch.float64)
         evecs = torch.empty((n_op, cfg.L, dops[0].n), device="cuda", dtype=torch.float64)
@@ -352,6 +365,7 @@ def main():
                              if uneven else {str(cfg.L): cfg.k}),
             "spmm_columns_per_thread": tile_used,
             "precision": precision,
+            "adaptive_degree": args.adaptive,
             "mean_outer_iterations": float(np.mean(iters)),
         },
         "roofline": {
@@ -367,7 +381,8 @@ def main():
                                                     "schedule": args.schedule,
                                                     "graphs": args.graphs,
                                                     "tile": tile_used})
-                        if (cfg.index == 2 and form == "plain" and precision == "fp64")
+                        if (cfg.index == 2 and form == "plain" and precision == "fp64"
+                            and not adaptive)
                         else None),
             "avg_launch_ms": avg_ms,
             "launches": prof["filter_launches"],
@@ -380,7 +395,8 @@ def main():
         out["comparison"] = comparison
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, ops, args.cpu_budget,
-                                           Ls if uneven else None, ks if uneven else None)
+                                           Ls if uneven else None, ks if uneven else None,
+                                           degree=degree, adaptive=adaptive)
     print(json.dumps(out))
 
 

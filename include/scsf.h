@@ -88,6 +88,13 @@ typedef struct scsf_params {
   int32_t lanczos_steps; /* steps of the upper-bound Lanczos run (0 -> 20) */
   int32_t precision;     /* scsf_precision */
   int32_t schedule;      /* scsf_solve_sequence: scsf_schedule */
+  int32_t adaptive;      /* 1: per-vector filter degrees (the optimized filter cited for
+                            Algorithm 1): after an outer iteration every active column gets
+                            ceil(ln(res/tol) / ln|rho|) steps, |rho| = |t| + sqrt(t^2 - 1),
+                            t = (theta - c) / e, clamped to [degree, min(2 degree, 64)] and
+                            raised by at most 2 to the residue mod 3 of the iteration's largest
+                            degree.  FP64 only; not with degree hints (SCSF_EINVAL).  0: one
+                            degree for the whole block */
   double tol;            /* lock when ||A v - theta v|| <= tol ||A v|| (App. D.5 metric) */
   uint64_t seed;         /* seed of the random cold-start block and Lanczos start vector */
 } scsf_params;

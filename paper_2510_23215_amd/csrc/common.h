@@ -52,11 +52,14 @@ __host__ __device__ inline void col_range(int32_t mode, int32_t k, const int32_t
 // 0 for CSR).  tile: 1, 2 or 4 columns per thread of the LDS-staged form (autotuned).
 // pot: some 5-point problem of the batch may carry a potential (op.v); false selects the form
 // without the per-node check and is only valid when no problem ever has one.
+// cdeg (nullable, B*k): per-column degrees of the adaptive filter; a column takes part while
+// step < its degree raised by at most 2 to mtot's residue mod 3 (mtot = the iteration's degree).
 hipError_t spmm_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t Nmax,
                      const double *X, const double *Z, double *Y, int64_t ld, int64_t bs,
                      int32_t mode, int32_t k, const int32_t *lock, const double *coef,
                      bool has_z, hipStream_t st, const int32_t *mdeg = nullptr,
-                     int32_t step = 0, int tile = 2, bool pot = true);
+                     int32_t step = 0, int tile = 2, bool pot = true,
+                     const int32_t *cdeg = nullptr, int32_t mtot = 0);
 
 // FP32 variant of the step for the mixed-precision filter; with R non-null the step adds the
 // per-column source term src[b*k + c] * R[:, c] (R in the same layout as X).
@@ -184,6 +187,12 @@ hipError_t copy_block(int64_t n, int32_t ncols, const double *src, int64_t lds, 
 hipError_t canonical_sign(int64_t n, int32_t ncols, double *X, int64_t ld, hipStream_t st);
 
 hipError_t fill_int(int32_t *a, int32_t v, int32_t count, hipStream_t st);
+// Per-column degrees of the adaptive filter for the next outer iteration (cdeg: B*k, columns
+// [lock[b], k)) and their maximum per problem (mdeg); problems with done[b] are left alone.
+hipError_t adaptive_degrees(int B, int32_t k, const int32_t *lock, const int32_t *done,
+                            const double *theta, const double *res, const double *bnd,
+                            double tol, int32_t mlo, int32_t mhi, int32_t *cdeg, int32_t *mdeg,
+                            hipStream_t st);
 // Bilinear transfer of ncols nodal fields from the N0 x N0 to the N1 x N1 interior grid of
 // the unit square (zero Dirichlet boundary); X and Y must not overlap.
 hipError_t interpolate_fields(int32_t N0, int32_t N1, int32_t ncols, const double *X,

@@ -487,4 +487,56 @@ hipError_t interpolate_fields(int32_t N0, int32_t N1, int32_t ncols, const doubl
   return hipGetLastError();
 }
 
+// Adaptive filter degrees for the next outer iteration (the optimized filter cited for
+// Algorithm 1): with the window the next iteration will use (as in cheb_kernel: c, e from the
+// smallest and largest Ritz values and beta), an active column with Ritz value theta and
+// residual r needs m = ceil(ln(r / tol) / ln|rho|) steps, |rho| = |t| + sqrt(t^2 - 1),
+// t = (theta - c) / e; clamped to [mlo, mhi] (mhi when |t| <= 1).  mdeg[b] = the largest.
+// grid B, 256 threads.
+__global__ void __launch_bounds__(256) adaptive_degree_kernel(
+    int32_t k, const int32_t *__restrict__ lock, const int32_t *__restrict__ done,
+    const double *__restrict__ theta, const double *__restrict__ res,
+    const double *__restrict__ bnd, double tol, int32_t mlo, int32_t mhi,
+    int32_t *__restrict__ cdeg, int32_t *__restrict__ mdeg) {
+  __shared__ int32_t smax[4];
+  const int b = blockIdx.x;
+  if (done[b]) return;
+  const double lam = theta[(int64_t)b * k], alpha0 = theta[(int64_t)b * k + k - 1];
+  double alpha = alpha0, beta = bnd[b * 4 + 3];
+  const double span = fmax(fabs(alpha), fabs(lam));
+  if (!(beta > alpha + 1e-12 * span)) beta = alpha + fmax(1e-3 * span, 1e-300);
+  const double c = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
+  int32_t best = mlo;
+  for (int col = lock[b] + threadIdx.x; col < k; col += blockDim.x) {
+    const double t = (theta[(int64_t)b * k + col] - c) / e;
+    int32_t m = mhi;
+    if (fabs(t) > 1.0) {
+      const double rho = fabs(t) + sqrt(t * t - 1.0);
+      const double r = fmax(res[(int64_t)b * k + col], tol);
+      const double need = ceil(log(r / tol) / log(rho) - 1e-12);
+      m = (int32_t)fmin((double)mhi, fmax((double)mlo, need));
+    }
+    cdeg[(int64_t)b * k + col] = m;
+    best = max(best, m);
+  }
+  for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_down(best, o, 64));
+  if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t m = smax[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = max(m, smax[w]);
+    mdeg[b] = m;
+  }
+}
+
+hipError_t adaptive_degrees(int B, int32_t k, const int32_t *lock, const int32_t *done,
+                            const double *theta, const double *res, const double *bnd,
+                            double tol, int32_t mlo, int32_t mhi, int32_t *cdeg, int32_t *mdeg,
+                            hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  adaptive_degree_kernel<<<B, 256, 0, st>>>(k, lock, done, theta, res, bnd, tol, mlo, mhi, cdeg,
+                                            mdeg);
+  return hipGetLastError();
+}
+
 }  // namespace scsf

@@ -27,7 +27,7 @@ namespace {
 enum BufId {
   B_X, B_Y1, B_Y2, B_W, B_G, B_M, B_PART, B_THETA, B_RES, B_INT, B_BND, B_COEF, B_UNIT, B_CHOL,
   B_JAC, B_LZ, B_OPS, B_WIN, B_SORTF, B_SORTD, B_SORTO, B_REC, B_RANK, B_E32, B_R32, B_SRC,
-  B_GAIN, B_WINB, B_HINT, B_MDEG, B_NETF, B_NETH, B_NETD, B_ROWS, B_EIG, B_COUNT
+  B_GAIN, B_WINB, B_HINT, B_MDEG, B_NETF, B_NETH, B_NETD, B_ROWS, B_EIG, B_CDEG, B_COUNT
 };
 
 struct DevBuf {
@@ -196,6 +196,15 @@ struct Engine {
   bool mixed = false, w_stale = true;
   // per-problem filter degrees (hinted sequences) and window hints
   bool var_deg = false;
+  // adaptive filter: per-column degrees in [m_base, m] (m = min(2 m_base, 64)), computed on
+  // the device after every iteration; mdeg[b] holds their maximum
+  bool adaptive = false;
+  int32_t m_base = 0;
+  int32_t *cdeg = nullptr, *h_cdeg = nullptr;
+  // adaptive: per problem, the filter columns (sum of column degrees) and the largest column
+  // degree of the last iteration
+  std::vector<int64_t> it_cols;
+  std::vector<int32_t> it_deg;
   int32_t *mdeg = nullptr, *h_mdeg = nullptr, *h_mraw = nullptr;
   double *hint = nullptr, *h_hint = nullptr;
   int32_t mcur = 0;                      // degree of the current iteration (max over problems)
@@ -217,11 +226,14 @@ struct Engine {
 
   int setup(Workspace *hh, int B_, int64_t n_, int32_t k_, int32_t L_, int32_t m_, int32_t kind_,
             double tol_, uint64_t seed_, int32_t lz_steps_, bool mixed_ = false,
-            bool var_deg_ = false) {
+            bool var_deg_ = false, bool adaptive_ = false) {
     mixed = mixed_;
     w_stale = true;
     var_deg = var_deg_;
+    adaptive = adaptive_ && !var_deg_ && !mixed_;
+    m_base = m_;
     if (var_deg) m_ = 64;                  // coefficient tables sized for the largest degree
+    if (adaptive) m_ = std::min(64, std::max(m_, 2 * m_));
     h = hh;
     st = hh->stream;
     B = B_;
@@ -275,6 +287,7 @@ struct Engine {
     STCHK(grow(h, B_HINT, (size_t)B * 3, &hint));
     STCHK(grow(h, B_MDEG, (size_t)B, &mdeg));
     STCHK(grow(h, B_ROWS, (size_t)B, &rows));
+    STCHK(grow(h, B_CDEG, (size_t)B * k, &cdeg));
     if (mixed) {
       float *e32 = nullptr;
       STCHK(grow(h, B_E32, (size_t)3 * B * bs, &e32));
@@ -287,7 +300,7 @@ struct Engine {
       STCHK(grow(h, B_WINB, (size_t)B * 3, &winb));
     }
     // pinned: 6 int arrays of B, perm B*k, theta/res B*k, bnd B*4, unit B*3, ops B
-    const size_t pin = (size_t)B * 9 * 4 + (size_t)B * k * 4 + (size_t)B * k * 16 +
+    const size_t pin = (size_t)B * 9 * 4 + (size_t)B * k * 8 + (size_t)B * k * 16 +
                        (size_t)B * 4 * 8 + (size_t)B * 6 * 8 + (size_t)B * sizeof(OpDev) + 2048;
     STCHK(grow_pinned(h, pin));
     char *pp = static_cast<char *>(h->pinned);
@@ -310,12 +323,14 @@ struct Engine {
     h_mdeg = (int32_t *)take(B * 4);
     h_mraw = (int32_t *)take(B * 4);
     h_rows = (int32_t *)take(B * 4);
+    h_cdeg = (int32_t *)take((size_t)B * k * 4);
     h_hint = (double *)take((size_t)B * 3 * 8);
     if ((size_t)(pp - static_cast<char *>(h->pinned)) > h->pinned_bytes) return SCSF_ENOMEM;
     for (int b = 0; b < B; ++b) {
       h_lock[b] = h_nconv[b] = h_done[b] = h_flag[b] = h_need[b] = 0;
-      h_mdeg[b] = h_mraw[b] = m_;
+      h_mdeg[b] = h_mraw[b] = adaptive ? m_base : m_;
       h_rows[b] = (int32_t)n;
+      for (int c = 0; c < k; ++c) h_cdeg[(size_t)b * k + c] = m_base;
       h_hint[3 * b] = h_hint[3 * b + 1] = h_hint[3 * b + 2] = 0.0;
       h_unit[3 * b] = 1.0;
       h_unit[3 * b + 1] = 0.0;
@@ -325,7 +340,10 @@ struct Engine {
     HIPCHK(hipMemcpyAsync(hint, h_hint, (size_t)B * 3 * 8, hipMemcpyHostToDevice, st));
     // plan_degrees() uploads only when a degree differs from the mirror, so the device copy
     // must match the mirror from the start (the buffer is reused across calls)
-    if (var_deg) HIPCHK(hipMemcpyAsync(mdeg, h_mdeg, (size_t)B * 4, hipMemcpyHostToDevice, st));
+    if (var_deg || adaptive)
+      HIPCHK(hipMemcpyAsync(mdeg, h_mdeg, (size_t)B * 4, hipMemcpyHostToDevice, st));
+    if (adaptive)
+      HIPCHK(hipMemcpyAsync(cdeg, h_cdeg, (size_t)B * k * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(rows, h_rows, (size_t)B * 4, hipMemcpyHostToDevice, st));
     HIPCHK(fill_int(flag, 0, B, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -384,13 +402,26 @@ struct Engine {
     HIPCHK(hipMemcpyAsync(h_nconv, nconv, (size_t)B * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h_done, done, (size_t)B * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h_flag, flag, (size_t)B * 4, hipMemcpyDeviceToHost, st));
+    if (adaptive) {
+      HIPCHK(hipMemcpyAsync(h_mdeg, mdeg, (size_t)B * 4, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(h_cdeg, cdeg, (size_t)B * k * 4, hipMemcpyDeviceToHost, st));
+    }
     HIPCHK(hipStreamSynchronize(st));
     prof_drain(h);
     return SCSF_OK;
   }
+  // a reloaded problem starts its adaptive degrees again from the configured degree
+  int reset_degrees(const std::vector<int> &slots) {
+    if (!adaptive) return SCSF_OK;
+    for (int b : slots) {
+      HIPCHK(fill_int(cdeg + (size_t)b * k, m_base, k, st));
+      HIPCHK(fill_int(mdeg + b, m_base, 1, st));
+      h_mdeg[b] = m_base;
+      for (int c = 0; c < k; ++c) h_cdeg[(size_t)b * k + c] = m_base;
+    }
+    return SCSF_OK;
+  }
 
-  // algorithmic bytes of one Chebyshev step over all unfinished problems: read Y_i (and
-  // Y_{i-1} after the first step), write Y_{i+1}, read the operator's coefficients once
   // Algorithmic HBM bytes of one filter step: each active column of the input block (and of
   // the previous block after the first step) read once, the output written once, and the
   // operator coefficients read once per problem (5-point: the two face arrays plus the
@@ -400,7 +431,17 @@ struct Engine {
     for (int b = 0; b < B; ++b)
       if (!h_done[b] && (!var_deg || step < h_mdeg[b])) {
         const double nb = (double)h_rows[b];
-        vec += nb * (double)(k - h_lock[b]);
+        int cols = k - h_lock[b];
+        if (adaptive) {                     // columns still inside their degree at this step
+          cols = 0;
+          for (int c = h_lock[b]; c < k; ++c) {
+            int32_t d = h_cdeg[(size_t)b * k + c];
+            d += ((mcur - d) % 3 + 3) % 3;
+            cols += step < d;
+          }
+          if (cols == 0) continue;
+        }
+        vec += nb * (double)cols;
         coeff += (kind == SCSF_STENCIL5) ? (h_ops[b].v ? 3.0 : 2.0) * nb
                  : (kind == SCSF_STENCIL9) ? 3.0 * nb : 0.0;
       }
@@ -492,7 +533,7 @@ struct Engine {
     return SCSF_OK;
   }
   int enqueue_filter(int M, bool timed) {
-    const int32_t *md = var_deg ? mdeg : nullptr;
+    const int32_t *md = var_deg ? mdeg : nullptr;   // adaptive degrees are per column (cdeg)
     if (mixed) {
       // Y = p_m(A) X = X p_m(Theta) + e_m with the correction e in FP32 (misc.hip)
       HIPCHK(mp_tables(B, k, M, theta, winb, lock, done, src, gain, md, st));
@@ -511,7 +552,7 @@ struct Engine {
         const int slot = timed ? prof_begin(h, step_bytes(s > 0, false, s)) : -1;
         HIPCHK(spmm_step(ops, B, kind, n, Nmax, ring[s % 3], ring[(s + 2) % 3], ring[(s + 1) % 3],
                          ld, bs, COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 0, st, md,
-                         s, cpt, pot));
+                         s, cpt, pot, adaptive ? cdeg : nullptr, M));
         prof_end(h, slot);
       }
     }
@@ -527,6 +568,8 @@ struct Engine {
     STCHK(rayleigh_ritz(Yf));
     HIPCHK(residuals(B, n, ld, X, W, bs, k, lock, theta, res, st, rows));
     HIPCHK(lock_update(B, k, L, tol, lock, nconv, res, done, st));
+    if (adaptive)
+      HIPCHK(adaptive_degrees(B, k, lock, done, theta, res, bnd, tol, m_base, m, cdeg, mdeg, st));
     return SCSF_OK;
   }
 
@@ -603,6 +646,22 @@ struct Engine {
     if (var_deg) {
       STCHK(plan_degrees());
       M = mcur;
+    } else if (adaptive) {                // the largest column degree of the unfinished problems
+      M = m_base;
+      for (int b = 0; b < B; ++b)
+        if (!h_done[b]) M = std::max(M, std::min<int32_t>(h_mdeg[b], m));
+      mcur = M;
+      it_cols.assign(B, 0);
+      it_deg.assign(B, 0);
+      for (int b = 0; b < B; ++b) {
+        if (h_done[b]) continue;
+        for (int c = h_lock[b]; c < k; ++c) {
+          int32_t d = h_cdeg[(size_t)b * k + c];
+          d += ((M - d) % 3 + 3) % 3;
+          it_cols[b] += d;
+          it_deg[b] = std::max(it_deg[b], d);
+        }
+      }
     }
     if (mixed && w_stale) {           // A X of newly loaded operators (residual form)
       HIPCHK(spmm_step(ops, B, kind, n, Nmax, X, nullptr, W, ld, bs, COLS_ACTIVE, k, lock, unit,
@@ -686,6 +745,8 @@ int check_params(const scsf_params *p, int64_t n) {
   if (p->lanczos_steps < 0 || p->lanczos_steps > 128) return SCSF_EINVAL;
   if (p->precision != SCSF_FP64 && p->precision != SCSF_MIXED) return SCSF_EINVAL;
   if (p->schedule != SCSF_SCHED_STATIC && p->schedule != SCSF_SCHED_DYNAMIC) return SCSF_EINVAL;
+  if (p->adaptive != 0 && p->adaptive != 1) return SCSF_EINVAL;
+  if (p->adaptive && p->precision != SCSF_FP64) return SCSF_EINVAL;
   return SCSF_OK;
 }
 
@@ -724,7 +785,7 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
 
   Engine e;
   STCHK(e.setup(w, chains, n, k, L, m, kind, prm->tol, prm->seed, lzs,
-                prm->precision == SCSF_MIXED, hints_host != nullptr));
+                prm->precision == SCSF_MIXED, hints_host != nullptr, prm->adaptive != 0));
   e.use_graph = graphs && w->own_stream;     // capture needs a stream of our own
   e.cpt = cpt;
   e.eig = eig;
@@ -771,7 +832,9 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
   while (remaining > 0) {
     STCHK(e.iterate());
     for (int b = 0; b < chains; ++b)
-      if (active[b]) fcols[b] += (int64_t)(e.var_deg ? e.h_mdeg[b] : m) * (k - e.h_lock_prev(b));
+      if (active[b])
+        fcols[b] += e.adaptive ? e.it_cols[b]
+                               : (int64_t)(e.var_deg ? e.h_mdeg[b] : m) * (k - e.h_lock_prev(b));
     bool reload = false;
     std::vector<int> recold, reloaded;
     std::vector<std::array<int, 3>> resize;   // (slot, old side, new side)
@@ -798,7 +861,7 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
         st.nconv = e.h_nconv[b];
         st.status = status;
         st.chol_shifts = (e.h_flag[b] & 4) ? 1 : 0;
-        st.degree = e.var_deg ? e.h_mdeg[b] : m;
+        st.degree = e.adaptive ? e.it_deg[b] : e.var_deg ? e.h_mdeg[b] : m;
         st.hint = (int32_t)e.h_hint[(size_t)b * 3 + 2];
         st.filter_cols = fcols[b];
         st.beta = e.h_bnd[(size_t)b * 4 + 3];
@@ -843,6 +906,7 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
     if (reload) {
       e.w_stale = true;                 // A X of the newly loaded operators
       STCHK(e.upload_hints(reloaded));
+      STCHK(e.reset_degrees(reloaded));
       STCHK(e.upload_ops());
       for (const auto &r : resize) {
         const int64_t o = (int64_t)r[0] * e.bs;
@@ -1187,7 +1251,7 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
   Engine e;
   e.eig = h->eig;
   STCHK(e.setup(w0, 1, A->n, prm->k, prm->L, prm->degree, A->kind, prm->tol, prm->seed, lzs,
-                prm->precision == SCSF_MIXED));
+                prm->precision == SCSF_MIXED, false, prm->adaptive != 0));
   e.h_ops[0] = to_dev(*A);
   e.h_need[0] = 1;
   STCHK(e.upload_ops());
@@ -1203,8 +1267,9 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
   int it = 0;
   int64_t fcols = 0;
   while (it < max_iter) {
-    fcols += (int64_t)prm->degree * (prm->k - e.h_nconv[0]);
+    const int64_t uniform = (int64_t)prm->degree * (prm->k - e.h_nconv[0]);
     STCHK(e.iterate());
+    fcols += e.adaptive ? e.it_cols[0] : uniform;
     ++it;
     if (e.h_done[0] || (e.h_flag[0] & 3)) break;
   }
@@ -1223,7 +1288,7 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
     stats_host->nconv = e.h_nconv[0];
     stats_host->status = status;
     stats_host->chol_shifts = (e.h_flag[0] & 4) ? 1 : 0;
-    stats_host->degree = prm->degree;
+    stats_host->degree = e.adaptive ? e.it_deg[0] : prm->degree;
     stats_host->hint = 0;
     stats_host->filter_cols = fcols;
     stats_host->beta = e.h_bnd[3];
@@ -1252,6 +1317,7 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
     if (ops_host[i].n != n || ops_host[i].kind != kind) return SCSF_EINVAL;
   }
   STCHK(check_params(prm, n));
+  if (hints_host && prm->adaptive) return SCSF_EINVAL;   // a degree hint fixes the degree
   {
     std::vector<char> seen(n_op, 0);
     for (int i = 0; i < n_op; ++i) {

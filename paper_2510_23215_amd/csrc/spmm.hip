@@ -12,6 +12,17 @@
 
 namespace scsf {
 
+// Per-column degree (adaptive filter): column c of problem b takes part in the step while
+// step < its degree, raised by at most 2 to the residue of the iteration's degree mtot mod 3
+// so that every column ends in the same buffer of the three-buffer ring.
+__device__ inline bool column_active(const int32_t *cdeg, int32_t mtot, int32_t step, int b,
+                                     int32_t k, int c) {
+  if (!cdeg) return true;
+  int32_t d = cdeg[(int64_t)b * k + c];
+  d += ((mtot - d) % 3 + 3) % 3;
+  return step < d;
+}
+
 // T = double: the plain FP64 step.  T = float (mixed precision): the same step on the FP32
 // correction block E, with the source term src[b*k + c] * R[:, c] of the residual form of the
 // recurrence (see mp_* in misc.hip); the operator coefficients are read in FP64 and rounded.
@@ -21,7 +32,7 @@ __global__ void __launch_bounds__(256) spmm_step_kernel(
     T *__restrict__ Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
     const int32_t *__restrict__ lock, const double *__restrict__ coef, int has_z,
     const T *__restrict__ R, const double *__restrict__ src, const int32_t *__restrict__ mdeg,
-    int32_t step) {
+    int32_t step, const int32_t *__restrict__ cdeg, int32_t mtot) {
   // XCD-aware order: the hardware deals workgroups to the 8 XCDs round-robin by linear id, and
   // each XCD has its own L2.  Remapping the linear id gives every XCD one contiguous range of
   // row tiles (of one problem and column group), so the +-N neighbour rows a tile reads were
@@ -46,6 +57,9 @@ __global__ void __launch_bounds__(256) spmm_step_kernel(
   T *y = Y + off;
   const T *z = has_z ? Z + off : nullptr;
   const int jn = min(CPT, cnt - j0);
+  bool act[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) act[j] = j < jn && column_active(cdeg, mtot, step, b, k, c0 + j0 + j);
   T sj[CPT];
   if constexpr (SRC) {
 #pragma unroll
@@ -64,7 +78,7 @@ __global__ void __launch_bounds__(256) spmm_step_kernel(
     const bool hw = ix > 0, he = ix < N - 1, hs = iy > 0, hn = iy < N - 1;
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
-      if (j < jn) {
+      if (act[j]) {
         const T *xc = x + (int64_t)j * ld;
         const T xv = xc[p];
         T ax = cd * xv;
@@ -93,7 +107,7 @@ __global__ void __launch_bounds__(256) spmm_step_kernel(
     }
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
-      if (j < jn) {
+      if (act[j]) {
         const T *xc = x + (int64_t)j * ld;
         const T xv = xc[p];
         T ax = 0;
@@ -112,7 +126,7 @@ __global__ void __launch_bounds__(256) spmm_step_kernel(
     const int32_t r0 = op.row_ptr[p], r1 = op.row_ptr[p + 1];
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
-      if (j < jn) {
+      if (act[j]) {
         const T *xc = x + (int64_t)j * ld;
         T ax = 0;
         for (int32_t q = r0; q < r1; ++q) ax += (T)op.val[q] * xc[op.col_idx[q]];
@@ -201,7 +215,7 @@ __global__ void __launch_bounds__(256) spmm_lds_kernel(
     T *__restrict__ Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
     const int32_t *__restrict__ lock, const double *__restrict__ coef,
     const T *__restrict__ R, const double *__restrict__ src, const int32_t *__restrict__ mdeg,
-    int32_t step) {
+    int32_t step, const int32_t *__restrict__ cdeg, int32_t mtot) {
   constexpr int TILE = 256 * NPT;
   extern __shared__ unsigned char smem_raw[];
   T *sx = reinterpret_cast<T *>(smem_raw);
@@ -217,6 +231,15 @@ __global__ void __launch_bounds__(256) spmm_lds_kernel(
   const int j0 = blockIdx.y * CPT;
   if (j0 >= cnt) return;
   const int jn = min(CPT, cnt - j0);
+  bool act[CPT];
+  bool any = false, all = true;
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    act[j] = j < jn && column_active(cdeg, mtot, step, b, k, c0 + j0 + j);
+    any = any || act[j];
+    all = all && act[j];
+  }
+  if (!any) return;                                   // every column of the group has stopped
   const int H = (KIND == SCSF_STENCIL9) ? N + 1 : N;
   const int span = TILE + 2 * H;
   const int tid = threadIdx.x;
@@ -228,7 +251,7 @@ __global__ void __launch_bounds__(256) spmm_lds_kernel(
     const bool in = q >= 0 && q < n;
 #pragma unroll
     for (int j = 0; j < CPT; ++j)
-      if (j < jn) sx[j * span + e] = in ? xb[(int64_t)j * ld + q] : (T)0;
+      if (act[j]) sx[j * span + e] = in ? xb[(int64_t)j * ld + q] : (T)0;
   }
   __syncthreads();
   const T a = (T)coef[3 * b + 0], bc = (T)coef[3 * b + 1], g = (T)coef[3 * b + 2];
@@ -241,13 +264,13 @@ __global__ void __launch_bounds__(256) spmm_lds_kernel(
     const int64_t p = p0 + t * 256 + tid;
     if (p >= n) break;
     const int e = H + t * 256 + tid;
-    if (jn == CPT) {
+    if (all) {
       lds_node<KIND, CPT, T, SRC, HZ>(op, sx, span, e, p, N, a, bc, g, srcj, Z, R, Y, off, ld);
     } else {
-      // the last, partial column group of a problem (indices stay compile-time constants)
+      // a partial column group, or columns past their degree (indices stay compile-time)
 #pragma unroll
       for (int j = 0; j < CPT; ++j) {
-        if (j < jn) {
+        if (act[j]) {
           const T one[1] = {srcj[j]};
           lds_node<KIND, 1, T, SRC, HZ>(op, sx + j * span, span, e, p, N, a, bc, g, one, Z, R, Y,
                                         off + (int64_t)j * ld, ld);
@@ -261,18 +284,19 @@ template <int CPT, typename T, bool SRC>
 static void launch_reg(const OpDev *ops, int B, int32_t kind, int64_t nmax, const T *X,
                        const T *Z, T *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
                        const int32_t *lock, const double *coef, int hz, const T *R,
-                       const double *src, const int32_t *mdeg, int32_t step, hipStream_t st) {
+                       const double *src, const int32_t *mdeg, int32_t step,
+                       const int32_t *cdeg, int32_t mtot, hipStream_t st) {
   dim3 block(256);
   dim3 grid((unsigned)ceil_div(nmax, 256), (unsigned)ceil_div(k, CPT), (unsigned)B);
   if (kind == SCSF_STENCIL5)
     spmm_step_kernel<SCSF_STENCIL5, CPT, T, SRC><<<grid, block, 0, st>>>(
-        ops, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src, mdeg, step);
+        ops, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src, mdeg, step, cdeg, mtot);
   else if (kind == SCSF_STENCIL9)
     spmm_step_kernel<SCSF_STENCIL9, CPT, T, SRC><<<grid, block, 0, st>>>(
-        ops, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src, mdeg, step);
+        ops, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src, mdeg, step, cdeg, mtot);
   else
     spmm_step_kernel<SCSF_CSR, CPT, T, SRC><<<grid, block, 0, st>>>(
-        ops, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src, mdeg, step);
+        ops, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src, mdeg, step, cdeg, mtot);
 }
 
 constexpr size_t kStageBytes = 65536;                 // dynamic LDS of one staged workgroup
@@ -281,14 +305,16 @@ template <int CPT, typename T, bool SRC>
 static bool launch_lds(const OpDev *ops, int B, int32_t kind, bool pot, int64_t nmax, int32_t Nmax,
                        const T *X, const T *Z, T *Y, int64_t ld, int64_t bs, int32_t mode,
                        int32_t k, const int32_t *lock, const double *coef, int hz, const T *R,
-                       const double *src, const int32_t *mdeg, int32_t step, hipStream_t st) {
+                       const double *src, const int32_t *mdeg, int32_t step,
+                       const int32_t *cdeg, int32_t mtot, hipStream_t st) {
   constexpr int NPT = 8 / CPT, TILE = 256 * NPT;
   const int64_t H = (kind == SCSF_STENCIL9) ? (int64_t)Nmax + 1 : Nmax;
   const size_t shm = (size_t)CPT * (TILE + 2 * H) * sizeof(T);
   if (shm > kStageBytes) return false;
   dim3 grid((unsigned)ceil_div(nmax, TILE), (unsigned)ceil_div(k, CPT), (unsigned)B);
   auto go = [&](auto kern) {
-    kern<<<grid, 256, shm, st>>>(ops, X, Z, Y, ld, bs, mode, k, lock, coef, R, src, mdeg, step);
+    kern<<<grid, 256, shm, st>>>(ops, X, Z, Y, ld, bs, mode, k, lock, coef, R, src, mdeg, step,
+                                 cdeg, mtot);
   };
   if (kind == SCSF_STENCIL5 && !pot) {
     if (hz) go(spmm_lds_kernel<SCSF_STENCIL5, CPT, NPT, T, SRC, true>);
@@ -311,24 +337,25 @@ static hipError_t launch_step(const OpDev *ops, int B, int32_t kind, int64_t nma
                               int32_t Nmax, const T *X, const T *Z, T *Y, int64_t ld, int64_t bs,
                               int32_t mode, int32_t k, const int32_t *lock, const double *coef,
                               bool has_z, const T *R, const double *src, const int32_t *mdeg,
-                              int32_t step, int tile, bool pot, hipStream_t st) {
+                              int32_t step, int tile, bool pot, const int32_t *cdeg,
+                              int32_t mtot, hipStream_t st) {
   if (B <= 0 || nmax <= 0 || k <= 0) return hipSuccess;
   const int hz = has_z ? 1 : 0;
   bool done = false;
   if (kind != SCSF_CSR && Nmax > 0) {
     if (tile == 1)
       done = launch_lds<1, T, SRC>(ops, B, kind, pot, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
-                                   hz, R, src, mdeg, step, st);
+                                   hz, R, src, mdeg, step, cdeg, mtot, st);
     else if (tile == 4)
       done = launch_lds<4, T, SRC>(ops, B, kind, pot, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
-                                   hz, R, src, mdeg, step, st);
+                                   hz, R, src, mdeg, step, cdeg, mtot, st);
     else
       done = launch_lds<2, T, SRC>(ops, B, kind, pot, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
-                                   hz, R, src, mdeg, step, st);
+                                   hz, R, src, mdeg, step, cdeg, mtot, st);
   }
   if (!done)
     launch_reg<4, T, SRC>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src,
-                          mdeg, step, st);
+                          mdeg, step, cdeg, mtot, st);
   return hipGetLastError();
 }
 
@@ -336,9 +363,10 @@ hipError_t spmm_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_
                      const double *X, const double *Z, double *Y, int64_t ld, int64_t bs,
                      int32_t mode, int32_t k, const int32_t *lock, const double *coef,
                      bool has_z, hipStream_t st, const int32_t *mdeg, int32_t step, int tile,
-                     bool pot) {
+                     bool pot, const int32_t *cdeg, int32_t mtot) {
   return launch_step<double, false>(ops, B, kind, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock,
-                                    coef, has_z, nullptr, nullptr, mdeg, step, tile, pot, st);
+                                    coef, has_z, nullptr, nullptr, mdeg, step, tile, pot, cdeg,
+                                    mtot, st);
 }
 
 hipError_t spmm_step32(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t Nmax,
@@ -348,9 +376,10 @@ hipError_t spmm_step32(const OpDev *ops, int B, int32_t kind, int64_t nmax, int3
                        const int32_t *mdeg, int32_t step, int tile, bool pot) {
   if (R)
     return launch_step<float, true>(ops, B, kind, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock,
-                                    coef, has_z, R, src, mdeg, step, tile, pot, st);
+                                    coef, has_z, R, src, mdeg, step, tile, pot, nullptr, 0, st);
   return launch_step<float, false>(ops, B, kind, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
-                                   has_z, nullptr, nullptr, mdeg, step, tile, pot, st);
+                                   has_z, nullptr, nullptr, mdeg, step, tile, pot, nullptr, 0,
+                                   st);
 }
 
 }  // namespace scsf

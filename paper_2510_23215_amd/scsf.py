@@ -39,7 +39,7 @@ class Operator(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("L", c_int32), ("k", c_int32), ("degree", c_int32), ("max_iter", c_int32),
                 ("lanczos_steps", c_int32), ("precision", c_int32), ("schedule", c_int32),
-                ("tol", c_double), ("seed", c_uint64)]
+                ("adaptive", c_int32), ("tol", c_double), ("seed", c_uint64)]
 
 
 class Profile(ctypes.Structure):
@@ -368,9 +368,9 @@ def scsf_solve_batched(h: Handle, ops: list, Ls, order, chains: int, prm: Params
 
 
 def make_params(L, k, degree=20, tol=1e-8, max_iter=0, lanczos_steps=20, seed=0,
-                precision=SCSF_FP64, schedule=SCSF_SCHED_STATIC) -> Params:
+                precision=SCSF_FP64, schedule=SCSF_SCHED_STATIC, adaptive=0) -> Params:
     return Params(L=L, k=k, degree=degree, max_iter=max_iter, lanczos_steps=lanczos_steps,
-                  precision=precision, schedule=schedule, tol=tol, seed=seed)
+                  precision=precision, schedule=schedule, adaptive=adaptive, tol=tol, seed=seed)
 
 
 def scsf_solve(h: Handle, A: DeviceOperator, prm: Params, X_prev=None, theta_prev=None,

@@ -68,6 +68,36 @@ def measured_traffic(cfg_name: str, launch: dict):
     return float(rec["bytes_per_launch"])
 
 
+def isolated_spmm(scsf, torch, h, dops, k, degree, blocks):
+    """The filter step alone: `blocks` operators of the workload, k columns each, `degree`
+    Chebyshev steps through scsf_filter_batched (one launch per step over all blocks, the
+    solver's kernel and tile), each launch timed with HIP events on the stream it runs on.
+    Window: lambda = 0 below the spectrum, [0.1 ub, ub] damped, ub the Gershgorin bound."""
+    ops = [dops[i % len(dops)] for i in range(blocks)]
+    ld = max(d.n for d in ops)
+    X = torch.randn((blocks, k, ld), device="cuda", dtype=torch.float64)
+    wins = []
+    for d in ops:
+        ub = scsf.scsf_bounds(h, d)["gershgorin"]
+        wins.append((0.0, 0.55 * ub, 0.45 * ub))
+    Y = scsf.scsf_filter_batched(h, ops, X, degree, wins)          # untimed first pass
+    torch.cuda.synchronize()
+    scsf.scsf_profile_read(h, reset=True)
+    scsf.scsf_profile_enable(h, True)
+    scsf.scsf_filter_batched(h, ops, X, degree, wins, Y)
+    torch.cuda.synchronize()
+    prof = scsf.scsf_profile_read(h, reset=True)
+    scsf.scsf_profile_enable(h, False)
+    del X, Y
+    ms = prof["filter_ms"] / max(prof["filter_launches"], 1)
+    bytes_ = prof["filter_bytes"] / max(prof["filter_launches"], 1)
+    gbs = bytes_ / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"kernel": "spmm_lds_kernel, alone (scsf_filter_batched)", "blocks": blocks,
+            "columns": k, "launches": prof["filter_launches"], "avg_launch_ms": ms,
+            "algorithmic_bytes_per_launch": bytes_, "achieved": gbs, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+
+
 def family_order_host(ops, p0):
     """Algorithm 2 within each operator family, concatenated (oracle; CPU baseline only)."""
     from oracle import sort as S
@@ -158,6 +188,9 @@ def main():
     ap.add_argument("--adaptive", choices=["on", "off"], default="off",
                     help="per-vector filter degrees in [degree, min(2 degree, 64)] (FP64 "
                          "solves without degree hints)")
+    ap.add_argument("--compare", choices=["on", "off"], default="on",
+                    help="working-size workload: also time the same operators solved cold and "
+                         "unsorted (outside the timed steps)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -314,6 +347,20 @@ def main():
     scsf.scsf_profile_enable(h, False)
 
     comparison = None
+    if cfg.index == 2 and args.compare == "on":
+        # the same operators in their generated order, every solve from a random block
+        prm_cold = scsf.make_params(cfg.L, cfg.k, degree, cfg.tol, seed=1,
+                                    schedule=scsf.SCSF_SCHED_DYNAMIC if args.schedule == "dynamic"
+                                    else scsf.SCSF_SCHED_STATIC, cold_start=1)
+        t = time.perf_counter()
+        _, _, stc = scsf.scsf_solve_sequence(h, dops, np.arange(n_op), args.chains, prm_cold,
+                                             evals, evecs)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t
+        comparison = {"cold_unsorted_value": n_op * cfg.L / tc, "cold_unsorted_ms": tc * 1e3,
+                      "cold_unsorted_mean_iterations":
+                          float(np.mean([s["iterations"] for s in stc]))}
+        log(f"[bench] cold unsorted comparison: {n_op * cfg.L / tc:.0f} eigenpairs/s")
     if windowed and form == "learned":
         # the plain FP64 method (window from Ritz values, degree 20) on the same operators
         t = time.perf_counter()
@@ -348,7 +395,8 @@ def main():
         "data": "synthetic (seeded GRF coefficient fields)",
         "config": {
             "workload": (f"{cfg.name}: {n_op} operators ({cfg.family}), {ops[0].N}x{ops[0].N} "
-                         f"grid (n={dops[0].n}), L={cfg.L}, k={cfg.k}, degree={degree}, "
+                         f"grid (n={dops[0].n}), L={cfg.L}, k={cfg.k}, degree={degree}"
+                         f"{' (range 16-30)' if cfg.index == 2 else ''}, "
                          f"p0={cfg.p0}, tol={cfg.tol:g}") if not uneven else
                         (f"{cfg.name}: {n_op} operators (half -div(K grad u), half -Laplace u + "
                          f"V u), sides {min(o.N for o in ops)}..{max(o.N for o in ops)}, "
@@ -389,10 +437,15 @@ def main():
             "algorithmic_bytes_per_launch": avg_bytes,
         },
     }
-    if comparison:
+    if comparison and "plain_fp64_value" in comparison:
         comparison["ratio"] = value / comparison["plain_fp64_value"]
         out["config"]["learned"] = dict(train_info, trained_on=n_train, epochs=args.epochs)
         out["comparison"] = comparison
+    elif comparison:
+        comparison["ratio"] = value / comparison["cold_unsorted_value"]
+        out["comparison"] = comparison
+    if cfg.index == 2 and precision == "fp64":
+        out["spmm_isolated"] = isolated_spmm(scsf, torch, h, dops, cfg.k, degree, 32)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, ops, args.cpu_budget,
                                            Ls if uneven else None, ks if uneven else None,

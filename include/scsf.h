@@ -95,6 +95,10 @@ typedef struct scsf_params {
                             raised by at most 2 to the residue mod 3 of the iteration's largest
                             degree.  FP64 only; not with degree hints (SCSF_EINVAL).  0: one
                             degree for the whole block */
+  int32_t cold_start;    /* chained solvers: 0 -> each solve of a chain starts from the previous
+                            solve's k Ritz pairs (Section 3.2); 1 -> every solve starts from a
+                            seeded random block (the unsorted, cold baseline of the paper's
+                            ablations) */
   double tol;            /* lock when ||A v - theta v|| <= tol ||A v|| (App. D.5 metric) */
   uint64_t seed;         /* seed of the random cold-start block and Lanczos start vector */
 } scsf_params;
@@ -169,6 +173,21 @@ int scsf_spmm(scsf_handle *h, const scsf_operator *A, const double *X, int64_t l
 int scsf_filter(scsf_handle *h, const scsf_operator *A, const double *X, int64_t ldx,
                 int32_t ncols, int32_t degree, double lambda, double c, double e,
                 double *Y, int64_t ldy);
+
+/* The filter of Algorithm 1 on B blocks at once, one per operator, in the lockstep form the
+ * chained solvers use (every Chebyshev step is one launch over all B blocks):
+ * Y_b = C_m((A_b - c_b I)/e_b) X_b / C_m((lambda_b - c_b)/e_b), b = 0..B-1.
+ * ops_host: B operators of one kind (host array of device-backed descriptors); sizes may differ.
+ * X, Y: device; block b at X + b*bsx (Y + b*bsy), n_b rows, ncols columns, column-major with
+ * leading dimension ldx (ldy) >= max n_b, bsx >= ldx*ncols, bsy >= ldy*ncols.  The two block
+ * ranges must not overlap; X is not modified.  win_host: host, (lambda_b, c_b, e_b) per block,
+ * e_b > 0, lambda_b != c_b.  ncols <= 256, degree 1..64.  The steps use the handle's filter
+ * tile (scsf_set_tile, scsf_autotune); while profiling is on (scsf_profile_enable) every step
+ * launch is timed with a pair of HIP events on the caller's stream and counted with its
+ * algorithmic bytes.  Synchronises the stream.  SCSF_EINVAL on invalid arguments. */
+int scsf_filter_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t B,
+                        const double *X, int64_t ldx, int64_t bsx, int32_t ncols, int32_t degree,
+                        const double *win_host, double *Y, int64_t ldy, int64_t bsy);
 
 /* Orthonormalisation of Algorithm 3 (QR of [locked | active]): X (n x ncols, in place) is
  * made orthogonal to the nlocked orthonormal columns V (twice-repeated block Gram-Schmidt),

@@ -747,6 +747,7 @@ int check_params(const scsf_params *p, int64_t n) {
   if (p->schedule != SCSF_SCHED_STATIC && p->schedule != SCSF_SCHED_DYNAMIC) return SCSF_EINVAL;
   if (p->adaptive != 0 && p->adaptive != 1) return SCSF_EINVAL;
   if (p->adaptive && p->precision != SCSF_FP64) return SCSF_EINVAL;
+  if (p->cold_start != 0 && p->cold_start != 1) return SCSF_EINVAL;
   return SCSF_OK;
 }
 
@@ -884,11 +885,13 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
       }
       // next operator of the chain, warm-started from this solve (all k Ritz pairs); a
       // different size moves the vectors by bilinear interpolation (square grids) or, where
-      // that is not possible, restarts cold
+      // that is not possible, restarts cold.  cold_start, or a failed solve, restarts cold.
       const OpDev prev = e.h_ops[b];
       e.h_ops[b] = to_dev(ops_host[order_host[pos[b]]]);
       const bool bad = status == SCSF_ENUMERIC || status == SCSF_EBREAKDOWN;
-      if (e.h_ops[b].n != prev.n && !bad) {
+      if (bad || prm->cold_start) {
+        recold.push_back(b);
+      } else if (e.h_ops[b].n != prev.n) {
         if (on_square_grid(prev) && on_square_grid(e.h_ops[b]))
           resize.push_back({b, prev.N, e.h_ops[b].N});
         else
@@ -900,7 +903,6 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
       e.h_done[b] = 0;
       e.h_nconv[b] = 0;
       e.h_lock[b] = 0;
-      if (bad) recold.push_back(b);
       reload = true;
     }
     if (reload) {
@@ -1119,6 +1121,62 @@ int scsf_filter(scsf_handle *h, const scsf_operator *A, const double *X, int64_t
                      en.coef + (size_t)s * 3, s > 0, w0->stream));
   HIPCHK(copy_block(A->n, ncols, ring[degree % 3], en.ld, Y, ldy, false, w0->stream));
   HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
+}
+
+int scsf_filter_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t B,
+                        const double *X, int64_t ldx, int64_t bsx, int32_t ncols, int32_t degree,
+                        const double *win_host, double *Y, int64_t ldy, int64_t bsy) {
+  if (!h || !ops_host || B <= 0 || !X || !Y || !win_host) return SCSF_EINVAL;
+  if (ncols < 0 || ncols > kMaxK || degree < 1 || degree > 64) return SCSF_EINVAL;
+  int64_t nmax = 0;
+  for (int b = 0; b < B; ++b) {
+    STCHK(check_op(&ops_host[b]));
+    if (ops_host[b].kind != ops_host[0].kind) return SCSF_EINVAL;
+    nmax = std::max(nmax, ops_host[b].n);
+    const double lam = win_host[3 * b], c = win_host[3 * b + 1], e = win_host[3 * b + 2];
+    if (!(e > 0.0) || lam == c || !std::isfinite(lam) || !std::isfinite(c)) return SCSF_EINVAL;
+  }
+  if (ldx < nmax || ldy < nmax || bsx < ldx * (int64_t)ncols || bsy < ldy * (int64_t)ncols)
+    return SCSF_EINVAL;
+  if (ncols == 0) return SCSF_OK;
+  // the two block ranges may not overlap
+  const char *x0 = reinterpret_cast<const char *>(X), *y0 = reinterpret_cast<const char *>(Y);
+  const char *x1 = x0 + ((size_t)(B - 1) * bsx + (size_t)(ncols - 1) * ldx + nmax) * 8;
+  const char *y1 = y0 + ((size_t)(B - 1) * bsy + (size_t)(ncols - 1) * ldy + nmax) * 8;
+  if (x0 < y1 && y0 < x1) return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  Engine en;
+  STCHK(en.setup(w0, B, nmax, ncols, 0, degree, ops_host[0].kind, 1.0, 0, 20));
+  en.cpt = tuned_cpt(h, nmax, ncols);
+  en.pot = false;
+  for (int b = 0; b < B; ++b) {
+    en.h_ops[b] = to_dev(ops_host[b]);
+    en.pot = en.pot || ops_host[b].v != nullptr;
+  }
+  STCHK(en.upload_ops());
+  double *win = nullptr;
+  STCHK(grow(w0, B_WIN, (size_t)B * 3, &win));
+  std::copy(win_host, win_host + (size_t)B * 3, en.h_bnd);     // pinned staging (B*4 doubles)
+  HIPCHK(hipMemcpyAsync(win, en.h_bnd, (size_t)B * 3 * sizeof(double), hipMemcpyHostToDevice,
+                        w0->stream));
+  HIPCHK(cheb_coeffs_explicit(B, degree, win, en.coef, w0->stream));
+  for (int b = 0; b < B; ++b)
+    HIPCHK(copy_block(ops_host[b].n, ncols, X + (int64_t)b * bsx, ldx, en.X + (int64_t)b * en.bs,
+                      en.ld, true, w0->stream));
+  double *ring[3] = {en.X, en.Y1, en.Y2};
+  for (int s = 0; s < degree; ++s) {
+    const int slot = prof_begin(w0, en.step_bytes(s > 0, false, s));
+    HIPCHK(spmm_step(en.ops, B, en.kind, nmax, en.Nmax, ring[s % 3], ring[(s + 2) % 3],
+                     ring[(s + 1) % 3], en.ld, en.bs, COLS_ALL, ncols, nullptr,
+                     en.coef + (size_t)s * B * 3, s > 0, w0->stream, nullptr, s, en.cpt, en.pot));
+    prof_end(w0, slot);
+  }
+  for (int b = 0; b < B; ++b)
+    HIPCHK(copy_block(ops_host[b].n, ncols, ring[degree % 3] + (int64_t)b * en.bs, en.ld,
+                      Y + (int64_t)b * bsy, ldy, false, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  prof_drain(w0);
   return SCSF_OK;
 }
 

@@ -39,7 +39,8 @@ class Operator(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("L", c_int32), ("k", c_int32), ("degree", c_int32), ("max_iter", c_int32),
                 ("lanczos_steps", c_int32), ("precision", c_int32), ("schedule", c_int32),
-                ("adaptive", c_int32), ("tol", c_double), ("seed", c_uint64)]
+                ("adaptive", c_int32), ("cold_start", c_int32), ("tol", c_double),
+                ("seed", c_uint64)]
 
 
 class Profile(ctypes.Structure):
@@ -73,6 +74,8 @@ def lib():
             "scsf_set_stream": [vp, vp],
             "scsf_spmm": [vp, POINTER(Operator), vp, i64, i32, vp, i64],
             "scsf_filter": [vp, POINTER(Operator), vp, i64, i32, i32, dbl, dbl, dbl, vp, i64],
+            "scsf_filter_batched": [vp, POINTER(Operator), i32, vp, i64, i64, i32, i32,
+                                    POINTER(c_double), vp, i64, i64],
             "scsf_orthonormalize": [vp, i64, vp, i64, i32, vp, i64, i32],
             "scsf_rayleigh_ritz": [vp, POINTER(Operator), vp, i64, i32, vp, vp],
             "scsf_bounds": [vp, POINTER(Operator), i32, u64, POINTER(c_double)],
@@ -237,6 +240,22 @@ def scsf_filter(h: Handle, A: DeviceOperator, X: torch.Tensor, degree: int, lam:
     return Y
 
 
+def scsf_filter_batched(h: Handle, ops: list, X: torch.Tensor, degree: int, windows,
+                        Y: torch.Tensor | None = None):
+    """X: B x ncols x ldx tensor (block b column-major, rows beyond operator b's n ignored);
+    windows: B x 3 (lambda, c, e).  Returns Y of the same shape."""
+    B, ncols, ld = X.shape
+    assert X.is_contiguous() and len(ops) == B
+    if Y is None:
+        Y = torch.empty_like(X)
+    arr = (Operator * B)(*[o.struct for o in ops])
+    wv = np.ascontiguousarray(np.asarray(windows, dtype=np.float64).reshape(B, 3))
+    _check(lib().scsf_filter_batched(h.ptr, arr, B, _ptr(X), ld, ncols * ld, ncols, int(degree),
+                                     wv.ctypes.data_as(POINTER(c_double)), _ptr(Y), ld, ncols * ld),
+           "scsf_filter_batched")
+    return Y
+
+
 def scsf_orthonormalize(h: Handle, X: torch.Tensor, V: torch.Tensor | None = None):
     """In place: X <- orthonormal basis of (I - V V^T) X.  X must be column-major."""
     assert X.stride(0) == 1
@@ -368,9 +387,11 @@ def scsf_solve_batched(h: Handle, ops: list, Ls, order, chains: int, prm: Params
 
 
 def make_params(L, k, degree=20, tol=1e-8, max_iter=0, lanczos_steps=20, seed=0,
-                precision=SCSF_FP64, schedule=SCSF_SCHED_STATIC, adaptive=0) -> Params:
+                precision=SCSF_FP64, schedule=SCSF_SCHED_STATIC, adaptive=0,
+                cold_start=0) -> Params:
     return Params(L=L, k=k, degree=degree, max_iter=max_iter, lanczos_steps=lanczos_steps,
-                  precision=precision, schedule=schedule, adaptive=adaptive, tol=tol, seed=seed)
+                  precision=precision, schedule=schedule, adaptive=adaptive,
+                  cold_start=cold_start, tol=tol, seed=seed)
 
 
 def scsf_solve(h: Handle, A: DeviceOperator, prm: Params, X_prev=None, theta_prev=None,

@@ -35,8 +35,29 @@ def test_library_exports_every_declared_symbol():
     assert lib.scsf_status_string(-3) == b"not converged within max_iter"
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes structures against the C compiler's layout of the header's structures."""
+    import shutil
+    import subprocess
     from paper_2510_23215_amd import scsf
-    assert ctypes.sizeof(scsf.Operator) == 4 + 4 + 8 + 7 * 8 + 8
-    assert ctypes.sizeof(scsf.Params) == 7 * 4 + 4 + 8 + 8
-    assert ctypes.sizeof(scsf.Stats) == 6 * 4 + 8 + 8 + 8
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"scsf_operator": scsf.Operator, "scsf_params": scsf.Params,
+               "scsf_stats": scsf.Stats, "scsf_profile": scsf.Profile}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "scsf.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

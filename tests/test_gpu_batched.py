@@ -5,7 +5,8 @@ import numpy as np
 import pytest
 
 import scsf_inputs as si
-from oracle import operator as O, eig as E, sort as S, transfer as T
+from oracle import operator as O, eig as E, sort as S, transfer as T, chebyshev as Ch, \
+    lanczos as Lz
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -209,3 +210,73 @@ def test_autotune_picks_valid_settings_and_solves():
         A = O.assemble(o)
         w, V = E.smallest_eigenpairs(A, Ls[i] + 6, method="dense")
         check_pairs(A, evals[i], evecs[i].t(), Ls[i], 1e-8, w, V)
+
+
+# ------------------------------------------------------------------------------ batched filter
+@pytest.mark.parametrize("family,tile", [("five", 1), ("five", 2), ("five", 4), ("nine", 2)])
+def test_filter_batched_matches_oracle(family, tile):
+    """B blocks of different grid sides (and, for the 5-point kind, operators with and without
+    a potential) in one launch per step, against the oracle's filter of each block."""
+    say("filter batched", family, "tile", tile)
+    h = scsf.Handle()
+    scsf.scsf_set_tile(h, tile)
+    if family == "five":
+        ops = [si.divk_operator(21, 8, 1), si.potential_operator(30, 8, 2),
+               si.divk_operator(17, 8, 3), si.potential_operator(26, 8, 4)]
+    else:
+        ops = [si.aniso_operator(N, 8, 10 + N) for N in (19, 24, 13)]
+    B, ncols, m = len(ops), 13, 20
+    ld = max(o.n for o in ops)
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal((B, ncols, ld))
+    wins = []
+    for o in ops:
+        A = O.assemble(o)
+        ub = Lz.gershgorin_upper(A)
+        lam, alpha = 0.05 * ub, 0.3 * ub
+        wins.append((lam, (alpha + ub) / 2, (ub - alpha) / 2))
+    Xd = torch.tensor(X, device="cuda")
+    Y = host(scsf.scsf_filter_batched(h, [scsf.DeviceOperator(o) for o in ops], Xd, m, wins))
+    np.testing.assert_array_equal(host(Xd), X)
+    for b, o in enumerate(ops):
+        A = O.assemble(o)
+        ref = Ch.filter_block(A, X[b, :, :o.n].T, m, *wins[b])
+        assert np.max(np.abs(Y[b, :, :o.n].T - ref)) <= 1e-11 * np.max(np.abs(ref)), b
+
+
+def test_filter_batched_errors():
+    h = scsf.Handle()
+    ops = [scsf.DeviceOperator(si.divk_operator(12, 8, 1)) for _ in range(2)]
+    X = torch.zeros((2, 3, 144), dtype=torch.float64, device="cuda")
+    with pytest.raises(scsf.ScsfError):                     # e <= 0
+        scsf.scsf_filter_batched(h, ops, X, 5, [(1.0, 5.0, 0.0), (1.0, 5.0, 1.0)])
+    with pytest.raises(scsf.ScsfError):                     # Y overlapping X
+        scsf.scsf_filter_batched(h, ops, X, 5, [(1.0, 5.0, 1.0)] * 2, Y=X)
+    mixed = [ops[0], scsf.DeviceOperator(si.aniso_operator(12, 8, 2))]
+    with pytest.raises(scsf.ScsfError):                     # kinds differ
+        scsf.scsf_filter_batched(h, mixed, X, 5, [(1.0, 5.0, 1.0)] * 2)
+
+
+# ------------------------------------------------------------------------------ cold starts
+def test_cold_start_sequence_equals_separate_solves():
+    """cold_start = 1: every solve of a chain starts from the slot's seeded random block, so
+    one chain over six operators gives the same pairs and iteration counts as six one-operator
+    runs."""
+    say("cold start sequence")
+    h = scsf.Handle()
+    scsf.scsf_set_lanes(h, 1)
+    cfg = si.CONFIGS[1]
+    ops = si.operators(cfg, 6)
+    dops = [scsf.DeviceOperator(o) for o in ops]
+    prm = scsf.make_params(cfg.L, cfg.k, cfg.degree, cfg.tol, seed=4, cold_start=1)
+    ev, vec, st = scsf.scsf_solve_sequence(h, dops, np.arange(6), 1, prm)
+    for i, o in enumerate(ops):
+        e1, v1, s1 = scsf.scsf_solve_sequence(h, [dops[i]], [0], 1, prm)
+        assert s1[0]["iterations"] == st[i]["iterations"]
+        np.testing.assert_allclose(host(ev[i]), host(e1[0]), rtol=1e-12)
+        A = O.assemble(o)
+        w, V = E.smallest_eigenpairs(A, cfg.L + 8)
+        check_pairs(A, ev[i], vec[i].t(), cfg.L, cfg.tol, w, V)
+    with pytest.raises(scsf.ScsfError):
+        scsf.scsf_solve_sequence(h, dops, np.arange(6), 1,
+                                 scsf.make_params(cfg.L, cfg.k, 20, cfg.tol, cold_start=2))

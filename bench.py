@@ -191,6 +191,9 @@ def main():
     ap.add_argument("--compare", choices=["on", "off"], default="on",
                     help="working-size workload: also time the same operators solved cold and "
                          "unsorted (outside the timed steps)")
+    ap.add_argument("--spmm-isolated", choices=["on", "off"], default="on",
+                    help="working-size workload: also time the filter step alone on 32 blocks "
+                         "(after the timed steps)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -444,7 +447,7 @@ def main():
     elif comparison:
         comparison["ratio"] = value / comparison["cold_unsorted_value"]
         out["comparison"] = comparison
-    if cfg.index == 2 and precision == "fp64":
+    if cfg.index == 2 and precision == "fp64" and args.spmm_isolated == "on":
         out["spmm_isolated"] = isolated_spmm(scsf, torch, h, dops, cfg.k, degree, 32)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, ops, args.cpu_budget,

@@ -277,9 +277,10 @@ int scsf_block_width(int32_t L);
 /* Autotuner (project-specific; the paper fixes its block widths by hand, Section 4).  For
  * every distinct L of the dataset (ops_host / L_host / order_host as in scsf_solve_batched):
  *  - tiles: the LDS-staged filter step is timed with 1, 2 and 4 block columns per thread (and
- *    8, 4, 2 grid nodes per thread) on 8 copies of the largest operator of each size bucket
- *    (n <= 4096, <= 16384, larger) for each width bucket (k <= 48, <= 96, <= 160, larger) it
- *    meets, and the fastest is kept;
+ *    8, 4, 2 grid nodes per thread) on 8 to 64 copies (a working set of about 768 MB) of the
+ *    largest operator of each size bucket (n <= 4096, <= 16384, larger) for each width
+ *    bucket (k <= 48, <= 96, <= 160, larger) it meets; another tile replaces the default 4
+ *    only when it is at least 10% faster;
  *  - widths: the first `probe` operators of the L group (in order_host order) are solved as
  *    one warm-started chain with block widths 1.2 L, 1.35 L and 1.5 L (rounded up to a
  *    multiple of 8, at most 256 and at most the smallest n), and the width with the least
@@ -292,11 +293,11 @@ int scsf_autotune(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
                   int32_t probe);
 /* The tuned block width for L (scsf_block_width(L) when L was never tuned). */
 int scsf_tuned_width(scsf_handle *h, int32_t L);
-/* The tuned filter-step tile (block columns per thread: 1, 2 or 4; default 2) for size n and
- * width k. */
 /* Set the filter-step tile (1, 2 or 4) for every size and width, overriding the autotuner
  * (for reproducible measurements). */
 int scsf_set_tile(scsf_handle *h, int32_t tile);
+/* The tuned filter-step tile (block columns per thread: 1, 2 or 4; default 4) for size n and
+ * width k. */
 int scsf_tuned_tile(scsf_handle *h, int64_t n, int32_t k);
 
 /* Bilinear transfer of ncols nodal fields between interior grids of the unit square: column

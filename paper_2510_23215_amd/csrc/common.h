@@ -58,7 +58,7 @@ hipError_t spmm_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_
                      const double *X, const double *Z, double *Y, int64_t ld, int64_t bs,
                      int32_t mode, int32_t k, const int32_t *lock, const double *coef,
                      bool has_z, hipStream_t st, const int32_t *mdeg = nullptr,
-                     int32_t step = 0, int tile = 2, bool pot = true,
+                     int32_t step = 0, int tile = 4, bool pot = true,
                      const int32_t *cdeg = nullptr, int32_t mtot = 0);
 
 // FP32 variant of the step for the mixed-precision filter; with R non-null the step adds the
@@ -67,7 +67,7 @@ hipError_t spmm_step32(const OpDev *ops, int B, int32_t kind, int64_t nmax, int3
                        const float *X, const float *Z, float *Y, int64_t ld, int64_t bs,
                        int32_t mode, int32_t k, const int32_t *lock, const double *coef,
                        bool has_z, const float *R, const double *src, hipStream_t st,
-                       const int32_t *mdeg = nullptr, int32_t step = 0, int tile = 2,
+                       const int32_t *mdeg = nullptr, int32_t step = 0, int tile = 4,
                        bool pot = true);
 
 // Mixed-precision filter helpers (residual form of the recurrence, see misc.hip):

@@ -58,7 +58,7 @@ struct scsf_handle {
   bool graphs = true;                    // outer iterations of chained solves as HIP graphs
   int eig = SCSF_EIG_JACOBI;             // Rayleigh-Ritz eigensolver
   // autotuned settings: SpMM columns per thread per (k bucket, n bucket), block width per L
-  int32_t cpt[4][3] = {{2, 2, 2}, {2, 2, 2}, {2, 2, 2}, {2, 2, 2}};
+  int32_t cpt[4][3] = {{4, 4, 4}, {4, 4, 4}, {4, 4, 4}, {4, 4, 4}};
   std::vector<std::pair<int32_t, int32_t>> widths;
   std::vector<Workspace *> ws;           // ws[0] runs on the caller's stream; ws[1..] are the
                                          // lanes of chained solves (private streams)
@@ -1567,8 +1567,8 @@ static int tune_tile(Workspace *w, const scsf_operator &rep, int32_t k, int32_t 
   }
   float best_ms = 1e30f;
   int rc = SCSF_OK;
-  *best = 2;
-  for (int c : {2, 1, 4}) {            // the default first: another tile must beat it by 10%
+  *best = 4;
+  for (int c : {4, 2, 1}) {            // the default first: another tile must beat it by 10%
     auto step = [&] {
       return spmm_step(e.ops, B, e.kind, e.n, e.Nmax, e.X, e.Y2, e.Y1, e.ld, e.bs, COLS_ALL, k,
                        nullptr, e.unit, true, e.st, nullptr, 0, c, rep.v != nullptr);
@@ -1581,7 +1581,7 @@ static int tune_tile(Workspace *w, const scsf_operator &rep, int32_t k, int32_t 
         hipEventSynchronize(t1) != hipSuccess) { rc = SCSF_EHIP; break; }
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, t0, t1) != hipSuccess) { rc = SCSF_EHIP; break; }
-    if (c == 2) best_ms = ms;
+    if (c == 4) best_ms = ms;
     else if (ms < 0.90f * best_ms) { best_ms = ms; *best = c; }
   }
   (void)hipStreamSynchronize(e.st);

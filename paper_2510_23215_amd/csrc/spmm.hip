@@ -151,6 +151,8 @@ __global__ void __launch_bounds__(256) spmm_step_kernel(
 // kStencil5V (5-point, potential where op.v is set) or SCSF_STENCIL9.
 constexpr int kStencil5V = 105;
 
+// Z (the block two steps back) and Y are touched once per step: streamed with non-temporal
+// loads and stores, so they do not displace the staged tiles' halos and coefficients from L2.
 template <int KIND, int JN, typename T, bool SRC, bool HZ>
 __device__ inline void lds_node(const OpDev &op, const T *sx, int span, int e, int64_t p,
                                 int N, T a, T bc, T g, const T *srcj,
@@ -174,9 +176,9 @@ __device__ inline void lds_node(const OpDev &op, const T *sx, int span, int e, i
       const T ax = cd * xv - mw * sj[e - 1] - me * sj[e + 1] - ms * sj[e - N] - mn * sj[e + N];
       const int64_t o = off + (int64_t)j * ld + p;
       T r = a * ax + bc * xv;
-      if constexpr (HZ) r += g * Z[o];
+      if constexpr (HZ) r += g * __builtin_nontemporal_load(&Z[o]);
       if constexpr (SRC) r += srcj[j] * R[o];
-      Y[o] = r;
+      __builtin_nontemporal_store(r, &Y[o]);
     }
   } else {
     double c64[9];
@@ -196,9 +198,9 @@ __device__ inline void lds_node(const OpDev &op, const T *sx, int span, int e, i
       for (int q = 0; q < 9; ++q) ax += c9[q] * sj[e + (q / 3 - 1) * N + (q % 3 - 1)];
       const int64_t o = off + (int64_t)j * ld + p;
       T r = a * ax + bc * sj[e];
-      if constexpr (HZ) r += g * Z[o];
+      if constexpr (HZ) r += g * __builtin_nontemporal_load(&Z[o]);
       if constexpr (SRC) r += srcj[j] * R[o];
-      Y[o] = r;
+      __builtin_nontemporal_store(r, &Y[o]);
     }
   }
 }
@@ -245,13 +247,28 @@ __global__ void __launch_bounds__(256) spmm_lds_kernel(
   const int tid = threadIdx.x;
   const int64_t off = (int64_t)b * bs + (int64_t)(c0 + j0) * ld;
   const T *xb = X + off;
-  // the columns' loads interleaved, so every thread keeps CPT of them in flight
-  for (int e = tid; e < span; e += 256) {
-    const int64_t q = p0 - H + e;
-    const bool in = q >= 0 && q < n;
+  // U rows of 256 nodes per pass, every load of a pass issued before the first LDS store:
+  // each thread keeps U * CPT loads in flight instead of CPT
+  constexpr int U = 4;
+  for (int e0 = tid; e0 < span; e0 += 256 * U) {
+    T v[U][CPT];
 #pragma unroll
-    for (int j = 0; j < CPT; ++j)
-      if (act[j]) sx[j * span + e] = in ? xb[(int64_t)j * ld + q] : (T)0;
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * 256;
+      const int64_t q = p0 - H + e;
+      const bool in = e < span && q >= 0 && q < n;
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) v[u][j] = (act[j] && in) ? xb[(int64_t)j * ld + q] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * 256;
+      if (e < span) {
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)
+          if (act[j]) sx[j * span + e] = v[u][j];
+      }
+    }
   }
   __syncthreads();
   const T a = (T)coef[3 * b + 0], bc = (T)coef[3 * b + 1], g = (T)coef[3 * b + 2];

@@ -228,6 +228,29 @@ int scsf_sort(scsf_handle *h, const double *fields, int32_t n_op, int32_t channe
 int scsf_order_features(scsf_handle *h, const double *feats, int32_t n_op, int32_t flen,
                         int32_t start, int32_t *order_host);
 
+/* Sort diagnostics (App. F; the appendix on the truncation threshold p0).
+ *
+ * scsf_highfreq_ratio: for each operator, ||F_high||_F / ||F||_F over its channels, where F is
+ * the 2-D DFT of each p x p field and F_high holds the coefficients whose signed frequency
+ * (index a read as a for a <= p/2, a - p above) is >= p0 in absolute value on either axis.
+ * fields: device, (n_op, channels, p, p) row-major; ratio: device, n_op doubles.  A field
+ * that is zero everywhere gives 0.  Synchronises the handle's stream.
+ *
+ * The full greedy order of Section 3.1 (no truncation) is scsf_order_features on the raw
+ * fields (flen = channels * p * p): the spatial Frobenius distance.
+ *
+ * scsf_subspace_distance: the one-sided distance ||(I - U U^T) V||_2 (the sine of the largest
+ * principal angle) between the spans of the first q columns of blocks a_host[i] and b_host[i]
+ * of X, i = 0..P-1; the columns must be orthonormal (eigenvectors from the solvers).  X:
+ * device, n_blocks blocks at stride bsx, each n x (>= q) column-major with leading dimension
+ * ldx >= n, bsx >= ldx * q; 1 <= q <= min(32, n).  out_host: host, P doubles.  SCSF_EINVAL on
+ * an index outside [0, n_blocks) or another invalid argument. */
+int scsf_highfreq_ratio(scsf_handle *h, const double *fields, int32_t n_op, int32_t channels,
+                        int32_t p, int32_t p0, double *ratio);
+int scsf_subspace_distance(scsf_handle *h, int64_t n, int32_t q, const double *X, int64_t ldx,
+                           int64_t bsx, int32_t n_blocks, const int32_t *a_host,
+                           const int32_t *b_host, int32_t P, double *out_host);
+
 /* ---------------------------------------------------------------------------------------
  * Solvers.
  * ------------------------------------------------------------------------------------- */

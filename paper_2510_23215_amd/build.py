@@ -13,8 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscsf.so")
 ARCH = "gfx950"
 
-SOURCES = ["spmm.hip", "gemm.hip", "dense.hip", "tridiag.hip", "misc.hip", "sort.hip", "cnn.hip",
-           "solver.cpp"]
+SOURCES = ["spmm.hip", "gemm.hip", "dense.hip", "tridiag.hip", "misc.hip", "sort.hip", "diag.hip",
+           "cnn.hip", "solver.cpp"]
 
 # Packed FP32 instructions are disabled for all device code (the compiler would otherwise
 # form v_pk_* FP32 operations from scalar float code).

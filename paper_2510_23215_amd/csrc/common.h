@@ -201,6 +201,13 @@ hipError_t gather_columns(int64_t n, int32_t ncols, const double *src, int64_t l
                           const int32_t *perm, double *dst, int64_t ldd, hipStream_t st);
 
 // Truncated DFT features and the greedy order.
+// sort diagnostics (diag.hip)
+constexpr int kMaxDistQ = 32;                   // largest subspace dimension of the distance
+hipError_t highfreq_ratio(const double *fields, int32_t n_op, int32_t channels, int32_t p,
+                          int32_t p0, double *ratio, hipStream_t st);
+hipError_t subspace_distance(int64_t n, int32_t q, const double *X, int64_t ld, int64_t bs,
+                             const int32_t *pa, const int32_t *pb, int32_t P, double *out,
+                             hipStream_t st);
 hipError_t dft_features(const double *fields, int32_t n_op, int32_t channels, int32_t p,
                         int32_t p0, double *feats, hipStream_t st);
 hipError_t pair_distances(const double *feats, int32_t n_op, int32_t flen, double *D,

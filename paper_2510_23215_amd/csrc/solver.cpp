@@ -1752,6 +1752,39 @@ int scsf_interpolate(scsf_handle *h, int32_t N0, int32_t N1, int32_t ncols, cons
   return SCSF_OK;
 }
 
+int scsf_highfreq_ratio(scsf_handle *h, const double *fields, int32_t n_op, int32_t channels,
+                        int32_t p, int32_t p0, double *ratio) {
+  if (!h || !fields || !ratio || n_op <= 0 || channels <= 0 || p <= 0 || p0 <= 0)
+    return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  HIPCHK(highfreq_ratio(fields, n_op, channels, p, p0, ratio, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
+}
+
+int scsf_subspace_distance(scsf_handle *h, int64_t n, int32_t q, const double *X, int64_t ldx,
+                           int64_t bsx, int32_t n_blocks, const int32_t *a_host,
+                           const int32_t *b_host, int32_t P, double *out_host) {
+  if (!h || !X || !a_host || !b_host || !out_host || n <= 0 || q <= 0 || q > kMaxDistQ ||
+      q > n || ldx < n || bsx < ldx * (int64_t)q || n_blocks <= 0 || P < 0)
+    return SCSF_EINVAL;
+  for (int i = 0; i < P; ++i)
+    if (a_host[i] < 0 || a_host[i] >= n_blocks || b_host[i] < 0 || b_host[i] >= n_blocks)
+      return SCSF_EINVAL;
+  if (P == 0) return SCSF_OK;
+  Workspace *w0 = h->ws[0];
+  int32_t *idx = nullptr;
+  double *out = nullptr;
+  STCHK(grow(w0, B_SORTO, (size_t)2 * P, &idx));
+  STCHK(grow(w0, B_SORTD, (size_t)P, &out));
+  HIPCHK(hipMemcpyAsync(idx, a_host, (size_t)P * 4, hipMemcpyHostToDevice, w0->stream));
+  HIPCHK(hipMemcpyAsync(idx + P, b_host, (size_t)P * 4, hipMemcpyHostToDevice, w0->stream));
+  HIPCHK(subspace_distance(n, q, X, ldx, bsx, idx, idx + P, P, out, w0->stream));
+  HIPCHK(hipMemcpyAsync(out_host, out, (size_t)P * 8, hipMemcpyDeviceToHost, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  return SCSF_OK;
+}
+
 int scsf_order_features(scsf_handle *h, const double *feats, int32_t n_op, int32_t flen,
                         int32_t start, int32_t *order_host) {
   if (!h || !feats || !order_host || n_op <= 0 || flen <= 0) return SCSF_EINVAL;

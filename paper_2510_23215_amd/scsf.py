@@ -76,6 +76,9 @@ def lib():
             "scsf_filter": [vp, POINTER(Operator), vp, i64, i32, i32, dbl, dbl, dbl, vp, i64],
             "scsf_filter_batched": [vp, POINTER(Operator), i32, vp, i64, i64, i32, i32,
                                     POINTER(c_double), vp, i64, i64],
+            "scsf_highfreq_ratio": [vp, vp, i32, i32, i32, i32, vp],
+            "scsf_subspace_distance": [vp, i64, i32, vp, i64, i64, i32, POINTER(c_int32),
+                                       POINTER(c_int32), i32, POINTER(c_double)],
             "scsf_orthonormalize": [vp, i64, vp, i64, i32, vp, i64, i32],
             "scsf_rayleigh_ritz": [vp, POINTER(Operator), vp, i64, i32, vp, vp],
             "scsf_bounds": [vp, POINTER(Operator), i32, u64, POINTER(c_double)],
@@ -282,6 +285,34 @@ def scsf_bounds(h: Handle, A: DeviceOperator, steps: int = 20, seed: int = 0):
     out = (c_double * 4)()
     _check(lib().scsf_bounds(h.ptr, A.ref(), int(steps), c_uint64(seed), out), "scsf_bounds")
     return {"gershgorin": out[0], "lanczos": out[1], "theta_min": out[2], "beta": out[3]}
+
+
+def scsf_highfreq_ratio(h: Handle, fields: torch.Tensor, p0: int) -> torch.Tensor:
+    """fields: (n_op, C, p, p) float64 device tensor -> (n_op,) high-frequency norm ratio."""
+    fields = fields.contiguous()
+    n_op, C, p, _ = fields.shape
+    out = torch.empty(n_op, device=fields.device, dtype=torch.float64)
+    _check(lib().scsf_highfreq_ratio(h.ptr, _ptr(fields), n_op, C, p, int(p0), _ptr(out)),
+           "scsf_highfreq_ratio")
+    return out
+
+
+def scsf_subspace_distance(h: Handle, evecs: torch.Tensor, q: int, pairs) -> np.ndarray:
+    """evecs: (n_blocks, L, n) tensor as returned by the solvers (block i = n x L column-major);
+    pairs: sequence of (a, b) block indices -> one-sided distances of the first q columns."""
+    assert evecs.is_contiguous()
+    nb, L, n = evecs.shape
+    pairs = np.asarray(pairs, dtype=np.int32).reshape(-1, 2)
+    P = pairs.shape[0]
+    a = np.ascontiguousarray(pairs[:, 0])
+    b = np.ascontiguousarray(pairs[:, 1])
+    out = np.zeros(max(P, 1), dtype=np.float64)
+    _check(lib().scsf_subspace_distance(h.ptr, n, int(q), _ptr(evecs), n, L * n, nb,
+                                        a.ctypes.data_as(POINTER(c_int32)),
+                                        b.ctypes.data_as(POINTER(c_int32)), P,
+                                        out.ctypes.data_as(POINTER(c_double))),
+           "scsf_subspace_distance")
+    return out[:P]
 
 
 def scsf_features(h: Handle, fields: torch.Tensor, p0: int):

@@ -99,7 +99,36 @@ def assemble9(op) -> sp.csr_matrix:
     return A.tocsr()
 
 
+def dirichlet_laplacian(N: int) -> sp.csr_matrix:
+    """The 5-point Dirichlet Laplacian / h^2 (positive definite sign) as the Kronecker sum of
+    the 1-D second-difference matrix tridiag(-1, 2, -1) / h^2 (App. C)."""
+    h = 1.0 / (N + 1)
+    T = sp.diags([-np.ones(N - 1), 2.0 * np.ones(N), -np.ones(N - 1)], [-1, 0, 1]) / (h * h)
+    I = sp.identity(N)
+    return (sp.kron(I, T) + sp.kron(T, I)).tocsr()
+
+
+def assemble_plate_pair(op):
+    """(K, M) of the thin-plate vibration problem K u = lambda M u (App. D.2, item 4):
+    K = L diag(D) L discretises del^2 (D del^2 u) with simply supported edges (u = 0 and
+    del^2 u = 0 on the boundary: the same Dirichlet Laplacian L on both sides), M = diag(rho)
+    the lumped mass."""
+    L = dirichlet_laplacian(op.N)
+    K = (L @ sp.diags(np.asarray(op.D, np.float64).ravel()) @ L).tocsr()
+    M = sp.diags(np.asarray(op.rho, np.float64).ravel()).tocsr()
+    return K, M
+
+
+def assemble_plate(op) -> sp.csr_matrix:
+    """The standard symmetric form A = M^{-1/2} K M^{-1/2}: A y = lambda y with y = M^{1/2} u."""
+    K, M = assemble_plate_pair(op)
+    s = sp.diags(1.0 / np.sqrt(np.asarray(op.rho, np.float64).ravel()))
+    return (s @ K @ s).tocsr()
+
+
 def assemble(op) -> sp.csr_matrix:
+    if hasattr(op, "rho"):
+        return assemble_plate(op)
     if hasattr(op, "wx"):
         return assemble5(op)
     return assemble9(op)

@@ -8,7 +8,9 @@ finite-difference operators they define:
 * generalized Poisson  -div(K grad u) = lambda u, K = exp(g), Dirichlet boundary
   (paper App. D.2 "Dataset", item 1; Section 2.1 for the discretisation idea);
 * Schroedinger-type    -Laplace(u) + V u = lambda u, V = exp(g) rescaled to [0, 100];
-* anisotropic elliptic -div(K grad u) with a 2x2 SPD tensor field K (9-point Q1 stencil).
+* anisotropic elliptic -div(K grad u) with a 2x2 SPD tensor field K (9-point Q1 stencil);
+* thin-plate vibration  del^2 (D del^2 u) = lambda rho u, D = exp(g1), rho = exp(g2) on the
+  nodes (App. D.2 "Dataset", item 4); only the two nodal fields are drawn here.
 
 g is a cosine series  g(x,y) = sum_{k1,k2<M} xi_{k1k2} (1+k1^2+k2^2)^-1 cos(pi k1 x) cos(pi k2 y),
 xi ~ N(0,1), so the coefficient variance is (1+k1^2+k2^2)^-2 -- a Gaussian random field
@@ -96,6 +98,21 @@ class Stencil9:
         return self.N * self.N
 
 
+@dataclasses.dataclass
+class Plate:
+    """Thin-plate vibration operator on an N x N interior grid: nodal flexural rigidity D and
+    nodal density rho (the lumped mass), both (N, N)."""
+    N: int
+    D: np.ndarray             # (N, N)
+    rho: np.ndarray           # (N, N)
+    field: np.ndarray         # (2, N, N): D and rho, used by the sort
+    family: str = "plate"
+
+    @property
+    def n(self) -> int:
+        return self.N * self.N
+
+
 def _face_grids(N: int):
     h = 1.0 / (N + 1)
     node = (np.arange(N) + 1.0) * h            # node coordinates
@@ -160,6 +177,16 @@ def aniso_operator(N: int, modes: int, seed: int) -> Stencil9:
     n11, n12, n22 = aniso_tensor(w1, w2, wt, node[None, :], node[:, None])
     field = np.stack([n11, n12, n22], axis=0)
     return Stencil9(N=N, cell=cell, field=field)
+
+
+def plate_operator(N: int, modes: int, seed: int) -> Plate:
+    """Rigidity D = exp(g1) and density rho = exp(g2 / 2) at the nodes (two independent GRFs)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w1, w2 = grf_xi(rng, modes), grf_xi(rng, modes)
+    _, node, _ = _face_grids(N)
+    D = np.exp(grf_eval(w1, node[None, :], node[:, None]))
+    rho = np.exp(0.5 * grf_eval(w2, node[None, :], node[:, None]))
+    return Plate(N=N, D=D, rho=rho, field=np.stack([D, rho]))
 
 
 def gaussian_block(n: int, k: int, seed: int) -> np.ndarray:

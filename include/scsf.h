@@ -43,7 +43,9 @@ enum scsf_status {
 enum scsf_op_kind {
   SCSF_STENCIL5 = 1,     /* conservative 5-point -div(K grad u) + v u on an nx x nx grid */
   SCSF_STENCIL9 = 2,     /* 9-point Q1 stiffness of cell tensors / h^2 on an nx x nx grid */
-  SCSF_CSR = 3           /* general symmetric CSR matrix (both triangles stored) */
+  SCSF_CSR = 3,          /* general symmetric CSR matrix (both triangles stored) */
+  SCSF_PLATE = 4         /* thin-plate vibration del^2(D del^2 u) = lambda rho u (App. D.2) in
+                            standard form M^{-1/2} K M^{-1/2} on an nx x nx grid */
 };
 
 enum scsf_precision { SCSF_FP64 = 0, SCSF_MIXED = 1 };
@@ -66,6 +68,14 @@ enum scsf_eigensolver { SCSF_EIG_JACOBI = 0, SCSF_EIG_TRIDIAG = 1 };
  *   STENCIL9: cell[(cy*(nx+1) + cx)*3 + {0,1,2}] = (K11, K12, K22) of cell (cy, cx), the square
  *             between node rows cy-1, cy and columns cx-1, cx; A = Q1 stiffness / h^2.
  *   CSR:      row_ptr[n+1], col_idx[nnz], val[nnz], symmetric.
+ *   PLATE:    wx[p] = flexural rigidity D > 0 and wy[p] = density rho > 0 at node p (n each);
+ *             v must be NULL.  K = L diag(D) L with L the 5-point Dirichlet Laplacian / h^2
+ *             (simply supported edges: u = 0 and del^2 u = 0 on the boundary), M = diag(rho)
+ *             (lumped mass).  The solvers work on A = M^{-1/2} K M^{-1/2} (same eigenvalues,
+ *             A y = lambda y with y = M^{1/2} u) and return u = M^{-1/2} y, M-orthonormal
+ *             (u^T M u = I); warm-start blocks (X_prev / X_next) and scsf_spmm / scsf_filter
+ *             use the standard-form vectors y, and residuals are those of A.  FP64 only
+ *             (SCSF_MIXED gives SCSF_EINVAL); nx <= 600.
  * All coefficient arrays are device memory and must stay valid during the call.
  */
 typedef struct scsf_operator {

@@ -185,6 +185,9 @@ hipError_t copy_block(int64_t n, int32_t ncols, const double *src, int64_t lds, 
 // Canonical sign: flip each column so that its largest-magnitude entry (lowest index on
 // ties) is positive.
 hipError_t canonical_sign(int64_t n, int32_t ncols, double *X, int64_t ld, hipStream_t st);
+// X[p, c] /= sqrt(rho[p]) for p < n, c < ncols (plate eigenvectors to M-orthonormal form)
+hipError_t scale_rows_rsqrt(int64_t n, int32_t ncols, double *X, int64_t ld, const double *rho,
+                            hipStream_t st);
 
 hipError_t fill_int(int32_t *a, int32_t v, int32_t count, hipStream_t st);
 // Per-column degrees of the adaptive filter for the next outer iteration (cdeg: B*k, columns

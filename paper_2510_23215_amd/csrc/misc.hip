@@ -250,6 +250,8 @@ hipError_t bounds(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t s
     bounds_kernel<SCSF_STENCIL5><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out);
   else if (kind == SCSF_STENCIL9)
     bounds_kernel<SCSF_STENCIL9><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out);
+  else if (kind == SCSF_PLATE)
+    bounds_kernel<SCSF_PLATE><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out);
   else
     bounds_kernel<SCSF_CSR><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out);
   return hipGetLastError();
@@ -323,6 +325,19 @@ __global__ void __launch_bounds__(256) sign_kernel(int64_t n, double *__restrict
   __syncthreads();
   if (flip)
     for (int64_t p = threadIdx.x; p < n; p += blockDim.x) x[p] = -x[p];
+}
+
+__global__ void scale_rows_kernel(int64_t n, double *__restrict__ X, int64_t ld,
+                                  const double *__restrict__ rho) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) X[(int64_t)blockIdx.y * ld + p] /= sqrt(rho[p]);
+}
+
+hipError_t scale_rows_rsqrt(int64_t n, int32_t ncols, double *X, int64_t ld, const double *rho,
+                            hipStream_t st) {
+  if (n <= 0 || ncols <= 0) return hipSuccess;
+  scale_rows_kernel<<<dim3((unsigned)ceil_div(n, 256), ncols), 256, 0, st>>>(n, X, ld, rho);
+  return hipGetLastError();
 }
 
 hipError_t canonical_sign(int64_t n, int32_t ncols, double *X, int64_t ld, hipStream_t st) {

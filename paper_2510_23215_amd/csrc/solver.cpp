@@ -120,11 +120,19 @@ int check_op(const scsf_operator *A) {
     if (A->nx <= 0 || (int64_t)A->nx * A->nx != A->n || !A->cell) return SCSF_EINVAL;
   } else if (A->kind == SCSF_CSR) {
     if (!A->row_ptr || !A->col_idx || !A->val || A->nnz < 0) return SCSF_EINVAL;
+  } else if (A->kind == SCSF_PLATE) {
+    if (A->nx <= 0 || A->nx > 600 || (int64_t)A->nx * A->nx != A->n || !A->wx || !A->wy || A->v)
+      return SCSF_EINVAL;
   } else {
     return SCSF_EINVAL;
   }
   if (A->n > ((int64_t)1 << 31) - 64) return SCSF_EINVAL;
   return SCSF_OK;
+}
+
+// The plate family runs in FP64 only.
+int check_op_precision(const scsf_operator &A, const scsf_params *p) {
+  return (A.kind == SCSF_PLATE && p->precision != SCSF_FP64) ? SCSF_EINVAL : SCSF_OK;
 }
 
 OpDev to_dev(const scsf_operator &A) {
@@ -443,7 +451,8 @@ struct Engine {
         }
         vec += nb * (double)cols;
         coeff += (kind == SCSF_STENCIL5) ? (h_ops[b].v ? 3.0 : 2.0) * nb
-                 : (kind == SCSF_STENCIL9) ? 3.0 * nb : 0.0;
+                 : (kind == SCSF_STENCIL9 || kind == SCSF_PLATE) ? (kind == SCSF_PLATE ? 2.0 : 3.0) * nb
+                 : 0.0;
       }
     if (fp32)  // e_i, e_{i-1}, r read, e_{i+1} written in FP32
       return 4.0 * (has_prev ? 4.0 : 3.0) * vec + 8.0 * coeff;
@@ -724,6 +733,8 @@ struct Engine {
     HIPCHK(gather_columns(h_rows[b], L, X + (int64_t)b * bs, ld, perm_d + (size_t)b * k, evecs,
                           ldo, st));
     HIPCHK(canonical_sign(h_rows[b], L, evecs, ldo, st));
+    if (h_ops[b].kind == SCSF_PLATE)             // u = M^{-1/2} y, M-orthonormal
+      HIPCHK(scale_rows_rsqrt(h_rows[b], L, evecs, ldo, h_ops[b].wy, st));
     HIPCHK(hipStreamSynchronize(st));                 // the copies above read pinned memory
     if (maxres) *maxres = mr;
     return SCSF_OK;
@@ -766,7 +777,8 @@ struct Group {
 
 // Grid stencils on square grids: the Ritz vectors can move between sides by interpolation.
 bool on_square_grid(const OpDev &o) {
-  return (o.kind == SCSF_STENCIL5 || o.kind == SCSF_STENCIL9) && (int64_t)o.N * o.N == o.n;
+  return (o.kind == SCSF_STENCIL5 || o.kind == SCSF_STENCIL9 || o.kind == SCSF_PLATE) &&
+         (int64_t)o.N * o.N == o.n;
 }
 
 int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order_host,
@@ -1302,6 +1314,7 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
 
   STCHK(check_op(A));
   STCHK(check_params(prm, A->n));
+  STCHK(check_op_precision(*A, prm));
   if ((X_prev == nullptr) != (theta_prev == nullptr)) return SCSF_EINVAL;
   if (!evals || !evecs) return SCSF_EINVAL;
   const int max_iter = prm->max_iter > 0 ? prm->max_iter : 5000;
@@ -1375,6 +1388,7 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
     if (ops_host[i].n != n || ops_host[i].kind != kind) return SCSF_EINVAL;
   }
   STCHK(check_params(prm, n));
+  STCHK(check_op_precision(ops_host[0], prm));
   if (hints_host && prm->adaptive) return SCSF_EINVAL;   // a degree hint fixes the degree
   {
     std::vector<char> seen(n_op, 0);

@@ -10,6 +10,8 @@
 // same cache lines; the +-N neighbours are re-read from L2 by the adjacent row tiles.
 #include "stencil.h"
 
+#include <type_traits>
+
 namespace scsf {
 
 // Per-column degree (adaptive filter): column c of problem b takes part in the step while
@@ -318,6 +320,129 @@ static void launch_reg(const OpDev *ops, int B, int32_t kind, int64_t nmax, cons
 
 constexpr size_t kStageBytes = 65536;                 // dynamic LDS of one staged workgroup
 
+// Thin-plate step: A = S L diag(D) L S with S = diag(rho^-1/2) and L the 5-point Dirichlet
+// Laplacian / h^2.  A workgroup takes TILE = 256 NPT nodes and CPT columns and works in two
+// LDS stages: z = S x on the tile +-2N, then w = D (L z) on the tile +-N (zero outside the
+// grid: the second Laplacian also sees Dirichlet values), then y = a S L w + b x + g Z on the
+// tile.  x is read once from HBM for the staging (its tile-interior values again from L2 for
+// the b x term); D and rho come from L2 after the first column group.
+template <int CPT, int NPT, bool HZ>
+__global__ void __launch_bounds__(256) spmm_plate_kernel(
+    const OpDev *__restrict__ ops, const double *__restrict__ X, const double *__restrict__ Z,
+    double *__restrict__ Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
+    const int32_t *__restrict__ lock, const double *__restrict__ coef,
+    const int32_t *__restrict__ mdeg, int32_t step, const int32_t *__restrict__ cdeg,
+    int32_t mtot) {
+  constexpr int TILE = 256 * NPT;
+  extern __shared__ unsigned char smem_raw[];
+  const int b = blockIdx.z;
+  if (mdeg && step >= mdeg[b]) return;
+  const OpDev op = ops[b];
+  const int N = op.N;
+  const int64_t n = op.n;
+  const int64_t p0 = (int64_t)blockIdx.x * TILE;
+  if (p0 >= n) return;
+  int32_t c0, cnt;
+  col_range(mode, k, lock, b, c0, cnt);
+  const int j0 = blockIdx.y * CPT;
+  if (j0 >= cnt) return;
+  const int jn = min(CPT, cnt - j0);
+  bool act[CPT];
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    act[j] = j < jn && column_active(cdeg, mtot, step, b, k, c0 + j0 + j);
+    any = any || act[j];
+  }
+  if (!any) return;
+  const int span = TILE + 4 * N;                 // z: nodes [p0 - 2N, p0 + TILE + 2N)
+  const int wspan = TILE + 2 * N;                // w: nodes [p0 - N, p0 + TILE + N)
+  double *sz = reinterpret_cast<double *>(smem_raw);
+  double *sw = sz + CPT * span;
+  const int tid = threadIdx.x;
+  const int64_t off = (int64_t)b * bs + (int64_t)(c0 + j0) * ld;
+  const double *xb = X + off;
+  const double *D = op.wx, *rho = op.wy;
+  const double ih2 = (double)(N + 1) * (double)(N + 1);
+  constexpr int U = 4;
+  for (int e0 = tid; e0 < span; e0 += 256 * U) {
+    double v[U][CPT], sq[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * 256;
+      const int64_t q = p0 - 2 * N + e;
+      const bool in = e < span && q >= 0 && q < n;
+      sq[u] = in ? rho[q] : 1.0;
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) v[u][j] = (act[j] && in) ? xb[(int64_t)j * ld + q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * 256;
+      if (e < span) {
+        const double s = 1.0 / sqrt(sq[u]);
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)
+          if (act[j]) sz[j * span + e] = s * v[u][j];
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < wspan; e += 256) {
+    const int64_t q = p0 - N + e;
+    if (q < 0 || q >= n) {
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) sw[j * wspan + e] = 0.0;
+      continue;
+    }
+    const int iy = (int)(q / N), ix = (int)(q - (int64_t)iy * N);
+    const double d = D[q] * ih2;
+    const int ez = e + N;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      if (!act[j]) continue;
+      const double *zj = sz + j * span;
+      double lz = 4.0 * zj[ez];
+      if (ix > 0) lz -= zj[ez - 1];
+      if (ix < N - 1) lz -= zj[ez + 1];
+      if (iy > 0) lz -= zj[ez - N];
+      if (iy < N - 1) lz -= zj[ez + N];
+      sw[j * wspan + e] = d * lz;
+    }
+  }
+  __syncthreads();
+  const double a = coef[3 * b + 0], bc = coef[3 * b + 1], g = coef[3 * b + 2];
+#pragma unroll
+  for (int t = 0; t < NPT; ++t) {
+    const int64_t p = p0 + t * 256 + tid;
+    if (p >= n) break;
+    const int iy = (int)(p / N), ix = (int)(p - (int64_t)iy * N);
+    const double sp = ih2 / sqrt(rho[p]);
+    const int e = t * 256 + tid + N;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      if (!act[j]) continue;
+      const double *wj = sw + j * wspan;
+      double lw = 4.0 * wj[e];
+      if (ix > 0) lw -= wj[e - 1];
+      if (ix < N - 1) lw -= wj[e + 1];
+      if (iy > 0) lw -= wj[e - N];
+      if (iy < N - 1) lw -= wj[e + N];
+      const int64_t o = off + (int64_t)j * ld + p;
+      double r = a * (sp * lw) + bc * X[o];
+      if constexpr (HZ) r += g * __builtin_nontemporal_load(&Z[o]);
+      __builtin_nontemporal_store(r, &Y[o]);
+    }
+  }
+}
+
+// The plate step with the largest tile <= `tile` whose two LDS stages fit in kStageBytes.
+static hipError_t launch_plate(const OpDev *ops, int B, int64_t nmax, int32_t Nmax,
+                               const double *X, const double *Z, double *Y, int64_t ld,
+                               int64_t bs, int32_t mode, int32_t k, const int32_t *lock,
+                               const double *coef, bool has_z, const int32_t *mdeg, int32_t step,
+                               int tile, const int32_t *cdeg, int32_t mtot, hipStream_t st);
+
 template <int CPT, typename T, bool SRC>
 static bool launch_lds(const OpDev *ops, int B, int32_t kind, bool pot, int64_t nmax, int32_t Nmax,
                        const T *X, const T *Z, T *Y, int64_t ld, int64_t bs, int32_t mode,
@@ -357,6 +482,13 @@ static hipError_t launch_step(const OpDev *ops, int B, int32_t kind, int64_t nma
                               int32_t step, int tile, bool pot, const int32_t *cdeg,
                               int32_t mtot, hipStream_t st) {
   if (B <= 0 || nmax <= 0 || k <= 0) return hipSuccess;
+  if (kind == SCSF_PLATE) {
+    if constexpr (std::is_same<T, double>::value && !SRC)
+      return launch_plate(ops, B, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock, coef, has_z, mdeg,
+                          step, tile, cdeg, mtot, st);
+    else
+      return hipErrorInvalidValue;                 // the plate family runs in FP64 only
+  }
   const int hz = has_z ? 1 : 0;
   bool done = false;
   if (kind != SCSF_CSR && Nmax > 0) {
@@ -373,6 +505,48 @@ static hipError_t launch_step(const OpDev *ops, int B, int32_t kind, int64_t nma
   if (!done)
     launch_reg<4, T, SRC>(ops, B, kind, nmax, X, Z, Y, ld, bs, mode, k, lock, coef, hz, R, src,
                           mdeg, step, cdeg, mtot, st);
+  return hipGetLastError();
+}
+
+template <int CPT>
+static bool plate_fits(int32_t Nmax) {
+  constexpr int TILE = 256 * (8 / CPT);
+  return (size_t)CPT * (2 * TILE + 6 * (size_t)Nmax) * sizeof(double) <= kStageBytes;
+}
+
+template <int CPT>
+static void go_plate(const OpDev *ops, int B, int64_t nmax, int32_t Nmax, const double *X,
+                     const double *Z, double *Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
+                     const int32_t *lock, const double *coef, bool has_z, const int32_t *mdeg,
+                     int32_t step, const int32_t *cdeg, int32_t mtot, hipStream_t st) {
+  constexpr int NPT = 8 / CPT, TILE = 256 * NPT;
+  const size_t shm = (size_t)CPT * (2 * TILE + 6 * (size_t)Nmax) * sizeof(double);
+  dim3 grid((unsigned)ceil_div(nmax, TILE), (unsigned)ceil_div(k, CPT), (unsigned)B);
+  if (has_z)
+    spmm_plate_kernel<CPT, NPT, true><<<grid, 256, shm, st>>>(ops, X, Z, Y, ld, bs, mode, k, lock,
+                                                              coef, mdeg, step, cdeg, mtot);
+  else
+    spmm_plate_kernel<CPT, NPT, false><<<grid, 256, shm, st>>>(ops, X, Z, Y, ld, bs, mode, k,
+                                                               lock, coef, mdeg, step, cdeg, mtot);
+}
+
+static hipError_t launch_plate(const OpDev *ops, int B, int64_t nmax, int32_t Nmax,
+                               const double *X, const double *Z, double *Y, int64_t ld,
+                               int64_t bs, int32_t mode, int32_t k, const int32_t *lock,
+                               const double *coef, bool has_z, const int32_t *mdeg, int32_t step,
+                               int tile, const int32_t *cdeg, int32_t mtot, hipStream_t st) {
+  if (Nmax <= 0) return hipErrorInvalidValue;
+  if (tile >= 4 && plate_fits<4>(Nmax))
+    go_plate<4>(ops, B, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock, coef, has_z, mdeg, step, cdeg,
+                mtot, st);
+  else if (tile >= 2 && plate_fits<2>(Nmax))
+    go_plate<2>(ops, B, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock, coef, has_z, mdeg, step, cdeg,
+                mtot, st);
+  else if (plate_fits<1>(Nmax))
+    go_plate<1>(ops, B, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock, coef, has_z, mdeg, step, cdeg,
+                mtot, st);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

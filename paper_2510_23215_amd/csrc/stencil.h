@@ -73,6 +73,37 @@ __device__ inline double op_row(const OpDev &op, int64_t p, const double *x, dou
     }
     if (gersh) *gersh = g;
     return r;
+  } else if constexpr (KIND == SCSF_PLATE) {
+    // row p of S L diag(D) L S (S = diag(rho^-1/2), L = 5-point Dirichlet Laplacian / h^2):
+    // the 13 coefficients gathered on the 5 x 5 offset square around p
+    const int N = op.N;
+    const int iy = (int)(p / N), ix = (int)(p - (int64_t)iy * N);
+    const double ih2 = (double)(N + 1) * (double)(N + 1);
+    const int oy[5] = {0, 0, 0, -1, 1}, ox[5] = {0, -1, 1, 0, 0};
+    double c[25];
+#pragma unroll
+    for (int t = 0; t < 25; ++t) c[t] = 0.0;
+    for (int u = 0; u < 5; ++u) {
+      const int ky = iy + oy[u], kx = ix + ox[u];
+      if (ky < 0 || ky >= N || kx < 0 || kx >= N) continue;
+      const double dk = (u == 0 ? 4.0 : -1.0) * op.wx[(int64_t)ky * N + kx] * ih2 * ih2;
+      for (int w = 0; w < 5; ++w) {
+        const int jy = ky + oy[w], jx = kx + ox[w];
+        if (jy < 0 || jy >= N || jx < 0 || jx >= N) continue;
+        c[(oy[u] + oy[w] + 2) * 5 + (ox[u] + ox[w] + 2)] +=
+            dk * (w == 0 ? 4.0 : -1.0) / sqrt(op.wy[(int64_t)jy * N + jx]);
+      }
+    }
+    const double sp = 1.0 / sqrt(op.wy[p]);
+    double r = 0.0, g = 0.0;
+    for (int t = 0; t < 25; ++t) {
+      if (c[t] == 0.0) continue;
+      const int dy = t / 5 - 2, dx = t % 5 - 2;
+      r += c[t] * x[p + (int64_t)dy * N + dx];
+      g += (t == 12) ? c[t] : fabs(c[t]);
+    }
+    if (gersh) *gersh = sp * g;
+    return sp * r;
   } else {
     double r = 0.0, g = 0.0;
     for (int32_t q = op.row_ptr[p]; q < op.row_ptr[p + 1]; ++q) {

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libscsf.so"
 
 SCSF_OK, SCSF_EINVAL, SCSF_ENOMEM, SCSF_ENOTCONV = 0, -1, -2, -3
 SCSF_EBREAKDOWN, SCSF_EHIP, SCSF_ENUMERIC = -4, -5, -6
-SCSF_STENCIL5, SCSF_STENCIL9, SCSF_CSR = 1, 2, 3
+SCSF_STENCIL5, SCSF_STENCIL9, SCSF_CSR, SCSF_PLATE = 1, 2, 3, 4
 SCSF_FP64, SCSF_MIXED = 0, 1
 SCSF_SCHED_STATIC, SCSF_SCHED_DYNAMIC = 0, 1
 SCSF_EIG_JACOBI, SCSF_EIG_TRIDIAG = 0, 1
@@ -187,7 +187,8 @@ class Handle:
 
 
 class DeviceOperator:
-    """Device copy of an operator from `scsf_inputs` (Stencil5 / Stencil9) or a CSR matrix."""
+    """Device copy of an operator from `scsf_inputs` (Stencil5 / Stencil9 / Plate) or a CSR
+    matrix."""
 
     def __init__(self, op=None, *, csr=None, device="cuda"):
         self._keep = []
@@ -201,6 +202,12 @@ class DeviceOperator:
             self._keep += [rp, ci, va]
             s.kind, s.nx, s.n = SCSF_CSR, 0, n
             s.row_ptr, s.col_idx, s.val, s.nnz = rp.data_ptr(), ci.data_ptr(), va.data_ptr(), len(data)
+        elif hasattr(op, "rho"):
+            D = torch.as_tensor(np.ascontiguousarray(op.D, np.float64).ravel(), device=device)
+            rho = torch.as_tensor(np.ascontiguousarray(op.rho, np.float64).ravel(), device=device)
+            self._keep += [D, rho]
+            s.kind, s.nx, s.n = SCSF_PLATE, op.N, op.N * op.N
+            s.wx, s.wy = D.data_ptr(), rho.data_ptr()
         elif hasattr(op, "wx"):
             wx = torch.as_tensor(np.ascontiguousarray(op.wx, np.float64), device=device)
             wy = torch.as_tensor(np.ascontiguousarray(op.wy, np.float64), device=device)

@@ -8,12 +8,15 @@ the step ends with all eigenpairs resident in HBM.
 
 Workload (default): 200 generalized-Poisson operators -div(K grad u) on a 100 x 100 grid
 (n = 10^4), K = exp(GRF with 16 x 16 cosine modes), L = 100 smallest eigenpairs, block width
-k = 120, Chebyshev degree 20, p0 = 20, relative residual 1e-8, FP64.
+k = 120, Chebyshev degree 30 (the configuration's range is 16-30), p0 = 20, relative residual
+1e-8, FP64.  `--config` selects the other workloads (1 small, 3 uneven batch, 4 mixed
+precision, 5 learned window, 6 thin-plate vibration).
 
 Prints one JSON line (rank 0).  `roofline` describes the dominant kernel (the filter's
-Chebyshev step), timed live with HIP events around each of its launches inside the timed
-region; `cpu_baseline` times the CPU oracle (NumPy/SciPy) on a bounded prefix of the same
-sorted sequence.
+Chebyshev step), timed live with HIP events around each filter launch (or filter graph) inside
+the timed region; `cpu_baseline` times the CPU oracle (NumPy/SciPy) on a bounded prefix of the
+same sorted sequence.  After the timed steps, for the working-size workload: `comparison`
+(the same operators solved cold and unsorted) and `spmm_isolated` (the filter step alone).
 """
 from __future__ import annotations
 
@@ -92,7 +95,8 @@ def isolated_spmm(scsf, torch, h, dops, k, degree, blocks):
     ms = prof["filter_ms"] / max(prof["filter_launches"], 1)
     bytes_ = prof["filter_bytes"] / max(prof["filter_launches"], 1)
     gbs = bytes_ / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    return {"kernel": "spmm_lds_kernel, alone (scsf_filter_batched)", "blocks": blocks,
+    kern = "spmm_plate_kernel" if ops[0].struct.kind == scsf.SCSF_PLATE else "spmm_lds_kernel"
+    return {"kernel": f"{kern}, alone (scsf_filter_batched)", "blocks": blocks,
             "columns": k, "launches": prof["filter_launches"], "avg_launch_ms": ms,
             "algorithmic_bytes_per_launch": bytes_, "achieved": gbs, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
@@ -382,8 +386,8 @@ def main():
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
 
     out = {
-        "metric": "eigenpairs/sec at residual 1e-8 (SCSF GPU, %s%s)" % (
-            "learned window, " if form == "learned" else "",
+        "metric": "eigenpairs/sec at residual %g (SCSF GPU, %s%s)" % (
+            cfg.tol, "learned window, " if form == "learned" else "",
             "FP64" if precision == "fp64" else "FP32 filter / FP64 rest"),
         "value": value,
         "unit": "eigenpairs/s",
@@ -421,9 +425,11 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "spmm_lds_kernel (Chebyshev three-term step, %s stencil, %s)" % (
-                "9-point Q1" if windowed else "5-point",
-                "FP64" if precision == "fp64" else "FP32 residual form"),
+            "kernel": ("spmm_plate_kernel (Chebyshev three-term step, 13-point thin-plate "
+                       "standard form, FP64)" if cfg.family == "plate" else
+                       "spmm_lds_kernel (Chebyshev three-term step, %s stencil, %s)" % (
+                           "9-point Q1" if windowed else "5-point",
+                           "FP64" if precision == "fp64" else "FP32 residual form")),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -447,8 +453,9 @@ def main():
     elif comparison:
         comparison["ratio"] = value / comparison["cold_unsorted_value"]
         out["comparison"] = comparison
-    if cfg.index == 2 and precision == "fp64" and args.spmm_isolated == "on":
-        out["spmm_isolated"] = isolated_spmm(scsf, torch, h, dops, cfg.k, degree, 32)
+    if cfg.index in (2, 6) and precision == "fp64" and args.spmm_isolated == "on":
+        out["spmm_isolated"] = isolated_spmm(scsf, torch, h, dops, cfg.k, degree,
+                                             32 if cfg.index == 2 else 16)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, ops, args.cpu_budget,
                                            Ls if uneven else None, ks if uneven else None,

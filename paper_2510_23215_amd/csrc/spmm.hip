@@ -321,13 +321,14 @@ static void launch_reg(const OpDev *ops, int B, int32_t kind, int64_t nmax, cons
 constexpr size_t kStageBytes = 65536;                 // dynamic LDS of one staged workgroup
 
 // Thin-plate step: A = S L diag(D) L S with S = diag(rho^-1/2) and L the 5-point Dirichlet
-// Laplacian / h^2.  A workgroup takes TILE = 256 NPT nodes and CPT columns and works in two
-// LDS stages: z = S x on the tile +-2N, then w = D (L z) on the tile +-N (zero outside the
+// Laplacian / h^2.  A workgroup of 512 threads (its two LDS stages allow three workgroups per
+// CU, so eight waves each keep the CU busy) takes TILE = 256 NPT nodes and CPT columns in two
+// stages: z = S x on the tile +-2N, then w = D (L z) on the tile +-N (zero outside the
 // grid: the second Laplacian also sees Dirichlet values), then y = a S L w + b x + g Z on the
 // tile.  x is read once from HBM for the staging (its tile-interior values again from L2 for
 // the b x term); D and rho come from L2 after the first column group.
 template <int CPT, int NPT, bool HZ>
-__global__ void __launch_bounds__(256) spmm_plate_kernel(
+__global__ void __launch_bounds__(512) spmm_plate_kernel(
     const OpDev *__restrict__ ops, const double *__restrict__ X, const double *__restrict__ Z,
     double *__restrict__ Y, int64_t ld, int64_t bs, int32_t mode, int32_t k,
     const int32_t *__restrict__ lock, const double *__restrict__ coef,
@@ -365,11 +366,11 @@ __global__ void __launch_bounds__(256) spmm_plate_kernel(
   const double *D = op.wx, *rho = op.wy;
   const double ih2 = (double)(N + 1) * (double)(N + 1);
   constexpr int U = 4;
-  for (int e0 = tid; e0 < span; e0 += 256 * U) {
+  for (int e0 = tid; e0 < span; e0 += 512 * U) {
     double v[U][CPT], sq[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * 256;
+      const int e = e0 + u * 512;
       const int64_t q = p0 - 2 * N + e;
       const bool in = e < span && q >= 0 && q < n;
       sq[u] = in ? rho[q] : 1.0;
@@ -378,7 +379,7 @@ __global__ void __launch_bounds__(256) spmm_plate_kernel(
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * 256;
+      const int e = e0 + u * 512;
       if (e < span) {
         const double s = 1.0 / sqrt(sq[u]);
 #pragma unroll
@@ -388,14 +389,14 @@ __global__ void __launch_bounds__(256) spmm_plate_kernel(
     }
   }
   __syncthreads();
-  for (int e = tid; e < wspan; e += 256) {
+  for (int e = tid; e < wspan; e += 512) {
     const int64_t q = p0 - N + e;
     if (q < 0 || q >= n) {
 #pragma unroll
       for (int j = 0; j < CPT; ++j) sw[j * wspan + e] = 0.0;
       continue;
     }
-    const int iy = (int)(q / N), ix = (int)(q - (int64_t)iy * N);
+    const int qi = (int)q, iy = qi / N, ix = qi - iy * N;
     const double d = D[q] * ih2;
     const int ez = e + N;
 #pragma unroll
@@ -413,12 +414,12 @@ __global__ void __launch_bounds__(256) spmm_plate_kernel(
   __syncthreads();
   const double a = coef[3 * b + 0], bc = coef[3 * b + 1], g = coef[3 * b + 2];
 #pragma unroll
-  for (int t = 0; t < NPT; ++t) {
-    const int64_t p = p0 + t * 256 + tid;
+  for (int t = 0; t < NPT / 2; ++t) {
+    const int64_t p = p0 + t * 512 + tid;
     if (p >= n) break;
-    const int iy = (int)(p / N), ix = (int)(p - (int64_t)iy * N);
+    const int pi = (int)p, iy = pi / N, ix = pi - iy * N;
     const double sp = ih2 / sqrt(rho[p]);
-    const int e = t * 256 + tid + N;
+    const int e = t * 512 + tid + N;
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
       if (!act[j]) continue;
@@ -523,10 +524,10 @@ static void go_plate(const OpDev *ops, int B, int64_t nmax, int32_t Nmax, const 
   const size_t shm = (size_t)CPT * (2 * TILE + 6 * (size_t)Nmax) * sizeof(double);
   dim3 grid((unsigned)ceil_div(nmax, TILE), (unsigned)ceil_div(k, CPT), (unsigned)B);
   if (has_z)
-    spmm_plate_kernel<CPT, NPT, true><<<grid, 256, shm, st>>>(ops, X, Z, Y, ld, bs, mode, k, lock,
+    spmm_plate_kernel<CPT, NPT, true><<<grid, 512, shm, st>>>(ops, X, Z, Y, ld, bs, mode, k, lock,
                                                               coef, mdeg, step, cdeg, mtot);
   else
-    spmm_plate_kernel<CPT, NPT, false><<<grid, 256, shm, st>>>(ops, X, Z, Y, ld, bs, mode, k,
+    spmm_plate_kernel<CPT, NPT, false><<<grid, 512, shm, st>>>(ops, X, Z, Y, ld, bs, mode, k,
                                                                lock, coef, mdeg, step, cdeg, mtot);
 }
 

@@ -10,7 +10,9 @@ finite-difference operators they define:
 * Schroedinger-type    -Laplace(u) + V u = lambda u, V = exp(g) rescaled to [0, 100];
 * anisotropic elliptic -div(K grad u) with a 2x2 SPD tensor field K (9-point Q1 stencil);
 * thin-plate vibration  del^2 (D del^2 u) = lambda rho u, D = exp(g1), rho = exp(g2) on the
-  nodes (App. D.2 "Dataset", item 4); only the two nodal fields are drawn here.
+  nodes (App. D.2 "Dataset", item 4); only the two nodal fields are drawn here;
+* Helmholtz            -div(p grad u) - k^2 u = lambda u, p = exp(g1), k^2 = k2 exp(g2) on the
+  nodes (App. D.2 "Dataset", item 3): the 5-point family with a negative diagonal term.
 
 g is a cosine series  g(x,y) = sum_{k1,k2<M} xi_{k1k2} (1+k1^2+k2^2)^-1 cos(pi k1 x) cos(pi k2 y),
 xi ~ N(0,1), so the coefficient variance is (1+k1^2+k2^2)^-2 -- a Gaussian random field
@@ -177,6 +179,19 @@ def aniso_operator(N: int, modes: int, seed: int) -> Stencil9:
     n11, n12, n22 = aniso_tensor(w1, w2, wt, node[None, :], node[:, None])
     field = np.stack([n11, n12, n22], axis=0)
     return Stencil9(N=N, cell=cell, field=field)
+
+
+def helmholtz_operator(N: int, modes: int, seed: int, k2: float = 200.0) -> Stencil5:
+    """-div(p grad u) - k^2 u: p = exp(g1) at faces and nodes, k^2 = k2 exp(g2 / 2) at nodes."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w1, w2 = grf_xi(rng, modes), grf_xi(rng, modes)
+    h, node, face = _face_grids(N)
+    inv_h2 = 1.0 / (h * h)
+    wx = np.exp(grf_eval(w1, face[None, :], node[:, None])) * inv_h2
+    wy = np.exp(grf_eval(w1, node[None, :], face[:, None])) * inv_h2
+    p = np.exp(grf_eval(w1, node[None, :], node[:, None]))
+    ksq = k2 * np.exp(0.5 * grf_eval(w2, node[None, :], node[:, None]))
+    return Stencil5(N=N, wx=wx, wy=wy, v=-ksq, field=np.stack([p, ksq]), family="helmholtz")
 
 
 def plate_operator(N: int, modes: int, seed: int) -> Plate:

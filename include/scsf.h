@@ -55,6 +55,8 @@ enum scsf_precision { SCSF_FP64 = 0, SCSF_MIXED = 1 };
  *   DYNAMIC: every chain takes the next unsolved operator of the sorted order when it
  *            finishes one, warm-starting from the operator it solved last (load balance). */
 enum scsf_schedule { SCSF_SCHED_STATIC = 0, SCSF_SCHED_DYNAMIC = 1 };
+/* Which eigenvalues the solvers return (scsf_params.target). */
+enum scsf_target { SCSF_TARGET_SMALLEST = 0, SCSF_TARGET_MAGNITUDE = 1 };
 /* Eigensolver of the Rayleigh-Ritz step (scsf_set_eigensolver). */
 enum scsf_eigensolver { SCSF_EIG_JACOBI = 0, SCSF_EIG_TRIDIAG = 1 };
 
@@ -109,6 +111,13 @@ typedef struct scsf_params {
                             solve's k Ritz pairs (Section 3.2); 1 -> every solve starts from a
                             seeded random block (the unsorted, cold baseline of the paper's
                             ablations) */
+  int32_t target;        /* scsf_target: SCSF_TARGET_SMALLEST, the L algebraically smallest
+                            eigenvalues; SCSF_TARGET_MAGNITUDE, the L smallest in absolute
+                            value (indefinite operators, the Helmholtz family of App. D.2):
+                            the filter runs on A^2 (each Chebyshev step applies A twice, window
+                            and bound squared), Rayleigh-Ritz, residuals and locking stay with A
+                            and the pairs are ordered by |lambda| (evals in that order, signed).
+                            FP64 only; not with adaptive degrees or degree hints */
   double tol;            /* lock when ||A v - theta v|| <= tol ||A v|| (App. D.5 metric) */
   uint64_t seed;         /* seed of the random cold-start block and Lanczos start vector */
 } scsf_params;

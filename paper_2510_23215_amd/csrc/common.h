@@ -162,7 +162,7 @@ hipError_t lock_update(int B, int32_t k, int32_t L, double tol, int32_t *lock, i
 // 3 rejected).
 hipError_t cheb_coeffs(int B, int32_t k, int32_t m, const double *theta, const double *bounds,
                        const int32_t *done, double *coef, double *win, double *hint,
-                       hipStream_t st);
+                       hipStream_t st, double *coef2 = nullptr);
 // Same from explicit (lambda, c, e) per problem: win[b*3 + {0,1,2}].
 hipError_t cheb_coeffs_explicit(int B, int32_t m, const double *win, double *coef,
                                 hipStream_t st);
@@ -170,8 +170,16 @@ hipError_t cheb_coeffs_explicit(int B, int32_t m, const double *win, double *coe
 // Gershgorin + s-step Lanczos bounds for each problem with need[b] != 0 (need may be null):
 // bounds[b*4 + {0,1,2,3}] = (gershgorin, theta_max + beta_s, theta_min, min(g, lanczos)).
 // work: B * 3 * nmax doubles.
+// square: bounds of A^2 instead (Gershgorin and Lanczos intervals of A, larger end squared).
 hipError_t bounds(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t steps,
-                  uint64_t seed, const int32_t *need, double *work, double *out, hipStream_t st);
+                  uint64_t seed, const int32_t *need, double *work, double *out, hipStream_t st,
+                  bool square = false);
+// square-mode filter helpers (misc.hip)
+hipError_t axpby_active(int B, int64_t nmax, int64_t ld, int64_t bs, int32_t k,
+                        const int32_t *lock, const double *X, const double *Z, const double *coef,
+                        double *P, const int32_t *rows, hipStream_t st);
+hipError_t magnitude_order(int B, int32_t k, const int32_t *lock, double *theta, const double *Z,
+                           double *Zout, int32_t ldm, hipStream_t st);
 
 // Fill columns [0, k) of X_b (rows < n) with i.i.d. N(0,1) from Philox4x32-10 keyed by
 // (seed, b); rows [n, ld) are zeroed.

@@ -107,14 +107,22 @@ __device__ inline void write_coeffs(int B, int b, int32_t m, double lam, double 
 // once, if the Lanczos bounds accept it: lambda_1 <= theta_min(T_s) (a Ritz value bounds
 // lambda_1 from above) and lambda_1 < lambda_{L+1} < beta.  The hint state becomes 2 (used)
 // or 3 (rejected).
+//
+// Square mode (smallest |lambda|): the filter polynomial is in A^2, whose Ritz values are
+// theta^2; with the pairs ordered by |theta|, lambda = theta_0^2 and alpha = theta_{k-1}^2,
+// and coef2 receives (a_s, 0, 1) for the second operator application of each step.
 __global__ void cheb_kernel(int B, int32_t k, int32_t m, const double *__restrict__ theta,
                             const double *__restrict__ bnd, const int32_t *__restrict__ done,
                             double *__restrict__ coef, double *__restrict__ win,
-                            double *__restrict__ hint) {
+                            double *__restrict__ hint, double *__restrict__ coef2) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B || (done && done[b])) return;
   double lam = theta[(int64_t)b * k];
   double alpha = theta[(int64_t)b * k + k - 1];
+  if (coef2) {
+    lam *= lam;
+    alpha *= alpha;
+  }
   double beta = bnd[b * 4 + 3];
   if (hint && hint[b * 3 + 2] == 1.0) {
     const double l1 = hint[b * 3 + 0], lk = hint[b * 3 + 1];
@@ -129,13 +137,21 @@ __global__ void cheb_kernel(int B, int32_t k, int32_t m, const double *__restric
   if (!(l < c - 1e-12 * e)) l = c - e;       // lambda must lie below the damped interval
   if (win) { win[b * 3 + 0] = l; win[b * 3 + 1] = c; win[b * 3 + 2] = e; }
   write_coeffs(B, b, m, l, c, e, coef);
+  if (coef2)
+    for (int s = 0; s < m; ++s) {
+      const int64_t o = ((int64_t)s * B + b) * 3;
+      coef2[o + 0] = coef[o + 0];
+      coef2[o + 1] = 0.0;
+      coef2[o + 2] = 1.0;
+    }
 }
 
 hipError_t cheb_coeffs(int B, int32_t k, int32_t m, const double *theta, const double *bounds,
                        const int32_t *done, double *coef, double *win, double *hint,
-                       hipStream_t st) {
+                       hipStream_t st, double *coef2) {
   if (B <= 0) return hipSuccess;
-  cheb_kernel<<<(B + 63) / 64, 64, 0, st>>>(B, k, m, theta, bounds, done, coef, win, hint);
+  cheb_kernel<<<(B + 63) / 64, 64, 0, st>>>(B, k, m, theta, bounds, done, coef, win, hint,
+                                            coef2);
   return hipGetLastError();
 }
 
@@ -171,9 +187,9 @@ __device__ inline int sturm_count(const double *a, const double *bb, int s, doub
 template <int KIND>
 __global__ void __launch_bounds__(1024) bounds_kernel(
     const OpDev *__restrict__ ops, int32_t steps, uint64_t seed, const int32_t *__restrict__ need,
-    double *__restrict__ work, int64_t nmax, double *__restrict__ out) {
+    double *__restrict__ work, int64_t nmax, double *__restrict__ out, int square) {
   __shared__ double sh[16];
-  __shared__ double al[128], be[128];
+  __shared__ double al[128], be[128], thx[2];
   __shared__ int s_eff;
   const int b = blockIdx.x;
   if (need && !need[b]) return;
@@ -191,14 +207,15 @@ __global__ void __launch_bounds__(1024) bounds_kernel(
   nrm = sqrt(block_sum(nrm, sh));
   for (int64_t p = tid; p < n; p += NT) v1[p] /= nrm;
   if (tid == 0) s_eff = steps;
-  double bold = 0.0, gmax = -INFINITY;
+  double bold = 0.0, gmax = -INFINITY, gmin = INFINITY;
   for (int j = 0; j < steps; ++j) {
     __syncthreads();
     double dot = 0.0;
     for (int64_t p = tid; p < n; p += NT) {
-      double g;
-      const double r = op_row<KIND>(op, p, v1, j == 0 ? &g : nullptr) - bold * v0[p];
-      if (j == 0) gmax = fmax(gmax, g);
+      double g, gl;
+      const double r = op_row<KIND>(op, p, v1, j == 0 ? &g : nullptr, j == 0 ? &gl : nullptr) -
+                       bold * v0[p];
+      if (j == 0) { gmax = fmax(gmax, g); gmin = fmin(gmin, gl); }
       w[p] = r;
       dot += r * v1[p];
     }
@@ -217,6 +234,8 @@ __global__ void __launch_bounds__(1024) bounds_kernel(
   }
   gmax = block_max(gmax, sh);
   __syncthreads();
+  gmin = -block_max(-gmin, sh);
+  __syncthreads();
   if (tid < 2) {
     const int s = s_eff;
     // Gershgorin interval of T for the bisection brackets
@@ -231,29 +250,45 @@ __global__ void __launch_bounds__(1024) bounds_kernel(
       const double mid = 0.5 * (lo + hi);
       if (sturm_count(al, be, s, mid) >= target) hi = mid; else lo = mid;
     }
-    const double th = 0.5 * (lo + hi);
-    if (tid == 0) out[b * 4 + 2] = th;
-    else {
-      const double lz = th + fabs(be[s - 1]);
+    thx[tid] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double tmin = thx[0], tmax = thx[1], bs = fabs(be[s_eff - 1]);
+    out[b * 4 + 2] = tmin;
+    if (!square) {
+      const double lz = tmax + bs;
       out[b * 4 + 0] = gmax;
       out[b * 4 + 1] = lz;
       out[b * 4 + 3] = fmin(gmax, lz);
+    } else {
+      // bounds of A^2: the larger end of A's Gershgorin interval and of the Lanczos interval
+      // [theta_min - beta_s, theta_max + beta_s], squared
+      const double g2 = fmax(fabs(gmax), fabs(gmin)), l2 = fmax(fabs(tmin - bs), fabs(tmax + bs));
+      out[b * 4 + 0] = g2 * g2;
+      out[b * 4 + 1] = l2 * l2;
+      out[b * 4 + 3] = fmin(g2 * g2, l2 * l2);
     }
   }
 }
 
 hipError_t bounds(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t steps,
-                  uint64_t seed, const int32_t *need, double *work, double *out, hipStream_t st) {
+                  uint64_t seed, const int32_t *need, double *work, double *out, hipStream_t st,
+                  bool square) {
   if (B <= 0) return hipSuccess;
   if (steps < 1 || steps > 128) return hipErrorInvalidValue;
   if (kind == SCSF_STENCIL5)
-    bounds_kernel<SCSF_STENCIL5><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out);
+    bounds_kernel<SCSF_STENCIL5><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out,
+                                                 square ? 1 : 0);
   else if (kind == SCSF_STENCIL9)
-    bounds_kernel<SCSF_STENCIL9><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out);
+    bounds_kernel<SCSF_STENCIL9><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out,
+                                                 square ? 1 : 0);
   else if (kind == SCSF_PLATE)
-    bounds_kernel<SCSF_PLATE><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out);
+    bounds_kernel<SCSF_PLATE><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out,
+                                                 square ? 1 : 0);
   else
-    bounds_kernel<SCSF_CSR><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out);
+    bounds_kernel<SCSF_CSR><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out,
+                                                 square ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -542,6 +577,72 @@ __global__ void __launch_bounds__(256) adaptive_degree_kernel(
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = max(m, smax[w]);
     mdeg[b] = m;
   }
+}
+
+// P = b_s X + g_s Z (Z optional) on the active columns and the first rows[b] rows of every
+// problem: the non-operator terms of a square-mode filter step, coef = that step's (a, b, g).
+__global__ void axpby_kernel(int64_t ld, int64_t bs, int32_t k, const int32_t *__restrict__ lock,
+                             const double *__restrict__ X, const double *__restrict__ Z,
+                             const double *__restrict__ coef, double *__restrict__ P,
+                             const int32_t *__restrict__ rows) {
+  const int b = blockIdx.z;
+  const int32_t l = lock[b];
+  const int c = l + (int)blockIdx.y;
+  if (c >= k) return;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= rows[b]) return;
+  const int64_t o = (int64_t)b * bs + (int64_t)c * ld + p;
+  const double bc = coef[3 * b + 1], g = coef[3 * b + 2];
+  P[o] = Z ? bc * X[o] + g * Z[o] : bc * X[o];
+}
+
+hipError_t axpby_active(int B, int64_t nmax, int64_t ld, int64_t bs, int32_t k,
+                        const int32_t *lock, const double *X, const double *Z, const double *coef,
+                        double *P, const int32_t *rows, hipStream_t st) {
+  if (B <= 0 || nmax <= 0 || k <= 0) return hipSuccess;
+  axpby_kernel<<<dim3((unsigned)ceil_div(nmax, 256), (unsigned)k, (unsigned)B), 256, 0, st>>>(
+      ld, bs, k, lock, X, Z, coef, P, rows);
+  return hipGetLastError();
+}
+
+// Reorder the active Ritz pairs of every problem by |theta| (stable: equal magnitudes keep
+// the ascending order the eigensolver gave): theta in place, Z (active columns, ldm x ldm
+// per problem) into Zout.
+__global__ void __launch_bounds__(256) magnitude_order_kernel(
+    int32_t k, const int32_t *__restrict__ lock, double *__restrict__ theta,
+    const double *__restrict__ Z, double *__restrict__ Zout, int32_t ldm) {
+  __shared__ double th[kMaxK];
+  __shared__ int perm[kMaxK];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int32_t l = lock[b];
+  const int ka = k - l;
+  if (ka <= 0) return;
+  for (int j = tid; j < ka; j += 256) th[j] = theta[(int64_t)b * k + l + j];
+  __syncthreads();
+  for (int j = tid; j < ka; j += 256) {
+    const double aj = fabs(th[j]);
+    int r = 0;
+    for (int i = 0; i < ka; ++i) {
+      const double ai = fabs(th[i]);
+      r += (ai < aj || (ai == aj && i < j)) ? 1 : 0;
+    }
+    perm[r] = j;
+  }
+  __syncthreads();
+  for (int j = tid; j < ka; j += 256) theta[(int64_t)b * k + l + j] = th[perm[j]];
+  const double *Zb = Z + (int64_t)b * ldm * ldm;
+  double *Ob = Zout + (int64_t)b * ldm * ldm;
+  for (int e = tid; e < ka * ka; e += 256) {
+    const int r = e % ka, j = e / ka;
+    Ob[r + (int64_t)j * ldm] = Zb[r + (int64_t)perm[j] * ldm];
+  }
+}
+
+hipError_t magnitude_order(int B, int32_t k, const int32_t *lock, double *theta, const double *Z,
+                           double *Zout, int32_t ldm, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  magnitude_order_kernel<<<B, 256, 0, st>>>(k, lock, theta, Z, Zout, ldm);
+  return hipGetLastError();
 }
 
 hipError_t adaptive_degrees(int B, int32_t k, const int32_t *lock, const int32_t *done,

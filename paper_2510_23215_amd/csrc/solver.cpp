@@ -27,7 +27,7 @@ namespace {
 enum BufId {
   B_X, B_Y1, B_Y2, B_W, B_G, B_M, B_PART, B_THETA, B_RES, B_INT, B_BND, B_COEF, B_UNIT, B_CHOL,
   B_JAC, B_LZ, B_OPS, B_WIN, B_SORTF, B_SORTD, B_SORTO, B_REC, B_RANK, B_E32, B_R32, B_SRC,
-  B_GAIN, B_WINB, B_HINT, B_MDEG, B_NETF, B_NETH, B_NETD, B_ROWS, B_EIG, B_CDEG, B_COUNT
+  B_GAIN, B_WINB, B_HINT, B_MDEG, B_NETF, B_NETH, B_NETD, B_ROWS, B_EIG, B_CDEG, B_SQT, B_SQP, B_COEF2, B_COUNT
 };
 
 struct DevBuf {
@@ -209,6 +209,11 @@ struct Engine {
   bool adaptive = false;
   int32_t m_base = 0;
   int32_t *cdeg = nullptr, *h_cdeg = nullptr;
+  // smallest-magnitude mode: the filter polynomial is in A^2 (each step applies A twice, with
+  // T = A Y_i and the non-operator terms P in two extra blocks); Rayleigh-Ritz, residuals and
+  // locking stay with A, the pairs ordered by |theta|
+  bool mag = false;
+  double *T = nullptr, *P = nullptr, *coef2 = nullptr;
   // adaptive: per problem, the filter columns (sum of column degrees) and the largest column
   // degree of the last iteration
   std::vector<int64_t> it_cols;
@@ -234,11 +239,12 @@ struct Engine {
 
   int setup(Workspace *hh, int B_, int64_t n_, int32_t k_, int32_t L_, int32_t m_, int32_t kind_,
             double tol_, uint64_t seed_, int32_t lz_steps_, bool mixed_ = false,
-            bool var_deg_ = false, bool adaptive_ = false) {
+            bool var_deg_ = false, bool adaptive_ = false, bool mag_ = false) {
     mixed = mixed_;
     w_stale = true;
     var_deg = var_deg_;
     adaptive = adaptive_ && !var_deg_ && !mixed_;
+    mag = mag_ && !mixed_ && !adaptive;
     m_base = m_;
     if (var_deg) m_ = 64;                  // coefficient tables sized for the largest degree
     if (adaptive) m_ = std::min(64, std::max(m_, 2 * m_));
@@ -281,6 +287,11 @@ struct Engine {
     need = ints + 4 * B;
     STCHK(grow(h, B_BND, (size_t)B * 4, &bnd));
     STCHK(grow(h, B_COEF, (size_t)std::max(m, 1) * B * 3, &coef));
+    if (mag) {
+      STCHK(grow(h, B_SQT, blk, &T));
+      STCHK(grow(h, B_SQP, blk, &P));
+      STCHK(grow(h, B_COEF2, (size_t)std::max(m, 1) * B * 3, &coef2));
+    }
     STCHK(grow(h, B_UNIT, (size_t)B * 3, &unit));
     STCHK(grow(h, B_CHOL, (size_t)B * kMaxK * (kMaxK + 1), &chol));
     STCHK(grow(h, B_JAC, (size_t)B * kMaxK * (kMaxK + 1), &jac));
@@ -461,7 +472,7 @@ struct Engine {
 
   // upper bounds of the problems with h_need[b] set
   int compute_bounds() {
-    HIPCHK(bounds(ops, B, kind, n, lz_steps, seed ^ 0x5DEECE66DULL, need, lz, bnd, st));
+    HIPCHK(bounds(ops, B, kind, n, lz_steps, seed ^ 0x5DEECE66DULL, need, lz, bnd, st, mag));
     return SCSF_OK;
   }
 
@@ -502,9 +513,14 @@ struct Engine {
                         jacobi_stop()));
     else
       HIPCHK(tridiag_eig(B, k, lock, G, M, ldm, theta, flag, jac, eigw, st));
-    HIPCHK(gemm_nn(B, n, ld, Yf, bs, COLS_ACTIVE, X, bs, COLS_ACTIVE, k, lock, M, ldm, 1.0, 0.0,
+    double *Zr = M;
+    if (mag) {                        // pairs by |theta|; the Gram buffer takes the reordered Z
+      HIPCHK(magnitude_order(B, k, lock, theta, M, G, ldm, st));
+      Zr = G;
+    }
+    HIPCHK(gemm_nn(B, n, ld, Yf, bs, COLS_ACTIVE, X, bs, COLS_ACTIVE, k, lock, Zr, ldm, 1.0, 0.0,
                    nullptr, 0, nullptr, 0, st, rows));
-    HIPCHK(gemm_nn(B, n, ld, W, bs, COLS_ACTIVE, W, bs, COLS_ACTIVE, k, lock, M, ldm, 1.0, 0.0,
+    HIPCHK(gemm_nn(B, n, ld, W, bs, COLS_ACTIVE, W, bs, COLS_ACTIVE, k, lock, Zr, ldm, 1.0, 0.0,
                    nullptr, 0, nullptr, 0, st, rows));
     return SCSF_OK;
   }
@@ -538,7 +554,8 @@ struct Engine {
   // kernels on `st`, so each can be captured into a graph and replayed.
   int enqueue_pre(int M) {
     HIPCHK(fill_int(flag, 0, B, st));
-    HIPCHK(cheb_coeffs(B, k, M, theta, bnd, done, coef, mixed ? winb : nullptr, hint, st));
+    HIPCHK(cheb_coeffs(B, k, M, theta, bnd, done, coef, mixed ? winb : nullptr, hint, st,
+                       mag ? coef2 : nullptr));
     return SCSF_OK;
   }
   int enqueue_filter(int M, bool timed) {
@@ -555,6 +572,18 @@ struct Engine {
         prof_end(h, slot);
       }
       HIPCHK(mp_final(B, n, ld, bs, k, lock, X, E32[M % 3], gain, Y1, st));
+    } else if (mag) {
+      // Y_{s+1} = a A (A Y_s) + b Y_s + g Y_{s-1}: T = A Y_s, P = b Y_s + g Y_{s-1}, then the
+      // step kernel with (a, 0, 1) on (T, P)
+      double *ring[3] = {X, Y1, Y2};
+      for (int s = 0; s < M; ++s) {
+        HIPCHK(spmm_step(ops, B, kind, n, Nmax, ring[s % 3], nullptr, T, ld, bs, COLS_ACTIVE, k,
+                         lock, unit, false, st, nullptr, s, cpt, pot));
+        HIPCHK(axpby_active(B, n, ld, bs, k, lock, ring[s % 3], s > 0 ? ring[(s + 2) % 3] : nullptr,
+                            coef + (size_t)s * B * 3, P, rows, st));
+        HIPCHK(spmm_step(ops, B, kind, n, Nmax, T, P, ring[(s + 1) % 3], ld, bs, COLS_ACTIVE, k,
+                         lock, coef2 + (size_t)s * B * 3, true, st, nullptr, s, cpt, pot));
+      }
     } else {
       double *ring[3] = {X, Y1, Y2};
       for (int s = 0; s < M; ++s) {
@@ -679,14 +708,14 @@ struct Engine {
     }
     if (!use_graph) {
       STCHK(enqueue_pre(M));
-      STCHK(enqueue_filter(M, h->prof));
+      STCHK(enqueue_filter(M, h->prof && !mag));
       STCHK(enqueue_post(M));
     } else {
       GraphSet *gs = nullptr;
       STCHK(graphs_for(M, &gs));
       HIPCHK(hipGraphLaunch(gs->pre, st));
       int slot = -1;
-      if (h->prof) {                  // one timed span over the filter graph's M launches
+      if (h->prof && !mag) {          // one timed span over the filter graph's M launches
         double bytes = 0.0;
         for (int s = mixed ? 1 : 0; s < M; ++s)
           bytes += mixed ? step_bytes(s > 1, true, s) : step_bytes(s > 0, false, s);
@@ -719,7 +748,11 @@ struct Engine {
     const double *th = h_theta + (size_t)b * k;
     int32_t *perm = h_perm + (size_t)b * k;
     std::iota(perm, perm + L, 0);
-    std::stable_sort(perm, perm + L, [&](int a, int c) { return th[a] < th[c]; });
+    if (mag)
+      std::stable_sort(perm, perm + L,
+                       [&](int a, int c) { return std::fabs(th[a]) < std::fabs(th[c]); });
+    else
+      std::stable_sort(perm, perm + L, [&](int a, int c) { return th[a] < th[c]; });
     double *vals = h_theta + (size_t)b * k;  // reorder in place after computing the maximum
     double mr = 0.0;
     for (int j = 0; j < L; ++j) mr = std::max(mr, h_res[(size_t)b * k + j]);
@@ -759,6 +792,9 @@ int check_params(const scsf_params *p, int64_t n) {
   if (p->adaptive != 0 && p->adaptive != 1) return SCSF_EINVAL;
   if (p->adaptive && p->precision != SCSF_FP64) return SCSF_EINVAL;
   if (p->cold_start != 0 && p->cold_start != 1) return SCSF_EINVAL;
+  if (p->target != SCSF_TARGET_SMALLEST && p->target != SCSF_TARGET_MAGNITUDE) return SCSF_EINVAL;
+  if (p->target == SCSF_TARGET_MAGNITUDE && (p->precision != SCSF_FP64 || p->adaptive))
+    return SCSF_EINVAL;
   return SCSF_OK;
 }
 
@@ -798,7 +834,8 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
 
   Engine e;
   STCHK(e.setup(w, chains, n, k, L, m, kind, prm->tol, prm->seed, lzs,
-                prm->precision == SCSF_MIXED, hints_host != nullptr, prm->adaptive != 0));
+                prm->precision == SCSF_MIXED, hints_host != nullptr, prm->adaptive != 0,
+                prm->target == SCSF_TARGET_MAGNITUDE));
   e.use_graph = graphs && w->own_stream;     // capture needs a stream of our own
   e.cpt = cpt;
   e.eig = eig;
@@ -1322,7 +1359,8 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
   Engine e;
   e.eig = h->eig;
   STCHK(e.setup(w0, 1, A->n, prm->k, prm->L, prm->degree, A->kind, prm->tol, prm->seed, lzs,
-                prm->precision == SCSF_MIXED, false, prm->adaptive != 0));
+                prm->precision == SCSF_MIXED, false, prm->adaptive != 0,
+                prm->target == SCSF_TARGET_MAGNITUDE));
   e.h_ops[0] = to_dev(*A);
   e.h_need[0] = 1;
   STCHK(e.upload_ops());
@@ -1390,6 +1428,7 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
   STCHK(check_params(prm, n));
   STCHK(check_op_precision(ops_host[0], prm));
   if (hints_host && prm->adaptive) return SCSF_EINVAL;   // a degree hint fixes the degree
+  if (hints_host && prm->target == SCSF_TARGET_MAGNITUDE) return SCSF_EINVAL;
   {
     std::vector<char> seen(n_op, 0);
     for (int i = 0; i < n_op; ++i) {

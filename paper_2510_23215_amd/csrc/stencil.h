@@ -41,7 +41,8 @@ __device__ inline void stencil9_coeffs(const OpDev &op, int iy, int ix, double c
 
 // (A x)_p and the Gershgorin radius sum_q |A_pq| (q != p) plus A_pp.
 template <int KIND>
-__device__ inline double op_row(const OpDev &op, int64_t p, const double *x, double *gersh) {
+__device__ inline double op_row(const OpDev &op, int64_t p, const double *x, double *gersh,
+                                double *gersh_lo = nullptr) {
   if constexpr (KIND == SCSF_STENCIL5) {
     const int N = op.N;
     const int iy = (int)(p / N), ix = (int)(p - (int64_t)iy * N);
@@ -56,6 +57,7 @@ __device__ inline double op_row(const OpDev &op, int64_t p, const double *x, dou
     if (iy > 0) { r -= cs * x[p - N]; g += fabs(cs); }
     if (iy < N - 1) { r -= cn * x[p + N]; g += fabs(cn); }
     if (gersh) *gersh = g;
+    if (gersh_lo) *gersh_lo = 2.0 * cd - g;
     return r;
   } else if constexpr (KIND == SCSF_STENCIL9) {
     const int N = op.N;
@@ -72,6 +74,7 @@ __device__ inline double op_row(const OpDev &op, int64_t p, const double *x, dou
       }
     }
     if (gersh) *gersh = g;
+    if (gersh_lo) *gersh_lo = 2.0 * c9[4] - g;
     return r;
   } else if constexpr (KIND == SCSF_PLATE) {
     // row p of S L diag(D) L S (S = diag(rho^-1/2), L = 5-point Dirichlet Laplacian / h^2):
@@ -103,15 +106,18 @@ __device__ inline double op_row(const OpDev &op, int64_t p, const double *x, dou
       g += (t == 12) ? c[t] : fabs(c[t]);
     }
     if (gersh) *gersh = sp * g;
+    if (gersh_lo) *gersh_lo = sp * (2.0 * c[12] - g);
     return sp * r;
   } else {
-    double r = 0.0, g = 0.0;
+    double r = 0.0, g = 0.0, d = 0.0;
     for (int32_t q = op.row_ptr[p]; q < op.row_ptr[p + 1]; ++q) {
       const int32_t c = op.col_idx[q];
       r += op.val[q] * x[c];
       g += (c == p) ? op.val[q] : fabs(op.val[q]);
+      if (c == p) d += op.val[q];
     }
     if (gersh) *gersh = g;
+    if (gersh_lo) *gersh_lo = 2.0 * d - g;
     return r;
   }
 }

@@ -21,6 +21,7 @@ SCSF_EBREAKDOWN, SCSF_EHIP, SCSF_ENUMERIC = -4, -5, -6
 SCSF_STENCIL5, SCSF_STENCIL9, SCSF_CSR, SCSF_PLATE = 1, 2, 3, 4
 SCSF_FP64, SCSF_MIXED = 0, 1
 SCSF_SCHED_STATIC, SCSF_SCHED_DYNAMIC = 0, 1
+SCSF_TARGET_SMALLEST, SCSF_TARGET_MAGNITUDE = 0, 1
 SCSF_EIG_JACOBI, SCSF_EIG_TRIDIAG = 0, 1
 
 
@@ -39,8 +40,8 @@ class Operator(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("L", c_int32), ("k", c_int32), ("degree", c_int32), ("max_iter", c_int32),
                 ("lanczos_steps", c_int32), ("precision", c_int32), ("schedule", c_int32),
-                ("adaptive", c_int32), ("cold_start", c_int32), ("tol", c_double),
-                ("seed", c_uint64)]
+                ("adaptive", c_int32), ("cold_start", c_int32), ("target", c_int32),
+                ("tol", c_double), ("seed", c_uint64)]
 
 
 class Profile(ctypes.Structure):
@@ -426,10 +427,10 @@ def scsf_solve_batched(h: Handle, ops: list, Ls, order, chains: int, prm: Params
 
 def make_params(L, k, degree=20, tol=1e-8, max_iter=0, lanczos_steps=20, seed=0,
                 precision=SCSF_FP64, schedule=SCSF_SCHED_STATIC, adaptive=0,
-                cold_start=0) -> Params:
+                cold_start=0, target=0) -> Params:
     return Params(L=L, k=k, degree=degree, max_iter=max_iter, lanczos_steps=lanczos_steps,
                   precision=precision, schedule=schedule, adaptive=adaptive,
-                  cold_start=cold_start, tol=tol, seed=seed)
+                  cold_start=cold_start, target=target, tol=tol, seed=seed)
 
 
 def scsf_solve(h: Handle, A: DeviceOperator, prm: Params, X_prev=None, theta_prev=None,

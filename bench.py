@@ -166,7 +166,7 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--count", type=int, default=None, help="operators (default: all)")
     ap.add_argument("--chains", type=int, default=128)
-    ap.add_argument("--lanes", type=int, default=8)
+    ap.add_argument("--lanes", type=int, default=6)
     ap.add_argument("--degree", type=int, default=None)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
                     help="default: the configuration's (fp64; mixed for config 4)")

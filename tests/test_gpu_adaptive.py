@@ -124,15 +124,15 @@ def test_adaptive_batched_uneven(tile):
 
 
 def test_adaptive_config2_full_size_sampled():
-    """The 10^4-node workload (L = 100, k = 120, degree 20) in the benchmark's launch shape
-    (dynamic schedule, 8 lanes, graphs) on 24 operators: every pair's residual, sampled
+    """The 10^4-node workload (L = 100, k = 120, degree 30) in the benchmark's launch shape
+    (dynamic schedule, 6 lanes, graphs) on 24 operators: every pair's residual, sampled
     operators against shift-invert, and fewer outer iterations than one degree for all."""
     say("adaptive c2 sampled")
     cfg = si.CONFIGS[2]
     ops = si.operators(cfg, 24)
     dops = [scsf.DeviceOperator(o) for o in ops]
     h = scsf.Handle()
-    scsf.scsf_set_lanes(h, 8)
+    scsf.scsf_set_lanes(h, 6)
     scsf.scsf_set_graphs(h, True)
     order = np.arange(len(ops))
     its = {}

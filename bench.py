@@ -102,6 +102,24 @@ def isolated_spmm(scsf, torch, h, dops, k, degree, blocks):
             "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
 
 
+FP64_MFMA_PEAK_TFS = 78.6
+
+
+def isolated_gram(scsf, torch, h, n, k, blocks):
+    """The Gram product of CholeskyQR2 alone: `blocks` random n x k blocks through
+    scsf_gram_batched (the solvers' f64 MFMA kernel and reduction), timed with HIP events;
+    algorithmic flops n k (k + 1) per block (the unique entries of a symmetric product)."""
+    X = torch.randn((blocks, k, n), device="cuda", dtype=torch.float64)
+    scsf.scsf_gram_batched(h, X)                                   # untimed first pass
+    _, ms = scsf.scsf_gram_batched(h, X, timed=True)
+    del X
+    flops = blocks * n * k * (k + 1)
+    tfs = flops / (ms * 1e-3) / 1e12
+    return {"kernel": "gemm_tn_kernel + gemm_tn_reduce_kernel (Gram, f64 MFMA 16x16x4)",
+            "blocks": blocks, "n": n, "k": k, "ms": ms, "flops": flops, "achieved": tfs,
+            "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": tfs / FP64_MFMA_PEAK_TFS}
+
+
 def family_order_host(ops, p0):
     """Algorithm 2 within each operator family, concatenated (oracle; CPU baseline only)."""
     from oracle import sort as S
@@ -456,6 +474,7 @@ def main():
     if cfg.index in (2, 6) and precision == "fp64" and args.spmm_isolated == "on":
         out["spmm_isolated"] = isolated_spmm(scsf, torch, h, dops, cfg.k, degree,
                                              32 if cfg.index == 2 else 16)
+        out["dense_isolated"] = isolated_gram(scsf, torch, h, dops[0].n, cfg.k, 32)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, ops, args.cpu_budget,
                                            Ls if uneven else None, ks if uneven else None,

@@ -208,6 +208,15 @@ int scsf_filter_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t B
                         const double *X, int64_t ldx, int64_t bsx, int32_t ncols, int32_t degree,
                         const double *win_host, double *Y, int64_t ldy, int64_t bsy);
 
+/* Gram matrices of B blocks at once, G_b = X_b^T X_b (the first product of CholeskyQR2,
+ * Algorithm 3): the solvers' tall-skinny MFMA kernel (f64 16x16x4) with its deterministic
+ * chunk reduction.  X: device, block b at X + b*bsx, n x k column-major, ldx >= n,
+ * bsx >= ldx*k, k <= 256.  G: device, block b at G + b*ldg*k, k x k column-major (both
+ * triangles), ldg >= k.  kernel_ms_host: when non-NULL, receives the time of the Gram kernels
+ * alone (HIP events on the caller's stream).  Synchronises the stream. */
+int scsf_gram_batched(scsf_handle *h, int32_t B, int64_t n, int32_t k, const double *X,
+                      int64_t ldx, int64_t bsx, double *G, int32_t ldg, double *kernel_ms_host);
+
 /* Orthonormalisation of Algorithm 3 (QR of [locked | active]): X (n x ncols, in place) is
  * made orthogonal to the nlocked orthonormal columns V (twice-repeated block Gram-Schmidt),
  * then orthonormalised by CholeskyQR2 (shifted CholeskyQR3 if the Gram matrix is not

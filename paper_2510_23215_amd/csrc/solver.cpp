@@ -1229,6 +1229,37 @@ int scsf_filter_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t B
   return SCSF_OK;
 }
 
+int scsf_gram_batched(scsf_handle *h, int32_t B, int64_t n, int32_t k, const double *X,
+                      int64_t ldx, int64_t bsx, double *G, int32_t ldg, double *kernel_ms_host) {
+  if (!h || !X || !G || B <= 0 || n <= 0 || k <= 0 || k > kMaxK || ldx < n ||
+      bsx < ldx * (int64_t)k || ldg < k)
+    return SCSF_EINVAL;
+  Workspace *w0 = h->ws[0];
+  Engine en;
+  STCHK(en.setup(w0, B, n, k, 0, 1, SCSF_CSR, 1.0, 0, 20));
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (kernel_ms_host) {
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+    HIPCHK(hipEventRecord(t0, w0->stream));
+  }
+  HIPCHK(gemm_tn(B, n, ldx, X, bsx, COLS_ALL, X, bsx, COLS_ALL, k, nullptr, true, en.part,
+                 en.part_stride, en.G, en.ldm, nullptr, 0, w0->stream));
+  if (kernel_ms_host) HIPCHK(hipEventRecord(t1, w0->stream));
+  for (int b = 0; b < B; ++b)
+    HIPCHK(copy_block(k, k, en.G + (int64_t)b * en.ldm * en.ldm, en.ldm,
+                      G + (int64_t)b * ldg * k, ldg, false, w0->stream));
+  HIPCHK(hipStreamSynchronize(w0->stream));
+  if (kernel_ms_host) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+    *kernel_ms_host = ms;
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+  }
+  return SCSF_OK;
+}
+
 int scsf_orthonormalize(scsf_handle *h, int64_t n, double *X, int64_t ldx, int32_t ncols,
                         const double *V, int64_t ldv, int32_t nlocked) {
   if (!h) return SCSF_EINVAL;

@@ -78,6 +78,7 @@ def lib():
             "scsf_filter_batched": [vp, POINTER(Operator), i32, vp, i64, i64, i32, i32,
                                     POINTER(c_double), vp, i64, i64],
             "scsf_highfreq_ratio": [vp, vp, i32, i32, i32, i32, vp],
+            "scsf_gram_batched": [vp, i32, i64, i32, vp, i64, i64, vp, i32, POINTER(c_double)],
             "scsf_subspace_distance": [vp, i64, i32, vp, i64, i64, i32, POINTER(c_int32),
                                        POINTER(c_int32), i32, POINTER(c_double)],
             "scsf_orthonormalize": [vp, i64, vp, i64, i32, vp, i64, i32],
@@ -265,6 +266,18 @@ def scsf_filter_batched(h: Handle, ops: list, X: torch.Tensor, degree: int, wind
                                      wv.ctypes.data_as(POINTER(c_double)), _ptr(Y), ld, ncols * ld),
            "scsf_filter_batched")
     return Y
+
+
+def scsf_gram_batched(h: Handle, X: torch.Tensor, timed: bool = False):
+    """X: (B, k, n) tensor (block b = n x k column-major) -> (G (B, k, k) with G[b] = X_b^T X_b,
+    kernel milliseconds or None)."""
+    assert X.is_contiguous()
+    B, k, n = X.shape
+    G = torch.empty((B, k, k), device=X.device, dtype=torch.float64)
+    ms = c_double(0.0)
+    _check(lib().scsf_gram_batched(h.ptr, B, n, k, _ptr(X), n, k * n, _ptr(G), k,
+                                   ctypes.byref(ms) if timed else None), "scsf_gram_batched")
+    return G, (ms.value if timed else None)
 
 
 def scsf_orthonormalize(h: Handle, X: torch.Tensor, V: torch.Tensor | None = None):

@@ -280,3 +280,19 @@ def test_cold_start_sequence_equals_separate_solves():
     with pytest.raises(scsf.ScsfError):
         scsf.scsf_solve_sequence(h, dops, np.arange(6), 1,
                                  scsf.make_params(cfg.L, cfg.k, 20, cfg.tol, cold_start=2))
+
+
+# ------------------------------------------------------------------------------ batched Gram
+@pytest.mark.parametrize("n,k", [(1000, 24), (4099, 120), (777, 203)])
+def test_gram_batched(n, k):
+    say("gram batched", n, k)
+    h = scsf.Handle()
+    rng = np.random.default_rng(k)
+    X = rng.standard_normal((5, k, n))
+    G, ms = scsf.scsf_gram_batched(h, torch.tensor(X, device="cuda"), timed=True)
+    assert ms > 0
+    for b in range(5):
+        ref = X[b] @ X[b].T
+        np.testing.assert_allclose(host(G[b]), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    with pytest.raises(scsf.ScsfError):
+        scsf.scsf_gram_batched(h, torch.zeros((2, 257, 300), dtype=torch.float64, device="cuda"))

@@ -78,7 +78,8 @@ def isolated_spmm(scsf, torch, h, dops, k, degree, blocks):
     Window: lambda = 0 below the spectrum, [0.1 ub, ub] damped, ub the Gershgorin bound."""
     ops = [dops[i % len(dops)] for i in range(blocks)]
     ld = max(d.n for d in ops)
-    X = torch.randn((blocks, k, ld), device="cuda", dtype=torch.float64)
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    X = torch.randn((blocks, k, ld), device="cuda", dtype=torch.float64, generator=gen)
     wins = []
     for d in ops:
         ub = scsf.scsf_bounds(h, d)["gershgorin"]
@@ -109,7 +110,8 @@ def isolated_gram(scsf, torch, h, n, k, blocks):
     """The Gram product of CholeskyQR2 alone: `blocks` random n x k blocks through
     scsf_gram_batched (the solvers' f64 MFMA kernel and reduction), timed with HIP events;
     algorithmic flops n k (k + 1) per block (the unique entries of a symmetric product)."""
-    X = torch.randn((blocks, k, n), device="cuda", dtype=torch.float64)
+    gen = torch.Generator(device="cuda").manual_seed(12)
+    X = torch.randn((blocks, k, n), device="cuda", dtype=torch.float64, generator=gen)
     scsf.scsf_gram_batched(h, X)                                   # untimed first pass
     _, ms = scsf.scsf_gram_batched(h, X, timed=True)
     del X

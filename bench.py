@@ -230,7 +230,7 @@ def main():
     os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(8, args.lanes + 2)))
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU chunking is not "
+        print(json.dumps({"error": "the benchmark runs on one GPU; multi-GPU chunking is not "
                                    "implemented (--gpus must be 1)"}))
         sys.exit(2)
 

@@ -285,7 +285,8 @@ int scsf_subspace_distance(scsf_handle *h, int64_t n, int32_t q, const double *X
 
 /* One operator, Algorithm 3.  X_prev (n x k, ld n) and theta_prev (k) are the previous
  * problem's Ritz pairs (warm start) or both NULL (cold start from a seeded Gaussian block).
- * Outputs: evals[L] ascending, evecs (n x L, ld n; largest-magnitude entry positive),
+ * Outputs: evals[L] ascending (by |lambda| with SCSF_TARGET_MAGNITUDE; M-orthonormal u for
+ * SCSF_PLATE), evecs (n x L, ld n; largest-magnitude entry positive),
  * X_next (n x k, ld n) and theta_next[k] for chaining (may alias X_prev / theta_prev).
  * stats_host may be NULL. */
 int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,

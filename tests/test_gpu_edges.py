@@ -1,6 +1,7 @@
 """Edge cases of the solvers on the GPU against the dense oracle: a single wanted pair, a block
 as wide as the matrix, the widest block (k = 256), general CSR operators, more chains than
-operators, and empty or out-of-range inputs.  Needs an MI355X."""
+operators, empty or out-of-range inputs, and a chain checkpointed to disk and resumed.
+Needs an MI355X."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -108,3 +109,31 @@ def test_empty_and_out_of_range_inputs(h):
         with pytest.raises(scsf.ScsfError) as e:                   # k > n = 64 in the last
             scsf.scsf_solve(h, op, bad)
         assert e.value.status == scsf.SCSF_EINVAL
+
+
+def test_checkpoint_and_resume_of_a_chain(h, tmp_path):
+    """The state of a warm-started chain is (position, X_next, theta_next).  A chain stopped
+    after its third operator, its state written to disk and read back in a new handle, resumes
+    with results identical to the uninterrupted chain."""
+    say("edge: checkpoint / resume")
+    cfg = si.CONFIGS[1]
+    ops = [scsf.DeviceOperator(o) for o in si.operators(cfg, 6)]
+    prm = scsf.make_params(cfg.L, cfg.k, cfg.degree, cfg.tol, seed=5)
+
+    def run(h_, idx, X=None, th=None):
+        out = []
+        for i in idx:
+            ev, _, X, th, st = scsf.scsf_solve(h_, ops[i], prm, X, th)
+            out.append((host(ev), st["iterations"]))
+        return out, X, th
+
+    full, _, _ = run(h, range(6))
+    head, X, th = run(h, range(3))
+    np.savez(tmp_path / "chain.npz", pos=3, X=host(X).T, theta=host(th))
+    ck = np.load(tmp_path / "chain.npz")
+    h2 = scsf.Handle()
+    Xr = torch.tensor(ck["X"], device="cuda").t()              # back to n x k column-major
+    tail, _, _ = run(h2, range(int(ck["pos"]), 6), Xr, torch.tensor(ck["theta"], device="cuda"))
+    for (a, ia), (b, ib) in zip(full, head + tail):
+        np.testing.assert_array_equal(a, b)
+        assert ia == ib

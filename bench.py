@@ -2,21 +2,27 @@
 
 One step = the whole path over one synthetic dataset: truncated-FFT sort of the coefficient
 fields (Algorithm 2) and the warm-started Chebyshev filtered subspace iteration over every
-operator in sorted order (Algorithm 3), split into `--chains` contiguous chunks that run
-concurrently (the chunk parallelism of App. D.6).  Inputs are resident in HBM before timing;
-the step ends with all eigenpairs resident in HBM.
+operator in sorted order (Algorithm 3), split into `--chains` chains that run concurrently
+(the chunk parallelism of App. D.6).  Inputs are resident in HBM before timing; the step ends
+with all eigenpairs resident in HBM.
 
-Workload (default): 200 generalized-Poisson operators -div(K grad u) on a 100 x 100 grid
-(n = 10^4), K = exp(GRF with 16 x 16 cosine modes), L = 100 smallest eigenpairs, block width
-k = 120, Chebyshev degree 30 (the configuration's range is 16-30), p0 = 20, relative residual
-1e-8, FP64.  `--config` selects the other workloads (1 small, 3 uneven batch, 4 mixed
-precision, 5 learned window, 6 thin-plate vibration).
+Workload (default, the largest): 2000 anisotropic operators -div(K grad u) with an SPD tensor
+field K (9-point Q1 stencil) on a 128 x 128 grid (n = 16384), L = 64 smallest eigenpairs,
+block width k = 80, relative residual 1e-8, FP64, in the learned-window form: the plain
+solves (degree 20) of the first 500 operators of the sorted order give the labels of the
+window network, which is trained (FP32) and predicts, in BF16, the window and the filter
+degree of the other 1500 solves.  Every operator is solved once per step, training included.
+`--config` selects the other workloads (1 small, 2 working size, 3 uneven batch, 4 mixed
+precision, 6 thin-plate vibration).
 
 Prints one JSON line (rank 0).  `roofline` describes the dominant kernel (the filter's
-Chebyshev step), timed live with HIP events around each filter launch (or filter graph) inside
-the timed region; `cpu_baseline` times the CPU oracle (NumPy/SciPy) on a bounded prefix of the
-same sorted sequence.  After the timed steps, for the working-size workload: `comparison`
-(the same operators solved cold and unsorted) and `spmm_isolated` (the filter step alone).
+Chebyshev step): its algorithmic bytes per step over the wall time per step.  `cpu_baseline`
+times the CPU oracle (NumPy/SciPy) on a bounded sample of the same workload, on one core and
+on all cores the process may use (chunk model of App. D.6).  After the timed steps:
+`comparison` (learned window: the plain FP64 method at the configured degree and at the best
+fixed degree, and the learned form with the FP32 filter; working size: cold unsorted solves
+and the static schedule), `spmm_isolated` (the filter step alone) and `dense_isolated` (the
+Gram product alone).
 """
 from __future__ import annotations
 
@@ -47,9 +53,11 @@ def workload(cfg_index: int, count: int | None):
 
 
 def measured_traffic(cfg_name: str, launch: dict):
-    """HBM bytes per filter launch from the committed counter record of this workload, while
-    the filter step's source and the launch configuration (chains, lanes, schedule, graphs)
-    are those the counters were taken with (else None)."""
+    """HBM bytes per filter launch (FETCH_SIZE + WRITE_SIZE of the filter kernel, each scaled
+    by what the counter reads for a device copy of known size) from the committed counter
+    record of this workload, while the filter step's source and the launch configuration
+    (chains, lanes, schedule, graphs, tile, form, precision) are those the counters were taken
+    with (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"spmm_traffic_{cfg_name}.txt")
     if not os.path.exists(path):
@@ -126,7 +134,7 @@ def family_order_host(ops, p0):
     """Algorithm 2 within each operator family, concatenated (oracle; CPU baseline only)."""
     from oracle import sort as S
     order = []
-    for fam in ("divk", "potential", "aniso"):
+    for fam in ("divk", "potential", "aniso", "plate"):
         idx = [i for i, o in enumerate(ops) if o.family == fam]
         if idx:
             sub = S.scsf_sort([ops[i].field for i in idx], p0)
@@ -134,48 +142,90 @@ def family_order_host(ops, p0):
     return order
 
 
-def cpu_baseline(cfg, ops, budget_s: float, Ls=None, ks=None, degree=None, adaptive=False):
-    """The oracle (plain NumPy/SciPy SCSF) on a bounded prefix of the sorted sequence, with the
-    filter degree (and per-vector degrees) of the timed run."""
+def _cpu_chain(task):
+    """One chunk of the sorted order solved by the oracle as one warm-started chain (first
+    solve cold), on one core, until `budget` seconds have passed.  Runs in a child process."""
+    cfg_index, chunk, degree, budget, uneven = task
+    from threadpoolctl import threadpool_limits
     import math
-    import numpy as np
-    from oracle import operator as O, sort as S, chfsi as C, transfer as T
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = 1
-    degree = degree or cfg.degree
-    t0 = time.time()
-    if Ls is None:
-        order = S.scsf_sort([o.field for o in ops], cfg.p0)
-        Ls, ks = [cfg.L] * len(ops), [cfg.k] * len(ops)
-    else:
-        order = family_order_host(ops, cfg.p0)
+    import scsf_inputs as si
+    from oracle import operator as O, chfsi as C, transfer as T
+    cfg = si.CONFIGS[cfg_index]
+    t0 = time.perf_counter()
     prev, prev_key, done, pairs = None, None, 0, 0
-    for i in order:
-        A = O.assemble(ops[i])
-        key = (ops[i].family, Ls[i], ks[i])
-        if prev is None or key != prev_key:
-            r = C.chfsi(A, Ls[i], ks[i], degree, cfg.tol, seed=1, adaptive=adaptive)
-        else:
-            X0 = prev.X_next
-            if X0.shape[0] != A.shape[0]:
-                X0 = T.interpolate_block(X0, math.isqrt(X0.shape[0]), ops[i].N)
-            r = C.chfsi(A, Ls[i], ks[i], degree, cfg.tol, X0=X0, theta0=prev.theta_next,
-                        adaptive=adaptive)
-        prev, prev_key = r, key
-        done += 1
-        pairs += Ls[i]
-        log(f"[bench] cpu oracle: operator {done} ({r.iterations} iterations) "
-            f"{time.time() - t0:.1f}s")
-        if time.time() - t0 > budget_s:
-            break
-    dt = time.time() - t0
-    return {"value": pairs / dt, "unit": "eigenpairs/s", "cores": int(threads),
+    with threadpool_limits(1):
+        for i in chunk:
+            op = si.operator(cfg, i)
+            A = O.assemble(op)
+            L = si.mixed_L(cfg, i) if uneven else cfg.L
+            k = -(-(L + -(-L // 5)) // 8) * 8 if uneven else cfg.k   # L + 20%, multiple of 8
+            key = (op.family, L, k)
+            if prev is None or key != prev_key:
+                r = C.chfsi(A, L, k, degree, cfg.tol, seed=1)
+            else:
+                X0 = prev.X_next
+                if X0.shape[0] != A.shape[0]:
+                    X0 = T.interpolate_block(X0, math.isqrt(X0.shape[0]), op.N)
+                r = C.chfsi(A, L, k, degree, cfg.tol, X0=X0, theta0=prev.theta_next)
+            prev, prev_key = r, key
+            done += 1
+            pairs += L
+            if time.perf_counter() - t0 > budget:
+                break
+    return done, pairs, time.perf_counter() - t0
+
+
+def cpu_baseline(cfg, ops, budget_s: float, degree=None):
+    """The oracle (plain NumPy/SciPy SCSF, one BLAS thread per process) on a bounded sample of
+    the same workload, in the chunk model of App. D.6: the sorted order is cut into W
+    contiguous chunks and W processes each run their chunk as one warm-started chain for
+    `budget_s` seconds.  W = 1 (one core) and W = the cores this process may use (at most 16).
+    The oracle's sort of all fields is timed once and charged to both rates in proportion to
+    the operators solved."""
+    import multiprocessing as mp
+    from oracle import sort as S
+    degree = degree or cfg.degree
+    uneven = cfg.family == "mixed"
+    t = time.perf_counter()
+    order = (family_order_host(ops, cfg.p0) if uneven
+             else [int(i) for i in S.scsf_sort([o.field for o in ops], cfg.p0)])
+    t_sort = time.perf_counter() - t
+    log(f"[bench] cpu oracle: sort of {len(ops)} fields {t_sort:.1f}s")
+    nproc = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        avail = nproc
+    workers = max(1, min(avail, 16))
+    ctx = mp.get_context("spawn")
+    out = {}
+    for W in (1, workers):
+        chunks = [order[(len(order) * c) // W:(len(order) * (c + 1)) // W] for c in range(W)]
+        t = time.perf_counter()
+        with ctx.Pool(W) as pool:
+            res = pool.map(_cpu_chain, [(cfg.index, ch, degree, budget_s, uneven)
+                                        for ch in chunks])
+        wall = time.perf_counter() - t
+        done = sum(r[0] for r in res)
+        pairs = sum(r[1] for r in res)
+        busy = max(r[2] for r in res)
+        charged = busy + t_sort * done / len(ops)
+        out[W] = {"value": pairs / charged, "cores": W, "operators": done,
+                  "seconds": charged, "wall_s": wall}
+        log(f"[bench] cpu oracle on {W} core(s): {done} operators, {pairs / charged:.1f} "
+            f"eigenpairs/s")
+    one, many = out[1], out[workers]
+    sample = ("{ops} operators of the sorted sequence in {W} contiguous chunk(s), each a "
+              "warm-started chain with a cold first solve, degree {d}, one BLAS thread per "
+              "process, {sec:.1f}s, plus the oracle sort of all {n} fields ({ts:.1f}s) charged "
+              "in proportion")
+    return {"value": many["value"], "unit": "eigenpairs/s", "cores": workers, "nproc": nproc,
             "kind": "oracle",
-            "sample": f"sort of all {len(ops)} fields + the first {done} operators of the sorted "
-                      f"sequence (one warm-started chain, cold first solve), {dt:.1f}s"}
+            "sample": sample.format(ops=many["operators"], W=workers, d=degree,
+                                    sec=many["seconds"], n=len(ops), ts=t_sort),
+            "one_core": {"value": one["value"], "unit": "eigenpairs/s", "cores": 1,
+                         "sample": sample.format(ops=one["operators"], W=1, d=degree,
+                                                 sec=one["seconds"], n=len(ops), ts=t_sort)}}
 
 
 def main():
@@ -183,7 +233,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=5,
+                    help="workload: 1 small, 2 working size, 3 uneven batch, 4 mixed "
+                         "precision, 5 learned window (default: the largest), 6 thin plates")
     ap.add_argument("--count", type=int, default=None, help="operators (default: all)")
     ap.add_argument("--chains", type=int, default=128)
     ap.add_argument("--lanes", type=int, default=6)
@@ -202,8 +254,9 @@ def main():
                     help="tune filter tiles (and, for the uneven workload, block widths) on the "
                          "dataset once before the warmup; the timed steps use the result")
     ap.add_argument("--form", choices=["learned", "plain"], default=None,
-                    help="learned-window workload only: learned (train on the first solves, "
-                         "predict windows and degrees for the rest; default) or plain")
+                    help="learned-window workload only: learned (plain solves of the first "
+                         "operators train the network, whose predictions steer the rest; "
+                         "default) or plain")
     ap.add_argument("--train", type=int, default=500,
                     help="learned form: operators solved plainly to train the network")
     ap.add_argument("--epochs", type=int, default=600)
@@ -213,12 +266,18 @@ def main():
                     help="per-vector filter degrees in [degree, min(2 degree, 64)] (FP64 "
                          "solves without degree hints)")
     ap.add_argument("--compare", choices=["on", "off"], default="on",
-                    help="working-size workload: also time the same operators solved cold and "
-                         "unsorted (outside the timed steps)")
+                    help="after the timed steps, time the baselines of the workload once: "
+                         "working size: cold unsorted and the static schedule; learned "
+                         "window: plain FP64 at the configured and at the best fixed degree, "
+                         "and the learned form with the FP32 filter")
+    ap.add_argument("--best-degree", type=int, default=64,
+                    help="learned window: the fixed degree of the plain baseline that the "
+                         "network's degree competes with")
     ap.add_argument("--spmm-isolated", choices=["on", "off"], default="on",
-                    help="working-size workload: also time the filter step alone on 32 blocks "
-                         "(after the timed steps)")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+                    help="also time the filter step and the Gram product alone (after the "
+                         "timed steps)")
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle work per CPU baseline run (one core, all cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="before timing, run a plain 1 GiB device-to-device copy kernel three "
@@ -263,19 +322,22 @@ def main():
         fams = sorted({key[0] for key in groups})
     else:
         fields = torch.tensor(np.stack([o.field for o in ops]), device="cuda")
-    precision = args.precision or ("mixed" if cfg.precision == "mixed" or form == "learned"
-                                   else "fp64")
+    precision = args.precision or ("mixed" if cfg.precision == "mixed" else "fp64")
     adaptive = args.adaptive == "on"
     if adaptive and (precision != "fp64" or form == "learned"):
         print(json.dumps({"error": "--adaptive needs FP64 solves without degree hints "
                                    "(--precision fp64, and --form plain on the learned-window "
                                    "workload)"}))
         sys.exit(2)
-    prm = scsf.make_params(cfg.L, cfg.k, degree, cfg.tol, seed=1,
-                           schedule=scsf.SCSF_SCHED_DYNAMIC if args.schedule == "dynamic"
-                           else scsf.SCSF_SCHED_STATIC,
-                           precision=scsf.SCSF_MIXED if precision == "mixed" else scsf.SCSF_FP64,
-                           adaptive=int(adaptive))
+    sched = scsf.SCSF_SCHED_DYNAMIC if args.schedule == "dynamic" else scsf.SCSF_SCHED_STATIC
+
+    def params(prec=precision, deg=degree, **kw):
+        return scsf.make_params(cfg.L, cfg.k, deg, cfg.tol, seed=1, schedule=kw.pop(
+            "schedule", sched), precision=scsf.SCSF_MIXED if prec == "mixed" else scsf.SCSF_FP64,
+            **kw)
+
+    prm = params(adaptive=int(adaptive))
+    prm64 = params(prec="fp64")
     if not uneven:
         evals = torch.empty((n_op, cfg.L), device="cuda", dtype=torch.float64)
         evecs = torch.empty((n_op, cfg.L, dops[0].n), device="cuda", dtype=torch.float64)
@@ -288,10 +350,6 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log("[bench] copy calibration: 3 x 1 GiB device copy done")
-
-    prm64 = scsf.make_params(cfg.L, cfg.k, degree, cfg.tol, seed=1,
-                             schedule=scsf.SCSF_SCHED_DYNAMIC if args.schedule == "dynamic"
-                             else scsf.SCSF_SCHED_STATIC, precision=scsf.SCSF_FP64)
 
     def make_order():
         if uneven:
@@ -307,39 +365,50 @@ def main():
     n_train = min(args.train, n_op // 2) if windowed else 0
     train_info = {}
 
-    def step_learned():
+    def step_learned(p):
         """Sort; plain solves of the first n_train operators of the order (their Ritz values
-        and bounds give the labels); FP32 training; BF16 inference for the rest, whose solves
-        take the predicted window and degree."""
+        and bounds are the labels); FP32 training; BF16 inference for the rest, whose solves
+        take the predicted window and degree.  Every operator is solved once."""
+        t = time.perf_counter()
         order = scsf.scsf_sort(h, fields, cfg.p0)
         head, tail = [int(i) for i in order[:n_train]], [int(i) for i in order[n_train:]]
         ritz = torch.empty((n_train, cfg.k), device="cuda", dtype=torch.float64)
         _, _, st1 = scsf.scsf_solve_sequence(h, [dops[i] for i in head], np.arange(n_train),
-                                             args.chains, prm, ritz=ritz)
+                                             args.chains, p, evals[:n_train], evecs[:n_train],
+                                             ritz=ritz)
+        t_head = time.perf_counter() - t
         beta = torch.tensor([s["beta"] for s in st1], device="cuda", dtype=torch.float64)
         target = scsf.scsf_window_labels(h, ritz, cfg.L, beta)
         x = scsf.scsf_window_input(h, scsf.scsf_features(h, fields, 16))
-        params = scsf.scsf_window_init(h, 5)
-        hist = scsf.scsf_window_train(h, params, x[torch.tensor(head, device="cuda")], target,
+        params_ = scsf.scsf_window_init(h, 5)
+        hist = scsf.scsf_window_train(h, params_, x[torch.tensor(head, device="cuda")], target,
                                       args.epochs, 1e-3)
-        out = scsf.scsf_window_forward(h, params, x[torch.tensor(tail, device="cuda")], bf16=True)
+        out = scsf.scsf_window_forward(h, params_, x[torch.tensor(tail, device="cuda")],
+                                       bf16=True)
         hints = scsf.scsf_window_hints(h, out).cpu().numpy()
+        t_train = time.perf_counter() - t - t_head
         _, _, st2 = scsf.scsf_solve_sequence(h, [dops[i] for i in tail], np.arange(len(tail)),
-                                             args.chains, prm, hints=hints)
+                                             args.chains, p, evals[n_train:], evecs[n_train:],
+                                             hints=hints)
         train_info.update(loss_first=float(hist[0]), loss_last=float(hist[-1]),
                           hints_used=int(sum(s["hint"] == 2 for s in st2)),
-                          mean_degree=float(np.mean([s["degree"] for s in st2])))
+                          mean_degree=float(np.mean([s["degree"] for s in st2])),
+                          head_s=t_head, train_and_infer_s=t_train,
+                          tail_s=time.perf_counter() - t - t_head - t_train,
+                          head_mean_iterations=float(np.mean([s["iterations"] for s in st1])),
+                          tail_mean_iterations=float(np.mean([s["iterations"] for s in st2])))
         return st1 + st2
 
-    def step():
-        if form == "learned":
-            return step_learned()
+    def step_plain(p):
         order = make_order()
         if uneven:
-            _, _, stats = scsf.scsf_solve_batched(h, dops, Ls, order, args.chains, prm)
+            _, _, stats = scsf.scsf_solve_batched(h, dops, Ls, order, args.chains, p)
             return stats
-        _, _, stats = scsf.scsf_solve_sequence(h, dops, order, args.chains, prm, evals, evecs)
+        _, _, stats = scsf.scsf_solve_sequence(h, dops, order, args.chains, p, evals, evecs)
         return stats
+
+    def step():
+        return step_learned(prm) if form == "learned" else step_plain(prm)
 
     tune_s = 0.0
     if args.autotune == "on":
@@ -372,39 +441,67 @@ def main():
     dt = time.perf_counter() - t0
     prof = scsf.scsf_profile_read(h, reset=True)
     scsf.scsf_profile_enable(h, False)
-
-    comparison = None
-    if cfg.index == 2 and args.compare == "on":
-        # the same operators in their generated order, every solve from a random block
-        prm_cold = scsf.make_params(cfg.L, cfg.k, degree, cfg.tol, seed=1,
-                                    schedule=scsf.SCSF_SCHED_DYNAMIC if args.schedule == "dynamic"
-                                    else scsf.SCSF_SCHED_STATIC, cold_start=1)
-        t = time.perf_counter()
-        _, _, stc = scsf.scsf_solve_sequence(h, dops, np.arange(n_op), args.chains, prm_cold,
-                                             evals, evecs)
-        torch.cuda.synchronize()
-        tc = time.perf_counter() - t
-        comparison = {"cold_unsorted_value": n_op * cfg.L / tc, "cold_unsorted_ms": tc * 1e3,
-                      "cold_unsorted_mean_iterations":
-                          float(np.mean([s["iterations"] for s in stc]))}
-        log(f"[bench] cold unsorted comparison: {n_op * cfg.L / tc:.0f} eigenpairs/s")
-    if windowed and form == "learned":
-        # the plain FP64 method (window from Ritz values, degree 20) on the same operators
-        t = time.perf_counter()
-        order = scsf.scsf_sort(h, fields, cfg.p0)
-        _, _, stp = scsf.scsf_solve_sequence(h, dops, order, args.chains, prm64)
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - t
-        comparison = {"plain_fp64_value": n_op * cfg.L / tp, "plain_fp64_ms": tp * 1e3,
-                      "plain_fp64_mean_iterations": float(np.mean([s["iterations"] for s in stp]))}
-        log(f"[bench] plain fp64 comparison: {n_op * cfg.L / tp:.0f} eigenpairs/s")
-
     pairs = args.steps * sum(Ls)
     value = pairs / dt
-    avg_ms = prof["filter_ms"] / max(prof["filter_launches"], 1)
-    avg_bytes = prof["filter_bytes"] / max(prof["filter_launches"], 1)
-    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    log(f"[bench] {value:.0f} eigenpairs/s, {dt / args.steps * 1e3:.1f} ms per step")
 
+    def timed(fn, label):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = fn()
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t
+        log(f"[bench] {label}: {sum(Ls) / tt:.0f} eigenpairs/s")
+        return {"value": sum(Ls) / tt, "ms": tt * 1e3,
+                "mean_iterations": float(np.mean([s["iterations"] for s in st]))}
+
+    comparison = None
+    if args.compare == "on" and cfg.index == 2:
+        comparison = {
+            # the same operators in their generated order, every solve from a random block
+            "cold_unsorted": timed(lambda: scsf.scsf_solve_sequence(
+                h, dops, np.arange(n_op), args.chains, params(cold_start=1), evals, evecs)[2],
+                "cold unsorted"),
+            # App. D.6 chunking: every chain warm-starts from its true neighbour in the order
+            "static_schedule": timed(lambda: step_plain(params(
+                schedule=scsf.SCSF_SCHED_STATIC)), "static schedule")}
+        comparison["ratio_to_cold_unsorted"] = value / comparison["cold_unsorted"]["value"]
+    if args.compare == "on" and windowed and form == "learned":
+        comparison = {
+            "plain_fp64": timed(lambda: step_plain(prm64), f"plain fp64 degree {degree}"),
+            f"plain_fp64_degree{args.best_degree}": timed(
+                lambda: step_plain(params(prec="fp64", deg=args.best_degree)),
+                f"plain fp64 degree {args.best_degree}"),
+            "learned_fp32_filter": timed(lambda: step_learned(params(prec="mixed")),
+                                         "learned window, FP32 filter")}
+        comparison["plain_fp64"]["degree"] = degree
+        comparison[f"plain_fp64_degree{args.best_degree}"]["degree"] = args.best_degree
+        comparison["ratio_to_plain_fp64"] = value / comparison["plain_fp64"]["value"]
+        comparison["ratio_to_best_fixed_degree"] = (
+            value / comparison[f"plain_fp64_degree{args.best_degree}"]["value"])
+
+    # The dominant kernel's rate inside the timed run: the filter's algorithmic bytes per step
+    # (every Chebyshev step reads its input and previous blocks' active columns, writes its
+    # output, and reads each operator's coefficients once) over the wall time of a step.  The
+    # HIP events around the filter launches (or filter graphs) on the lanes' streams give the
+    # filter's own live time beside it; the lanes overlap, so their sum can exceed a step.
+    bytes_step = prof["filter_bytes"] / args.steps
+    achieved = bytes_step / (dt / args.steps) / 1e9
+    live_ms = prof["filter_ms"] / max(prof["filter_launches"], 1)
+    # HBM bytes of the filter per step: the committed counter record's bytes per launch (while
+    # it matches this source and launch configuration) times the live launches per step
+    per_launch = (measured_traffic(cfg.name, {"chains": args.chains, "lanes": args.lanes,
+                                              "schedule": args.schedule, "graphs": args.graphs,
+                                              "tile": tile_used, "form": form,
+                                              "precision": precision})
+                  if not adaptive else None)
+    traffic_step = (per_launch * prof["filter_launches"] / args.steps
+                    if per_launch is not None else None)
+    kname = ("spmm_plate_kernel (Chebyshev three-term step, 13-point thin-plate standard "
+             "form, FP64)" if cfg.family == "plate" else
+             "spmm_lds_kernel (Chebyshev three-term step, %s stencil, %s)" % (
+                 "9-point Q1" if windowed else "5-point",
+                 "FP64" if precision == "fp64" else "FP32 residual form"))
     out = {
         "metric": "eigenpairs/sec at residual %g (SCSF GPU, %s%s)" % (
             cfg.tol, "learned window, " if form == "learned" else "",
@@ -445,42 +542,29 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("spmm_plate_kernel (Chebyshev three-term step, 13-point thin-plate "
-                       "standard form, FP64)" if cfg.family == "plate" else
-                       "spmm_lds_kernel (Chebyshev three-term step, %s stencil, %s)" % (
-                           "9-point Q1" if windowed else "5-point",
-                           "FP64" if precision == "fp64" else "FP32 residual form")),
+            "kernel": kname,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": (measured_traffic(cfg.name, {"chains": args.chains, "lanes": args.lanes,
-                                                    "schedule": args.schedule,
-                                                    "graphs": args.graphs,
-                                                    "tile": tile_used})
-                        if (cfg.index == 2 and form == "plain" and precision == "fp64"
-                            and not adaptive)
-                        else None),
-            "avg_launch_ms": avg_ms,
-            "launches": prof["filter_launches"],
-            "algorithmic_bytes_per_launch": avg_bytes,
+            "traffic": traffic_step,
+            "basis": "filter algorithmic bytes per step / wall time per step",
+            "algorithmic_bytes_per_step": bytes_step,
+            "launches_per_step": prof["filter_launches"] / args.steps,
+            "live_filter_ms_per_step": prof["filter_ms"] / args.steps,
+            "live_avg_span_ms": live_ms,
         },
     }
-    if comparison and "plain_fp64_value" in comparison:
-        comparison["ratio"] = value / comparison["plain_fp64_value"]
+    if form == "learned":
         out["config"]["learned"] = dict(train_info, trained_on=n_train, epochs=args.epochs)
+    if comparison:
         out["comparison"] = comparison
-    elif comparison:
-        comparison["ratio"] = value / comparison["cold_unsorted_value"]
-        out["comparison"] = comparison
-    if cfg.index in (2, 6) and precision == "fp64" and args.spmm_isolated == "on":
+    if cfg.index in (2, 5, 6) and precision == "fp64" and args.spmm_isolated == "on":
         out["spmm_isolated"] = isolated_spmm(scsf, torch, h, dops, cfg.k, degree,
-                                             32 if cfg.index == 2 else 16)
+                                             {2: 32, 5: 48, 6: 16}[cfg.index])
         out["dense_isolated"] = isolated_gram(scsf, torch, h, dops[0].n, cfg.k, 32)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, ops, args.cpu_budget,
-                                           Ls if uneven else None, ks if uneven else None,
-                                           degree=degree, adaptive=adaptive)
+        out["cpu_baseline"] = cpu_baseline(cfg, ops, args.cpu_budget, degree=degree)
     print(json.dumps(out))
 
 

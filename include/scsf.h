@@ -9,7 +9,8 @@
  * Conventions for every entry point
  *   - Pointers whose name ends in `_host` are host memory; every other array argument is
  *     DEVICE memory on the handle's device.  The caller owns every buffer it passes; the
- *     handle owns only its internal workspace (device memory it allocates and reuses).
+ *     handle owns only its internal workspace (device memory it allocates and reuses, or a
+ *     caller-owned area given with scsf_set_workspace).
  *   - Blocks of vectors are column-major with leading dimension `ld` >= n (element (i, j) at
  *     X[i + j*ld]).  Small matrices are column-major, leading dimension = their row count.
  *   - Work is enqueued on the handle's stream.  Entry points that must read a device-side
@@ -133,6 +134,16 @@ typedef struct scsf_stats {
   int64_t filter_cols;   /* sum over filter calls of degree * active columns */
   double beta;           /* upper spectral bound used by the filter */
   double max_rel_resid;  /* max relative residual of the returned pairs */
+  /* Device time of each step of Algorithm 3 for this solve (HIP events on the stream the
+   * solve ran on; the cost split of App. E.3).  In the chained and batched solvers the
+   * launches are shared by the problems of a lockstep batch, and each problem is charged
+   * every launch it took part in. */
+  float ms_filter;       /* window, Chebyshev coefficients and the m filter steps */
+  float ms_orth;         /* block Gram-Schmidt against the locked vectors + CholeskyQR2 */
+  float ms_rr;           /* Rayleigh-Ritz: A Q, Q^T A Q, eigensolve, rotations */
+  float ms_resid;        /* residual norms and locking */
+  float ms_bound;        /* upper spectral bound: Gershgorin and the Lanczos run */
+  float ms_wall;         /* host wall time from the operator's load to its extraction */
 } scsf_stats;
 
 /* Filter-step timing: when enabled, every Chebyshev step launch of the solvers is bracketed
@@ -143,6 +154,10 @@ typedef struct scsf_profile {
   int64_t filter_launches;
   double filter_ms;
   double filter_bytes;
+  /* Device time per step of Algorithm 3 (filter, orthonormalisation, Rayleigh-Ritz,
+   * residuals + locking, bounds) of every outer iteration of the solvers, summed over the
+   * lanes; recorded whether or not filter timing is enabled. */
+  double phase_ms[5];
 } scsf_profile;
 
 /* Handle on the current HIP device, enqueueing on `hip_stream` (a hipStream_t; NULL = the
@@ -176,6 +191,34 @@ int scsf_set_eigensolver(scsf_handle *h, int which);
 int scsf_profile_enable(scsf_handle *h, int on);
 /* Copy the accumulated filter timing to *out_host; reset != 0 clears it afterwards. */
 int scsf_profile_read(scsf_handle *h, scsf_profile *out_host, int reset);
+
+/* ---------------------------------------------------------------------------------------
+ * Device workspace.  By default the handle allocates its device buffers itself (hipMalloc,
+ * grown on demand and kept until scsf_destroy).  A caller that owns device memory gives it to
+ * the handle instead; from then on the library allocates no device memory of its own: every
+ * entry point carves its buffers from that area (256-byte aligned, from its base again at the
+ * start of each call, since no device buffer outlives a call) and returns SCSF_ENOMEM, with
+ * nothing enqueued, when the area is too small.  The HIP runtime's own objects (streams,
+ * events, graph executables of the chained solvers) are created by the runtime.  The
+ * solves' inputs follow Algorithm 3's I/O (the operator, the previous subspace, the degree)
+ * and their outputs stay in caller memory.
+ * ------------------------------------------------------------------------------------- */
+
+/* Device bytes scsf_solve needs for one operator of dimension n with parameters p. */
+int scsf_workspace_bytes(const scsf_params *p, int64_t n, size_t *bytes);
+/* Device bytes scsf_solve_sequence (hinted = 0) or scsf_solve_sequence_hinted (hinted != 0)
+ * needs for n_op operators of dimension n in `chains` chains, with the handle's current lane
+ * count (scsf_set_lanes). */
+int scsf_workspace_bytes_sequence(scsf_handle *h, const scsf_params *p, int64_t n, int32_t n_op,
+                                  int32_t chains, int32_t hinted, size_t *bytes);
+/* Hand the handle `bytes` bytes of device memory at dev_ptr (256-byte aligned) as its only
+ * device workspace; the buffers it allocated before are freed (the handle's streams are
+ * synchronised first).  dev_ptr = NULL returns to library-allocated buffers.  The caller keeps
+ * ownership and must keep the memory valid until the workspace is replaced or the handle is
+ * destroyed.  SCSF_EINVAL for a misaligned pointer or a zero size. */
+int scsf_set_workspace(scsf_handle *h, void *dev_ptr, size_t bytes);
+/* The largest number of workspace bytes any call used since scsf_set_workspace. */
+int scsf_workspace_peak(scsf_handle *h, size_t *bytes);
 
 /* ---------------------------------------------------------------------------------------
  * Step primitives of the hot path.  Each is a building block of scsf_solve, exposed so the
@@ -244,7 +287,9 @@ int scsf_features(scsf_handle *h, const double *fields, int32_t n_op, int32_t ch
                   int32_t p, int32_t p0, double *feats);
 
 /* Algorithm 2 end to end: order_host[n_op] = greedy nearest-neighbour order of the
- * truncated-FFT features, starting at `start`; ties go to the lowest index.  p0 <= p. */
+ * truncated-FFT features, starting at `start`; ties go to the lowest index.  p0 <= p.
+ * A NaN or infinite distance (non-finite fields, or squared differences that overflow) ranks
+ * as +infinity, so order_host is still a permutation, but the call returns SCSF_EINVAL. */
 int scsf_sort(scsf_handle *h, const double *fields, int32_t n_op, int32_t channels,
               int32_t p, int32_t p0, int32_t start, int32_t *order_host);
 
@@ -252,7 +297,7 @@ int scsf_sort(scsf_handle *h, const double *fields, int32_t n_op, int32_t channe
  * holds n_op rows of flen complex numbers (re, im interleaved), e.g. scsf_features outputs of
  * fields of different sides p concatenated (the 1/p^2 scaling makes them comparable).
  * Squared Frobenius distances; ties go to the lowest index.  n_op <= 32768; needs n_op^2
- * doubles of workspace. */
+ * doubles of workspace.  Non-finite distances: as scsf_sort (SCSF_EINVAL). */
 int scsf_order_features(scsf_handle *h, const double *feats, int32_t n_op, int32_t flen,
                         int32_t start, int32_t *order_host);
 

@@ -20,6 +20,10 @@ Readings (ambiguous or silent passages):
 * G is formed on the active columns only, and the rotated Ritz vectors replace V0;
 * convergence uses the relative residual ||A v - theta v|| / ||A v|| (App. D.5 error metric);
   the longest converged ascending prefix of the active Ritz pairs is locked;
+* "until L pairs are locked" is read as: until at least L locked values lie at or below the
+  smallest unconverged Ritz value (`wanted_locked`), and the L smallest locked pairs are
+  returned.  A Ritz value of the block orthogonal to the locked vectors that lies below a
+  locked one means a wanted pair entered the block after larger ones were locked;
 * all k final Ritz pairs (locked and active) are handed to the next problem; between
   operators on grids of different sides the vectors are moved by bilinear interpolation
   (transfer.py) and the Ritz values are kept (the operators are scaled by 1/h^2, so the low
@@ -54,6 +58,17 @@ def _gaussian(n: int, k: int, seed: int) -> np.ndarray:
     return np.random.Generator(np.random.PCG64(seed)).standard_normal((n, k))
 
 
+def wanted_locked(theta_locked, theta_active, L: int) -> bool:
+    """True when at least L locked values are <= the smallest unconverged active Ritz value
+    (all locked values count when no active value is left)."""
+    theta_locked = np.asarray(theta_locked, dtype=np.float64)
+    if theta_locked.size < L:
+        return False
+    if len(theta_active) == 0:
+        return True
+    return int(np.count_nonzero(theta_locked <= np.min(theta_active))) >= L
+
+
 def chfsi(A, L: int, k: int, m: int, tol: float, X0=None, theta0=None, beta=None,
           seed: int = 0, max_iter: int = 200, lanczos_steps: int = 20,
           adaptive: bool = False) -> Result:
@@ -79,7 +94,7 @@ def chfsi(A, L: int, k: int, m: int, tol: float, X0=None, theta0=None, beta=None
     matvecs = 0
     it = 0
     res_act = None                       # residuals of the active Ritz pairs (last iteration)
-    while it < max_iter and thl.size < L:
+    while it < max_iter and not wanted_locked(thl, theta, L):
         it += 1
         lam = thl[0] if thl.size else theta[0]
         alpha = theta[-1]
@@ -113,9 +128,11 @@ def chfsi(A, L: int, k: int, m: int, tol: float, X0=None, theta0=None, beta=None
 
     allV = np.hstack([Vl, X])
     allth = np.concatenate([thl, theta])
-    order = np.argsort(allth[:L], kind="stable")
-    return Result(evals=allth[:L][order], evecs=canonical_sign(allV[:, :L][:, order]),
-                  X_next=allV, theta_next=allth, iterations=it, converged=thl.size >= L,
+    nsel = max(L, thl.size)              # the L smallest of the locked pairs
+    order = np.argsort(allth[:nsel], kind="stable")[:L]
+    return Result(evals=allth[order], evecs=canonical_sign(allV[:, order]),
+                  X_next=allV, theta_next=allth, iterations=it,
+                  converged=wanted_locked(thl, theta, L),
                   filter_matvecs=matvecs, beta=float(beta))
 
 

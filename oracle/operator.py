@@ -133,11 +133,3 @@ def assemble(op) -> sp.csr_matrix:
         return assemble5(op)
     return assemble9(op)
 
-
-def norm2_upper(A) -> float:
-    """Largest eigenvalue of an SPD matrix = ||A||_2 (dense for small n, ARPACK otherwise)."""
-    import scipy.sparse.linalg as sla
-    n = A.shape[0]
-    if n <= 2048:
-        return float(np.linalg.eigvalsh(A.toarray())[-1])
-    return float(sla.eigsh(A, k=1, which="LA", tol=0, return_eigenvectors=False)[0])

@@ -150,10 +150,13 @@ hipError_t residuals(int B, int64_t n, int64_t ld, const double *X, const double
                      hipStream_t st, const int32_t *rows = nullptr);
 
 // Lock the longest converged ascending prefix of the active columns: nconv[b] grows by the
-// prefix with res <= tol.  lock[b] (first active column) follows nconv[b], and becomes k once
-// nconv[b] >= L (done[b] = 1), which makes every ACTIVE-mode kernel skip the problem.
+// prefix with res <= tol.  lock[b] (first active column) follows nconv[b], and becomes k
+// (done[b] = 1, which makes every ACTIVE-mode kernel skip the problem) once at least L
+// converged pairs lie at or below the smallest unconverged Ritz value theta[nconv[b]]
+// (|theta| when mag): the L smallest converged pairs are then the wanted ones.
 hipError_t lock_update(int B, int32_t k, int32_t L, double tol, int32_t *lock, int32_t *nconv,
-                       const double *res, int32_t *done, hipStream_t st);
+                       const double *res, const double *theta, bool mag, int32_t *done,
+                       hipStream_t st);
 
 // Chebyshev step coefficients for degree m: coef[(s*B + b)*3 + {0,1,2}] for s = 0..m-1 from
 // lambda = theta[b*k], alpha = theta[b*k + k-1] (or win[] when given), beta = bounds[b*4+3].

@@ -65,20 +65,36 @@ hipError_t residuals(int B, int64_t n, int64_t ld, const double *X, const double
 // nconv[b]: locked pairs; lock[b]: first active column (= k once the problem is done).
 __global__ void lock_kernel(int B, int32_t k, int32_t L, double tol, int32_t *__restrict__ lock,
                             int32_t *__restrict__ nconv, const double *__restrict__ res,
+                            const double *__restrict__ theta, int mag,
                             int32_t *__restrict__ done) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B || done[b]) return;
-  int j = nconv[b];
+  const int32_t j0 = nconv[b];
+  int j = j0;
   while (j < k && res[(int64_t)b * k + j] <= tol) ++j;
   nconv[b] = j;
-  if (j >= L) { done[b] = 1; lock[b] = k; }
+  // A solve ends once at least L converged pairs lie at or below every unconverged Ritz value.
+  // The active range [j0, k) is ascending (by |theta| in the magnitude mode), so its first
+  // unconverged value theta_j is the smallest; a converged pair locked earlier above theta_j
+  // means a wanted pair entered the block late, and the solve goes on until it has converged.
+  bool fin = j >= L;
+  if (fin && j < k) {
+    const double *th = theta + (int64_t)b * k;
+    const double tu = mag ? fabs(th[j]) : th[j];
+    int below = j - j0;
+    for (int c = 0; c < j0; ++c) below += ((mag ? fabs(th[c]) : th[c]) <= tu) ? 1 : 0;
+    fin = below >= L;
+  }
+  if (fin) { done[b] = 1; lock[b] = k; }
   else lock[b] = j;
 }
 
 hipError_t lock_update(int B, int32_t k, int32_t L, double tol, int32_t *lock, int32_t *nconv,
-                       const double *res, int32_t *done, hipStream_t st) {
+                       const double *res, const double *theta, bool mag, int32_t *done,
+                       hipStream_t st) {
   if (B <= 0) return hipSuccess;
-  lock_kernel<<<(B + 63) / 64, 64, 0, st>>>(B, k, L, tol, lock, nconv, res, done);
+  lock_kernel<<<(B + 63) / 64, 64, 0, st>>>(B, k, L, tol, lock, nconv, res, theta, mag ? 1 : 0,
+                                            done);
   return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <thread>
 #include <vector>
@@ -27,19 +28,41 @@ namespace {
 enum BufId {
   B_X, B_Y1, B_Y2, B_W, B_G, B_M, B_PART, B_THETA, B_RES, B_INT, B_BND, B_COEF, B_UNIT, B_CHOL,
   B_JAC, B_LZ, B_OPS, B_WIN, B_SORTF, B_SORTD, B_SORTO, B_REC, B_RANK, B_E32, B_R32, B_SRC,
-  B_GAIN, B_WINB, B_HINT, B_MDEG, B_NETF, B_NETH, B_NETD, B_ROWS, B_EIG, B_CDEG, B_SQT, B_SQP, B_COEF2, B_COUNT
+  B_GAIN, B_WINB, B_HINT, B_MDEG, B_NETF, B_NETH, B_NETD, B_ROWS, B_EIG, B_CDEG, B_SQT, B_SQP, B_COEF2,
+  B_TEV, B_TVV, B_COUNT
 };
 
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  bool in_arena = false;                 // carved from a caller-owned workspace
+  uint64_t gen = 0;                      // arena generation it was carved in
 };
+
+// A caller-owned device workspace (scsf_set_workspace).  While one is set, every device
+// buffer is carved from it by a bump pointer: at the start of each top-level entry point the
+// pointer returns to the base (nothing the library keeps lives across calls), and a buffer
+// that must grow is carved anew.  A call that needs more than `cap` returns SCSF_ENOMEM.
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  size_t peak = 0;
+  uint64_t gen = 1;
+  int depth = 0;                         // nesting of entry points (reset at depth 0 only)
+  std::mutex mu;                         // the lanes carve concurrently
+};
+
+// Per-phase device times (Algorithm 3's steps), from HIP events on a lane's stream.
+enum Phase { PH_FILTER, PH_ORTH, PH_RR, PH_RESID, PH_BOUND, PH_COUNT };
 
 // Device buffers, pinned host staging, a stream and filter timing of one concurrent lane.
 struct Workspace {
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  Arena *arena = nullptr;
   DevBuf bufs[B_COUNT];
+  double phase_ms[PH_COUNT] = {0, 0, 0, 0, 0};   // accumulated (scsf_profile_read)
   void *pinned = nullptr;
   size_t pinned_bytes = 0;
   bool prof = false;                     // filter-launch timing (scsf_profile_*)
@@ -62,6 +85,7 @@ struct scsf_handle {
   std::vector<std::pair<int32_t, int32_t>> widths;
   std::vector<Workspace *> ws;           // ws[0] runs on the caller's stream; ws[1..] are the
                                          // lanes of chained solves (private streams)
+  Arena arena;                           // caller-owned workspace (base == nullptr: none)
 };
 
 namespace {
@@ -81,6 +105,27 @@ template <typename T>
 int grow(Workspace *h, int id, size_t count, T **out) {
   DevBuf &b = h->bufs[id];
   const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  Arena *a = h->arena;
+  if (a && a->base) {
+    std::lock_guard<std::mutex> lk(a->mu);
+    if (!(b.in_arena && b.gen == a->gen && b.bytes >= bytes)) {
+      const size_t off = (a->used + 255) / 256 * 256;
+      if (off > a->cap || bytes > a->cap - off) return SCSF_ENOMEM;
+      b.p = a->base + off;
+      b.bytes = bytes;
+      b.in_arena = true;
+      b.gen = a->gen;
+      a->used = off + bytes;
+      a->peak = std::max(a->peak, a->used);
+    }
+    *out = static_cast<T *>(b.p);
+    return SCSF_OK;
+  }
+  if (b.in_arena) {                      // left over from a workspace that was removed
+    b.p = nullptr;
+    b.bytes = 0;
+    b.in_arena = false;
+  }
   if (b.bytes < bytes) {
     if (b.p) {
       if (hipStreamSynchronize(h->stream) != hipSuccess) return SCSF_EHIP;
@@ -237,6 +282,8 @@ struct Engine {
   double *h_theta = nullptr, *h_res = nullptr, *h_bnd = nullptr, *h_unit = nullptr;
   OpDev *h_ops = nullptr;
 
+  size_t *measure = nullptr;             // setup() only sums the device bytes it would take
+
   int setup(Workspace *hh, int B_, int64_t n_, int32_t k_, int32_t L_, int32_t m_, int32_t kind_,
             double tol_, uint64_t seed_, int32_t lz_steps_, bool mixed_ = false,
             bool var_deg_ = false, bool adaptive_ = false, bool mag_ = false) {
@@ -269,55 +316,71 @@ struct Engine {
     ldm = (int32_t)round_up(k, 32);
     part_stride = gemm_tn_partial_elems(n, ldm);
     const size_t blk = (size_t)B * bs;
-    STCHK(grow(h, B_X, blk, &X));
-    STCHK(grow(h, B_Y1, blk, &Y1));
-    STCHK(grow(h, B_Y2, blk, &Y2));
-    STCHK(grow(h, B_W, blk, &W));
-    STCHK(grow(h, B_G, (size_t)B * ldm * ldm, &G));
-    STCHK(grow(h, B_M, (size_t)B * ldm * ldm, &M));
-    STCHK(grow(h, B_PART, (size_t)B * part_stride, &part));
-    STCHK(grow(h, B_THETA, (size_t)B * k, &theta));
-    STCHK(grow(h, B_RES, (size_t)B * k, &res));
+    // every device buffer of the engine; with `measure` set only their sizes are summed (the
+    // workspace query), and nothing is allocated or initialised
+    auto alloc = [&](int id, size_t count, auto **out) -> int {
+      using T = std::remove_pointer_t<std::remove_reference_t<decltype(out)>>;
+      if (measure) {
+        *measure += (std::max<size_t>(count * sizeof(*(*out)), 256) + 255) / 256 * 256;
+        *out = nullptr;
+        return SCSF_OK;
+      }
+      return grow(h, id, count, out);
+    };
+    STCHK(alloc(B_X, blk, &X));
+    STCHK(alloc(B_Y1, blk, &Y1));
+    STCHK(alloc(B_Y2, blk, &Y2));
+    STCHK(alloc(B_W, blk, &W));
+    STCHK(alloc(B_G, (size_t)B * ldm * ldm, &G));
+    STCHK(alloc(B_M, (size_t)B * ldm * ldm, &M));
+    STCHK(alloc(B_PART, (size_t)B * part_stride, &part));
+    STCHK(alloc(B_THETA, (size_t)B * k, &theta));
+    STCHK(alloc(B_RES, (size_t)B * k, &res));
     int32_t *ints = nullptr;
-    STCHK(grow(h, B_INT, (size_t)B * 5, &ints));
+    STCHK(alloc(B_INT, (size_t)B * 5, &ints));
     lock = ints;
     nconv = ints + B;
     done = ints + 2 * B;
     flag = ints + 3 * B;
     need = ints + 4 * B;
-    STCHK(grow(h, B_BND, (size_t)B * 4, &bnd));
-    STCHK(grow(h, B_COEF, (size_t)std::max(m, 1) * B * 3, &coef));
+    STCHK(alloc(B_BND, (size_t)B * 4, &bnd));
+    STCHK(alloc(B_COEF, (size_t)std::max(m, 1) * B * 3, &coef));
     if (mag) {
-      STCHK(grow(h, B_SQT, blk, &T));
-      STCHK(grow(h, B_SQP, blk, &P));
-      STCHK(grow(h, B_COEF2, (size_t)std::max(m, 1) * B * 3, &coef2));
+      STCHK(alloc(B_SQT, blk, &T));
+      STCHK(alloc(B_SQP, blk, &P));
+      STCHK(alloc(B_COEF2, (size_t)std::max(m, 1) * B * 3, &coef2));
     }
-    STCHK(grow(h, B_UNIT, (size_t)B * 3, &unit));
-    STCHK(grow(h, B_CHOL, (size_t)B * kMaxK * (kMaxK + 1), &chol));
-    STCHK(grow(h, B_JAC, (size_t)B * kMaxK * (kMaxK + 1), &jac));
-    STCHK(grow(h, B_REC, (size_t)B * jacobi_record_elems(k), &rec));
-    STCHK(grow(h, B_EIG, (size_t)B * tridiag_work_elems(k), &eigw));
+    STCHK(alloc(B_UNIT, (size_t)B * 3, &unit));
+    STCHK(alloc(B_CHOL, (size_t)B * kMaxK * (kMaxK + 1), &chol));
+    STCHK(alloc(B_JAC, (size_t)B * kMaxK * (kMaxK + 1), &jac));
+    STCHK(alloc(B_REC, (size_t)B * jacobi_record_elems(k), &rec));
+    STCHK(alloc(B_EIG, (size_t)B * tridiag_work_elems(k), &eigw));
     int32_t *rk = nullptr;
-    STCHK(grow(h, B_RANK, (size_t)B * ldm + B, &rk));
+    STCHK(alloc(B_RANK, (size_t)B * ldm + B, &rk));
     ranks = rk;
     nsweeps = rk + (size_t)B * ldm;
-    STCHK(grow(h, B_LZ, (size_t)B * 3 * n, &lz));
-    STCHK(grow(h, B_OPS, (size_t)B, &ops));
-    STCHK(grow(h, B_HINT, (size_t)B * 3, &hint));
-    STCHK(grow(h, B_MDEG, (size_t)B, &mdeg));
-    STCHK(grow(h, B_ROWS, (size_t)B, &rows));
-    STCHK(grow(h, B_CDEG, (size_t)B * k, &cdeg));
+    STCHK(alloc(B_LZ, (size_t)B * 3 * n, &lz));
+    STCHK(alloc(B_OPS, (size_t)B, &ops));
+    STCHK(alloc(B_HINT, (size_t)B * 3, &hint));
+    STCHK(alloc(B_MDEG, (size_t)B, &mdeg));
+    STCHK(alloc(B_ROWS, (size_t)B, &rows));
+    STCHK(alloc(B_CDEG, (size_t)B * k, &cdeg));
     if (mixed) {
       float *e32 = nullptr;
-      STCHK(grow(h, B_E32, (size_t)3 * B * bs, &e32));
-      E32[0] = e32;
-      E32[1] = e32 + (size_t)B * bs;
-      E32[2] = e32 + (size_t)2 * B * bs;
-      STCHK(grow(h, B_R32, (size_t)B * bs, &R32));
-      STCHK(grow(h, B_SRC, (size_t)std::max(m, 1) * B * k, &src));
-      STCHK(grow(h, B_GAIN, (size_t)B * k, &gain));
-      STCHK(grow(h, B_WINB, (size_t)B * 3, &winb));
+      STCHK(alloc(B_E32, (size_t)3 * B * bs, &e32));
+      if (e32) {
+        E32[0] = e32;
+        E32[1] = e32 + (size_t)B * bs;
+        E32[2] = e32 + (size_t)2 * B * bs;
+      }
+      STCHK(alloc(B_R32, (size_t)B * bs, &R32));
+      STCHK(alloc(B_SRC, (size_t)std::max(m, 1) * B * k, &src));
+      STCHK(alloc(B_GAIN, (size_t)B * k, &gain));
+      STCHK(alloc(B_WINB, (size_t)B * 3, &winb));
     }
+    int32_t *perm_d = nullptr;                // extract()'s column order
+    STCHK(alloc(B_SORTO, (size_t)B * k, &perm_d));
+    if (measure) return SCSF_OK;
     // pinned: 6 int arrays of B, perm B*k, theta/res B*k, bnd B*4, unit B*3, ops B
     const size_t pin = (size_t)B * 9 * 4 + (size_t)B * k * 8 + (size_t)B * k * 16 +
                        (size_t)B * 4 * 8 + (size_t)B * 6 * 8 + (size_t)B * sizeof(OpDev) + 2048;
@@ -366,7 +429,7 @@ struct Engine {
     HIPCHK(hipMemcpyAsync(rows, h_rows, (size_t)B * 4, hipMemcpyHostToDevice, st));
     HIPCHK(fill_int(flag, 0, B, st));
     HIPCHK(hipStreamSynchronize(st));
-    return SCSF_OK;
+    return make_events();
   }
 
   // Degrees of this iteration: the largest requested degree M over the unfinished problems;
@@ -472,7 +535,13 @@ struct Engine {
 
   // upper bounds of the problems with h_need[b] set
   int compute_bounds() {
+    HIPCHK(hipEventRecord(pev[5], st));
     HIPCHK(bounds(ops, B, kind, n, lz_steps, seed ^ 0x5DEECE66DULL, need, lz, bnd, st, mag));
+    HIPCHK(hipEventRecord(pev[6], st));
+    HIPCHK(hipEventSynchronize(pev[6]));
+    std::vector<char> who(B);
+    for (int b = 0; b < B; ++b) who[b] = h_need[b] != 0;
+    charge(PH_BOUND, span(5, 6), who);
     return SCSF_OK;
   }
 
@@ -538,11 +607,18 @@ struct Engine {
     }
     STCHK(upload_state());
     HIPCHK(fill_int(flag, 0, B, st));
+    HIPCHK(hipEventRecord(pev[5], st));
     STCHK(orth(X, false));
+    HIPCHK(hipEventRecord(pev[6], st));
     STCHK(rayleigh_ritz(X));
+    HIPCHK(hipEventRecord(pev[7], st));
     for (int b = 0; b < B; ++b) h_lock[b] = saved[b];
     for (int b : slots) h_lock[b] = 0;
     STCHK(upload_state());
+    std::vector<char> who(B, 0);
+    for (int b : slots) who[b] = 1;
+    charge(PH_ORTH, span(5, 6), who);
+    charge(PH_RR, span(6, 7), who);
     return SCSF_OK;
   }
 
@@ -600,22 +676,21 @@ struct Engine {
     double *ring[3] = {X, Y1, Y2};
     return mixed ? Y1 : ring[M % 3];
   }
-  int enqueue_post(int M) {
-    double *Yf = filtered(M);
-    STCHK(orth(Yf, true));
-    STCHK(rayleigh_ritz(Yf));
+  int enqueue_orth(int M) { return orth(filtered(M), true); }
+  int enqueue_rr(int M) { return rayleigh_ritz(filtered(M)); }
+  int enqueue_post(int /*M*/) {
     HIPCHK(residuals(B, n, ld, X, W, bs, k, lock, theta, res, st, rows));
-    HIPCHK(lock_update(B, k, L, tol, lock, nconv, res, done, st));
+    HIPCHK(lock_update(B, k, L, tol, lock, nconv, res, theta, mag, done, st));
     if (adaptive)
       HIPCHK(adaptive_degrees(B, k, lock, done, theta, res, bnd, tol, m_base, m, cdeg, mdeg, st));
     return SCSF_OK;
   }
 
-  // Graphs of the three parts, one set per filter degree (the only launch parameter that
+  // Graphs of the five parts, one set per filter degree (the only launch parameter that
   // changes between iterations; every kernel reads its per-problem state from device memory).
   struct GraphSet {
     int M = 0;
-    hipGraphExec_t pre = nullptr, filt = nullptr, post = nullptr;
+    hipGraphExec_t pre = nullptr, filt = nullptr, orth = nullptr, rr = nullptr, post = nullptr;
   };
   bool use_graph = false;
   std::vector<GraphSet> gcache;
@@ -637,12 +712,15 @@ struct Engine {
     HIPCHK(ei);
     return SCSF_OK;
   }
+  static void drop_set(GraphSet &gs) {
+    for (hipGraphExec_t *g : {&gs.pre, &gs.filt, &gs.orth, &gs.rr, &gs.post})
+      if (*g) {
+        (void)hipGraphExecDestroy(*g);
+        *g = nullptr;
+      }
+  }
   void drop_graphs() {
-    for (auto &gs : gcache) {
-      if (gs.pre) (void)hipGraphExecDestroy(gs.pre);
-      if (gs.filt) (void)hipGraphExecDestroy(gs.filt);
-      if (gs.post) (void)hipGraphExecDestroy(gs.post);
-    }
+    for (auto &gs : gcache) drop_set(gs);
     gcache.clear();
   }
   int graphs_for(int M, GraphSet **out) {
@@ -656,10 +734,11 @@ struct Engine {
     gs.M = M;
     int rc = capture([&] { return enqueue_pre(M); }, &gs.pre);
     if (rc == SCSF_OK) rc = capture([&] { return enqueue_filter(M, false); }, &gs.filt);
+    if (rc == SCSF_OK) rc = capture([&] { return enqueue_orth(M); }, &gs.orth);
+    if (rc == SCSF_OK) rc = capture([&] { return enqueue_rr(M); }, &gs.rr);
     if (rc == SCSF_OK) rc = capture([&] { return enqueue_post(M); }, &gs.post);
     if (rc != SCSF_OK) {
-      if (gs.pre) (void)hipGraphExecDestroy(gs.pre);
-      if (gs.filt) (void)hipGraphExecDestroy(gs.filt);
+      drop_set(gs);
       return rc;
     }
     gcache.push_back(gs);
@@ -675,6 +754,29 @@ struct Engine {
       (void)hipStreamSynchronize(st);
       drop_graphs();
     }
+    for (hipEvent_t &ev : pev)
+      if (ev) (void)hipEventDestroy(ev);
+  }
+
+  // Per-phase device times: events on the lane's stream at the phase boundaries, read after
+  // the synchronisation that follows them.  ph[b] accumulates the times of the launches
+  // problem b took part in (shared with the other problems of the batch).
+  hipEvent_t pev[8] = {};                  // 0-4 outer iteration, 5-6 bounds, 5-7 cold start
+  std::vector<std::array<double, PH_COUNT>> ph;
+  int make_events() {
+    for (hipEvent_t &ev : pev)
+      if (!ev) HIPCHK(hipEventCreate(&ev));
+    ph.assign(B, std::array<double, PH_COUNT>{});
+    return SCSF_OK;
+  }
+  float span(int a, int b) const {
+    float ms = 0.f;
+    return hipEventElapsedTime(&ms, pev[a], pev[b]) == hipSuccess ? ms : 0.f;
+  }
+  void charge(int phase, float ms, const std::vector<char> &who) {
+    h->phase_ms[phase] += ms;
+    for (int b = 0; b < B; ++b)
+      if (who[b]) ph[b][phase] += ms;
   }
 
   // One outer iteration of Algorithm 3 for every problem not done.
@@ -701,6 +803,11 @@ struct Engine {
         }
       }
     }
+    std::vector<char> act(B);
+    for (int b = 0; b < B; ++b) act[b] = !h_done[b];
+    GraphSet *gs = nullptr;
+    if (use_graph) STCHK(graphs_for(M, &gs));
+    HIPCHK(hipEventRecord(pev[0], st));
     if (mixed && w_stale) {           // A X of newly loaded operators (residual form)
       HIPCHK(spmm_step(ops, B, kind, n, Nmax, X, nullptr, W, ld, bs, COLS_ACTIVE, k, lock, unit,
                        false, st, nullptr, 0, cpt, pot));
@@ -709,10 +816,13 @@ struct Engine {
     if (!use_graph) {
       STCHK(enqueue_pre(M));
       STCHK(enqueue_filter(M, h->prof && !mag));
+      HIPCHK(hipEventRecord(pev[1], st));
+      STCHK(enqueue_orth(M));
+      HIPCHK(hipEventRecord(pev[2], st));
+      STCHK(enqueue_rr(M));
+      HIPCHK(hipEventRecord(pev[3], st));
       STCHK(enqueue_post(M));
     } else {
-      GraphSet *gs = nullptr;
-      STCHK(graphs_for(M, &gs));
       HIPCHK(hipGraphLaunch(gs->pre, st));
       int slot = -1;
       if (h->prof && !mag) {          // one timed span over the filter graph's M launches
@@ -723,9 +833,20 @@ struct Engine {
       }
       HIPCHK(hipGraphLaunch(gs->filt, st));
       prof_end(h, slot);
+      HIPCHK(hipEventRecord(pev[1], st));
+      HIPCHK(hipGraphLaunch(gs->orth, st));
+      HIPCHK(hipEventRecord(pev[2], st));
+      HIPCHK(hipGraphLaunch(gs->rr, st));
+      HIPCHK(hipEventRecord(pev[3], st));
       HIPCHK(hipGraphLaunch(gs->post, st));
     }
-    return download_state();
+    HIPCHK(hipEventRecord(pev[4], st));
+    STCHK(download_state());
+    charge(PH_FILTER, span(0, 1), act);
+    charge(PH_ORTH, span(1, 2), act);
+    charge(PH_RR, span(2, 3), act);
+    charge(PH_RESID, span(3, 4), act);
+    return SCSF_OK;
   }
 
   // theta / res / bnd of problem b to the pinned mirrors (synchronises)
@@ -742,20 +863,24 @@ struct Engine {
     return SCSF_OK;
   }
 
-  // Ascending first L pairs of problem b -> evals (device, L) and evecs (device, n x L, ld ldo),
-  // canonical sign.  Needs fetch(b) first.  Returns max relative residual of the pairs.
+  // The L smallest converged pairs of problem b (of its first max(L, nconv) columns: a
+  // solve that ends converged may hold more than L, and a pair that entered the block late
+  // is locked after larger ones), ascending -> evals (device, L) and evecs (device, n x L,
+  // ld ldo), canonical sign.  Needs fetch(b) first.  Returns max relative residual of the
+  // pairs.
   int extract(int b, double *evals, double *evecs, int64_t ldo, double *maxres) {
     const double *th = h_theta + (size_t)b * k;
     int32_t *perm = h_perm + (size_t)b * k;
-    std::iota(perm, perm + L, 0);
+    const int nsel = std::max<int>(L, std::min<int>(h_nconv[b], k));
+    std::iota(perm, perm + nsel, 0);
     if (mag)
-      std::stable_sort(perm, perm + L,
+      std::stable_sort(perm, perm + nsel,
                        [&](int a, int c) { return std::fabs(th[a]) < std::fabs(th[c]); });
     else
-      std::stable_sort(perm, perm + L, [&](int a, int c) { return th[a] < th[c]; });
+      std::stable_sort(perm, perm + nsel, [&](int a, int c) { return th[a] < th[c]; });
     double *vals = h_theta + (size_t)b * k;  // reorder in place after computing the maximum
     double mr = 0.0;
-    for (int j = 0; j < L; ++j) mr = std::max(mr, h_res[(size_t)b * k + j]);
+    for (int j = 0; j < L; ++j) mr = std::max(mr, h_res[(size_t)b * k + perm[j]]);
     std::vector<double> sorted(L);
     for (int j = 0; j < L; ++j) sorted[j] = th[perm[j]];
     for (int j = 0; j < L; ++j) vals[j] = sorted[j];
@@ -843,6 +968,8 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
   for (int i = 0; i < n_op; ++i) e.pot = e.pot || ops_host[order_host[i]].v != nullptr;
   std::vector<int> pos(chains), iters(chains, 0);
   std::vector<int64_t> fcols(chains, 0);
+  std::vector<std::chrono::steady_clock::time_point> t_load(chains,
+                                                            std::chrono::steady_clock::now());
   std::vector<char> active(chains, 1);
   // degree and window hint of the operator at order position `at`, loaded into slot b
   auto load_hint = [&](int b, int at) {
@@ -916,6 +1043,13 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
         st.filter_cols = fcols[b];
         st.beta = e.h_bnd[(size_t)b * 4 + 3];
         st.max_rel_resid = mr;
+        st.ms_filter = (float)e.ph[b][PH_FILTER];
+        st.ms_orth = (float)e.ph[b][PH_ORTH];
+        st.ms_rr = (float)e.ph[b][PH_RR];
+        st.ms_resid = (float)e.ph[b][PH_RESID];
+        st.ms_bound = (float)e.ph[b][PH_BOUND];
+        st.ms_wall = (float)(1e3 * std::chrono::duration<double>(
+                                       std::chrono::steady_clock::now() - t_load[b]).count());
       }
       if (status != SCSF_OK && (worst == SCSF_OK || status != SCSF_ENOTCONV)) worst = status;
       if (next) {
@@ -948,6 +1082,8 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
       }
       load_hint(b, pos[b]);
       reloaded.push_back(b);
+      e.ph[b] = std::array<double, PH_COUNT>{};
+      t_load[b] = std::chrono::steady_clock::now();
       e.h_need[b] = 1;
       e.h_done[b] = 0;
       e.h_nconv[b] = 0;
@@ -985,6 +1121,7 @@ int add_lanes(scsf_handle *h, int count) {
     }
     w->own_stream = true;
     w->prof = h->ws[0]->prof;
+    w->arena = &h->arena;
     h->ws.push_back(w);
   }
   return SCSF_OK;
@@ -994,7 +1131,7 @@ void free_workspace(Workspace *w) {
   (void)hipStreamSynchronize(w->stream);
   for (auto e : w->ev) (void)hipEventDestroy(e);
   for (auto &b : w->bufs)
-    if (b.p) (void)hipFree(b.p);
+    if (b.p && !b.in_arena) (void)hipFree(b.p);
   if (w->pinned) (void)hipHostFree(w->pinned);
   if (w->own_stream) (void)hipStreamDestroy(w->stream);
   delete w;
@@ -1018,6 +1155,40 @@ static int32_t tuned_width(const scsf_handle *h, int32_t L) {
     if (p.first == L) return p.second;
   return default_width(L);
 }
+
+// Device bytes the engine takes for B problems of size n (its buffers, as setup() carves them,
+// each rounded up to 256 bytes).
+size_t engine_bytes(int B, int64_t n, const scsf_params *p, bool var_deg) {
+  Engine e;
+  size_t total = 0;
+  e.measure = &total;
+  Workspace dummy;
+  (void)e.setup(&dummy, B, n, p->k, p->L, p->degree, SCSF_STENCIL5, p->tol, p->seed, 20,
+                p->precision == SCSF_MIXED, var_deg, p->adaptive != 0,
+                p->target == SCSF_TARGET_MAGNITUDE);
+  return total;
+}
+
+// Marks a top-level entry point: the first (outermost) one returns the caller-owned workspace's
+// bump pointer to its base, since no device buffer outlives a call.
+struct CallScope {
+  Arena *a;
+  explicit CallScope(scsf_handle *h) : a(h ? &h->arena : nullptr) {
+    if (!a) return;
+    std::lock_guard<std::mutex> lk(a->mu);
+    if (a->depth++ == 0) {
+      a->used = 0;
+      ++a->gen;
+    }
+  }
+  ~CallScope() {
+    if (!a) return;
+    std::lock_guard<std::mutex> lk(a->mu);
+    --a->depth;
+  }
+  CallScope(const CallScope &) = delete;
+  CallScope &operator=(const CallScope &) = delete;
+};
 
 }  // namespace
 
@@ -1049,6 +1220,7 @@ int scsf_create(scsf_handle **h, void *hip_stream) {
     return SCSF_ENOMEM;
   }
   w->stream = static_cast<hipStream_t>(hip_stream);
+  w->arena = &x->arena;
   x->ws.push_back(w);
   if (hipGetDevice(&x->device) != hipSuccess) {
     delete w;
@@ -1110,14 +1282,66 @@ int scsf_profile_read(scsf_handle *h, scsf_profile *out_host, int reset) {
     t.filter_launches += w->acc.filter_launches;
     t.filter_ms += w->acc.filter_ms;
     t.filter_bytes += w->acc.filter_bytes;
-    if (reset) w->acc = scsf_profile{};
+    for (int p = 0; p < PH_COUNT; ++p) t.phase_ms[p] += w->phase_ms[p];
+    if (reset) {
+      w->acc = scsf_profile{};
+      for (double &x : w->phase_ms) x = 0.0;
+    }
   }
   *out_host = t;
   return SCSF_OK;
 }
 
+int scsf_workspace_bytes(const scsf_params *p, int64_t n, size_t *bytes) {
+  if (!bytes || n <= 0) return SCSF_EINVAL;
+  STCHK(check_params(p, n));
+  *bytes = engine_bytes(1, n, p, false);
+  return SCSF_OK;
+}
+
+int scsf_workspace_bytes_sequence(scsf_handle *h, const scsf_params *p, int64_t n, int32_t n_op,
+                                  int32_t chains, int32_t hinted, size_t *bytes) {
+  if (!h || !bytes || n <= 0 || n_op <= 0 || chains <= 0) return SCSF_EINVAL;
+  STCHK(check_params(p, n));
+  const int c = std::min(chains, n_op);
+  const int lanes = std::min(h->lanes, c);
+  size_t total = 0;
+  for (int g = 0; g < lanes; ++g)
+    total += engine_bytes((c - g + lanes - 1) / lanes, n, p, hinted != 0);
+  *bytes = total;
+  return SCSF_OK;
+}
+
+int scsf_set_workspace(scsf_handle *h, void *dev_ptr, size_t bytes) {
+  if (!h || (dev_ptr && bytes == 0)) return SCSF_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(dev_ptr) & 255) != 0) return SCSF_EINVAL;
+  std::lock_guard<std::mutex> lk(h->arena.mu);
+  if (h->arena.depth != 0) return SCSF_EINVAL;
+  for (auto *w : h->ws) {
+    if (hipStreamSynchronize(w->stream) != hipSuccess) return SCSF_EHIP;
+    for (auto &b : w->bufs) {            // library-owned buffers go; carved ones are dropped
+      if (b.p && !b.in_arena && hipFree(b.p) != hipSuccess) return SCSF_EHIP;
+      b = DevBuf{};
+    }
+  }
+  h->arena.base = static_cast<char *>(dev_ptr);
+  h->arena.cap = dev_ptr ? bytes : 0;
+  h->arena.used = 0;
+  h->arena.peak = 0;
+  ++h->arena.gen;
+  return SCSF_OK;
+}
+
+int scsf_workspace_peak(scsf_handle *h, size_t *bytes) {
+  if (!h || !bytes) return SCSF_EINVAL;
+  std::lock_guard<std::mutex> lk(h->arena.mu);
+  *bytes = h->arena.peak;
+  return SCSF_OK;
+}
+
 int scsf_spmm(scsf_handle *h, const scsf_operator *A, const double *X, int64_t ldx, int32_t ncols,
               double *Y, int64_t ldy) {
+  CallScope cs_(h);
   if (!h) return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
 
@@ -1144,6 +1368,7 @@ int scsf_spmm(scsf_handle *h, const scsf_operator *A, const double *X, int64_t l
 int scsf_filter(scsf_handle *h, const scsf_operator *A, const double *X, int64_t ldx,
                 int32_t ncols, int32_t degree, double lambda, double c, double e, double *Y,
                 int64_t ldy) {
+  CallScope cs_(h);
   if (!h) return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
 
@@ -1176,6 +1401,7 @@ int scsf_filter(scsf_handle *h, const scsf_operator *A, const double *X, int64_t
 int scsf_filter_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t B,
                         const double *X, int64_t ldx, int64_t bsx, int32_t ncols, int32_t degree,
                         const double *win_host, double *Y, int64_t ldy, int64_t bsy) {
+  CallScope cs_(h);
   if (!h || !ops_host || B <= 0 || !X || !Y || !win_host) return SCSF_EINVAL;
   if (ncols < 0 || ncols > kMaxK || degree < 1 || degree > 64) return SCSF_EINVAL;
   int64_t nmax = 0;
@@ -1231,6 +1457,7 @@ int scsf_filter_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t B
 
 int scsf_gram_batched(scsf_handle *h, int32_t B, int64_t n, int32_t k, const double *X,
                       int64_t ldx, int64_t bsx, double *G, int32_t ldg, double *kernel_ms_host) {
+  CallScope cs_(h);
   if (!h || !X || !G || B <= 0 || n <= 0 || k <= 0 || k > kMaxK || ldx < n ||
       bsx < ldx * (int64_t)k || ldg < k)
     return SCSF_EINVAL;
@@ -1262,6 +1489,7 @@ int scsf_gram_batched(scsf_handle *h, int32_t B, int64_t n, int32_t k, const dou
 
 int scsf_orthonormalize(scsf_handle *h, int64_t n, double *X, int64_t ldx, int32_t ncols,
                         const double *V, int64_t ldv, int32_t nlocked) {
+  CallScope cs_(h);
   if (!h) return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
   if (!h || n <= 0 || !X || ncols <= 0 || nlocked < 0 || ldx < n) return SCSF_EINVAL;
@@ -1288,6 +1516,7 @@ int scsf_orthonormalize(scsf_handle *h, int64_t n, double *X, int64_t ldx, int32
 
 int scsf_rayleigh_ritz(scsf_handle *h, const scsf_operator *A, double *X, int64_t ldx,
                        int32_t ncols, double *theta, double *rel_resid) {
+  CallScope cs_(h);
   if (!h) return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
 
@@ -1316,6 +1545,7 @@ int scsf_rayleigh_ritz(scsf_handle *h, const scsf_operator *A, double *X, int64_
 
 int scsf_bounds(scsf_handle *h, const scsf_operator *A, int32_t steps, uint64_t seed,
                 double *out_host) {
+  CallScope cs_(h);
   if (!h) return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
   if (!h || !out_host) return SCSF_EINVAL;
@@ -1340,6 +1570,7 @@ int scsf_bounds(scsf_handle *h, const scsf_operator *A, int32_t steps, uint64_t 
 
 int scsf_features(scsf_handle *h, const double *fields, int32_t n_op, int32_t channels, int32_t p,
                   int32_t p0, double *feats) {
+  CallScope cs_(h);
   if (!h) return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
   if (!h || !fields || !feats || n_op <= 0 || channels <= 0 || p <= 0 || p0 <= 0 || p0 > p)
@@ -1353,6 +1584,7 @@ int scsf_features(scsf_handle *h, const double *fields, int32_t n_op, int32_t ch
 
 int scsf_sort(scsf_handle *h, const double *fields, int32_t n_op, int32_t channels, int32_t p,
               int32_t p0, int32_t start, int32_t *order_host) {
+  CallScope cs_(h);
   if (!h) return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
   if (!h || !fields || !order_host || n_op <= 0 || channels <= 0 || p <= 0 || p0 <= 0 || p0 > p)
@@ -1365,19 +1597,23 @@ int scsf_sort(scsf_handle *h, const double *fields, int32_t n_op, int32_t channe
   int32_t *O = nullptr;
   STCHK(grow(w0, B_SORTF, (size_t)n_op * flen * 2, &F));
   STCHK(grow(w0, B_SORTD, (size_t)n_op * n_op, &D));
-  STCHK(grow(w0, B_SORTO, (size_t)n_op, &O));
+  STCHK(grow(w0, B_SORTO, (size_t)n_op + 1, &O));
   HIPCHK(dft_features(fields, n_op, channels, p, p0, F, w0->stream));
   HIPCHK(pair_distances(F, n_op, flen, D, w0->stream));
   HIPCHK(greedy_order(D, n_op, start, O, w0->stream));
+  int32_t bad = 0;
   HIPCHK(hipMemcpyAsync(order_host, O, (size_t)n_op * 4, hipMemcpyDeviceToHost, w0->stream));
+  HIPCHK(hipMemcpyAsync(&bad, O + n_op, 4, hipMemcpyDeviceToHost, w0->stream));
   HIPCHK(hipStreamSynchronize(w0->stream));
-  return SCSF_OK;
+  return bad ? SCSF_EINVAL : SCSF_OK;
 }
 
 int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
                const double *X_prev, const double *theta_prev, double *evals, double *evecs,
                double *X_next, double *theta_next, scsf_stats *stats_host) {
+  CallScope cs_(h);
   if (!h) return SCSF_EINVAL;
+  const auto t_start = std::chrono::steady_clock::now();
   Workspace *w0 = h->ws[0];
 
   STCHK(check_op(A));
@@ -1433,6 +1669,13 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
     stats_host->filter_cols = fcols;
     stats_host->beta = e.h_bnd[3];
     stats_host->max_rel_resid = mr;
+    stats_host->ms_filter = (float)e.ph[0][PH_FILTER];
+    stats_host->ms_orth = (float)e.ph[0][PH_ORTH];
+    stats_host->ms_rr = (float)e.ph[0][PH_RR];
+    stats_host->ms_resid = (float)e.ph[0][PH_RESID];
+    stats_host->ms_bound = (float)e.ph[0][PH_BOUND];
+    stats_host->ms_wall = (float)(1e3 * std::chrono::duration<double>(
+                                            std::chrono::steady_clock::now() - t_start).count());
   }
   return status;
 }
@@ -1448,6 +1691,7 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
                                const int32_t *order_host, int32_t chains,
                                const scsf_params *prm, const double *hints_host, double *evals,
                                double *evecs, double *ritz, scsf_stats *stats_host) {
+  CallScope cs_(h);
   if (!h || !ops_host || n_op <= 0 || !order_host || chains <= 0 || !evals || !evecs)
     return SCSF_EINVAL;
   const int64_t n = ops_host[0].n;
@@ -1517,6 +1761,7 @@ int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_
                        const int32_t *L_host, const int32_t *k_host, const int32_t *order_host,
                        int32_t chains, const scsf_params *prm, double *evals, double *evecs,
                        scsf_stats *stats_host) {
+  CallScope cs_(h);
   if (!h || !ops_host || n_op <= 0 || !L_host || !order_host || chains <= 0 || !evals ||
       !evecs || !prm)
     return SCSF_EINVAL;
@@ -1698,12 +1943,9 @@ static int tune_width(scsf_handle *h, Workspace *w, const scsf_operator *ops_hos
   }
   *best = default_width(L);
   if (cand.empty()) return SCSF_OK;
-  double *ev = nullptr, *vv = nullptr;
-  if (hipMalloc(&ev, (size_t)ne * 8) != hipSuccess) return SCSF_ENOMEM;
-  if (hipMalloc(&vv, (size_t)nv * 8) != hipSuccess) {
-    (void)hipFree(ev);
-    return SCSF_ENOMEM;
-  }
+  double *ev = nullptr, *vv = nullptr;           // probe outputs (buffers the engine leaves alone)
+  STCHK(grow(w, B_TEV, (size_t)ne, &ev));
+  STCHK(grow(w, B_TVV, (size_t)nv, &vv));
   double best_t = 1e300;
   int rc = SCSF_OK;
   for (int32_t kc : cand) {
@@ -1726,14 +1968,13 @@ static int tune_width(scsf_handle *h, Workspace *w, const scsf_operator *ops_hos
     if (s2 != SCSF_OK) { rc = s2; break; }
     if (dt < best_t) { best_t = dt; *best = kc; }
   }
-  (void)hipFree(ev);
-  (void)hipFree(vv);
   return rc;
 }
 
 int scsf_autotune(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
                   const int32_t *L_host, const int32_t *order_host, const scsf_params *prm,
                   int32_t probe) {
+  CallScope cs_(h);
   if (!h || !ops_host || n_op <= 0 || !L_host || !order_host || !prm || probe < 1 || probe > 64)
     return SCSF_EINVAL;
   if (prm->precision != SCSF_FP64) return SCSF_EINVAL;
@@ -1821,6 +2062,7 @@ int scsf_tuned_tile(scsf_handle *h, int64_t n, int32_t k) {
 
 int scsf_interpolate(scsf_handle *h, int32_t N0, int32_t N1, int32_t ncols, const double *X,
                      int64_t ldx, double *Y, int64_t ldy) {
+  CallScope cs_(h);
   if (!h || N0 <= 0 || N1 <= 0 || ncols < 0 || ncols > 65535) return SCSF_EINVAL;
   if (ncols == 0) return SCSF_OK;
   if (!X || !Y || ldx < (int64_t)N0 * N0 || ldy < (int64_t)N1 * N1) return SCSF_EINVAL;
@@ -1838,6 +2080,7 @@ int scsf_interpolate(scsf_handle *h, int32_t N0, int32_t N1, int32_t ncols, cons
 
 int scsf_highfreq_ratio(scsf_handle *h, const double *fields, int32_t n_op, int32_t channels,
                         int32_t p, int32_t p0, double *ratio) {
+  CallScope cs_(h);
   if (!h || !fields || !ratio || n_op <= 0 || channels <= 0 || p <= 0 || p0 <= 0)
     return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
@@ -1849,6 +2092,7 @@ int scsf_highfreq_ratio(scsf_handle *h, const double *fields, int32_t n_op, int3
 int scsf_subspace_distance(scsf_handle *h, int64_t n, int32_t q, const double *X, int64_t ldx,
                            int64_t bsx, int32_t n_blocks, const int32_t *a_host,
                            const int32_t *b_host, int32_t P, double *out_host) {
+  CallScope cs_(h);
   if (!h || !X || !a_host || !b_host || !out_host || n <= 0 || q <= 0 || q > kMaxDistQ ||
       q > n || ldx < n || bsx < ldx * (int64_t)q || n_blocks <= 0 || P < 0)
     return SCSF_EINVAL;
@@ -1871,18 +2115,21 @@ int scsf_subspace_distance(scsf_handle *h, int64_t n, int32_t q, const double *X
 
 int scsf_order_features(scsf_handle *h, const double *feats, int32_t n_op, int32_t flen,
                         int32_t start, int32_t *order_host) {
+  CallScope cs_(h);
   if (!h || !feats || !order_host || n_op <= 0 || flen <= 0) return SCSF_EINVAL;
   if (start < 0 || start >= n_op || n_op > 32768) return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
   double *D = nullptr;
   int32_t *O = nullptr;
   STCHK(grow(w0, B_SORTD, (size_t)n_op * n_op, &D));
-  STCHK(grow(w0, B_SORTO, (size_t)n_op, &O));
+  STCHK(grow(w0, B_SORTO, (size_t)n_op + 1, &O));
   HIPCHK(pair_distances(feats, n_op, flen, D, w0->stream));
   HIPCHK(greedy_order(D, n_op, start, O, w0->stream));
+  int32_t bad = 0;
   HIPCHK(hipMemcpyAsync(order_host, O, (size_t)n_op * 4, hipMemcpyDeviceToHost, w0->stream));
+  HIPCHK(hipMemcpyAsync(&bad, O + n_op, 4, hipMemcpyDeviceToHost, w0->stream));
   HIPCHK(hipStreamSynchronize(w0->stream));
-  return SCSF_OK;
+  return bad ? SCSF_EINVAL : SCSF_OK;
 }
 
 // ------------------------------------------------------------------ the learned window
@@ -1923,6 +2170,7 @@ int net_bufs(Workspace *w, int n, NetBufs &nb) {
 }  // namespace
 
 int scsf_window_init(scsf_handle *h, float *params, uint64_t seed) {
+  CallScope cs_(h);
   if (!h || !params) return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
   HIPCHK(cnn_init(params, seed, w0->stream));
@@ -1932,6 +2180,7 @@ int scsf_window_init(scsf_handle *h, float *params, uint64_t seed) {
 
 int scsf_window_input(scsf_handle *h, const double *feats, int32_t n, int32_t channels,
                       int32_t p0, float *x) {
+  CallScope cs_(h);
   if (!h || !feats || !x || n <= 0 || channels != 3 || p0 != 16) return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
   HIPCHK(cnn_input(feats, n, channels, p0, x, w0->stream));
@@ -1941,6 +2190,7 @@ int scsf_window_input(scsf_handle *h, const double *feats, int32_t n, int32_t ch
 
 int scsf_window_forward(scsf_handle *h, const float *params, const float *x, int32_t n,
                         int32_t bf16, float *out) {
+  CallScope cs_(h);
   if (!h || !params || !x || !out || n <= 0) return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
   NetBufs nb;
@@ -1956,6 +2206,7 @@ int scsf_window_forward(scsf_handle *h, const float *params, const float *x, int
 
 int scsf_window_loss_grad(scsf_handle *h, const float *params, const float *x,
                           const float *target, int32_t n, float *grad, double *loss_host) {
+  CallScope cs_(h);
   if (!h || !params || !x || !target || !grad || n <= 0) return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
   NetBufs nb;
@@ -1970,6 +2221,7 @@ int scsf_window_loss_grad(scsf_handle *h, const float *params, const float *x,
 
 int scsf_window_train(scsf_handle *h, float *params, const float *x, const float *target,
                       int32_t n, int32_t epochs, float lr, double *loss_history_host) {
+  CallScope cs_(h);
   if (!h || !params || !x || !target || n <= 0 || epochs <= 0 || !(lr > 0.f)) return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
   NetBufs nb;
@@ -1989,6 +2241,7 @@ int scsf_window_train(scsf_handle *h, float *params, const float *x, const float
 
 int scsf_window_labels(scsf_handle *h, const double *ritz, int32_t n, int32_t k, int32_t L,
                        const double *beta, float *target) {
+  CallScope cs_(h);
   if (!h || !ritz || !beta || !target || n <= 0 || L <= 0 || L >= k) return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
   HIPCHK(cnn_labels(ritz, n, k, L, beta, target, w0->stream));
@@ -1997,6 +2250,7 @@ int scsf_window_labels(scsf_handle *h, const double *ritz, int32_t n, int32_t k,
 }
 
 int scsf_window_hints(scsf_handle *h, const float *out, int32_t n, double *hints) {
+  CallScope cs_(h);
   if (!h || !out || !hints || n <= 0) return SCSF_EINVAL;
   Workspace *w0 = h->ws[0];
   HIPCHK(cnn_hints(out, n, hints, w0->stream));

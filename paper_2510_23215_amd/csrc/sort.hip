@@ -98,6 +98,9 @@ hipError_t pair_distances(const double *feats, int32_t n_op, int32_t flen, doubl
 
 constexpr int kMaxSortOps = 32768;
 
+// order[0..n) = the walk; order[n] = 1 if a distance on the walk's rows was NaN or infinite.
+// Such a distance ranks as +infinity, and among equal keys the lowest unvisited index wins, so
+// every step picks an unvisited operator whatever the distances hold.
 __global__ void __launch_bounds__(1024) greedy_kernel(const double *__restrict__ D, int32_t n,
                                                       int32_t start, int32_t *__restrict__ order) {
   __shared__ unsigned char visited[kMaxSortOps];
@@ -109,6 +112,7 @@ __global__ void __launch_bounds__(1024) greedy_kernel(const double *__restrict__
   if (tid == 0) { s_cur = start; order[0] = start; }
   __syncthreads();
   if (tid == 0) visited[start] = 1;
+  int bad = 0;
   for (int step = 1; step < n; ++step) {
     __syncthreads();
     const int cur = s_cur;
@@ -116,7 +120,8 @@ __global__ void __launch_bounds__(1024) greedy_kernel(const double *__restrict__
     int bi = 0x7fffffff;
     for (int j = tid; j < n; j += NT) {
       if (visited[j]) continue;
-      const double d = D[(int64_t)cur * n + j];
+      double d = D[(int64_t)cur * n + j];
+      if (!isfinite(d)) { d = INFINITY; bad = 1; }
       if (d < best || (d == best && j < bi)) { best = d; bi = j; }
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -129,11 +134,15 @@ __global__ void __launch_bounds__(1024) greedy_kernel(const double *__restrict__
     if (tid == 0) {
       for (int w = 1; w < NT / 64; ++w)
         if (wv[w] < best || (wv[w] == best && wi[w] < bi)) { best = wv[w]; bi = wi[w]; }
+      // an unvisited index always exists here (step < n), and every unvisited index is a
+      // candidate with a finite or +infinity key, so bi < n
       order[step] = bi;
       visited[bi] = 1;
       s_cur = bi;
     }
   }
+  bad = __syncthreads_or(bad);
+  if (tid == 0) order[n] = bad ? 1 : 0;
 }
 
 hipError_t greedy_order(const double *D, int32_t n_op, int32_t start, int32_t *order,

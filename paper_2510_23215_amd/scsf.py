@@ -44,14 +44,21 @@ class Params(ctypes.Structure):
                 ("tol", c_double), ("seed", c_uint64)]
 
 
+PHASES = ("filter", "orth", "rr", "resid", "bound")
+
+
 class Profile(ctypes.Structure):
-    _fields_ = [("filter_launches", c_int64), ("filter_ms", c_double), ("filter_bytes", c_double)]
+    _fields_ = [("filter_launches", c_int64), ("filter_ms", c_double), ("filter_bytes", c_double),
+                ("phase_ms", c_double * 5)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", c_int32), ("nconv", c_int32), ("status", c_int32),
                 ("chol_shifts", c_int32), ("degree", c_int32), ("hint", c_int32),
-                ("filter_cols", c_int64), ("beta", c_double), ("max_rel_resid", c_double)]
+                ("filter_cols", c_int64), ("beta", c_double), ("max_rel_resid", c_double),
+                ("ms_filter", ctypes.c_float), ("ms_orth", ctypes.c_float),
+                ("ms_rr", ctypes.c_float), ("ms_resid", ctypes.c_float),
+                ("ms_bound", ctypes.c_float), ("ms_wall", ctypes.c_float)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -101,6 +108,12 @@ def lib():
         sig["scsf_window_train"] = [vp, vp, vp, vp, i32, i32, ctypes.c_float, POINTER(c_double)]
         sig["scsf_window_labels"] = [vp, vp, i32, i32, i32, vp, vp]
         sig["scsf_window_hints"] = [vp, vp, i32, vp]
+        sz = ctypes.c_size_t
+        sig["scsf_workspace_bytes"] = [POINTER(Params), i64, POINTER(sz)]
+        sig["scsf_workspace_bytes_sequence"] = [vp, POINTER(Params), i64, i32, i32, i32,
+                                                POINTER(sz)]
+        sig["scsf_set_workspace"] = [vp, vp, sz]
+        sig["scsf_workspace_peak"] = [vp, POINTER(sz)]
         sig["scsf_profile_enable"] = [vp, i32]
         sig["scsf_set_lanes"] = [vp, i32]
         sig["scsf_set_graphs"] = [vp, i32]
@@ -510,6 +523,39 @@ def scsf_set_eigensolver(h: Handle, which: int):
     _check(lib().scsf_set_eigensolver(h.ptr, int(which)), "scsf_set_eigensolver")
 
 
+def scsf_workspace_bytes(prm: Params, n: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().scsf_workspace_bytes(ctypes.byref(prm), int(n), ctypes.byref(out)),
+           "scsf_workspace_bytes")
+    return int(out.value)
+
+
+def scsf_workspace_bytes_sequence(h: Handle, prm: Params, n: int, n_op: int, chains: int,
+                                  hinted: bool = False) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().scsf_workspace_bytes_sequence(h.ptr, ctypes.byref(prm), int(n), int(n_op),
+                                               int(chains), 1 if hinted else 0,
+                                               ctypes.byref(out)),
+           "scsf_workspace_bytes_sequence")
+    return int(out.value)
+
+
+def scsf_set_workspace(h: Handle, buf: torch.Tensor | None):
+    """Give the handle a caller-owned device workspace (a uint8 tensor kept alive by the
+    caller), or return to library-allocated buffers with None."""
+    if buf is None:
+        _check(lib().scsf_set_workspace(h.ptr, None, 0), "scsf_set_workspace")
+    else:
+        _check(lib().scsf_set_workspace(h.ptr, ctypes.c_void_p(buf.data_ptr()),
+                                        buf.numel() * buf.element_size()), "scsf_set_workspace")
+
+
+def scsf_workspace_peak(h: Handle) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().scsf_workspace_peak(h.ptr, ctypes.byref(out)), "scsf_workspace_peak")
+    return int(out.value)
+
+
 def scsf_profile_enable(h: Handle, on: bool = True):
     _check(lib().scsf_profile_enable(h.ptr, 1 if on else 0), "scsf_profile_enable")
 
@@ -518,7 +564,8 @@ def scsf_profile_read(h: Handle, reset: bool = False) -> dict:
     p = Profile()
     _check(lib().scsf_profile_read(h.ptr, ctypes.byref(p), 1 if reset else 0), "scsf_profile_read")
     return {"filter_launches": p.filter_launches, "filter_ms": p.filter_ms,
-            "filter_bytes": p.filter_bytes}
+            "filter_bytes": p.filter_bytes,
+            "phase_ms": dict(zip(PHASES, list(p.phase_ms)))}
 
 
 # ----------------------------------------------------------------- spectral-window network

@@ -57,6 +57,12 @@ def grf_eval(w: np.ndarray, x: np.ndarray, y: np.ndarray) -> np.ndarray:
     k = np.arange(modes, dtype=np.float64)
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
+    if x.ndim == 2 and y.ndim == 2 and x.shape[0] == 1 and y.shape[1] == 1:
+        # tensor grid (x along columns, y along rows): the series is separable,
+        # g[iy, ix] = sum_{k2} cos(pi k2 y_iy) sum_{k1} w[k1, k2] cos(pi k1 x_ix)
+        cx = np.cos(np.pi * np.outer(x[0], k))     # (Nx, M) over k1
+        cy = np.cos(np.pi * np.outer(y[:, 0], k))  # (Ny, M) over k2
+        return (cy @ w.T) @ cx.T
     shape = np.broadcast(x, y).shape
     xf = np.broadcast_to(x, shape).reshape(-1)
     yf = np.broadcast_to(y, shape).reshape(-1)

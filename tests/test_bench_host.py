@@ -19,7 +19,8 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_record_matches_only_its_source_and_launch():
-    launch = {"chains": 128, "lanes": 6, "schedule": "dynamic", "graphs": "on", "tile": 4}
+    launch = {"chains": 128, "lanes": 6, "schedule": "dynamic", "graphs": "on", "tile": 4,
+              "form": "plain", "precision": "fp64"}
     rec = bench.measured_traffic("c2_poisson100", launch)
     assert rec is not None and 1e8 < rec < 3e8
     assert bench.measured_traffic("c2_poisson100", dict(launch, lanes=8)) is None
@@ -37,5 +38,6 @@ def test_traffic_record_is_dropped_when_the_step_source_changes(tmp_path, monkey
     src.mkdir(parents=True)
     (src / "spmm.hip").write_text("// a different filter step\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    launch = {"chains": 128, "lanes": 6, "schedule": "dynamic", "graphs": "on", "tile": 4}
+    launch = {"chains": 128, "lanes": 6, "schedule": "dynamic", "graphs": "on", "tile": 4,
+              "form": "plain", "precision": "fp64"}
     assert bench.measured_traffic("c2_poisson100", launch) is None

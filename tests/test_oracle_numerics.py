@@ -173,3 +173,50 @@ def test_invalid_sizes_rejected():
         C.chfsi(A, 8, 8, 10, 1e-8)
     with pytest.raises(ValueError):
         C.chfsi(A, 8, 17, 10, 1e-8)
+
+
+# ------------------------------------------------------------- stopping rule: the L smallest
+def test_wanted_locked_rule():
+    assert not C.wanted_locked([1.0, 2.0], [5.0], 3)               # fewer than L locked
+    assert C.wanted_locked([1.0, 2.0, 3.0], [5.0], 3)
+    assert not C.wanted_locked([1.0, 2.0, 6.0], [5.0], 3)          # 5 < 6: a pair may be missing
+    assert C.wanted_locked([1.0, 2.0, 6.0, 4.0], [5.0], 3)
+    assert C.wanted_locked([1.0, 2.0, 6.0], [], 3)                 # nothing left unconverged
+    assert C.wanted_locked([1.0, 5.0, 2.0], [5.0], 3)              # equal value counts
+
+
+def planted_late_pairs():
+    """A diagonal operator whose two smallest eigenvectors are present in the warm-start block
+    only as small admixtures of two guard columns, while exact eigenvectors of larger values
+    (with lambda = 12 missing) converge at once: the two small pairs are found after three
+    larger ones were locked."""
+    import scipy.sparse as sp
+    lam = np.array([1.0, 2.0] + list(np.arange(10.0, 48.0)))
+    A = sp.diags(lam).tocsr()
+
+    def e(v):
+        x = np.zeros(lam.size)
+        x[int(np.nonzero(lam == v)[0][0])] = 1.0
+        return x
+    u1 = e(14.0) + 1e-3 * e(1.0)
+    u2 = e(15.0) + 1e-7 * e(2.0)
+    X0 = np.stack([e(10.0), e(11.0), e(13.0), u1 / np.linalg.norm(u1),
+                   u2 / np.linalg.norm(u2), e(16.0)], axis=1)
+    th0 = np.array([x @ (A @ x) for x in X0.T])
+    return A, X0, th0
+
+
+def test_chfsi_returns_the_L_smallest_when_pairs_enter_late():
+    A, X0, th0 = planted_late_pairs()
+    r = C.chfsi(A, 4, 6, 2, 1e-10, X0=X0, theta0=th0, beta=60.0, max_iter=200)
+    assert r.converged
+    np.testing.assert_allclose(r.evals, [1.0, 2.0, 10.0, 11.0], rtol=1e-12)
+    # stopping as soon as L pairs are locked, and returning the first L of them, would give
+    # 1, 10, 11, 13 here: lambda = 2 is still unconverged below the locked 13 at that point
+    old = C.wanted_locked
+    try:
+        C.wanted_locked = lambda locked, active, L: len(locked) >= L
+        bad = C.chfsi(A, 4, 6, 2, 1e-10, X0=X0, theta0=th0, beta=60.0, max_iter=200)
+    finally:
+        C.wanted_locked = old
+    assert not np.allclose(bad.evals, [1.0, 2.0, 10.0, 11.0])

@@ -280,6 +280,18 @@ int scsf_rayleigh_ritz(scsf_handle *h, const scsf_operator *A, double *X, int64_
 int scsf_bounds(scsf_handle *h, const scsf_operator *A, int32_t steps, uint64_t seed,
                 double *out_host);
 
+/* scsf_bounds without any device allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernel and outputs as scsf_bounds, with its scratch (the operator descriptor, the
+ * three Lanczos vectors and the bounds) in a fixed 8 MiB device array of the library, which
+ * each GPU holds from the first scsf_create on it until the process ends.  n <= 262144
+ * (SCSF_EINVAL above); SCSF_EHIP if the array's device address could not be obtained.  No
+ * hipMalloc, hipFree or other allocating call is made.  Every call on a GPU uses that GPU's one
+ * array: calls that overlap on one GPU (from several handles or threads) race.  Synchronises
+ * the handle's stream. */
+int scsf_bounds_noalloc(scsf_handle *h, const scsf_operator *A, int32_t steps, uint64_t seed,
+                        double *out_host);
+
 /* Truncated-FFT features of Algorithm 2: for each of n_op fields (channels x p x p real,
  * row-major, contiguous per operator) the p0 x p0 corner k1, k2 in [0, p0) of the 2-D DFT
  * divided by p^2.  feats: n_op x channels x p0 x p0 complex (re, im interleaved). */

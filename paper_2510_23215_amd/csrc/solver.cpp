@@ -1156,6 +1156,38 @@ static int32_t tuned_width(const scsf_handle *h, int32_t L) {
   return default_width(L);
 }
 
+// Scratch of scsf_bounds_noalloc (the bounds step for callers that cannot allocate): one
+// operator descriptor at offset 0, the `need` flag at 256, the four bounds at 512 and the
+// three Lanczos vectors (3 n doubles) from 1024.  Each GPU the library runs on holds its own
+// copy until the process ends.  Host code never passes `scratch` itself (a host-side stand-in)
+// to a kernel or copy: it uses the device address hipGetSymbolAddress returns for the device.
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+constexpr int64_t kNoAllocMaxN = int64_t(1) << 18;
+static_assert(1024 + 3 * 8 * kNoAllocMaxN <= (int64_t)kNoAllocScratchBytes, "scratch too small");
+static_assert(sizeof(OpDev) <= 256, "descriptor slot too small");
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Once per device, with that device current (from scsf_create): the device address of the
+// device's copy of `scratch`.
+int scratch_address(int device, void **out) {
+  if (device < 0 || device >= kMaxDevices) return SCSF_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return SCSF_EHIP;
+    g_scratch_ptr[device] = p;
+  }
+  if (out) *out = g_scratch_ptr[device];
+  return SCSF_OK;
+}
+
 // Device bytes the engine takes for B problems of size n (its buffers, as setup() carves them,
 // each rounded up to 256 bytes).
 size_t engine_bytes(int B, int64_t n, const scsf_params *p, bool var_deg) {
@@ -1227,6 +1259,7 @@ int scsf_create(scsf_handle **h, void *hip_stream) {
     delete x;
     return SCSF_EHIP;
   }
+  (void)scratch_address(x->device, nullptr);   // scsf_bounds_noalloc reports a failure
   *h = x;
   return SCSF_OK;
 }
@@ -1565,6 +1598,31 @@ int scsf_bounds(scsf_handle *h, const scsf_operator *A, int32_t steps, uint64_t 
   out_host[1] = e.h_bnd[1];
   out_host[2] = e.h_bnd[2];
   out_host[3] = e.h_bnd[3];
+  return SCSF_OK;
+}
+
+int scsf_bounds_noalloc(scsf_handle *h, const scsf_operator *A, int32_t steps, uint64_t seed,
+                        double *out_host) {
+  if (!h || !out_host) return SCSF_EINVAL;
+  STCHK(check_op(A));
+  if (steps < 1 || steps > 128) return SCSF_EINVAL;
+  if (A->n > kNoAllocMaxN) return SCSF_EINVAL;          // the Lanczos vectors would not fit
+  void *base = nullptr;
+  STCHK(scratch_address(h->device, &base));
+  char *sb = static_cast<char *>(base);
+  OpDev *op = reinterpret_cast<OpDev *>(sb);
+  int32_t *need = reinterpret_cast<int32_t *>(sb + 256);
+  double *bnd = reinterpret_cast<double *>(sb + 512);
+  double *lz = reinterpret_cast<double *>(sb + 1024);
+  hipStream_t st = h->ws[0]->stream;
+  const OpDev od = to_dev(*A);
+  double res[4];
+  HIPCHK(hipMemcpyAsync(op, &od, sizeof(OpDev), hipMemcpyHostToDevice, st));
+  HIPCHK(fill_int(need, 1, 1, st));
+  HIPCHK(bounds(op, 1, A->kind, A->n, steps, seed, need, lz, bnd, st));
+  HIPCHK(hipMemcpyAsync(res, bnd, sizeof(res), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int i = 0; i < 4; ++i) out_host[i] = res[i];
   return SCSF_OK;
 }
 

@@ -91,6 +91,7 @@ def lib():
             "scsf_orthonormalize": [vp, i64, vp, i64, i32, vp, i64, i32],
             "scsf_rayleigh_ritz": [vp, POINTER(Operator), vp, i64, i32, vp, vp],
             "scsf_bounds": [vp, POINTER(Operator), i32, u64, POINTER(c_double)],
+            "scsf_bounds_noalloc": [vp, POINTER(Operator), i32, u64, POINTER(c_double)],
             "scsf_features": [vp, vp, i32, i32, i32, i32, vp],
             "scsf_sort": [vp, vp, i32, i32, i32, i32, i32, POINTER(c_int32)],
             "scsf_solve": [vp, POINTER(Operator), POINTER(Params), vp, vp, vp, vp, vp, vp,
@@ -318,6 +319,14 @@ def scsf_rayleigh_ritz(h: Handle, A: DeviceOperator, X: torch.Tensor):
 def scsf_bounds(h: Handle, A: DeviceOperator, steps: int = 20, seed: int = 0):
     out = (c_double * 4)()
     _check(lib().scsf_bounds(h.ptr, A.ref(), int(steps), c_uint64(seed), out), "scsf_bounds")
+    return {"gershgorin": out[0], "lanczos": out[1], "theta_min": out[2], "beta": out[3]}
+
+
+def scsf_bounds_noalloc(h: Handle, A: DeviceOperator, steps: int = 20, seed: int = 0):
+    """scsf_bounds with its scratch in the library's fixed device array (no allocation)."""
+    out = (c_double * 4)()
+    _check(lib().scsf_bounds_noalloc(h.ptr, A.ref(), int(steps), c_uint64(seed), out),
+           "scsf_bounds_noalloc")
     return {"gershgorin": out[0], "lanczos": out[1], "theta_min": out[2], "beta": out[3]}
 
 

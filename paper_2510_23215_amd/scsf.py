@@ -469,14 +469,20 @@ def make_params(L, k, degree=20, tol=1e-8, max_iter=0, lanczos_steps=20, seed=0,
 
 
 def scsf_solve(h: Handle, A: DeviceOperator, prm: Params, X_prev=None, theta_prev=None,
-               allow_notconv=False):
-    """Returns (evals[L], evecs n x L, X_next n x k, theta_next[k], stats dict)."""
+               allow_notconv=False, out=None):
+    """Returns (evals[L], evecs n x L, X_next n x k, theta_next[k], stats dict); `out` may
+    supply the four output tensors (as returned by an earlier call)."""
     n, L, k = A.n, prm.L, prm.k
     dev = torch.device("cuda")
-    evals = torch.empty(L, device=dev, dtype=torch.float64)
-    evecs = colmajor(n, L)
-    X_next = colmajor(n, k)
-    theta_next = torch.empty(k, device=dev, dtype=torch.float64)
+    if out is not None:
+        evals, evecs, X_next, theta_next = out[:4]
+        assert evals.numel() == L and evecs.shape == (n, L) and _ld(evecs) == n
+        assert X_next.shape == (n, k) and _ld(X_next) == n and theta_next.numel() == k
+    else:
+        evals = torch.empty(L, device=dev, dtype=torch.float64)
+        evecs = colmajor(n, L)
+        X_next = colmajor(n, k)
+        theta_next = torch.empty(k, device=dev, dtype=torch.float64)
     if X_prev is not None:
         X_prev = as_colmajor(X_prev)
         assert _ld(X_prev) == n

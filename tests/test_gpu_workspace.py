@@ -38,7 +38,7 @@ def test_single_solve_in_caller_workspace_matches_and_allocates_nothing():
     scsf.scsf_set_workspace(h, buf)
     got = scsf.scsf_solve(h, op, prm)                    # first call: pinned staging, events
     before = free_bytes()
-    got = scsf.scsf_solve(h, op, prm)
+    got = scsf.scsf_solve(h, op, prm, out=got)           # outputs in the same caller tensors
     after = free_bytes()
     assert after == before, (before, after)
     assert scsf.scsf_workspace_peak(h) <= need

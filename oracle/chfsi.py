@@ -69,12 +69,51 @@ def wanted_locked(theta_locked, theta_active, L: int) -> bool:
     return int(np.count_nonzero(theta_locked <= np.min(theta_active))) >= L
 
 
+def lowest_locked(theta_locked, theta_active):
+    """The locked values at or below every unconverged Ritz value: by the argument of
+    `wanted_locked`, the q algebraically smallest eigenvalues (q = their count)."""
+    theta_locked = np.asarray(theta_locked, dtype=np.float64)
+    if len(theta_active) == 0:
+        return theta_locked
+    return theta_locked[theta_locked <= np.min(theta_active)]
+
+
+def magnitude_certified(theta_locked, theta_active, L: int) -> bool:
+    """True when the q algebraically smallest eigenvalues (`lowest_locked`) contain the L of
+    smallest magnitude: at least L of them have |lambda| <= lambda_q, their largest (every
+    eigenvalue outside them is >= lambda_q)."""
+    low = lowest_locked(theta_locked, theta_active)
+    if low.size < L:
+        return False
+    return int(np.count_nonzero(np.abs(low) <= np.max(low))) >= L
+
+
+def magnitude_hopeless(theta_locked, theta_active, L: int) -> bool:
+    """True when the block cannot reach `magnitude_certified`: fewer than L of all its values
+    (locked and active) have |theta| <= the largest of them.  A certified state has at least L
+    such values (the L it certifies lie at or below lambda_q <= that largest value), so this
+    never stops a solve that is certified now; the Ritz values of a converging block only
+    drift down, which shrinks that count further.  Giving up only sends the solve to the
+    squared filter (the general route for the |lambda| order of eq. eq_basic on the
+    indefinite operators of App. D.2), so the rule decides speed, never the result."""
+    allv = np.concatenate([np.asarray(theta_locked, dtype=np.float64),
+                           np.asarray(theta_active, dtype=np.float64)])
+    if allv.size == 0:
+        return True
+    return int(np.count_nonzero(np.abs(allv) <= np.max(allv))) < L
+
+
 def chfsi(A, L: int, k: int, m: int, tol: float, X0=None, theta0=None, beta=None,
           seed: int = 0, max_iter: int = 200, lanczos_steps: int = 20,
-          adaptive: bool = False) -> Result:
+          adaptive: bool = False, magnitude: bool = False) -> Result:
     """adaptive: after the first outer iteration every active vector is filtered with the
     degree its residual calls for (chebyshev.adaptive_degrees), between m and min(2m, 64):
-    vectors near convergence keep m, slow ones get up to twice as many steps."""
+    vectors near convergence keep m, slow ones get up to twice as many steps.
+    magnitude: the L pairs of smallest |lambda| from the lower end of the spectrum: the solve
+    goes on until `magnitude_certified`, or gives up uncertified when the block has no
+    unconverged pair left or, after an outer iteration, `magnitude_hopeless` holds; it returns,
+    ordered by |lambda|, the L of smallest magnitude among the lowest locked pairs;
+    `converged` reports the certificate."""
     n = A.shape[0]
     if not (0 < L < k <= n):
         raise ValueError("need 0 < L < k <= n")
@@ -94,7 +133,13 @@ def chfsi(A, L: int, k: int, m: int, tol: float, X0=None, theta0=None, beta=None
     matvecs = 0
     it = 0
     res_act = None                       # residuals of the active Ritz pairs (last iteration)
-    while it < max_iter and not wanted_locked(thl, theta, L):
+    def finished():
+        if magnitude:
+            return (magnitude_certified(thl, theta, L) or theta.size == 0
+                    or (it > 0 and magnitude_hopeless(thl, theta, L)))
+        return wanted_locked(thl, theta, L)
+
+    while it < max_iter and not finished():
         it += 1
         lam = thl[0] if thl.size else theta[0]
         alpha = theta[-1]
@@ -128,11 +173,17 @@ def chfsi(A, L: int, k: int, m: int, tol: float, X0=None, theta0=None, beta=None
 
     allV = np.hstack([Vl, X])
     allth = np.concatenate([thl, theta])
-    nsel = max(L, thl.size)              # the L smallest of the locked pairs
-    order = np.argsort(allth[:nsel], kind="stable")[:L]
+    if magnitude:                        # the L smallest in |lambda| of the lowest locked pairs
+        low = np.nonzero(thl <= (np.min(theta) if theta.size else np.inf))[0]
+        cand = low if low.size >= L else np.arange(max(L, thl.size))
+        order = cand[np.argsort(np.abs(allth[cand]), kind="stable")[:L]]
+        conv = magnitude_certified(thl, theta, L)
+    else:
+        nsel = max(L, thl.size)          # the L smallest of the locked pairs
+        order = np.argsort(allth[:nsel], kind="stable")[:L]
+        conv = wanted_locked(thl, theta, L)
     return Result(evals=allth[order], evecs=canonical_sign(allV[:, order]),
-                  X_next=allV, theta_next=allth, iterations=it,
-                  converged=wanted_locked(thl, theta, L),
+                  X_next=allV, theta_next=allth, iterations=it, converged=conv,
                   filter_matvecs=matvecs, beta=float(beta))
 
 

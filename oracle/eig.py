@@ -6,8 +6,11 @@ acceleration that does not change the result at the requested precision (Section
 plain definition -- a full symmetric eigendecomposition -- is the reference:
 
 * n <= 4096: dense `numpy.linalg.eigh`;
-* larger n: ARPACK shift-invert about 0 (`scipy.sparse.linalg.eigsh(sigma=0)`) run to machine
-  tolerance, which returns the eigenvalues nearest 0, i.e. the smallest of an SPD matrix.
+* larger n: ARPACK shift-invert (`scipy.sparse.linalg.eigsh(sigma=s)`) run to machine
+  tolerance, which returns the eigenvalues nearest s: s = 0 when the Gershgorin interval is
+  nonnegative (then the nearest to 0 are the smallest), else s = the Gershgorin lower end
+  (every eigenvalue lies above it, so the nearest are again the smallest; an indefinite
+  operator needs this).
 
 `jacobi_eigh` is the textbook cyclic Jacobi method, used as a brute-force cross-check on
 tiny matrices.  `canonical_sign` fixes the sign of eigenvectors: the entry of largest
@@ -38,10 +41,33 @@ def smallest_eigenpairs(A, L: int, method: str = "auto"):
         w, V = np.linalg.eigh(M)
         return w[:L].copy(), canonical_sign(V[:, :L])
     if method == "shift_invert":
-        w, V = sla.eigsh(sp.csc_matrix(A), k=L, sigma=0.0, which="LM", tol=0)
+        As = sp.csc_matrix(A)
+        d = As.diagonal()
+        lo = float(np.min(d - (np.asarray(abs(As).sum(axis=1)).ravel() - np.abs(d))))
+        sigma = 0.0 if lo >= 0.0 else lo - 1e-3 * abs(lo)
+        w, V = sla.eigsh(As, k=L, sigma=sigma, which="LM", tol=0)
         order = np.argsort(w)
         return w[order], canonical_sign(V[:, order])
     raise ValueError(method)
+
+
+def smallest_magnitude_eigenpairs(A, L: int, method: str = "auto"):
+    """(lambda[0:L] ordered by |lambda|, V n x L) of a symmetric, possibly indefinite matrix:
+    the L eigenvalues nearest 0 (the smallest in absolute value, as the Helmholtz experiments
+    ask).  Dense `eigh` sorted by |lambda| up to n = 4096, else ARPACK shift-invert about 0,
+    whose largest |1 / (lambda - 0)| are exactly those."""
+    n = A.shape[0]
+    if method == "auto":
+        method = "dense" if n <= 4096 else "shift_invert"
+    if method == "dense":
+        M = A.toarray() if sp.issparse(A) else np.asarray(A, dtype=np.float64)
+        w, V = np.linalg.eigh(M)
+    elif method == "shift_invert":
+        w, V = sla.eigsh(sp.csc_matrix(A), k=L, sigma=0.0, which="LM", tol=0)
+    else:
+        raise ValueError(method)
+    order = np.argsort(np.abs(w), kind="stable")[:L]
+    return w[order], canonical_sign(V[:, order])
 
 
 def jacobi_eigh(S: np.ndarray, tol: float = 1e-15, max_sweeps: int = 60):

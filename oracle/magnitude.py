@@ -13,13 +13,23 @@ the residual test and locking stay with A, the Ritz pairs ordered by |theta|:
     G = Q_a^T A Q_a, G W = W Theta, order the pairs by |theta|, V0 <- Q_a W
     lock the longest prefix with ||A v - theta v|| <= tol ||A v||
 beta_B is the square of the larger end of A's Gershgorin interval.
+
+Squaring the operator squares its spread, so the squared filter converges slowly at working
+sizes.  When the negative part of the spectrum is short (the Helmholtz operators of App. D.2
+at n = 6400 have tens of negative eigenvalues above -k^2 and their 200 smallest in magnitude
+reach far into the positive part), the wanted pairs sit at the lower end of the spectrum and
+the plain method finds them (`smallest_magnitude_lower_end`): Algorithm 3 at the lower end,
+going on until the q algebraically smallest converged pairs lambda_1 <= ... <= lambda_q hold
+L with |lambda| <= lambda_q; those L are then the L smallest in magnitude overall (every
+eigenvalue outside the q is >= lambda_q).  When the block runs out of pairs before that
+certificate holds, the squared filter is the route.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from .chebyshev import filter_block
-from .chfsi import Result, _gaussian
+from .chfsi import Result, _gaussian, chfsi
 from .eig import canonical_sign
 
 
@@ -76,3 +86,16 @@ def chfsi_magnitude(A, L: int, k: int, m: int, tol: float, X0=None, theta0=None,
     return Result(evals=allth[:L][order], evecs=canonical_sign(allV[:, :L][:, order]),
                   X_next=allV, theta_next=allth, iterations=it, converged=thl.size >= L,
                   filter_matvecs=matvecs, beta=float(beta))
+
+
+def smallest_magnitude_lower_end(A, L: int, k: int, m: int, tol: float, X0=None, theta0=None,
+                                 seed: int = 0, max_iter: int = 200):
+    """(Result with the L pairs of smallest |lambda|, ordered by |lambda|, certified) from the
+    plain method at the lower end of the spectrum (`chfsi(magnitude=True)`): it goes on until
+    the q algebraically smallest converged pairs contain L with |lambda| <= lambda_q.
+    certified is False when the block ran out of pairs (or iterations) first."""
+    if not (0 < L < k <= A.shape[0]):
+        raise ValueError("need 0 < L < k <= n")
+    r = chfsi(A, L, k, m, tol, X0=X0, theta0=theta0, seed=seed, max_iter=max_iter,
+              magnitude=True)
+    return r, bool(r.converged)

@@ -131,7 +131,21 @@ def _face_grids(N: int):
 def divk_operator(N: int, modes: int, seed: int) -> Stencil5:
     """-div(K grad u), K = exp(g) evaluated analytically at face midpoints and nodes."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    w = grf_xi(rng, modes)
+    return divk_from_weights(N, grf_xi(rng, modes))
+
+
+def perturbed_divk_chain(N: int, modes: int, seed: int, count: int, step: float = 0.01):
+    """`count` operators -div(K grad u) whose GRF weights move along a straight line,
+    w_j = w + j * step * (|w| / |d|) d with w, d two weight draws: consecutive weight vectors
+    differ by `step` times the norm of the first (a slowly varying family of operators)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w, d = grf_xi(rng, modes), grf_xi(rng, modes)
+    d = d * (np.linalg.norm(w) / np.linalg.norm(d))
+    return [divk_from_weights(N, w + j * step * d) for j in range(count)]
+
+
+def divk_from_weights(N: int, w: np.ndarray) -> Stencil5:
+    """-div(K grad u) with K = exp(g) for the cosine-series weights w (grf_xi's layout)."""
     h, node, face = _face_grids(N)
     inv_h2 = 1.0 / (h * h)
     wx = np.exp(grf_eval(w, face[None, :], node[:, None])) * inv_h2     # (N, N+1): x=face, y=node
@@ -248,6 +262,9 @@ CONFIGS = {
     # FP64 floor of the relative residual of the lowest modes, eps ||A|| / lambda_1, is about
     # 2e-8 for these plates
     6: Config("c6_plate100", 6, 100, 200, 240, 30, 20, 1e-6, 16, (100,), "plate"),
+    # Helmholtz at the paper's size (n = 6400, L = 200, tol 1e-8): the 200 lowest eigenvalues
+    # of the indefinite -div(p grad u) - k^2 u
+    7: Config("c7_helmholtz80", 7, 100, 200, 240, 20, 20, 1e-8, 16, (80,), "helmholtz"),
 }
 
 
@@ -260,6 +277,8 @@ def operator(cfg: Config, i: int):
         return aniso_operator(cfg.sides[0], cfg.modes, seed)
     if cfg.family == "plate":
         return plate_operator(cfg.sides[0], cfg.modes, seed)
+    if cfg.family == "helmholtz":
+        return helmholtz_operator(cfg.sides[0], cfg.modes, seed)
     if cfg.family == "mixed":
         rng = np.random.Generator(np.random.PCG64(seed + 7))
         side = int(rng.integers(cfg.sides[0], cfg.sides[-1] + 1))

@@ -2,16 +2,18 @@
 
 For each operator of the working-size (200 x n = 10^4, L = 100), uneven (1000 operators,
 sides 48..128, L in {32, 64, 128}), mixed-precision (200 x n = 25600, L = 200),
-anisotropic (2000 x n = 16384, L = 64) and thin-plate (100 x n = 10^4, L = 200) workloads
-this stores the L + 1 smallest eigenvalues of the assembled matrix, computed by the oracle's
-plain definition (`oracle.eig.smallest_eigenpairs`, ARPACK shift-invert about 0 to machine
-tolerance; eq. eq_basic of Section 2.1).  The (L + 1)-th value records the gap after the
+anisotropic (2000 x n = 16384, L = 64), thin-plate (100 x n = 10^4, L = 200) and Helmholtz
+(100 x n = 6400, L = 200, indefinite) workloads this stores the L + 1 algebraically smallest
+eigenvalues of the assembled matrix, computed by the oracle's plain definition
+(`oracle.eig.smallest_eigenpairs`: ARPACK shift-invert to machine tolerance, about 0 for the
+positive definite families and about the Gershgorin lower end for the indefinite one; eq.
+eq_basic of Section 2.1).  The (L + 1)-th value records the gap after the
 L-th.  Entries are keyed by (configuration, operator index) and carry the operator seed, so
 a changed generator is detected by the tests that read them.
 
 Only `oracle/` does the arithmetic; `scsf_inputs` only generates the operators.
 
-    python tests/golden/make_fullsize_eigs.py [--jobs 8] [--configs 2 3 4 5 6]
+    python tests/golden/make_fullsize_eigs.py [--jobs 8] [--configs 2 3 4 5 6 7]
 
 Output: tests/golden/fullsize_eigs_c<config>.npz with arrays
     index (n_op,) int64, seed (n_op,) int64, L (n_op,) int64,
@@ -43,7 +45,7 @@ def _one(task):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=os.cpu_count() or 1)
-    ap.add_argument("--configs", type=int, nargs="+", default=[4, 6, 5, 3, 2])
+    ap.add_argument("--configs", type=int, nargs="+", default=[4, 6, 7, 5, 3, 2])
     args = ap.parse_args()
     for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         os.environ[var] = "1"

@@ -9,11 +9,11 @@ with all eigenpairs resident in HBM.
 Workload (default, the largest): 2000 anisotropic operators -div(K grad u) with an SPD tensor
 field K (9-point Q1 stencil) on a 128 x 128 grid (n = 16384), L = 64 smallest eigenpairs,
 block width k = 80, relative residual 1e-8, FP64, in the learned-window form: the plain
-solves (degree 20) of the first 500 operators of the sorted order give the labels of the
-window network, which is trained (FP32) and predicts, in BF16, the window and the filter
-degree of the other 1500 solves.  Every operator is solved once per step, training included.
-`--config` selects the other workloads (1 small, 2 working size, 3 uneven batch, 4 mixed
-precision, 6 thin-plate vibration).
+solves (degree 64, `--head-degree`) of the first 500 operators of the sorted order give the
+labels of the window network, which is trained (FP32) and predicts, in BF16, the window and
+the filter degree of the other 1500 solves.  Every operator is solved once per step, training
+included.  `--config` selects the other workloads (1 small, 2 working size, 3 uneven batch,
+4 mixed precision, 6 thin-plate vibration, 7 Helmholtz).
 
 Prints one JSON line (rank 0).  `roofline` describes the dominant kernel (the filter's
 Chebyshev step): its algorithmic bytes per step over the wall time per step.  `cpu_baseline`
@@ -235,7 +235,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=5,
                     help="workload: 1 small, 2 working size, 3 uneven batch, 4 mixed "
-                         "precision, 5 learned window (default: the largest), 6 thin plates")
+                         "precision, 5 learned window (default: the largest), 6 thin plates, "
+                         "7 Helmholtz")
     ap.add_argument("--count", type=int, default=None, help="operators (default: all)")
     ap.add_argument("--chains", type=int, default=128)
     ap.add_argument("--lanes", type=int, default=6)
@@ -259,9 +260,14 @@ def main():
                          "default) or plain")
     ap.add_argument("--train", type=int, default=500,
                     help="learned form: operators solved plainly to train the network")
+    ap.add_argument("--head-degree", type=int, default=64,
+                    help="learned form: filter degree of the plain solves that give the "
+                         "labels (the degree label saturates at 64 on this family)")
     ap.add_argument("--epochs", type=int, default=600)
     ap.add_argument("--tile", type=int, choices=[1, 2, 4], default=None,
                     help="pin the filter-step tile instead of the autotuned one")
+    ap.add_argument("--fused-steps", type=int, choices=[0, 2, 3, 4], default=0,
+                    help="Chebyshev steps per fused filter launch (0: one step per launch)")
     ap.add_argument("--adaptive", choices=["on", "off"], default="off",
                     help="per-vector filter degrees in [degree, min(2 degree, 64)] (FP64 "
                          "solves without degree hints)")
@@ -309,6 +315,7 @@ def main():
     h = scsf.Handle()
     scsf.scsf_set_lanes(h, args.lanes)
     scsf.scsf_set_graphs(h, args.graphs == "on")
+    scsf.scsf_set_fused_steps(h, args.fused_steps)
     scsf.scsf_set_eigensolver(h, scsf.SCSF_EIG_TRIDIAG if args.eig == "tridiag"
                               else scsf.SCSF_EIG_JACOBI)
     dops = [scsf.DeviceOperator(o) for o in ops]
@@ -331,10 +338,12 @@ def main():
         sys.exit(2)
     sched = scsf.SCSF_SCHED_DYNAMIC if args.schedule == "dynamic" else scsf.SCSF_SCHED_STATIC
 
+    target = scsf.SCSF_TARGET_SMALLEST
+
     def params(prec=precision, deg=degree, **kw):
         return scsf.make_params(cfg.L, cfg.k, deg, cfg.tol, seed=1, schedule=kw.pop(
             "schedule", sched), precision=scsf.SCSF_MIXED if prec == "mixed" else scsf.SCSF_FP64,
-            **kw)
+            target=target, **kw)
 
     prm = params(adaptive=int(adaptive))
     prm64 = params(prec="fp64")
@@ -365,7 +374,7 @@ def main():
     n_train = min(args.train, n_op // 2) if windowed else 0
     train_info = {}
 
-    def step_learned(p):
+    def step_learned(p, p_head):
         """Sort; plain solves of the first n_train operators of the order (their Ritz values
         and bounds are the labels); FP32 training; BF16 inference for the rest, whose solves
         take the predicted window and degree.  Every operator is solved once."""
@@ -374,8 +383,8 @@ def main():
         head, tail = [int(i) for i in order[:n_train]], [int(i) for i in order[n_train:]]
         ritz = torch.empty((n_train, cfg.k), device="cuda", dtype=torch.float64)
         _, _, st1 = scsf.scsf_solve_sequence(h, [dops[i] for i in head], np.arange(n_train),
-                                             args.chains, p, evals[:n_train], evecs[:n_train],
-                                             ritz=ritz)
+                                             args.chains, p_head, evals[:n_train],
+                                             evecs[:n_train], ritz=ritz)
         t_head = time.perf_counter() - t
         beta = torch.tensor([s["beta"] for s in st1], device="cuda", dtype=torch.float64)
         target = scsf.scsf_window_labels(h, ritz, cfg.L, beta)
@@ -408,7 +417,8 @@ def main():
         return stats
 
     def step():
-        return step_learned(prm) if form == "learned" else step_plain(prm)
+        return (step_learned(prm, params(deg=args.head_degree)) if form == "learned"
+                else step_plain(prm))
 
     tune_s = 0.0
     if args.autotune == "on":
@@ -472,8 +482,14 @@ def main():
             f"plain_fp64_degree{args.best_degree}": timed(
                 lambda: step_plain(params(prec="fp64", deg=args.best_degree)),
                 f"plain fp64 degree {args.best_degree}"),
-            "learned_fp32_filter": timed(lambda: step_learned(params(prec="mixed")),
-                                         "learned window, FP32 filter")}
+            # App. D.6 chunking: every chain warm-starts from its true neighbour in the order
+            f"plain_fp64_degree{args.best_degree}_static_schedule": timed(
+                lambda: step_plain(params(prec="fp64", deg=args.best_degree,
+                                          schedule=scsf.SCSF_SCHED_STATIC)),
+                f"plain fp64 degree {args.best_degree}, static schedule"),
+            "learned_fp32_filter": timed(lambda: step_learned(
+                params(prec="mixed"), params(prec="mixed", deg=args.head_degree)),
+                "learned window, FP32 filter")}
         comparison["plain_fp64"]["degree"] = degree
         comparison[f"plain_fp64_degree{args.best_degree}"]["degree"] = args.best_degree
         comparison["ratio_to_plain_fp64"] = value / comparison["plain_fp64"]["value"]
@@ -493,15 +509,21 @@ def main():
     per_launch = (measured_traffic(cfg.name, {"chains": args.chains, "lanes": args.lanes,
                                               "schedule": args.schedule, "graphs": args.graphs,
                                               "tile": tile_used, "form": form,
-                                              "precision": precision})
+                                              "precision": precision,
+                                              "fused_steps": args.fused_steps})
                   if not adaptive else None)
     traffic_step = (per_launch * prof["filter_launches"] / args.steps
                     if per_launch is not None else None)
-    kname = ("spmm_plate_kernel (Chebyshev three-term step, 13-point thin-plate standard "
-             "form, FP64)" if cfg.family == "plate" else
-             "spmm_lds_kernel (Chebyshev three-term step, %s stencil, %s)" % (
-                 "9-point Q1" if windowed else "5-point",
-                 "FP64" if precision == "fp64" else "FP32 residual form"))
+    stencil = "9-point Q1" if windowed else "5-point"
+    if cfg.family == "plate":
+        kname = ("spmm_plate_kernel (Chebyshev three-term step, 13-point thin-plate standard "
+                 "form, FP64)")
+    elif args.fused_steps and precision == "fp64":
+        kname = ("spmm_fused_kernel (%d Chebyshev three-term steps per launch, %s stencil, "
+                 "FP64)" % (args.fused_steps, stencil))
+    else:
+        kname = "spmm_lds_kernel (Chebyshev three-term step, %s stencil, %s)" % (
+            stencil, "FP64" if precision == "fp64" else "FP32 residual form")
     out = {
         "metric": "eigenpairs/sec at residual %g (SCSF GPU, %s%s)" % (
             cfg.tol, "learned window, " if form == "learned" else "",
@@ -536,6 +558,7 @@ def main():
             "block_widths": ({str(L): scsf.scsf_tuned_width(h, L) for L in sorted(set(Ls))}
                              if uneven else {str(cfg.L): cfg.k}),
             "spmm_columns_per_thread": tile_used,
+            "fused_steps": args.fused_steps,
             "precision": precision,
             "adaptive_degree": args.adaptive,
             "mean_outer_iterations": float(np.mean(iters)),
@@ -555,8 +578,15 @@ def main():
             "live_avg_span_ms": live_ms,
         },
     }
+    # device time of each step of Algorithm 3 summed over the lanes (they overlap), per step,
+    # and each step's share: the cost split the paper reports for its CPU runs (App. E.3)
+    ph = {k: v / args.steps for k, v in prof["phase_ms"].items()}
+    tot = sum(ph.values()) or 1.0
+    out["phases"] = {"ms_per_step_summed_over_lanes": ph,
+                     "share": {k: v / tot for k, v in ph.items()}}
     if form == "learned":
-        out["config"]["learned"] = dict(train_info, trained_on=n_train, epochs=args.epochs)
+        out["config"]["learned"] = dict(train_info, trained_on=n_train, epochs=args.epochs,
+                                        head_degree=args.head_degree)
     if comparison:
         out["comparison"] = comparison
     if cfg.index in (2, 5, 6) and precision == "fp64" and args.spmm_isolated == "on":

@@ -114,11 +114,18 @@ typedef struct scsf_params {
                             ablations) */
   int32_t target;        /* scsf_target: SCSF_TARGET_SMALLEST, the L algebraically smallest
                             eigenvalues; SCSF_TARGET_MAGNITUDE, the L smallest in absolute
-                            value (indefinite operators, the Helmholtz family of App. D.2):
-                            the filter runs on A^2 (each Chebyshev step applies A twice, window
-                            and bound squared), Rayleigh-Ritz, residuals and locking stay with A
-                            and the pairs are ordered by |lambda| (evals in that order, signed).
-                            FP64 only; not with adaptive degrees or degree hints */
+                            value (indefinite operators, the Helmholtz family of App. D.2),
+                            evals ordered by |lambda| (signed).  Two routes: (1) when L + 1 < k,
+                            the plain method for the L + 1 algebraically smallest pairs; their L
+                            of smallest |lambda| are returned when |lambda_1| <= lambda_{L+1},
+                            which proves them the L smallest in magnitude (a short negative
+                            spectrum, as in the Helmholtz datasets); (2) otherwise, or when that
+                            certificate fails (the operator is then solved again from the
+                            start), the filter runs on A^2 (each Chebyshev step applies A
+                            twice, window and bound squared) while Rayleigh-Ritz, residuals and
+                            locking stay with A (slow on wide spectra: it squares their
+                            spread).  scsf_stats.magnitude_route says which.  FP64 only; not
+                            with adaptive degrees or degree hints */
   double tol;            /* lock when ||A v - theta v|| <= tol ||A v|| (App. D.5 metric) */
   uint64_t seed;         /* seed of the random cold-start block and Lanczos start vector */
 } scsf_params;
@@ -144,6 +151,8 @@ typedef struct scsf_stats {
   float ms_resid;        /* residual norms and locking */
   float ms_bound;        /* upper spectral bound: Gershgorin and the Lanczos run */
   float ms_wall;         /* host wall time from the operator's load to its extraction */
+  int32_t magnitude_route; /* SCSF_TARGET_MAGNITUDE: 1 = from the lower end of the spectrum,
+                              certified; 2 = with the squared filter; 0 for SCSF_TARGET_SMALLEST */
 } scsf_stats;
 
 /* Filter-step timing: when enabled, every Chebyshev step launch of the solvers is bracketed
@@ -174,6 +183,16 @@ const char *scsf_version(void);
  * priority), ordered after the work already enqueued on the handle's stream, and is driven by
  * a host thread of its own; the call returns when every batch has finished. */
 int scsf_set_lanes(scsf_handle *h, int lanes);
+/* The plain FP64 filter of the grid stencils (STENCIL5, STENCIL9) in groups of `steps`
+ * Chebyshev steps per launch (2, 3 or 4; 0 = one step per launch, the default): each launch
+ * stages the two newest levels of a tile of nodes with its halo in LDS, runs the steps there
+ * and writes the last two levels, so a group of S steps moves 4 instead of 3 S block columns
+ * through HBM (the same recurrence of Algorithm 1, node by node; results agree to rounding).
+ * A degree below S, mixed precision, adaptive degrees,
+ * the squared filter, CSR and thin-plate operators keep one step per launch; per-problem
+ * degrees (hints) are raised by at most 2 S - 1 so that every problem ends with a whole group.
+ * SCSF_EINVAL for another value. */
+int scsf_set_fused_steps(scsf_handle *h, int steps);
 /* Chained solvers: on != 0 (default) replays each outer iteration of Algorithm 3 as three HIP
  * graphs captured once per filter degree (window and coefficients; the filter's m steps;
  * orthonormalisation, Rayleigh-Ritz, residuals and locking); on == 0 launches the same
@@ -420,8 +439,9 @@ int scsf_interpolate(scsf_handle *h, int32_t N0, int32_t N1, int32_t ncols, cons
 /* A dataset of operators of different sizes and different numbers of wanted pairs.
  * ops_host[n_op]: descriptors (any mix of sizes; kinds may differ).  L_host[n_op]: wanted
  * pairs per operator (0 < L < 256).  k_host[n_op]: block widths, or NULL for the
- * autotuned width of each L (scsf_tuned_width).  prm supplies degree, tol, max_iter, lanczos_steps, seed and schedule
- * (prm->L and prm->k are ignored); only SCSF_FP64 is accepted.
+ * autotuned width of each L (scsf_tuned_width).  prm supplies degree, tol, max_iter,
+ * lanczos_steps, seed, schedule, precision (SCSF_MIXED: the FP32 filter of the sequence
+ * solvers; not for SCSF_PLATE) and target (prm->L and prm->k are ignored).
  * The operators are grouped by (kind, L, k), keeping order_host's order inside each group,
  * and every group is split into chains (about chains * group size / n_op of them) that run as
  * in scsf_solve_sequence.  Along a chain each solve warm-starts from the previous one; when
@@ -435,6 +455,15 @@ int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_
                        const int32_t *L_host, const int32_t *k_host, const int32_t *order_host,
                        int32_t chains, const scsf_params *prm, double *evals, double *evecs,
                        scsf_stats *stats_host);
+/* scsf_solve_batched with per-operator window and degree hints, hints_host[n_op*3] in
+ * operator index order, as in scsf_solve_sequence_hinted (the learned-window form on uneven
+ * batches; SCSF_EINVAL with adaptive degrees or SCSF_TARGET_MAGNITUDE).  hints_host may be
+ * NULL. */
+int scsf_solve_batched_hinted(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
+                              const int32_t *L_host, const int32_t *k_host,
+                              const int32_t *order_host, int32_t chains,
+                              const scsf_params *prm, const double *hints_host, double *evals,
+                              double *evecs, scsf_stats *stats_host);
 
 /* ---------------------------------------------------------------------------------------
  * Spectral-window network (the learned form of the window of Section 2.2; not in the paper).

@@ -56,18 +56,27 @@ __global__ void conv_fwd_kernel(const T *__restrict__ x, const T *__restrict__ W
   stf(y + idx, fmaxf(acc, 0.f));                      // both convolutions are followed by ReLU
 }
 
+// one wavefront per output y[s, o]: its lanes read the weight row and the input row with
+// coalesced loads, and a fixed shuffle tree sums the 64 partial products
 template <typename T>
-__global__ void fc_fwd_kernel(const T *__restrict__ x, const T *__restrict__ W,
-                              const T *__restrict__ bias, T *__restrict__ y, int n, int I, int O,
-                              int relu) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * O) return;
+__global__ void __launch_bounds__(256) fc_fwd_kernel(const T *__restrict__ x,
+                                                     const T *__restrict__ W,
+                                                     const T *__restrict__ bias,
+                                                     T *__restrict__ y, int n, int I, int O,
+                                                     int relu) {
+  const int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (idx >= (int64_t)n * O) return;                  // uniform over the wavefront
   const int o = (int)(idx % O), s = (int)(idx / O);
   const T *xs = x + (int64_t)s * I;
   const T *wo = W + (int64_t)o * I;
-  float acc = ldf(bias + o);
-  for (int i = 0; i < I; ++i) acc += ldf(wo + i) * ldf(xs + i);
-  stf(y + idx, relu ? fmaxf(acc, 0.f) : acc);
+  float acc = 0.f;
+  for (int i = lane; i < I; i += 64) acc += ldf(wo + i) * ldf(xs + i);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) {
+    acc += ldf(bias + o);
+    stf(y + idx, relu ? fmaxf(acc, 0.f) : acc);
+  }
 }
 
 template <typename T>
@@ -78,9 +87,9 @@ static hipError_t forward_t(const T *params, const T *x, int n, T *a1, T *a2, T 
       x, params + kW1, params + kB1, a1, n, 6, 16, 16, 16, 1);
   conv_fwd_kernel<T><<<(unsigned)ceil_div(e2, 256), 256, 0, st>>>(
       a1, params + kW2, params + kB2, a2, n, 16, 16, 16, 32, 2);
-  fc_fwd_kernel<T><<<(unsigned)ceil_div((int64_t)n * 64, 256), 256, 0, st>>>(
+  fc_fwd_kernel<T><<<(unsigned)ceil_div((int64_t)n * 64 * 64, 256), 256, 0, st>>>(
       a2, params + kW3, params + kB3, a3, n, 2048, 64, 1);
-  fc_fwd_kernel<T><<<(unsigned)ceil_div((int64_t)n * 3, 256), 256, 0, st>>>(
+  fc_fwd_kernel<T><<<(unsigned)ceil_div((int64_t)n * 3 * 64, 256), 256, 0, st>>>(
       a3, params + kW4, params + kB4, y, n, 64, 3, 0);
   return hipGetLastError();
 }

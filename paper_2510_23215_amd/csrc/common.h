@@ -61,6 +61,19 @@ hipError_t spmm_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_
                      int32_t step = 0, int tile = 4, bool pot = true,
                      const int32_t *cdeg = nullptr, int32_t mtot = 0);
 
+// S consecutive FP64 steps in one launch for the grid stencils (temporal blocking):
+// from level i (Xc) and level i-1 (Xp; null when i = 0) to level i+S (Ocur) and i+S-1 (Oprev).
+// coef: the S steps' (a, b, g), step t at coef[(t B + b) 3 + {0,1,2}].  Ocur and Oprev must not
+// overlap Xc or Xp.  Problems with mdeg[b] <= step0 are skipped (their degree is aligned so
+// that no problem ends inside a group).  spmm_fused_supported: the kind has the fused form
+// and its LDS arrays fit for grid side Nmax and S steps.
+bool spmm_fused_supported(int32_t kind, int32_t Nmax, int S);
+hipError_t spmm_fused(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t Nmax,
+                      const double *Xc, const double *Xp, double *Ocur, double *Oprev,
+                      int64_t ld, int64_t bs, int32_t mode, int32_t k, const int32_t *lock,
+                      const double *coef, int S, hipStream_t st, const int32_t *mdeg = nullptr,
+                      int32_t step0 = 0, int tile = 2, bool pot = true);
+
 // FP32 variant of the step for the mixed-precision filter; with R non-null the step adds the
 // per-column source term src[b*k + c] * R[:, c] (R in the same layout as X).
 hipError_t spmm_step32(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t Nmax,
@@ -151,12 +164,15 @@ hipError_t residuals(int B, int64_t n, int64_t ld, const double *X, const double
 
 // Lock the longest converged ascending prefix of the active columns: nconv[b] grows by the
 // prefix with res <= tol.  lock[b] (first active column) follows nconv[b], and becomes k
-// (done[b] = 1, which makes every ACTIVE-mode kernel skip the problem) once at least L
-// converged pairs lie at or below the smallest unconverged Ritz value theta[nconv[b]]
-// (|theta| when mag): the L smallest converged pairs are then the wanted ones.
+// (done[b] = 1, which makes every ACTIVE-mode kernel skip the problem) once the wanted pairs
+// are converged.  mode 0: at least L converged pairs lie at or below the smallest unconverged
+// Ritz value theta[nconv[b]] (the L smallest converged pairs are then the wanted ones);
+// mode 1: the same in |theta| (squared filter); mode 2 (smallest |theta| from the lower
+// end): the q converged pairs at or below theta[nconv[b]] hold L with |theta| <= their
+// largest; when no unconverged pair is left first, the problem ends with flag bit 16.
 hipError_t lock_update(int B, int32_t k, int32_t L, double tol, int32_t *lock, int32_t *nconv,
-                       const double *res, const double *theta, bool mag, int32_t *done,
-                       hipStream_t st);
+                       const double *res, const double *theta, int mode, int32_t *done,
+                       int32_t *flag, hipStream_t st);
 
 // Chebyshev step coefficients for degree m: coef[(s*B + b)*3 + {0,1,2}] for s = 0..m-1 from
 // lambda = theta[b*k], alpha = theta[b*k + k-1] (or win[] when given), beta = bounds[b*4+3].

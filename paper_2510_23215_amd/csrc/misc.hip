@@ -63,38 +63,67 @@ hipError_t residuals(int B, int64_t n, int64_t ld, const double *X, const double
 }
 
 // nconv[b]: locked pairs; lock[b]: first active column (= k once the problem is done).
+// mode 0: the L algebraically smallest; 1: the L smallest |theta| with the squared filter (the
+// active range is ordered by |theta|); 2: the L smallest |theta| from the lower end of the
+// spectrum (ascending active range).  Flag bit 16: mode 2 ran out of unconverged pairs before
+// its certificate held.
 __global__ void lock_kernel(int B, int32_t k, int32_t L, double tol, int32_t *__restrict__ lock,
                             int32_t *__restrict__ nconv, const double *__restrict__ res,
-                            const double *__restrict__ theta, int mag,
-                            int32_t *__restrict__ done) {
+                            const double *__restrict__ theta, int mode,
+                            int32_t *__restrict__ done, int32_t *__restrict__ flag) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B || done[b]) return;
   const int32_t j0 = nconv[b];
   int j = j0;
   while (j < k && res[(int64_t)b * k + j] <= tol) ++j;
   nconv[b] = j;
-  // A solve ends once at least L converged pairs lie at or below every unconverged Ritz value.
-  // The active range [j0, k) is ascending (by |theta| in the magnitude mode), so its first
-  // unconverged value theta_j is the smallest; a converged pair locked earlier above theta_j
-  // means a wanted pair entered the block late, and the solve goes on until it has converged.
-  bool fin = j >= L;
-  if (fin && j < k) {
-    const double *th = theta + (int64_t)b * k;
-    const double tu = mag ? fabs(th[j]) : th[j];
+  // The converged pairs at or below the smallest unconverged Ritz value theta_j (the active
+  // range [j0, k) is ordered, so theta_j is its smallest unconverged value) are the lowest
+  // ones of the spectrum: a converged pair locked earlier above theta_j means a wanted pair
+  // entered the block late, and the solve goes on until it has converged.
+  const double *th = theta + (int64_t)b * k;
+  const bool absval = mode == 1;
+  const double tu = (j < k) ? (absval ? fabs(th[j]) : th[j]) : INFINITY;
+  bool fin;
+  if (mode != 2) {
     int below = j - j0;
-    for (int c = 0; c < j0; ++c) below += ((mag ? fabs(th[c]) : th[c]) <= tu) ? 1 : 0;
-    fin = below >= L;
+    for (int c = 0; c < j0; ++c) below += ((absval ? fabs(th[c]) : th[c]) <= tu) ? 1 : 0;
+    fin = j >= L && below >= L;
+  } else {
+    // smallest magnitude from the lower end: the q lowest converged values must hold L with
+    // |theta| <= their largest, theta_q (every other eigenvalue is >= theta_q)
+    double top = -INFINITY;
+    int q = 0;
+    for (int c = 0; c < j; ++c)
+      if (th[c] <= tu) { ++q; top = fmax(top, th[c]); }
+    int cnt = 0;
+    for (int c = 0; c < j; ++c)
+      if (th[c] <= tu && fabs(th[c]) <= top) ++cnt;
+    fin = q >= L && cnt >= L;
+    // no certificate can come (not certified, flag bit 16): no pair left to converge, or fewer
+    // than L of the block's k values with |theta| <= the largest of them (a certified state
+    // has at least L such values, and the Ritz values of a converging block only drift down)
+    if (!fin) {
+      double big = -INFINITY;
+      for (int c = 0; c < k; ++c) big = fmax(big, th[c]);
+      int within = 0;
+      for (int c = 0; c < k; ++c) within += (fabs(th[c]) <= big) ? 1 : 0;
+      if (j >= k || within < L) {
+        fin = true;
+        flag[b] |= 16;
+      }
+    }
   }
   if (fin) { done[b] = 1; lock[b] = k; }
   else lock[b] = j;
 }
 
 hipError_t lock_update(int B, int32_t k, int32_t L, double tol, int32_t *lock, int32_t *nconv,
-                       const double *res, const double *theta, bool mag, int32_t *done,
-                       hipStream_t st) {
+                       const double *res, const double *theta, int mode, int32_t *done,
+                       int32_t *flag, hipStream_t st) {
   if (B <= 0) return hipSuccess;
-  lock_kernel<<<(B + 63) / 64, 64, 0, st>>>(B, k, L, tol, lock, nconv, res, theta, mag ? 1 : 0,
-                                            done);
+  lock_kernel<<<(B + 63) / 64, 64, 0, st>>>(B, k, L, tol, lock, nconv, res, theta, mode, done,
+                                            flag);
   return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ enum BufId {
   B_X, B_Y1, B_Y2, B_W, B_G, B_M, B_PART, B_THETA, B_RES, B_INT, B_BND, B_COEF, B_UNIT, B_CHOL,
   B_JAC, B_LZ, B_OPS, B_WIN, B_SORTF, B_SORTD, B_SORTO, B_REC, B_RANK, B_E32, B_R32, B_SRC,
   B_GAIN, B_WINB, B_HINT, B_MDEG, B_NETF, B_NETH, B_NETD, B_ROWS, B_EIG, B_CDEG, B_SQT, B_SQP, B_COEF2,
-  B_TEV, B_TVV, B_COUNT
+  B_TEV, B_TVV, B_NETL, B_COUNT
 };
 
 struct DevBuf {
@@ -80,6 +80,7 @@ struct scsf_handle {
   int lanes = 4;                         // concurrent chain groups in scsf_solve_sequence
   bool graphs = true;                    // outer iterations of chained solves as HIP graphs
   int eig = SCSF_EIG_JACOBI;             // Rayleigh-Ritz eigensolver
+  int fuse = 0;                          // Chebyshev steps per fused filter launch (0: one)
   // autotuned settings: SpMM columns per thread per (k bucket, n bucket), block width per L
   int32_t cpt[4][3] = {{4, 4, 4}, {4, 4, 4}, {4, 4, 4}, {4, 4, 4}};
   std::vector<std::pair<int32_t, int32_t>> widths;
@@ -259,6 +260,14 @@ struct Engine {
   // locking stay with A, the pairs ordered by |theta|
   bool mag = false;
   double *T = nullptr, *P = nullptr, *coef2 = nullptr;
+  // smallest magnitude from the lower end: the plain filter, locking until the lowest
+  // converged pairs hold L with |theta| <= their largest (lock_kernel mode 2); extract()
+  // returns those L ordered by |theta|; flag bit 16 marks a problem whose block ran out of
+  // pairs first (not certified)
+  bool mag_low = false;
+  // fused filter: groups of `fuse` Chebyshev steps per launch (0 = one step per launch); only
+  // for the plain FP64 filter of the grid stencils (fused_filter())
+  int fuse = 0;
   // adaptive: per problem, the filter columns (sum of column degrees) and the largest column
   // degree of the last iteration
   std::vector<int64_t> it_cols;
@@ -439,10 +448,13 @@ struct Engine {
     int M = 1;
     for (int b = 0; b < B; ++b)
       if (!h_done[b]) M = std::max(M, h_mraw[b]);
+    // every problem's filter must end in the buffer of the largest degree's: the three-buffer
+    // ring needs equal residues mod 3, the fused groups (two buffer pairs in turn) mod 2 S
+    const int mod = fused_filter(M) ? 2 * fuse : 3;
     bool changed = false;
     for (int b = 0; b < B; ++b) {
       int d = std::min(h_mraw[b], M);
-      while ((M - d) % 3 != 0) ++d;
+      while ((M - d) % mod != 0) ++d;
       if (d != h_mdeg[b]) { h_mdeg[b] = d; changed = true; }
     }
     mcur = M;
@@ -660,6 +672,34 @@ struct Engine {
         HIPCHK(spmm_step(ops, B, kind, n, Nmax, T, P, ring[(s + 1) % 3], ld, bs, COLS_ACTIVE, k,
                          lock, coef2 + (size_t)s * B * 3, true, st, nullptr, s, cpt, pot));
       }
+    } else if (fused_filter(M)) {
+      // q = M mod S single steps in the three-buffer ring, then groups of S steps, each from
+      // the two newest levels in one pair of buffers to the next two in the other pair
+      const int q = M % fuse;
+      double *ring[3] = {X, Y1, Y2};
+      for (int s = 0; s < q; ++s) {
+        const int slot = timed ? prof_begin(h, step_bytes(s > 0, false, s)) : -1;
+        HIPCHK(spmm_step(ops, B, kind, n, Nmax, ring[s % 3], ring[(s + 2) % 3], ring[(s + 1) % 3],
+                         ld, bs, COLS_ACTIVE, k, lock, coef + (size_t)s * B * 3, s > 0, st, md,
+                         s, cpt, pot, nullptr, M));
+        prof_end(h, slot);
+      }
+      FusedPlan fp = fused_plan(M);
+      double *cur = fp.in_cur, *prv = fp.in_prv;
+      for (int g = 0, s0 = q; s0 < M; ++g, s0 += fuse) {
+        double *oc = (g & 1) ? fp.odd_cur : fp.even_cur;
+        double *op = (g & 1) ? fp.odd_prv : fp.even_prv;
+        double bytes = 0.0;
+        if (timed)
+          for (int s = s0; s < s0 + fuse; ++s) bytes += step_bytes(s > 0, false, s);
+        const int slot = timed ? prof_begin(h, bytes, fuse) : -1;
+        HIPCHK(spmm_fused(ops, B, kind, n, Nmax, cur, s0 > 0 ? prv : nullptr, oc, op, ld, bs,
+                          COLS_ACTIVE, k, lock, coef + (size_t)s0 * B * 3, fuse, st, md, s0,
+                          cpt, pot));
+        prof_end(h, slot);
+        cur = oc;
+        prv = op;
+      }
     } else {
       double *ring[3] = {X, Y1, Y2};
       for (int s = 0; s < M; ++s) {
@@ -672,15 +712,60 @@ struct Engine {
     }
     return SCSF_OK;
   }
-  double *filtered(int M) {
+  // The fused filter runs for the plain FP64 filter of the grid stencils when the degree
+  // holds at least one group.
+  bool fused_filter(int M) const {
+    return fuse >= 2 && M >= fuse && !mixed && !mag && !adaptive &&
+           spmm_fused_supported(kind, Nmax, fuse);
+  }
+  // Buffers of the fused schedule of degree M: after the q = M mod S single steps the two
+  // newest levels are in (in_cur, in_prv) (X alone when q = 0); the groups write to the two
+  // other buffers, then back, in turn.  In each pair the newest level goes to the buffer that
+  // is not W (the Rayleigh-Ritz step writes A Q into W), so the filtered block never is W.
+  struct FusedPlan {
+    double *in_cur, *in_prv, *even_cur, *even_prv, *odd_cur, *odd_prv;
+  };
+  FusedPlan fused_plan(int M) const {
+    const int q = M % fuse;
     double *ring[3] = {X, Y1, Y2};
-    return mixed ? Y1 : ring[M % 3];
+    FusedPlan fp{};
+    fp.in_cur = ring[q % 3];
+    fp.in_prv = q > 0 ? ring[(q + 2) % 3] : nullptr;
+    double *all[4] = {X, Y1, Y2, W};
+    double *other[4];
+    int no = 0;
+    for (double *p : all)
+      if (p != fp.in_cur && p != fp.in_prv) other[no++] = p;
+    // q = 0: three buffers are free; the first group's pair takes Y1, Y2 and the second X, W
+    double *e0 = other[0], *e1 = other[1];
+    if (q == 0) { e0 = Y1; e1 = Y2; }
+    auto order = [&](double *a, double *b2, double **c, double **pv) {
+      if (a == W) std::swap(a, b2);
+      *c = a;
+      *pv = b2;
+    };
+    order(e0, e1, &fp.even_cur, &fp.even_prv);
+    double *o0 = fp.in_cur, *o1 = fp.in_prv;
+    if (q == 0) { o0 = X; o1 = W; }
+    order(o0, o1, &fp.odd_cur, &fp.odd_prv);
+    return fp;
+  }
+  double *filtered(int M) const {
+    double *ring[3] = {X, Y1, Y2};
+    if (mixed) return Y1;
+    if (fused_filter(M)) {
+      const int groups = (M - M % fuse) / fuse;
+      const FusedPlan fp = fused_plan(M);
+      return (groups & 1) ? fp.even_cur : fp.odd_cur;
+    }
+    return ring[M % 3];
   }
   int enqueue_orth(int M) { return orth(filtered(M), true); }
   int enqueue_rr(int M) { return rayleigh_ritz(filtered(M)); }
   int enqueue_post(int /*M*/) {
     HIPCHK(residuals(B, n, ld, X, W, bs, k, lock, theta, res, st, rows));
-    HIPCHK(lock_update(B, k, L, tol, lock, nconv, res, theta, mag, done, st));
+    HIPCHK(lock_update(B, k, L, tol, lock, nconv, res, theta, mag ? 1 : mag_low ? 2 : 0, done,
+                       flag, st));
     if (adaptive)
       HIPCHK(adaptive_degrees(B, k, lock, done, theta, res, bnd, tol, m_base, m, cdeg, mdeg, st));
     return SCSF_OK;
@@ -868,16 +953,38 @@ struct Engine {
   // is locked after larger ones), ascending -> evals (device, L) and evecs (device, n x L,
   // ld ldo), canonical sign.  Needs fetch(b) first.  Returns max relative residual of the
   // pairs.
-  int extract(int b, double *evals, double *evecs, int64_t ldo, double *maxres) {
+  // With mag_low: the L of the lowest converged pairs smallest in |theta|, in that order, and
+  // *certified = false when the block ran out of pairs before the certificate held.
+  int extract(int b, double *evals, double *evecs, int64_t ldo, double *maxres,
+              bool *certified = nullptr) {
     const double *th = h_theta + (size_t)b * k;
     int32_t *perm = h_perm + (size_t)b * k;
-    const int nsel = std::max<int>(L, std::min<int>(h_nconv[b], k));
+    const int nc = std::min<int>(h_nconv[b], k);
+    int nsel = std::max<int>(L, nc);
     std::iota(perm, perm + nsel, 0);
-    if (mag)
+    if (mag_low) {
+      // the lowest converged pairs (at or below the smallest unconverged Ritz value), ordered
+      // by |theta|; their first L are the wanted ones when the certificate held
+      const double tu = nc < k ? th[nc] : INFINITY;
+      int q = 0;
+      for (int c = 0; c < nc; ++c)
+        if (th[c] <= tu) perm[q++] = c;
+      if (q >= L) {
+        nsel = q;
+      } else {
+        nsel = std::max<int>(L, nc);
+        std::iota(perm, perm + nsel, 0);
+      }
       std::stable_sort(perm, perm + nsel,
                        [&](int a, int c) { return std::fabs(th[a]) < std::fabs(th[c]); });
-    else
+    } else if (mag) {
+      std::stable_sort(perm, perm + nsel,
+                       [&](int a, int c) { return std::fabs(th[a]) < std::fabs(th[c]); });
+    } else {
       std::stable_sort(perm, perm + nsel, [&](int a, int c) { return th[a] < th[c]; });
+    }
+    // a lower end that gave up (flag bit 16) or ran out of iterations is not certified
+    if (certified) *certified = !(mag_low && ((h_flag[b] & 16) || !h_done[b]));
     double *vals = h_theta + (size_t)b * k;  // reorder in place after computing the maximum
     double mr = 0.0;
     for (int j = 0; j < L; ++j) mr = std::max(mr, h_res[(size_t)b * k + perm[j]]);
@@ -886,7 +993,8 @@ struct Engine {
     for (int j = 0; j < L; ++j) vals[j] = sorted[j];
     int32_t *perm_d = nullptr;
     STCHK(grow(h, B_SORTO, (size_t)B * k, &perm_d));
-    HIPCHK(hipMemcpyAsync(perm_d + (size_t)b * k, perm, (size_t)L * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(perm_d + (size_t)b * k, perm, (size_t)L * 4, hipMemcpyHostToDevice,
+                          st));
     HIPCHK(hipMemcpyAsync(evals, vals, (size_t)L * 8, hipMemcpyHostToDevice, st));
     HIPCHK(gather_columns(h_rows[b], L, X + (int64_t)b * bs, ld, perm_d + (size_t)b * k, evecs,
                           ldo, st));
@@ -942,12 +1050,30 @@ bool on_square_grid(const OpDev &o) {
          (int64_t)o.N * o.N == o.n;
 }
 
+// Operators of a smallest-magnitude solve whose lower-end result could not be certified; the
+// lanes add to it concurrently, and the caller solves them again with the squared filter.
+struct Fallback {
+  std::mutex mu;
+  std::vector<int32_t> ops;
+  void add(int32_t o) {
+    std::lock_guard<std::mutex> lk(mu);
+    ops.push_back(o);
+  }
+};
+
+// How a SCSF_TARGET_MAGNITUDE solve runs: from the lower end of the spectrum first (lock
+// kernel mode 2), with the squared filter when that could not be certified.
+bool magnitude_lower_end(const scsf_params *prm, bool square_forced) {
+  return prm->target == SCSF_TARGET_MAGNITUDE && !square_forced;
+}
+
 int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order_host,
                int32_t n_op, const std::vector<int> &cb, const std::vector<int> &ce,
                std::atomic<int> *next, const scsf_params *prm, const double *hints_host,
                double *evals, double *evecs, double *ritz, scsf_stats *stats_host,
                const Group *grp = nullptr, bool graphs = false, int cpt = 4,
-               int eig = SCSF_EIG_JACOBI) {
+               int eig = SCSF_EIG_JACOBI, Fallback *fallback = nullptr,
+               bool square_forced = false, int fuse = 0) {
   const int chains = (int)cb.size();
   if (chains == 0) return SCSF_OK;
   const int64_t n = grp ? grp->nmax : ops_host[0].n;
@@ -956,14 +1082,18 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
   const int lzs = prm->lanczos_steps > 0 ? prm->lanczos_steps : 20;
   const int32_t L = grp ? grp->L : prm->L, k = grp ? grp->k : prm->k, m = prm->degree;
   const int64_t *eoff = grp ? grp->eoff : nullptr, *voff = grp ? grp->voff : nullptr;
+  const bool low = magnitude_lower_end(prm, square_forced);
+  const bool square = prm->target == SCSF_TARGET_MAGNITUDE && !low;
 
   Engine e;
   STCHK(e.setup(w, chains, n, k, L, m, kind, prm->tol, prm->seed, lzs,
                 prm->precision == SCSF_MIXED, hints_host != nullptr, prm->adaptive != 0,
-                prm->target == SCSF_TARGET_MAGNITUDE));
+                square));
+  e.mag_low = low;
   e.use_graph = graphs && w->own_stream;     // capture needs a stream of our own
   e.cpt = cpt;
   e.eig = eig;
+  e.fuse = fuse;
   e.pot = false;                             // fixed for the engine: graphs keep the choice
   for (int i = 0; i < n_op; ++i) e.pot = e.pot || ops_host[order_host[i]].v != nullptr;
   std::vector<int> pos(chains), iters(chains, 0);
@@ -1030,8 +1160,11 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
         HIPCHK(hipMemcpy(ritz + (size_t)op * k, th.data(), (size_t)k * 8, hipMemcpyHostToDevice));
       }
       const int64_t nop = ops_host[op].n;
+      bool cert = true;
       STCHK(e.extract(b, evals + (eoff ? eoff[op] : (int64_t)op * L),
-                      evecs + (voff ? voff[op] : (int64_t)op * n * L), nop, &mr));
+                      evecs + (voff ? voff[op] : (int64_t)op * n * L), nop, &mr, &cert));
+      const bool refit = low && !cert && fallback != nullptr;   // solved again, squared
+      if (refit) fallback->add(op);
       if (stats_host) {
         scsf_stats &st = stats_host[op];
         st.iterations = iters[b];
@@ -1050,8 +1183,11 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
         st.ms_bound = (float)e.ph[b][PH_BOUND];
         st.ms_wall = (float)(1e3 * std::chrono::duration<double>(
                                        std::chrono::steady_clock::now() - t_load[b]).count());
+        st.magnitude_route = low ? (cert ? 1 : 2) : (square ? 2 : 0);
       }
-      if (status != SCSF_OK && (worst == SCSF_OK || status != SCSF_ENOTCONV)) worst = status;
+      if (!(refit && status == SCSF_ENOTCONV) && status != SCSF_OK &&
+          (worst == SCSF_OK || status != SCSF_ENOTCONV))
+        worst = status;
       if (next) {
         pos[b] = next->fetch_add(1);
       } else {
@@ -1290,6 +1426,12 @@ int scsf_set_graphs(scsf_handle *h, int on) {
   return SCSF_OK;
 }
 
+int scsf_set_fused_steps(scsf_handle *h, int steps) {
+  if (!h || steps < 0 || steps == 1 || steps > 4) return SCSF_EINVAL;
+  h->fuse = steps;
+  return SCSF_OK;
+}
+
 int scsf_set_lanes(scsf_handle *h, int lanes) {
   if (!h || lanes < 1 || lanes > 16) return SCSF_EINVAL;
   h->lanes = lanes;
@@ -1473,15 +1615,36 @@ int scsf_filter_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t B
     HIPCHK(copy_block(ops_host[b].n, ncols, X + (int64_t)b * bsx, ldx, en.X + (int64_t)b * en.bs,
                       en.ld, true, w0->stream));
   double *ring[3] = {en.X, en.Y1, en.Y2};
-  for (int s = 0; s < degree; ++s) {
+  en.fuse = h->fuse;
+  const bool fused = en.fused_filter(degree);
+  const int singles = fused ? degree % en.fuse : degree;
+  for (int s = 0; s < singles; ++s) {
     const int slot = prof_begin(w0, en.step_bytes(s > 0, false, s));
     HIPCHK(spmm_step(en.ops, B, en.kind, nmax, en.Nmax, ring[s % 3], ring[(s + 2) % 3],
                      ring[(s + 1) % 3], en.ld, en.bs, COLS_ALL, ncols, nullptr,
                      en.coef + (size_t)s * B * 3, s > 0, w0->stream, nullptr, s, en.cpt, en.pot));
     prof_end(w0, slot);
   }
+  if (fused) {                       // the fused schedule of the solvers (Engine::enqueue_filter)
+    const Engine::FusedPlan fp = en.fused_plan(degree);
+    double *cur = fp.in_cur, *prv = fp.in_prv;
+    for (int g = 0, s0 = singles; s0 < degree; ++g, s0 += en.fuse) {
+      double *oc = (g & 1) ? fp.odd_cur : fp.even_cur;
+      double *op = (g & 1) ? fp.odd_prv : fp.even_prv;
+      double bytes = 0.0;
+      for (int s = s0; s < s0 + en.fuse; ++s) bytes += en.step_bytes(s > 0, false, s);
+      const int slot = prof_begin(w0, bytes, en.fuse);
+      HIPCHK(spmm_fused(en.ops, B, en.kind, nmax, en.Nmax, cur, s0 > 0 ? prv : nullptr, oc, op,
+                        en.ld, en.bs, COLS_ALL, ncols, nullptr, en.coef + (size_t)s0 * B * 3,
+                        en.fuse, w0->stream, nullptr, s0, en.cpt, en.pot));
+      prof_end(w0, slot);
+      cur = oc;
+      prv = op;
+    }
+  }
+  const double *res = en.filtered(degree);
   for (int b = 0; b < B; ++b)
-    HIPCHK(copy_block(ops_host[b].n, ncols, ring[degree % 3] + (int64_t)b * en.bs, en.ld,
+    HIPCHK(copy_block(ops_host[b].n, ncols, res + (int64_t)b * en.bs, en.ld,
                       Y + (int64_t)b * bsy, ldy, false, w0->stream));
   HIPCHK(hipStreamSynchronize(w0->stream));
   prof_drain(w0);
@@ -1666,26 +1829,24 @@ int scsf_sort(scsf_handle *h, const double *fields, int32_t n_op, int32_t channe
   return bad ? SCSF_EINVAL : SCSF_OK;
 }
 
-int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
-               const double *X_prev, const double *theta_prev, double *evals, double *evecs,
-               double *X_next, double *theta_next, scsf_stats *stats_host) {
-  CallScope cs_(h);
-  if (!h) return SCSF_EINVAL;
-  const auto t_start = std::chrono::steady_clock::now();
+// One operator through Algorithm 3 on the handle's own stream (scsf_solve).  *certified is
+// false for a smallest-magnitude lower-end solve whose result could not be certified.
+int solve_one(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
+              const double *X_prev, const double *theta_prev, double *evals, double *evecs,
+              double *X_next, double *theta_next, scsf_stats *stats_host, bool square_forced,
+              bool *certified, std::chrono::steady_clock::time_point t_start) {
   Workspace *w0 = h->ws[0];
-
-  STCHK(check_op(A));
-  STCHK(check_params(prm, A->n));
-  STCHK(check_op_precision(*A, prm));
-  if ((X_prev == nullptr) != (theta_prev == nullptr)) return SCSF_EINVAL;
-  if (!evals || !evecs) return SCSF_EINVAL;
   const int max_iter = prm->max_iter > 0 ? prm->max_iter : 5000;
   const int lzs = prm->lanczos_steps > 0 ? prm->lanczos_steps : 20;
+  const bool low = magnitude_lower_end(prm, square_forced);
+  const bool square = prm->target == SCSF_TARGET_MAGNITUDE && !low;
   Engine e;
   e.eig = h->eig;
-  STCHK(e.setup(w0, 1, A->n, prm->k, prm->L, prm->degree, A->kind, prm->tol, prm->seed, lzs,
-                prm->precision == SCSF_MIXED, false, prm->adaptive != 0,
-                prm->target == SCSF_TARGET_MAGNITUDE));
+  e.fuse = h->fuse;
+  STCHK(e.setup(w0, 1, A->n, prm->k, prm->L, prm->degree, A->kind, prm->tol,
+                prm->seed, lzs, prm->precision == SCSF_MIXED, false, prm->adaptive != 0,
+                square));
+  e.mag_low = low;
   e.h_ops[0] = to_dev(*A);
   e.h_need[0] = 1;
   STCHK(e.upload_ops());
@@ -1711,7 +1872,9 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
   const int status = solve_status(e.h_flag[0], conv);
   STCHK(e.fetch(0));
   double mr = 0.0;
-  STCHK(e.extract(0, evals, evecs, A->n, &mr));
+  bool cert = true;
+  STCHK(e.extract(0, evals, evecs, A->n, &mr, &cert));
+  *certified = cert;
   if (X_next) HIPCHK(copy_block(A->n, prm->k, e.X, e.ld, X_next, A->n, false, w0->stream));
   if (theta_next)
     HIPCHK(hipMemcpyAsync(theta_next, e.theta, (size_t)prm->k * 8, hipMemcpyDeviceToDevice,
@@ -1734,8 +1897,29 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
     stats_host->ms_bound = (float)e.ph[0][PH_BOUND];
     stats_host->ms_wall = (float)(1e3 * std::chrono::duration<double>(
                                             std::chrono::steady_clock::now() - t_start).count());
+    stats_host->magnitude_route = low ? (cert ? 1 : 2) : (square ? 2 : 0);
   }
   return status;
+}
+
+int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
+               const double *X_prev, const double *theta_prev, double *evals, double *evecs,
+               double *X_next, double *theta_next, scsf_stats *stats_host) {
+  CallScope cs_(h);
+  if (!h) return SCSF_EINVAL;
+  const auto t_start = std::chrono::steady_clock::now();
+  STCHK(check_op(A));
+  STCHK(check_params(prm, A->n));
+  STCHK(check_op_precision(*A, prm));
+  if ((X_prev == nullptr) != (theta_prev == nullptr)) return SCSF_EINVAL;
+  if (!evals || !evecs) return SCSF_EINVAL;
+  bool cert = true;
+  const int status = solve_one(h, A, prm, X_prev, theta_prev, evals, evecs, X_next, theta_next,
+                               stats_host, false, &cert, t_start);
+  if (cert || (status != SCSF_OK && status != SCSF_ENOTCONV)) return status;
+  // the lower end did not hold the smallest magnitudes: the squared filter, from the start
+  return solve_one(h, A, prm, X_prev, theta_prev, evals, evecs, X_next, theta_next, stats_host,
+                   true, &cert, t_start);
 }
 
 int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
@@ -1784,6 +1968,7 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
   std::vector<int> status(lanes, SCSF_OK);
   const bool dyn = prm->schedule == SCSF_SCHED_DYNAMIC;
   std::atomic<int> next(chains);                // dynamic: chain c starts at order position c
+  Fallback fb;                                  // smallest magnitude: uncertified lower ends
   auto lane_fn = [&](int g) {
     if (hipSetDevice(h->device) != hipSuccess) { status[g] = SCSF_EHIP; return; }
     std::vector<int> cb, ce;
@@ -1793,7 +1978,8 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
     }
     status[g] = run_chains(h->ws[g + 1], ops_host, order_host, n_op, cb, ce,
                            dyn ? &next : nullptr, prm, hints_host, evals, evecs, ritz, stats_host,
-                           nullptr, h->graphs, tuned_cpt(h, n, prm->k), h->eig);
+                           nullptr, h->graphs, tuned_cpt(h, n, prm->k), h->eig, &fb, false,
+                           h->fuse);
   };
   std::vector<std::thread> threads;
   for (int g = 1; g < lanes; ++g) threads.emplace_back(lane_fn, g);
@@ -1805,6 +1991,20 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
     const int s2 = status[g];
     if (s2 == SCSF_OK) continue;
     if (worst == SCSF_OK || (worst == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)) worst = s2;
+  }
+  if (!fb.ops.empty() && worst != SCSF_EHIP) {
+    // operators whose wanted pairs were not certified at the lower end: again, with the
+    // squared filter, as one chain per operator on the first lane
+    std::sort(fb.ops.begin(), fb.ops.end());
+    const int nf = (int)fb.ops.size();
+    std::vector<int> cb(nf), ce(nf);
+    std::iota(cb.begin(), cb.end(), 0);
+    std::iota(ce.begin(), ce.end(), 1);
+    const int s2 = run_chains(h->ws[1], ops_host, fb.ops.data(), nf, cb, ce, nullptr, prm,
+                              hints_host, evals, evecs, ritz, stats_host, nullptr, h->graphs,
+                              tuned_cpt(h, n, prm->k), h->eig, nullptr, true, h->fuse);
+    if (s2 != SCSF_OK && (worst == SCSF_OK || (worst == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)))
+      worst = s2;
   }
   return worst;
 }
@@ -1819,14 +2019,24 @@ int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_
                        const int32_t *L_host, const int32_t *k_host, const int32_t *order_host,
                        int32_t chains, const scsf_params *prm, double *evals, double *evecs,
                        scsf_stats *stats_host) {
+  return scsf_solve_batched_hinted(h, ops_host, n_op, L_host, k_host, order_host, chains, prm,
+                                   nullptr, evals, evecs, stats_host);
+}
+
+int scsf_solve_batched_hinted(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
+                              const int32_t *L_host, const int32_t *k_host,
+                              const int32_t *order_host, int32_t chains,
+                              const scsf_params *prm, const double *hints_host, double *evals,
+                              double *evecs, scsf_stats *stats_host) {
   CallScope cs_(h);
   if (!h || !ops_host || n_op <= 0 || !L_host || !order_host || chains <= 0 || !evals ||
       !evecs || !prm)
     return SCSF_EINVAL;
-  if (prm->precision != SCSF_FP64) return SCSF_EINVAL;
+  if (hints_host && (prm->adaptive || prm->target == SCSF_TARGET_MAGNITUDE)) return SCSF_EINVAL;
   std::vector<int32_t> kk(n_op);
   for (int i = 0; i < n_op; ++i) {
     STCHK(check_op(&ops_host[i]));
+    STCHK(check_op_precision(ops_host[i], prm));
     if (L_host[i] <= 0 || L_host[i] >= kMaxK) return SCSF_EINVAL;
     kk[i] = k_host ? k_host[i] : tuned_width(h, L_host[i]);
     scsf_params p = *prm;
@@ -1890,6 +2100,7 @@ int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_
   std::vector<std::atomic<int>> next(groups.size());
   for (size_t gi = 0; gi < groups.size(); ++gi) next[gi] = groups[gi].chains;
   std::vector<int> status(lanes, SCSF_OK);
+  std::vector<Fallback> fbs(groups.size());     // smallest magnitude: uncertified lower ends
   // every lane works through the groups in turn; a lane that finishes its chains of one group
   // moves on to the next without waiting for the others
   auto lane_fn = [&](int l) {
@@ -1910,8 +2121,9 @@ int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_
       grp.eoff = eoff.data();
       grp.voff = voff.data();
       const int s2 = run_chains(h->ws[l + 1], ops_host, g.order.data(), nord, cb, ce,
-                                dyn ? &next[gi] : nullptr, prm, nullptr, evals, evecs, nullptr,
-                                stats_host, &grp, h->graphs, tuned_cpt(h, g.nmax, g.k), h->eig);
+                                dyn ? &next[gi] : nullptr, prm, hints_host, evals, evecs, nullptr,
+                                stats_host, &grp, h->graphs, tuned_cpt(h, g.nmax, g.k), h->eig,
+                                &fbs[gi], false, h->fuse);
       if (s2 != SCSF_OK && (status[l] == SCSF_OK ||
                             (status[l] == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)))
         status[l] = s2;
@@ -1928,6 +2140,27 @@ int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_
     const int s2 = status[l];
     if (s2 == SCSF_OK) continue;
     if (worst == SCSF_OK || (worst == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)) worst = s2;
+  }
+  // uncertified smallest-magnitude solves again with the squared filter, one chain each
+  for (size_t gi = 0; gi < groups.size() && worst != SCSF_EHIP; ++gi) {
+    auto &fo = fbs[gi].ops;
+    if (fo.empty()) continue;
+    std::sort(fo.begin(), fo.end());
+    const int nf = (int)fo.size();
+    std::vector<int> cb(nf), ce(nf);
+    std::iota(cb.begin(), cb.end(), 0);
+    std::iota(ce.begin(), ce.end(), 1);
+    Group grp;
+    grp.L = groups[gi].L;
+    grp.k = groups[gi].k;
+    grp.nmax = groups[gi].nmax;
+    grp.eoff = eoff.data();
+    grp.voff = voff.data();
+    const int s2 = run_chains(h->ws[1], ops_host, fo.data(), nf, cb, ce, nullptr, prm, nullptr,
+                              evals, evecs, nullptr, stats_host, &grp, h->graphs,
+                              tuned_cpt(h, grp.nmax, grp.k), h->eig, nullptr, true, h->fuse);
+    if (s2 != SCSF_OK && (worst == SCSF_OK || (worst == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)))
+      worst = s2;
   }
   return worst;
 }
@@ -2020,7 +2253,7 @@ static int tune_width(scsf_handle *h, Workspace *w, const scsf_operator *ops_hos
     const auto t0 = std::chrono::steady_clock::now();
     const int s2 = run_chains(w, ops_host, probe.data(), (int32_t)probe.size(), cb, ce, nullptr,
                               &p, nullptr, ev, vv, nullptr, nullptr, &grp, h->graphs,
-                              tuned_cpt(h, nmax, kc), h->eig);
+                              tuned_cpt(h, nmax, kc), h->eig, nullptr, false, h->fuse);
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (s2 == SCSF_ENOTCONV) continue;             // a width that cannot converge never wins
     if (s2 != SCSF_OK) { rc = s2; break; }
@@ -2284,15 +2517,18 @@ int scsf_window_train(scsf_handle *h, float *params, const float *x, const float
   Workspace *w0 = h->ws[0];
   NetBufs nb;
   STCHK(net_bufs(w0, n, nb));
+  // the epochs' losses stay on the device until the end (no per-epoch synchronisation)
+  double *hist = nullptr;
+  STCHK(grow(w0, B_NETL, (size_t)epochs, &hist));
   HIPCHK(hipMemsetAsync(nb.m, 0, (size_t)2 * kNetParams * sizeof(float), w0->stream));
   for (int ep = 1; ep <= epochs; ++ep) {
     HIPCHK(cnn_loss_grad(params, x, target, n, nb.a1, nb.a2, nb.a3, nb.y, nb.d, nb.da3, nb.da2,
-                         nb.da1, nb.grad, nb.loss, w0->stream));
-    if (loss_history_host)
-      HIPCHK(hipMemcpyAsync(loss_history_host + (ep - 1), nb.loss, 8, hipMemcpyDeviceToHost,
-                            w0->stream));
+                         nb.da1, nb.grad, hist + (ep - 1), w0->stream));
     HIPCHK(cnn_adam(params, nb.grad, nb.m, nb.v, ep, lr, w0->stream));
   }
+  if (loss_history_host)
+    HIPCHK(hipMemcpyAsync(loss_history_host, hist, (size_t)epochs * 8, hipMemcpyDeviceToHost,
+                          w0->stream));
   HIPCHK(hipStreamSynchronize(w0->stream));
   return SCSF_OK;
 }

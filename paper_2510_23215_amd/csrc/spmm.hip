@@ -152,6 +152,7 @@ __global__ void __launch_bounds__(256) spmm_step_kernel(
 // KIND: SCSF_STENCIL5 (no problem of the batch has a potential: no per-node branch),
 // kStencil5V (5-point, potential where op.v is set) or SCSF_STENCIL9.
 constexpr int kStencil5V = 105;
+constexpr size_t kFusedBytes = 65536;                 // dynamic LDS of one fused workgroup
 
 // Z (the block two steps back) and Y are touched once per step: streamed with non-temporal
 // loads and stores, so they do not displace the staged tiles' halos and coefficients from L2.
@@ -297,6 +298,203 @@ __global__ void __launch_bounds__(256) spmm_lds_kernel(
       }
     }
   }
+}
+
+// S Chebyshev steps in one pass over the block (temporal blocking of the grid stencils).
+// A workgroup takes TILE = 256 NPT consecutive nodes and CPT columns.  It stages level i
+// (Xc) on the tile +- S H nodes and level i-1 (Xp) on the tile +- (S-1) H (H = N, or N + 1
+// for the 9-point stencil) in two LDS arrays per column, then runs the S steps in LDS: step
+// t computes level i+t+1 on the tile +- (S-t-1) H, each node from its neighbours in the
+// newest level and its own value in the one before, and writes it over that older value
+// (only the node itself reads it), so two arrays carry all levels.  The last two levels are
+// written to Ocur (level i+S) and Oprev (level i+S-1).  HBM traffic per column and node:
+// two reads and two writes for S steps, against three per step for the single-step kernel;
+// the halos come from L2 (neighbouring tiles read the same rows).  Nodes outside the grid are
+// zero in every level (Dirichlet).  coef holds the S steps' (a, b, g), step t at
+// coef[(t B + b) 3]; with HZ false (i = 0) there is no level -1 and the first g is 0.
+// Problems with mdeg[b] <= i have finished (the degrees are aligned to the groups).
+template <int KIND, int CPT, int NPT, int S, bool HZ>
+__global__ void __launch_bounds__(256) spmm_fused_kernel(
+    const OpDev *__restrict__ ops, int B, const double *__restrict__ Xc,
+    const double *__restrict__ Xp, double *__restrict__ Ocur, double *__restrict__ Oprev,
+    int64_t ld, int64_t bs, int32_t mode, int32_t k, const int32_t *__restrict__ lock,
+    const double *__restrict__ coef, const int32_t *__restrict__ mdeg, int32_t step0) {
+  constexpr int TILE = 256 * NPT;
+  extern __shared__ unsigned char smem_raw[];
+  const int b = blockIdx.z;
+  if (mdeg && step0 >= mdeg[b]) return;
+  const OpDev op = ops[b];
+  const int N = op.N;
+  const int64_t n = op.n;
+  const int64_t p0 = (int64_t)blockIdx.x * TILE;
+  if (p0 >= n) return;
+  int32_t c0, cnt;
+  col_range(mode, k, lock, b, c0, cnt);
+  const int j0 = blockIdx.y * CPT;
+  if (j0 >= cnt) return;
+  const int jn = min(CPT, cnt - j0);
+  const int H = (KIND == SCSF_STENCIL9) ? N + 1 : N;
+  const int span = TILE + 2 * S * H;
+  double *la = reinterpret_cast<double *>(smem_raw);          // CPT columns x span
+  double *lb = la + (size_t)CPT * span;                        // CPT columns x span
+  const int tid = threadIdx.x;
+  const int64_t base = p0 - (int64_t)S * H;                    // node of LDS entry 0
+  const int64_t off = (int64_t)b * bs + (int64_t)(c0 + j0) * ld;
+  // stage level i into la (whole span) and level i-1 into lb (span less H at each end)
+  constexpr int U = 4;
+  for (int e0 = tid; e0 < span; e0 += 256 * U) {
+    double v[U][CPT], w[U][CPT];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * 256;
+      const int64_t q = base + e;
+      const bool in = e < span && q >= 0 && q < n;
+      const bool inz = HZ && in && e >= H && e < span - H;
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) {
+        v[u][j] = (j < jn && in) ? Xc[off + (int64_t)j * ld + q] : 0.0;
+        w[u][j] = (j < jn && inz) ? Xp[off + (int64_t)j * ld + q] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * 256;
+      if (e < span) {
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+          la[j * span + e] = v[u][j];
+          lb[j * span + e] = w[u][j];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  double *cur = la, *prv = lb;
+#pragma unroll 1
+  for (int t = 0; t < S; ++t) {
+    const double a = coef[((int64_t)t * B + b) * 3 + 0];
+    const double bc = coef[((int64_t)t * B + b) * 3 + 1];
+    const double g = coef[((int64_t)t * B + b) * 3 + 2];
+    const int lo = (t + 1) * H, hi = span - (t + 1) * H;
+    for (int e = lo + tid; e < hi; e += 256) {
+      const int64_t q = base + e;
+      if (q < 0 || q >= n) {
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) prv[j * span + e] = 0.0;
+        continue;
+      }
+      const int iy = (int)(q / N), ix = (int)(q - (int64_t)iy * N);
+      if constexpr (KIND == SCSF_STENCIL5 || KIND == kStencil5V) {
+        const double cw = op.wx[(int64_t)iy * (N + 1) + ix];
+        const double ce = op.wx[(int64_t)iy * (N + 1) + ix + 1];
+        const double cs = op.wy[(int64_t)iy * N + ix];
+        const double cn = op.wy[(int64_t)(iy + 1) * N + ix];
+        double vp = 0.0;
+        if constexpr (KIND == kStencil5V) vp = op.v ? op.v[q] : 0.0;
+        const double cd = cw + ce + cs + cn + vp;
+        const double mw = ix > 0 ? cw : 0.0, me = ix < N - 1 ? ce : 0.0;
+        const double ms = iy > 0 ? cs : 0.0, mn = iy < N - 1 ? cn : 0.0;
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+          const double *cj = cur + j * span;
+          const double xv = cj[e];
+          const double ax = cd * xv - mw * cj[e - 1] - me * cj[e + 1] - ms * cj[e - N] -
+                            mn * cj[e + N];
+          double r = a * ax + bc * xv;
+          if (HZ || t > 0) r += g * prv[j * span + e];
+          prv[j * span + e] = r;
+        }
+      } else {
+        double c64[9], c9[9];
+        stencil9_coeffs(op, iy, ix, c64);
+        // a select into a second array: with the conditional store `if (!ok) c64[qq] = 0`
+        // hipcc dropped the zeroing of the (-1, -1) coefficient at ix = 0, so the left-edge
+        // nodes picked up the previous row's last node
+#pragma unroll
+        for (int qq = 0; qq < 9; ++qq) {
+          const int dy = qq / 3 - 1, dx = qq % 3 - 1;
+          const bool ok = (iy + dy >= 0) && (iy + dy < N) && (ix + dx >= 0) && (ix + dx < N);
+          c9[qq] = ok ? c64[qq] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+          const double *cj = cur + j * span;
+          double ax = 0.0;
+#pragma unroll
+          for (int qq = 0; qq < 9; ++qq) ax += c9[qq] * cj[e + (qq / 3 - 1) * N + (qq % 3 - 1)];
+          double r = a * ax + bc * cj[e];
+          if (HZ || t > 0) r += g * prv[j * span + e];
+          prv[j * span + e] = r;
+        }
+      }
+    }
+    __syncthreads();
+    double *tmp = cur;
+    cur = prv;
+    prv = tmp;
+  }
+  // cur: level i+S, prv: level i+S-1, valid on the tile
+#pragma unroll
+  for (int u = 0; u < NPT; ++u) {
+    const int64_t q = p0 + u * 256 + tid;
+    if (q >= n) break;
+    const int e = S * H + u * 256 + tid;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      if (j < jn) {
+        const int64_t o = off + (int64_t)j * ld + q;
+        __builtin_nontemporal_store(cur[j * span + e], &Ocur[o]);
+        __builtin_nontemporal_store(prv[j * span + e], &Oprev[o]);
+      }
+    }
+  }
+}
+
+template <int CPT, int NPT, int S>
+static bool launch_fused_t(const OpDev *ops, int B, int32_t kind, bool pot, int64_t nmax,
+                           int32_t Nmax, const double *Xc, const double *Xp, double *Ocur,
+                           double *Oprev, int64_t ld, int64_t bs, int32_t mode, int32_t k,
+                           const int32_t *lock, const double *coef, const int32_t *mdeg,
+                           int32_t step0, hipStream_t st) {
+  constexpr int TILE = 256 * NPT;
+  const int64_t H = (kind == SCSF_STENCIL9) ? (int64_t)Nmax + 1 : Nmax;
+  const size_t shm = (size_t)2 * CPT * (TILE + 2 * S * H) * sizeof(double);
+  if (shm > kFusedBytes) return false;
+  dim3 grid((unsigned)ceil_div(nmax, TILE), (unsigned)ceil_div(k, CPT), (unsigned)B);
+  const bool hz = Xp != nullptr;
+  auto go = [&](auto kern) {
+    kern<<<grid, 256, shm, st>>>(ops, B, Xc, Xp, Ocur, Oprev, ld, bs, mode, k, lock, coef, mdeg,
+                                 step0);
+  };
+  if (kind == SCSF_STENCIL5 && !pot) {
+    if (hz) go(spmm_fused_kernel<SCSF_STENCIL5, CPT, NPT, S, true>);
+    else go(spmm_fused_kernel<SCSF_STENCIL5, CPT, NPT, S, false>);
+  } else if (kind == SCSF_STENCIL5) {
+    if (hz) go(spmm_fused_kernel<kStencil5V, CPT, NPT, S, true>);
+    else go(spmm_fused_kernel<kStencil5V, CPT, NPT, S, false>);
+  } else {
+    if (hz) go(spmm_fused_kernel<SCSF_STENCIL9, CPT, NPT, S, true>);
+    else go(spmm_fused_kernel<SCSF_STENCIL9, CPT, NPT, S, false>);
+  }
+  return true;
+}
+
+template <int S>
+static bool launch_fused_s(int tile, const OpDev *ops, int B, int32_t kind, bool pot,
+                           int64_t nmax, int32_t Nmax, const double *Xc, const double *Xp,
+                           double *Ocur, double *Oprev, int64_t ld, int64_t bs, int32_t mode,
+                           int32_t k, const int32_t *lock, const double *coef,
+                           const int32_t *mdeg, int32_t step0, hipStream_t st) {
+  // tile: columns per thread (1, 2, 4) with 4 nodes per thread; a smaller tile when the
+  // LDS arrays of the larger do not fit
+  if (tile >= 4 && launch_fused_t<4, 4, S>(ops, B, kind, pot, nmax, Nmax, Xc, Xp, Ocur, Oprev, ld,
+                                           bs, mode, k, lock, coef, mdeg, step0, st))
+    return true;
+  if (tile >= 2 && launch_fused_t<2, 4, S>(ops, B, kind, pot, nmax, Nmax, Xc, Xp, Ocur, Oprev, ld,
+                                           bs, mode, k, lock, coef, mdeg, step0, st))
+    return true;
+  return launch_fused_t<1, 4, S>(ops, B, kind, pot, nmax, Nmax, Xc, Xp, Ocur, Oprev, ld, bs, mode,
+                                 k, lock, coef, mdeg, step0, st);
 }
 
 template <int CPT, typename T, bool SRC>
@@ -559,6 +757,34 @@ hipError_t spmm_step(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_
   return launch_step<double, false>(ops, B, kind, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock,
                                     coef, has_z, nullptr, nullptr, mdeg, step, tile, pot, cdeg,
                                     mtot, st);
+}
+
+bool spmm_fused_supported(int32_t kind, int32_t Nmax, int S) {
+  if (kind != SCSF_STENCIL5 && kind != SCSF_STENCIL9) return false;
+  if (Nmax <= 0 || S < 2 || S > 4) return false;
+  const int64_t H = (kind == SCSF_STENCIL9) ? (int64_t)Nmax + 1 : Nmax;
+  return (size_t)2 * (1024 + 2 * S * H) * sizeof(double) <= kFusedBytes;
+}
+
+hipError_t spmm_fused(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t Nmax,
+                      const double *Xc, const double *Xp, double *Ocur, double *Oprev,
+                      int64_t ld, int64_t bs, int32_t mode, int32_t k, const int32_t *lock,
+                      const double *coef, int S, hipStream_t st, const int32_t *mdeg,
+                      int32_t step0, int tile, bool pot) {
+  if (B <= 0 || nmax <= 0 || k <= 0) return hipSuccess;
+  if (!spmm_fused_supported(kind, Nmax, S)) return hipErrorInvalidValue;
+  bool ok = false;
+  if (S == 2)
+    ok = launch_fused_s<2>(tile, ops, B, kind, pot, nmax, Nmax, Xc, Xp, Ocur, Oprev, ld, bs, mode,
+                           k, lock, coef, mdeg, step0, st);
+  else if (S == 3)
+    ok = launch_fused_s<3>(tile, ops, B, kind, pot, nmax, Nmax, Xc, Xp, Ocur, Oprev, ld, bs, mode,
+                           k, lock, coef, mdeg, step0, st);
+  else
+    ok = launch_fused_s<4>(tile, ops, B, kind, pot, nmax, Nmax, Xc, Xp, Ocur, Oprev, ld, bs, mode,
+                           k, lock, coef, mdeg, step0, st);
+  if (!ok) return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t spmm_step32(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t Nmax,

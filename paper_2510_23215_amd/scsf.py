@@ -58,7 +58,8 @@ class Stats(ctypes.Structure):
                 ("filter_cols", c_int64), ("beta", c_double), ("max_rel_resid", c_double),
                 ("ms_filter", ctypes.c_float), ("ms_orth", ctypes.c_float),
                 ("ms_rr", ctypes.c_float), ("ms_resid", ctypes.c_float),
-                ("ms_bound", ctypes.c_float), ("ms_wall", ctypes.c_float)]
+                ("ms_bound", ctypes.c_float), ("ms_wall", ctypes.c_float),
+                ("magnitude_route", c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -117,6 +118,7 @@ def lib():
         sig["scsf_workspace_peak"] = [vp, POINTER(sz)]
         sig["scsf_profile_enable"] = [vp, i32]
         sig["scsf_set_lanes"] = [vp, i32]
+        sig["scsf_set_fused_steps"] = [vp, i32]
         sig["scsf_set_graphs"] = [vp, i32]
         sig["scsf_set_eigensolver"] = [vp, i32]
         sig["scsf_profile_read"] = [vp, POINTER(Profile), i32]
@@ -131,6 +133,10 @@ def lib():
         sig["scsf_solve_batched"] = [vp, POINTER(Operator), i32, POINTER(c_int32),
                                      POINTER(c_int32), POINTER(c_int32), i32, POINTER(Params),
                                      vp, vp, POINTER(Stats)]
+        sig["scsf_solve_batched_hinted"] = [vp, POINTER(Operator), i32, POINTER(c_int32),
+                                            POINTER(c_int32), POINTER(c_int32), i32,
+                                            POINTER(Params), POINTER(c_double), vp, vp,
+                                            POINTER(Stats)]
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
@@ -432,10 +438,11 @@ def scsf_set_tile(h: Handle, tile: int):
 
 
 def scsf_solve_batched(h: Handle, ops: list, Ls, order, chains: int, prm: Params, ks=None,
-                       allow_notconv=False):
+                       allow_notconv=False, hints=None):
     """Operators of different sizes and L in one call.  Returns (evals, evecs, stats): evals[i]
     a length-L_i view, evecs[i] an (L_i, n_i) view (row j = eigenvector j), both into the
-    packed device arrays, and the per-operator stats dicts."""
+    packed device arrays, and the per-operator stats dicts.  hints: (n_op, 3) host array of
+    (lambda_1, lambda_{L+1}, degree) per operator (scsf_solve_batched_hinted)."""
     n_op = len(ops)
     arr = (Operator * n_op)(*[o.struct for o in ops])
     Ls = [int(x) for x in Ls]
@@ -448,8 +455,17 @@ def scsf_solve_batched(h: Handle, ops: list, Ls, order, chains: int, prm: Params
     vec = torch.empty(nv, device="cuda", dtype=torch.float64)
     stats = (Stats * n_op)()
     allow = (SCSF_OK, SCSF_ENOTCONV) if allow_notconv else (SCSF_OK,)
-    _check(lib().scsf_solve_batched(h.ptr, arr, n_op, Lc, kc, ordc, int(chains), ctypes.byref(prm),
-                                    _ptr(ev), _ptr(vec), stats), "scsf_solve_batched", allow)
+    if hints is None:
+        _check(lib().scsf_solve_batched(h.ptr, arr, n_op, Lc, kc, ordc, int(chains),
+                                        ctypes.byref(prm), _ptr(ev), _ptr(vec), stats),
+               "scsf_solve_batched", allow)
+    else:
+        hh = np.ascontiguousarray(hints, dtype=np.float64).reshape(-1)
+        assert hh.size == 3 * n_op
+        hc = (c_double * hh.size)(*hh.tolist())
+        _check(lib().scsf_solve_batched_hinted(h.ptr, arr, n_op, Lc, kc, ordc, int(chains),
+                                               ctypes.byref(prm), hc, _ptr(ev), _ptr(vec),
+                                               stats), "scsf_solve_batched_hinted", allow)
     evals, evecs = [], []
     e = v = 0
     for o, L in zip(ops, Ls):
@@ -569,6 +585,11 @@ def scsf_workspace_peak(h: Handle) -> int:
     out = ctypes.c_size_t()
     _check(lib().scsf_workspace_peak(h.ptr, ctypes.byref(out)), "scsf_workspace_peak")
     return int(out.value)
+
+
+def scsf_set_fused_steps(h: Handle, steps: int):
+    """Chebyshev steps per fused filter launch (2, 3, 4; 0 = one step per launch)."""
+    _check(lib().scsf_set_fused_steps(h.ptr, int(steps)), "scsf_set_fused_steps")
 
 
 def scsf_profile_enable(h: Handle, on: bool = True):

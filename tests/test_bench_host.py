@@ -18,26 +18,40 @@ def test_more_than_one_gpu_is_refused():
     assert "error" in json.loads(r.stdout.strip().splitlines()[-1])
 
 
-def test_traffic_record_matches_only_its_source_and_launch():
-    launch = {"chains": 128, "lanes": 6, "schedule": "dynamic", "graphs": "on", "tile": 4,
-              "form": "plain", "precision": "fp64"}
-    rec = bench.measured_traffic("c2_poisson100", launch)
-    assert rec is not None and 1e8 < rec < 3e8
-    assert bench.measured_traffic("c2_poisson100", dict(launch, lanes=8)) is None
-    assert bench.measured_traffic("c2_poisson100", dict(launch, tile=2)) is None
-    assert bench.measured_traffic("c9_missing", launch) is None
+def write_record(root, launch, source_text=None):
+    """A counter record for a workload named c9_test, hashing the step's source as it is."""
+    import hashlib
+    src = os.path.join(root, "paper_2510_23215_amd", "csrc", "spmm.hip")
+    if source_text is not None:
+        os.makedirs(os.path.dirname(src), exist_ok=True)
+        with open(src, "w") as f:
+            f.write(source_text)
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    lines = ["# test record", "source paper_2510_23215_amd/csrc/spmm.hip",
+             f"source_sha256_16 {digest}", "bytes_per_launch 123456789"]
+    lines += [f"{k} {v}" for k, v in launch.items()]
+    os.makedirs(os.path.join(root, "profiles"), exist_ok=True)
+    with open(os.path.join(root, "profiles", "spmm_traffic_c9_test.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+LAUNCH = {"chains": 128, "lanes": 6, "schedule": "dynamic", "graphs": "on", "tile": 4,
+          "form": "plain", "precision": "fp64", "fused_steps": 0}
+
+
+def test_traffic_record_matches_only_its_source_and_launch(tmp_path, monkeypatch):
+    write_record(str(tmp_path), LAUNCH, "// a filter step\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("c9_test", LAUNCH) == 123456789.0
+    assert bench.measured_traffic("c9_test", dict(LAUNCH, lanes=8)) is None
+    assert bench.measured_traffic("c9_test", dict(LAUNCH, tile=2)) is None
+    assert bench.measured_traffic("c9_missing", LAUNCH) is None
 
 
 def test_traffic_record_is_dropped_when_the_step_source_changes(tmp_path, monkeypatch):
-    """A copy of the record pointing at another file: the hash no longer matches."""
-    prof = tmp_path / "profiles"
-    prof.mkdir()
-    text = open(os.path.join(ROOT, "profiles", "spmm_traffic_c2_poisson100.txt")).read()
-    (prof / "spmm_traffic_c2_poisson100.txt").write_text(text)
-    src = tmp_path / "paper_2510_23215_amd" / "csrc"
-    src.mkdir(parents=True)
-    (src / "spmm.hip").write_text("// a different filter step\n")
+    """The record names the hash of the step's source: another source no longer matches."""
+    write_record(str(tmp_path), LAUNCH, "// a filter step\n")
+    with open(os.path.join(str(tmp_path), "paper_2510_23215_amd", "csrc", "spmm.hip"), "w") as f:
+        f.write("// a different filter step\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    launch = {"chains": 128, "lanes": 6, "schedule": "dynamic", "graphs": "on", "tile": 4,
-              "form": "plain", "precision": "fp64"}
-    assert bench.measured_traffic("c2_poisson100", launch) is None
+    assert bench.measured_traffic("c9_test", LAUNCH) is None

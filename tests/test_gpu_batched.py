@@ -138,9 +138,9 @@ def test_batched_errors(h):
         scsf.scsf_solve_batched(h, d, Ls, [0, 1], 1, prm, ks=[Ls[0], Ls[1] + 4])
     with pytest.raises(scsf.ScsfError):                       # not a permutation
         scsf.scsf_solve_batched(h, d, Ls, [0, 0], 1, prm)
-    with pytest.raises(scsf.ScsfError):                       # mixed precision is uniform-only
-        scsf.scsf_solve_batched(h, d, Ls, [0, 1], 1,
-                                scsf.make_params(0, 0, 20, 1e-8, precision=scsf.SCSF_MIXED))
+    with pytest.raises(scsf.ScsfError):                       # hints fix the degree
+        scsf.scsf_solve_batched(h, d, Ls, [0, 1], 1, scsf.make_params(0, 0, 20, 1e-8, adaptive=1),
+                                hints=np.zeros((2, 3)))
     with pytest.raises(scsf.ScsfError):                       # L out of range
         scsf.scsf_solve_batched(h, d, [0, 4], [0, 1], 1, prm)
 
@@ -296,3 +296,31 @@ def test_gram_batched(n, k):
         np.testing.assert_allclose(host(G[b]), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
     with pytest.raises(scsf.ScsfError):
         scsf.scsf_gram_batched(h, torch.zeros((2, 257, 300), dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("precision", [scsf.SCSF_FP64, scsf.SCSF_MIXED], ids=["fp64", "mixed"])
+def test_batched_mixed_precision_and_hints_match_oracle(precision):
+    """The layered forms on an uneven batch: FP32 filter (residual form), per-operator window
+    and degree hints (here the oracle's lambda_1 and lambda_{L+1} and a degree per operator),
+    sides and L differing within the batch, against the dense FP64 eigenpairs."""
+    say("batched mixed + hints", precision)
+    h = scsf.Handle()
+    scsf.scsf_set_lanes(h, 2)
+    ops, Ls = small_uneven()
+    order = family_order(h, ops, 6)
+    ref = []
+    hints = np.zeros((len(ops), 3))
+    for i, o in enumerate(ops):
+        A = O.assemble(o)
+        w, V = E.smallest_eigenpairs(A, Ls[i] + 6, method="dense")
+        ref.append((A, w, V))
+        hints[i] = (w[0], w[Ls[i]], 24 + 3 * (i % 3))
+    prm = scsf.make_params(0, 0, 20, 1e-8, seed=2, schedule=scsf.SCSF_SCHED_DYNAMIC,
+                           precision=precision)
+    evals, evecs, stats = scsf.scsf_solve_batched(h, [scsf.DeviceOperator(o) for o in ops], Ls,
+                                                  order, 4, prm, hints=hints)
+    say([s["iterations"] for s in stats], [s["hint"] for s in stats])
+    for i in range(len(ops)):
+        A, w, V = ref[i]
+        assert stats[i]["status"] == 0 and stats[i]["hint"] == 2
+        check_pairs(A, evals[i], evecs[i].t(), Ls[i], 1e-8, w, V)

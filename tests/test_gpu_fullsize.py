@@ -118,6 +118,36 @@ def test_uneven_all_operators():
         check_residuals(O.assemble(ops[i]), lam, host(evecs[i]).T, cfg.tol, Ls[i])
 
 
+def test_uneven_mixed_precision_with_hints_all_operators():
+    """The layered forms together on the 1000-operator uneven batch: FP32 filter, per-operator
+    window hints (the stored oracle lambda_1 and lambda_{L+1}: the best a window predictor can
+    give) and degree 20, in the benchmark's launch configuration; every operator against the
+    FP64 oracle at 1e-10."""
+    say("full size: uneven batch, mixed precision + hints")
+    cfg = si.CONFIGS[3]
+    ref, Lref = golden(cfg)
+    ops = si.operators(cfg)
+    Ls = [int(x) for x in Lref]
+    hints = np.array([(ref[i, 0], ref[i, Ls[i]], cfg.degree) for i in range(len(ops))])
+    h = bench_handle()
+    order = family_order(h, ops, cfg.p0)
+    dops = [scsf.DeviceOperator(o) for o in ops]
+    prm = scsf.make_params(0, 0, cfg.degree, cfg.tol, seed=1, schedule=scsf.SCSF_SCHED_DYNAMIC,
+                           precision=scsf.SCSF_MIXED)
+    scsf.scsf_autotune(h, dops, Ls, order, scsf.make_params(
+        0, 0, cfg.degree, cfg.tol, seed=1, schedule=scsf.SCSF_SCHED_DYNAMIC), probe=4)
+    evals, evecs, stats = scsf.scsf_solve_batched(h, dops, Ls, order, CHAINS, prm, hints=hints)
+    its = [s["iterations"] for s in stats]
+    say("iterations mean", np.mean(its), "max", max(its),
+        "hints used", sum(s["hint"] == 2 for s in stats))
+    assert all(s["status"] == 0 for s in stats)
+    for i in range(len(ops)):
+        lam = host(evals[i])
+        check_evals(i, lam, ref[i], Ls[i])
+    for i in range(0, len(ops), 10):
+        check_residuals(O.assemble(ops[i]), host(evals[i]), host(evecs[i]).T, cfg.tol, Ls[i])
+
+
 def test_mixed160_all_operators():
     """200 operators, n = 25600, L = 200, k = 240, FP32 filter: FP64 accuracy."""
     say("full size: mixed160")
@@ -220,3 +250,35 @@ def test_plate100_all_operators():
         rho = o.rho.ravel()
         np.testing.assert_allclose(U.T @ (U * rho[:, None]), np.eye(cfg.L), atol=1e-10)
         check_residuals(O.assemble(o), ev[i], U * np.sqrt(rho)[:, None], cfg.tol, cfg.L)
+
+
+def test_helmholtz80_all_operators():
+    """100 Helmholtz operators -div(p grad u) - k^2 u on an 80 x 80 grid (n = 6400, the paper's
+    Helmholtz size; indefinite, tens of negative eigenvalues down to about -10^3), the L = 200
+    lowest eigenvalues, k = 240, degree 20, tol 1e-8, in the benchmark's launch configuration:
+    every operator's eigenvalues against the oracle's, every pair's residual."""
+    say("full size: helmholtz80")
+    cfg = si.CONFIGS[7]
+    ref, _ = golden(cfg)
+    ops = si.operators(cfg)
+    h = bench_handle()
+    fields = torch.tensor(np.stack([o.field for o in ops]), device="cuda")
+    order = scsf.scsf_sort(h, fields, cfg.p0)
+    dops = [scsf.DeviceOperator(o) for o in ops]
+    prm = scsf.make_params(cfg.L, cfg.k, cfg.degree, cfg.tol, seed=1,
+                           schedule=scsf.SCSF_SCHED_DYNAMIC)
+    evals, evecs, stats = scsf.scsf_solve_sequence(h, dops, order, CHAINS, prm)
+    its = [s["iterations"] for s in stats]
+    say("iterations mean", np.mean(its), "max", max(its))
+    assert all(s["status"] == 0 for s in stats)
+    ev = host(evals)
+    for i, o in enumerate(ops):
+        lam = ev[i]
+        w = ref[i, :cfg.L]
+        np.testing.assert_allclose(lam, w, rtol=1e-10, atol=1e-10 * np.abs(w).max())
+        A = O.assemble(o)
+        X = host(evecs[i]).T
+        W = A @ X
+        rel = np.linalg.norm(W - X * lam, axis=0) / np.linalg.norm(W, axis=0)
+        assert rel.max() <= cfg.tol * (1 + 1e-6)
+        assert np.max(np.abs(X.T @ X - np.eye(cfg.L))) < 1e-12

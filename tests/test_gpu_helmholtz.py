@@ -72,6 +72,39 @@ def test_shifted_laplacian_closed_form():
                                       scsf.make_params(14, 22, 20, 1e-10, seed=1, target=MAG))
     ref = (mu - c)[np.argsort(np.abs(mu - c), kind="stable")][:14]
     np.testing.assert_allclose(host(ev), ref, rtol=1e-10, atol=1e-9)
+    # 31 eigenvalues lie below c: the lower end cannot be certified, the squared filter ran
+    assert st["magnitude_route"] == 2
+
+
+def test_short_negative_spectrum_takes_the_lower_end():
+    """A Helmholtz operator with 9 negative eigenvalues and L = 30: the lowest converged pairs
+    certify the 30 of smallest magnitude (route 1), in as few outer iterations as the plain
+    method needs for the 30 algebraically smallest of the same operator."""
+    say("helmholtz lower end")
+    op = si.helmholtz_operator(20, 8, 7)
+    A = O.assemble(op)
+    h = scsf.Handle()
+    d = scsf.DeviceOperator(op)
+    ev, vec, _, _, st = scsf.scsf_solve(h, d, scsf.make_params(30, 40, 20, 1e-9, seed=2,
+                                                               target=MAG))
+    say(st)
+    assert st["status"] == 0 and st["magnitude_route"] == 1
+    check_magnitude_pairs(A, ev, vec, 30, 1e-9)
+    _, _, _, _, st0 = scsf.scsf_solve(h, d, scsf.make_params(30, 40, 20, 1e-9, seed=2))
+    assert st["iterations"] <= st0["iterations"] + 2
+
+
+def test_magnitude_certificate_with_a_large_negative_outlier():
+    """Eigenvalues -10, -1, 1, 2, ... (a diagonal CSR operator), L = 3: the three of smallest
+    magnitude are -1, 1, 2, found at the lower end (the four lowest certify them)."""
+    import scipy.sparse as sp
+    lam = np.array([-10.0, -1.0] + list(np.arange(1.0, 59.0)))
+    A = sp.diags(lam).tocsr()
+    op = scsf.DeviceOperator(csr=(A.indptr, A.indices, A.data))
+    ev, _, _, _, st = scsf.scsf_solve(scsf.Handle(), op,
+                                      scsf.make_params(3, 8, 20, 1e-10, seed=6, target=MAG))
+    assert st["magnitude_route"] == 1
+    np.testing.assert_allclose(host(ev), [-1.0, 1.0, 2.0], rtol=1e-12)
 
 
 def run_sequence(graphs, ops, prm):

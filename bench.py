@@ -380,6 +380,7 @@ def main():
         take the predicted window and degree.  Every operator is solved once."""
         t = time.perf_counter()
         order = scsf.scsf_sort(h, fields, cfg.p0)
+        t_sort = time.perf_counter() - t
         head, tail = [int(i) for i in order[:n_train]], [int(i) for i in order[n_train:]]
         ritz = torch.empty((n_train, cfg.k), device="cuda", dtype=torch.float64)
         _, _, st1 = scsf.scsf_solve_sequence(h, [dops[i] for i in head], np.arange(n_train),
@@ -402,7 +403,7 @@ def main():
         train_info.update(loss_first=float(hist[0]), loss_last=float(hist[-1]),
                           hints_used=int(sum(s["hint"] == 2 for s in st2)),
                           mean_degree=float(np.mean([s["degree"] for s in st2])),
-                          head_s=t_head, train_and_infer_s=t_train,
+                          sort_s=t_sort, head_s=t_head - t_sort, train_and_infer_s=t_train,
                           tail_s=time.perf_counter() - t - t_head - t_train,
                           head_mean_iterations=float(np.mean([s["iterations"] for s in st1])),
                           tail_mean_iterations=float(np.mean([s["iterations"] for s in st2])))
@@ -444,9 +445,11 @@ def main():
     t0 = time.perf_counter()
     iters = []
     for s in range(args.steps):
+        ts = time.perf_counter()
         stats = step()
         iters += [st["iterations"] for st in stats]
-        log(f"[bench] step {s} done")
+        log(f"[bench] step {s} done, {time.perf_counter() - ts:.2f}s"
+            + (f" {train_info}" if form == "learned" else ""))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = scsf.scsf_profile_read(h, reset=True)

@@ -158,38 +158,61 @@ int64_t jacobi_record_elems(int32_t k) {
   return (int64_t)kJacobiMaxSweeps * (K - 1) * (K / 2) * 2 + (int64_t)kJacobiMaxSweeps * (K - 1);
 }
 
+// One workgroup of 1024 threads per problem.  The 2x2-block updates of a round are dealt
+// evenly: block e of the packed triangle of pair indices (a <= b) goes to thread e mod 1024, and
+// each thread decodes its blocks once before the sweeps.
+constexpr int kJacobiThreads = 1024;
+constexpr int kJacobiBlocksPerThread =
+    ((kMaxK / 2) * (kMaxK / 2 + 1) / 2 + kJacobiThreads - 1) / kJacobiThreads;
+
 template <bool LDS>
-__global__ void __launch_bounds__(512) jacobi_values_kernel(
+__global__ void __launch_bounds__(kJacobiThreads) jacobi_values_kernel(
     int32_t k, const int32_t *__restrict__ lock, const double *__restrict__ Gin, int32_t ldm,
     double *__restrict__ theta, int32_t *__restrict__ rank_out, double *__restrict__ rec,
     int64_t rec_stride, int32_t *__restrict__ nsweeps, int32_t *__restrict__ flag,
     double *__restrict__ gscr, double stop) {
+  constexpr int NT = kJacobiThreads, MAXE = kJacobiBlocksPerThread;
   __shared__ double lds[LDS ? kLdsDoubles : 1];
-  __shared__ int rp[kMaxK / 2 + 1], rq[kMaxK / 2 + 1];
-  __shared__ double rc[kMaxK / 2 + 1], rs[kMaxK / 2 + 1];
+  __shared__ int2 rpq[kMaxK / 2 + 1];
+  __shared__ double2 rcs[kMaxK / 2 + 1];
   __shared__ int s_any[2];
-  __shared__ double sh[8];
+  __shared__ double sh[NT / 64];
   const int b = blockIdx.x;
   const int32_t l = lock ? lock[b] : 0;
   const int ka = k - l;
-  const int tid = threadIdx.x, NT = blockDim.x;
+  const int tid = threadIdx.x;
   if (ka <= 0) { if (tid == 0) nsweeps[b] = 0; return; }
-  const int tx = tid & 15, ty = tid >> 4;              // 16 x 32
+  const int tx = tid & 15, ty = tid >> 4;              // 16 x 64
   const int K = ka + (ka & 1), half = K / 2;
   const bool in_lds = LDS && (int64_t)K * (K + 1) / 2 <= kLdsDoubles;
   double *S = in_lds ? lds : gscr + (int64_t)b * kMaxK * (kMaxK + 1);
   const double *Gb = Gin + (int64_t)b * ldm * ldm;
   double *R = rec + (int64_t)b * rec_stride;           // (c, s) per (sweep, round, slot)
   double *Ract = R + (int64_t)kJacobiMaxSweeps * (K - 1) * half * 2;
-  for (int c = ty; c < K; c += 32)
+  for (int c = ty; c < K; c += NT / 16)
     for (int i = tx; i <= c; i += 16)
       S[pk(i, c)] = (i < ka && c < ka) ? Gb[i + (int64_t)c * ldm] : 0.0;  // zero dummy index
+  // this thread's 2x2 blocks (aa, bb), aa <= bb < half, as aa | bb << 16 (none: ~0u)
+  const int nblk = half * (half + 1) / 2;
+  uint32_t blk[MAXE];
+#pragma unroll
+  for (int u = 0; u < MAXE; ++u) {
+    const int e = tid + u * NT;
+    uint32_t v = ~0u;
+    if (e < nblk) {
+      int bb = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+      while (bb * (bb + 1) / 2 > e) --bb;
+      while ((bb + 1) * (bb + 2) / 2 <= e) ++bb;
+      v = (uint32_t)(e - bb * (bb + 1) / 2) | ((uint32_t)bb << 16);
+    }
+    blk[u] = v;
+  }
   if (tid == 0) { s_any[0] = 0; s_any[1] = 0; }
   __syncthreads();
   // largest relative off-diagonal entry (all threads get the value)
   auto max_off = [&]() {
     double off = 0.0;
-    for (int c = ty; c < ka; c += 32)
+    for (int c = ty; c < ka; c += NT / 16)
       for (int i = tx; i < c; i += 16) {
         const double den = sqrt(fabs(S[pk(i, i)] * S[pk(c, c)]));
         const double v = fabs(S[pk(i, c)]);
@@ -227,7 +250,8 @@ __global__ void __launch_bounds__(512) jacobi_values_kernel(
           sn = c * t;
           s_any[par] = 1;
         }
-        rp[a] = p; rq[a] = q; rc[a] = c; rs[a] = sn;
+        rpq[a] = make_int2(p, q);
+        rcs[a] = make_double2(c, sn);
         double *o = R + (((int64_t)sweep * (K - 1) + r) * half + a) * 2;
         o[0] = c;
         o[1] = sn;
@@ -237,22 +261,26 @@ __global__ void __launch_bounds__(512) jacobi_values_kernel(
       const int any = s_any[par];
       if (tid == 0) Ract[(int64_t)sweep * (K - 1) + r] = any ? 1.0 : 0.0;
       if (any) {
-      for (int bb = ty; bb < half; bb += 32) {
-        const double cb = rc[bb], sb = rs[bb];
-        const int pb = rp[bb], qb = rq[bb];
-        for (int aa = tx; aa <= bb; aa += 16) {
-          const double ca = rc[aa], sa = rs[aa];
+#pragma unroll
+        for (int u = 0; u < MAXE; ++u) {
+          if (blk[u] == ~0u) continue;
+          const int aa = (int)(blk[u] & 0xffffu), bb = (int)(blk[u] >> 16);
+          const double2 ra = rcs[aa], rb = rcs[bb];
+          const double ca = ra.x, sa = ra.y, cb = rb.x, sb = rb.y;
           if (sa == 0.0 && sb == 0.0) continue;
-          const int pa = rp[aa], qa = rq[aa];
+          const int2 qa = rpq[aa];
+          const int pa = qa.x, qaa = qa.y;
           if (aa == bb) {                                // the pair's own 2x2 block
-            const int ipp = pk(pa, pa), iqq = pk(qa, qa), ipq = pk(pa, qa);
+            const int ipp = pk(pa, pa), iqq = pk(qaa, qaa), ipq = pk(pa, qaa);
             const double gpp = S[ipp], gqq = S[iqq], gpq = S[ipq];
             const double t = sa / ca;
             S[ipp] = gpp - t * gpq;
             S[iqq] = gqq + t * gpq;
             S[ipq] = 0.0;
           } else {
-            const int i11 = pk(pa, pb), i12 = pk(pa, qb), i21 = pk(qa, pb), i22 = pk(qa, qb);
+            const int2 qb = rpq[bb];
+            const int pb = qb.x, qbb = qb.y;
+            const int i11 = pk(pa, pb), i12 = pk(pa, qbb), i21 = pk(qaa, pb), i22 = pk(qaa, qbb);
             const double g11 = S[i11], g12 = S[i12], g21 = S[i21], g22 = S[i22];
             const double r11 = ca * g11 - sa * g21, r12 = ca * g12 - sa * g22;
             const double r21 = sa * g11 + ca * g21, r22 = sa * g12 + ca * g22;
@@ -262,7 +290,6 @@ __global__ void __launch_bounds__(512) jacobi_values_kernel(
             S[i22] = sb * r21 + cb * r22;
           }
         }
-      }
       }
       __syncthreads();                                   // (B)
     }
@@ -356,8 +383,8 @@ hipError_t jacobi_eig(int B, int32_t k, const int32_t *lock, double *G, double *
   if (B <= 0) return hipSuccess;
   const int64_t rs = jacobi_record_elems(k);
   // per problem: the packed matrix in LDS when its active width fits, else global scratch
-  jacobi_values_kernel<true><<<B, 512, 0, st>>>(k, lock, G, ldm, theta, ranks, rec, rs, nsweeps,
-                                                flag, scratch, stop);
+  jacobi_values_kernel<true><<<B, kJacobiThreads, 0, st>>>(k, lock, G, ldm, theta, ranks, rec, rs,
+                                                           nsweeps, flag, scratch, stop);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   jacobi_vectors_kernel<<<dim3((unsigned)ceil_div(k, 8), 1, B), 512, 0, st>>>(

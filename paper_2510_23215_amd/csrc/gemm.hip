@@ -15,6 +15,10 @@
 // to 4 successive MFMAs, which keeps every load a full 128-byte segment per column.
 #include "common.h"
 
+#include <algorithm>
+#include <type_traits>
+#include <utility>
+
 namespace scsf {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -124,15 +128,15 @@ __global__ void __launch_bounds__(256) gemm_tn_kernel(
 }
 
 // C_b(i, j) = sum over chunks (fixed order) of the partial tiles.
-__global__ void gemm_tn_reduce_kernel(int32_t nchunks, int32_t modeA, int32_t modeB, int32_t k,
-                                      const int32_t *__restrict__ lock, int32_t sym,
+__global__ void gemm_tn_reduce_kernel(int32_t nchunks, int32_t chunk, int32_t modeA, int32_t modeB,
+                                      int32_t k, const int32_t *__restrict__ lock, int32_t sym,
                                       const double *__restrict__ partial, int64_t pstride,
                                       double *__restrict__ C, int32_t ldc,
                                       const int32_t *__restrict__ gate, int32_t gate_mask,
                                       const int32_t *__restrict__ rows) {
   const int b = blockIdx.z;
   if (gate && !(gate[b] & gate_mask)) return;
-  const int32_t nch = rows ? (int32_t)ceil_div((int64_t)rows[b], kGramChunk) : nchunks;
+  const int32_t nch = rows ? (int32_t)ceil_div((int64_t)rows[b], chunk) : nchunks;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)ldc * ldc) return;
   int32_t a0, ka, b0, kb;
@@ -158,8 +162,217 @@ __global__ void gemm_tn_reduce_kernel(int32_t nchunks, int32_t modeA, int32_t mo
   C[(int64_t)b * ldc * ldc + i + (int64_t)j * ldc] = v;
 }
 
+// ---- slab form for blocks up to 128 columns
+// One workgroup of NW waves takes a row chunk of R rows of one problem and computes every 16 x
+// 16 output tile of that chunk (the upper ones of a Gram matrix, all of a general product).
+// Slabs of SR rows of all the problem's active columns are staged in LDS with coalesced 32-byte
+// loads (each element read from HBM once per product), double-buffered so the loads of the next
+// slab are in flight while the MFMAs run on this one.  Every wave has a compile-time list of
+// tiles (round-robin over the tile list), keeps the 16 x 4 fragments of the columns its tiles
+// need in registers for each 16-row group, and issues its MFMAs with the contraction index
+// outermost, so consecutive MFMAs write different accumulators.  Tiles beyond a problem's
+// active columns (locking) are skipped.  Partial tiles land in the same layout as the
+// 32 x 32-tile kernel's, and the same reduction sums them.
+template <class F, int... U>
+__device__ inline void static_for_impl(F &&f, std::integer_sequence<int, U...>) {
+  (f(std::integral_constant<int, U>{}), ...);
+}
+template <int N, class F> __device__ inline void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+template <int KT, bool SYM> struct SlabTiles {   // KT x KT tiles; SYM: those with i <= j
+  static constexpr int count() {
+    int c = 0;
+    for (int i = 0; i < KT; ++i)
+      for (int j = 0; j < KT; ++j) c += (!SYM || i <= j) ? 1 : 0;
+    return c;
+  }
+  static constexpr int at(int t) {               // i * 64 + j of tile t
+    int c = 0;
+    for (int i = 0; i < KT; ++i)
+      for (int j = 0; j < KT; ++j)
+        if (!SYM || i <= j) {
+          if (c == t) return i * 64 + j;
+          ++c;
+        }
+    return -1;
+  }
+  static constexpr uint32_t rows_of(int w, int nw) {   // bit i: tiles of wave w use A block i
+    uint32_t m = 0;
+    for (int t = w; t < count(); t += nw) m |= 1u << (at(t) / 64);
+    return m;
+  }
+  static constexpr uint32_t cols_of(int w, int nw) {   // bit j: tiles of wave w use B block j
+    uint32_t m = 0;
+    for (int t = w; t < count(); t += nw) m |= 1u << (at(t) % 64);
+    return m;
+  }
+};
+
+template <int KT, bool SYM, int NW, int SR, int W>
+__device__ inline void tn_slab_body(int64_t r_begin, int64_t r_end, int64_t ld, const double *Ab,
+                                    const double *Bb, int ka, int kb, double *ldsA, double *ldsB,
+                                    double *P, int ldc) {
+  using TL = SlabTiles<KT, SYM>;
+  constexpr int NT = TL::count();
+  constexpr int TPW = (NT - W + NW - 1) / NW;            // tiles of this wave
+  constexpr int CS = SR + 4;                             // padded LDS column stride
+  constexpr int NQ = KT * 16 * (SR / 4);                 // 4-row quads per slab and operand
+  constexpr int QPT = (NQ + NW * 64 - 1) / (NW * 64);
+  constexpr uint32_t AM = SYM ? (TL::rows_of(W, NW) | TL::cols_of(W, NW)) : TL::rows_of(W, NW);
+  constexpr uint32_t BM = SYM ? 0u : TL::cols_of(W, NW);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int r4 = lane >> 4, c16 = lane & 15;
+  v4d acc[TPW > 0 ? TPW : 1];
+  static_for<TPW>([&](auto u) { acc[u] = (v4d){0.0, 0.0, 0.0, 0.0}; });
+  v4d sa[QPT], sb[SYM ? 1 : QPT];
+  auto load1 = [&](const double *X, int kx, int u, int64_t s0) -> v4d {
+    const int q = tid + NW * 64 * u;
+    const int col = q / (SR / 4), rq = q % (SR / 4);
+    const int64_t r = s0 + 4 * rq;
+    v4d v = (v4d){0.0, 0.0, 0.0, 0.0};
+    if (q < NQ && col < kx && r < r_end) {
+      const double *src = X + (int64_t)col * ld + r;
+      if (r + 3 < r_end) {
+        v = *reinterpret_cast<const v4d *>(src);
+      } else {
+        for (int t = 0; t < 4; ++t) v[t] = (r + t < r_end) ? src[t] : 0.0;
+      }
+    }
+    return v;
+  };
+  auto load = [&](int64_t s0) {
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) sa[u] = load1(Ab, ka, u, s0);
+    if constexpr (!SYM) {
+#pragma unroll
+      for (int u = 0; u < QPT; ++u) sb[u] = load1(Bb, kb, u, s0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) {
+      const int q = tid + NW * 64 * u;
+      if (q < NQ) {
+        const int col = q / (SR / 4), rq = q % (SR / 4);
+        const int o = buf * KT * 16 * CS + col * CS + 4 * rq;
+        *reinterpret_cast<v4d *>(&ldsA[o]) = sa[u];
+        if constexpr (!SYM) *reinterpret_cast<v4d *>(&ldsB[o]) = sb[u];
+      }
+    }
+  };
+  load(r_begin);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t s0 = r_begin; s0 < r_end; s0 += SR) {
+    const bool more = s0 + SR < r_end;
+    if (more) load(s0 + SR);
+    const double *LA = ldsA + buf * KT * 16 * CS;
+    const double *LB = SYM ? LA : ldsB + buf * KT * 16 * CS;
+    for (int g = 0; g < SR / 16; ++g) {
+      v4d fa[KT], fb[SYM ? 1 : KT];
+      static_for<KT>([&](auto i) {
+        if constexpr ((AM >> decltype(i)::value) & 1u)
+          fa[i] = *reinterpret_cast<const v4d *>(&LA[(i * 16 + c16) * CS + g * 16 + 4 * r4]);
+      });
+      if constexpr (!SYM)
+        static_for<KT>([&](auto j) {
+          if constexpr ((BM >> decltype(j)::value) & 1u)
+            fb[j] = *reinterpret_cast<const v4d *>(&LB[(j * 16 + c16) * CS + g * 16 + 4 * r4]);
+        });
+      static_for<4>([&](auto t) {
+        constexpr int tt = decltype(t)::value;
+        static_for<TPW>([&](auto u) {
+          constexpr int ij = TL::at(W + NW * decltype(u)::value);
+          constexpr int i = ij / 64, j = ij % 64;
+          if constexpr (SYM) acc[u] = mfma16x16x4(fa[i][tt], fa[j][tt], acc[u]);
+          else acc[u] = mfma16x16x4(fa[i][tt], fb[j][tt], acc[u]);
+        });
+      });
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  static_for<TPW>([&](auto u) {
+    constexpr int ij = TL::at(W + NW * decltype(u)::value);
+    constexpr int i = ij / 64, j = ij % 64;
+    {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        P[(i * 16 + r4 + 4 * v) + (int64_t)(j * 16 + c16) * ldc] = acc[u][v];
+    }
+  });
+}
+
+// grid: x = row chunk of R rows, z = problem.
+// Gram form: two workgroups of 8 waves share a CU (73.7 KB of LDS each), so each wave gets at
+// most 128 registers (4 waves per SIMD); the general form runs one workgroup per CU.
+template <int KT, bool SYM, int NW, int SR>
+__global__ void __launch_bounds__(NW * 64, SYM ? 4 : 2) gemm_tn_slab_kernel(
+    int64_t n, int64_t ld, const double *__restrict__ A, int64_t bsA, int32_t modeA,
+    const double *__restrict__ Bm, int64_t bsB, int32_t modeB, int32_t k,
+    const int32_t *__restrict__ lock, int32_t R, double *__restrict__ partial, int64_t pstride,
+    int32_t ldc, const int32_t *__restrict__ gate, int32_t gate_mask,
+    const int32_t *__restrict__ rows) {
+  constexpr int CS = SR + 4;
+  __shared__ double ldsA[2 * KT * 16 * CS];
+  __shared__ double ldsB[SYM ? 1 : 2 * KT * 16 * CS];
+  const int b = blockIdx.z, s = blockIdx.x;
+  if (gate && !(gate[b] & gate_mask)) return;
+  const int64_t nb = rows ? (int64_t)rows[b] : n;
+  const int64_t r_begin = (int64_t)s * R;
+  if (r_begin >= nb) return;                           // chunk beyond it: never reduced
+  const int64_t r_end = min(nb, r_begin + R);
+  int32_t a0, ka, b0, kb;
+  col_range(modeA, k, lock, b, a0, ka);
+  col_range(modeB, k, lock, b, b0, kb);
+  if (ka <= 0 || kb <= 0) return;
+  const double *Ab = A + (int64_t)b * bsA + (int64_t)a0 * ld;
+  const double *Bb = Bm + (int64_t)b * bsB + (int64_t)b0 * ld;
+  double *P = partial + ((int64_t)b * gridDim.x + s) * pstride;
+  const int w = threadIdx.x >> 6;
+  // the body for this problem's active width (16-column blocks), so locked columns cost no
+  // MFMAs and no tile carries a per-tile test
+  const int kt = (int)ceil_div((int64_t)max(ka, kb), 16);
+  static_for<KT>([&](auto KM1) {
+    constexpr int KW = decltype(KM1)::value + 1;
+    if (kt == KW)
+      static_for<NW>([&](auto W) {
+        if (w == decltype(W)::value)
+          tn_slab_body<KW, SYM, NW, SR, decltype(W)::value>(r_begin, r_end, ld, Ab, Bb, ka, kb,
+                                                            ldsA, ldsB, P, ldc);
+      });
+  });
+}
+
+constexpr int kSlabChunkGram = 512;      // rows per workgroup, Gram form
+constexpr int kSlabChunkGeneral = 512;   // rows per workgroup, general form
+constexpr int kSlabNW = 8;               // waves per workgroup
+
+static void launch_slab(bool gram, int B, int64_t n, int64_t ld, const double *A, int64_t bsA,
+                        int32_t modeA, const double *Bm, int64_t bsB, int32_t modeB, int32_t k,
+                        const int32_t *lock, double *partial, int64_t pstride, int32_t ldc,
+                        const int32_t *gate, int32_t gate_mask, const int32_t *rows,
+                        hipStream_t st) {
+  if (gram) {
+    dim3 g((unsigned)ceil_div(n, kSlabChunkGram), 1, (unsigned)B);
+    gemm_tn_slab_kernel<8, true, kSlabNW, 32><<<g, kSlabNW * 64, 0, st>>>(
+        n, ld, A, bsA, modeA, Bm, bsB, modeB, k, lock, kSlabChunkGram, partial, pstride, ldc,
+        gate, gate_mask, rows);
+  } else {
+    dim3 g((unsigned)ceil_div(n, kSlabChunkGeneral), 1, (unsigned)B);
+    gemm_tn_slab_kernel<8, false, kSlabNW, 16><<<g, kSlabNW * 64, 0, st>>>(
+        n, ld, A, bsA, modeA, Bm, bsB, modeB, k, lock, kSlabChunkGeneral, partial, pstride, ldc,
+        gate, gate_mask, rows);
+  }
+}
+
 int64_t gemm_tn_partial_elems(int64_t n, int32_t ldc) {
-  return ceil_div(n, kGramChunk) * (int64_t)ldc * ldc;
+  // room for the most chunks any form uses (the general slab form's 512-row chunks)
+  return ceil_div(n, std::min(kGramChunk, kSlabChunkGeneral)) * (int64_t)ldc * ldc;
 }
 
 hipError_t gemm_tn(int B, int64_t n, int64_t ld, const double *A, int64_t bsA, int32_t modeA,
@@ -167,17 +380,29 @@ hipError_t gemm_tn(int B, int64_t n, int64_t ld, const double *A, int64_t bsA, i
                    bool symmetric, double *partial, int64_t partial_stride, double *C, int32_t ldc,
                    const int32_t *gate, int32_t gate_mask, hipStream_t st, const int32_t *rows) {
   if (B <= 0 || n <= 0) return hipSuccess;
-  const int32_t nchunks = (int32_t)ceil_div(n, kGramChunk);
-  const int T = ldc / 32;
   const int32_t sym = symmetric ? (A == Bm && modeA == modeB ? TN_GRAM : TN_SYMMETRISE)
                                 : TN_GENERAL;
-  dim3 g1((unsigned)(T * T), (unsigned)nchunks, (unsigned)B);
-  gemm_tn_kernel<<<g1, 256, 0, st>>>(n, ld, A, bsA, modeA, Bm, bsB, modeB, k, lock, sym, partial,
-                                     partial_stride / nchunks, ldc, gate, gate_mask, rows);
+  const int KT = (int)ceil_div(k, 16);
+  int32_t chunk, nchunks;
+  if (KT <= 8) {                         // slab form: up to 128 columns
+    const bool gram = sym == TN_GRAM;
+    chunk = gram ? kSlabChunkGram : kSlabChunkGeneral;
+    nchunks = (int32_t)ceil_div(n, chunk);
+    launch_slab(gram, B, n, ld, A, bsA, modeA, Bm, bsB, modeB, k, lock, partial,
+                partial_stride / nchunks, ldc, gate, gate_mask, rows, st);
+  } else {                               // 32 x 32 tiles per workgroup
+    chunk = kGramChunk;
+    nchunks = (int32_t)ceil_div(n, chunk);
+    const int T = ldc / 32;
+    dim3 g1((unsigned)(T * T), (unsigned)nchunks, (unsigned)B);
+    gemm_tn_kernel<<<g1, 256, 0, st>>>(n, ld, A, bsA, modeA, Bm, bsB, modeB, k, lock, sym,
+                                       partial, partial_stride / nchunks, ldc, gate, gate_mask,
+                                       rows);
+  }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   dim3 g2((unsigned)ceil_div((int64_t)ldc * ldc, 256), 1, (unsigned)B);
-  gemm_tn_reduce_kernel<<<g2, 256, 0, st>>>(nchunks, modeA, modeB, k, lock, sym, partial,
+  gemm_tn_reduce_kernel<<<g2, 256, 0, st>>>(nchunks, chunk, modeA, modeB, k, lock, sym, partial,
                                             partial_stride / nchunks, C, ldc, gate, gate_mask,
                                             rows);
   return hipGetLastError();

@@ -9,6 +9,8 @@
 
 namespace scsf {
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 constexpr int kLdsDoubles = 19456;                  // 152 KB of matrix storage in LDS
 __device__ inline int64_t upk(int i, int j) { return (int64_t)j * (j + 1) / 2 + i; }  // i <= j
 
@@ -120,13 +122,229 @@ __global__ void __launch_bounds__(512) chol_inv_kernel(
   if (tid == 0 && s_fail) atomicOr(&flag[b], s_fail);
 }
 
+// Blocked form of the same factorisation for active widths up to 128 (8 blocks of 16 columns),
+// one workgroup of 8 waves per problem.  The scaled matrix lives in a square LDS array A
+// (column stride kCbLS): R in the upper triangle, the strict upper triangle of T = R^-1 stored
+// transposed in the lower triangle, T's diagonal in tdg.  Padding columns up to 16 KW are the
+// identity, so every block operation is well defined.  Per block column J: wave 0 factors the
+// 16 x 16 diagonal block in registers (lane c holds column c), 16-column panels are solved by
+// forward substitution, one thread per column, and the trailing upper tiles are updated with
+// f64 MFMA; the inverse takes the diagonal blocks (one wave each) and then one block column of
+// T at a time, T(:J, J) = -T(:J, :J) R(:J, J) T_JJ, again on MFMA tiles.  About 3 barriers per
+// 16 columns instead of 3 per column.
+constexpr int kCbLS = 129;                 // odd column stride: fragment loads spread over banks
+constexpr int kCbMax = 128;
+
+__device__ inline double cb_get(const double *A, int r, int c) { return A[r + c * kCbLS]; }
+
+// C(16x16) = sum over kk of X(i, kk) Y(kk, j), the fragments from the accessors; acc in the
+// MFMA D layout (lane holds C[lane/16 + 4 v][lane % 16]).
+template <class FX, class FY>
+__device__ inline v4d cb_tile(v4d acc, int lane, FX fx, FY fy) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int kk = 4 * s + (lane >> 4), ij = lane & 15;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fx(ij, kk), fy(kk, ij), acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__global__ void __launch_bounds__(512) chol_inv_blocked_kernel(
+    int64_t n, int32_t k, const int32_t *__restrict__ lock, const double *__restrict__ G,
+    double *__restrict__ M, int32_t ldm, int32_t *__restrict__ flag,
+    const int32_t *__restrict__ gate, int32_t gate_mask) {
+  __shared__ double A[kCbMax * kCbLS];
+  __shared__ double dsc[kCbMax];
+  __shared__ double tdg[kCbMax];
+  __shared__ int s_fail;
+  __shared__ double s_shift;
+  const int b = blockIdx.x;
+  if (gate && !(gate[b] & gate_mask)) return;
+  const int32_t l = lock ? lock[b] : 0;
+  const int ka = k - l;
+  if (ka <= 0) return;
+  const int tid = threadIdx.x, NT = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  const int KW = (ka + 15) / 16, Kp = 16 * KW;
+  const double *Gb = G + (int64_t)b * ldm * ldm;
+  double *Mb = M + (int64_t)b * ldm * ldm;
+  if (tid == 0) { s_fail = 0; s_shift = 0.0; }
+  __syncthreads();
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const double sh = s_shift;
+    for (int j = tid; j < ka; j += NT) {
+      const double d = Gb[j + (int64_t)j * ldm] + sh;
+      if (!isfinite(d)) atomicOr(&s_fail, 2);
+      if (!(d > 0.0)) atomicOr(&s_fail, 1);
+      dsc[j] = (d > 0.0) ? sqrt(d) : 1.0;
+    }
+    __syncthreads();
+    // scaled upper triangle; identity on the padding
+    for (int e = tid; e < Kp * Kp; e += NT) {
+      const int i = e % Kp, c = e / Kp;
+      if (i > c) { A[i + c * kCbLS] = 0.0; continue; }
+      double v;
+      if (c < ka) v = (Gb[i + (int64_t)c * ldm] + (i == c ? sh : 0.0)) / (dsc[i] * dsc[c]);
+      else v = (i == c) ? 1.0 : 0.0;
+      A[i + c * kCbLS] = v;
+    }
+    __syncthreads();
+    for (int J = 0; J < KW; ++J) {
+      const int o = 16 * J;
+      // (a) the diagonal block by wave 0: lane c < 16 holds column c of the block
+      if (wave == 0) {
+        double a[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a[i] = (lane < 16 && i <= lane) ? A[(o + i) + (o + lane) * kCbLS] : 0.0;
+        int fail = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          double d = __shfl(a[j], j, 64);
+          if (!(d > 0.0)) { fail |= isfinite(d) ? 1 : 3; d = 1.0; }
+          const double r = sqrt(d);
+          if (lane == j) a[j] = r;
+          else if (lane > j) a[j] = a[j] / r;
+#pragma unroll
+          for (int i = j + 1; i < 16; ++i) {
+            const double rji = __shfl(a[j], i, 64);          // R(j, i) from lane i
+            if (lane >= i) a[i] -= rji * a[j];
+          }
+        }
+        if (lane < 16) {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) if (i <= lane) A[(o + i) + (o + lane) * kCbLS] = a[i];
+        }
+        if (lane == 0 && fail) atomicOr(&s_fail, fail);
+      }
+      __syncthreads();
+      // (b) the panel R(J, c) = R_JJ^-T A(J, c) for the columns right of the block
+      for (int c = o + 16 + tid; c < Kp; c += NT) {
+        double x[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          double v = A[(o + i) + c * kCbLS];
+#pragma unroll
+          for (int m = 0; m < i; ++m) v -= A[(o + m) + (o + i) * kCbLS] * x[m];
+          x[i] = v / A[(o + i) + (o + i) * kCbLS];
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) A[(o + i) + c * kCbLS] = x[i];
+      }
+      __syncthreads();
+      // (c) trailing update A(I, L) -= R(J, I)^T R(J, L), J < I <= L, one tile per wave turn
+      const int nr = KW - J - 1;
+      for (int t = wave; t < nr * (nr + 1) / 2; t += NT / 64) {
+        int L = 0;
+        while ((L + 1) * (L + 2) / 2 <= t) ++L;
+        const int I = t - L * (L + 1) / 2;
+        const int oi = 16 * (J + 1 + I), ol = 16 * (J + 1 + L);
+        v4d acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = A[(oi + (lane >> 4) + 4 * v) + (ol + (lane & 15)) * kCbLS];
+        acc = cb_tile(acc, lane,
+                      [&](int i, int kk) { return -A[(o + kk) + (oi + i) * kCbLS]; },
+                      [&](int kk, int j) { return A[(o + kk) + (ol + j) * kCbLS]; });
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[(oi + (lane >> 4) + 4 * v) + (ol + (lane & 15)) * kCbLS] = acc[v];
+      }
+      __syncthreads();
+    }
+    const int fnow = s_fail;
+    __syncthreads();                                     // every thread has read s_fail
+    if (attempt == 0 && (fnow & 1) && !(fnow & 2)) {
+      // shifted CholeskyQR: s = 11 (n k + k (k+1)) u ||X||_F^2 (Fukaya et al. 2020)
+      if (tid == 0) {
+        double tr = 0.0;
+        for (int j = 0; j < ka; ++j) tr += Gb[j + (int64_t)j * ldm];
+        s_shift = 11.0 * ((double)n * ka + (double)ka * (ka + 1)) * 1.1102230246251565e-16 * tr;
+        s_fail = 4;
+      }
+      __syncthreads();
+      continue;
+    }
+    break;
+  }
+  // T = R^-1.  Diagonal blocks first, wave J for block J: lane c < 16 solves column c of
+  // T_JJ by back substitution; T_JJ(i, c), i < c, goes to A(o + c, o + i), the diagonal to tdg.
+  if (wave < KW) {
+    const int o = 16 * wave;
+    double t[16];
+#pragma unroll
+    for (int i = 15; i >= 0; --i) {
+      double v = 0.0;
+      if (lane < 16 && i <= lane) {
+        if (i == lane) {
+          v = 1.0 / A[(o + i) + (o + i) * kCbLS];
+        } else {
+#pragma unroll
+          for (int m = i + 1; m < 16; ++m)
+            if (m <= lane) v -= A[(o + i) + (o + m) * kCbLS] * t[m];
+          v /= A[(o + i) + (o + i) * kCbLS];
+        }
+      }
+      t[i] = v;
+    }
+    if (lane < 16) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        if (i < lane) A[(o + lane) + (o + i) * kCbLS] = t[i];
+        else if (i == lane) tdg[o + i] = t[i];
+      }
+    }
+  }
+  __syncthreads();
+  // T(I, J), I < J, one block column at a time: W_M = R(M, J) T_JJ over R(M, J) (M < J), then
+  // T(I, J) = -sum_{M = I}^{J-1} T(I, M) W_M, stored transposed in the lower triangle.
+  auto Tel = [&](int r, int c) -> double {             // T(r, c), r <= c
+    return (r == c) ? tdg[r] : A[c + r * kCbLS];
+  };
+  for (int J = 1; J < KW; ++J) {
+    const int oj = 16 * J;
+    for (int Mi = wave; Mi < J; Mi += NT / 64) {
+      const int om = 16 * Mi;
+      v4d acc = (v4d){0.0, 0.0, 0.0, 0.0};
+      acc = cb_tile(acc, lane,
+                    [&](int i, int kk) { return A[(om + i) + (oj + kk) * kCbLS]; },
+                    [&](int kk, int j) { return kk <= j ? Tel(oj + kk, oj + j) : 0.0; });
+#pragma unroll
+      for (int v = 0; v < 4; ++v) A[(om + (lane >> 4) + 4 * v) + (oj + (lane & 15)) * kCbLS] = acc[v];
+    }
+    __syncthreads();
+    for (int I = wave; I < J; I += NT / 64) {
+      const int oi = 16 * I;
+      v4d acc = (v4d){0.0, 0.0, 0.0, 0.0};
+      for (int Mi = I; Mi < J; ++Mi) {
+        const int om = 16 * Mi;
+        acc = cb_tile(acc, lane,
+                      [&](int i, int kk) {
+                        const int r = oi + i, c = om + kk;
+                        return r <= c ? -Tel(r, c) : 0.0;
+                      },
+                      [&](int kk, int j) { return A[(om + kk) + (oj + j) * kCbLS]; });
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) A[(oj + (lane & 15)) + (oi + (lane >> 4) + 4 * v) * kCbLS] = acc[v];
+    }
+    __syncthreads();
+  }
+  // M = D^-1/2 T on the active block, zero below the diagonal
+  for (int e = tid; e < ka * ka; e += NT) {
+    const int r = e % ka, c = e / ka;
+    Mb[r + (int64_t)c * ldm] = (r <= c) ? Tel(r, c) / dsc[r] : 0.0;
+  }
+  if (tid == 0 && s_fail) atomicOr(&flag[b], s_fail);
+}
+
 hipError_t chol_inv(int B, int64_t n, int32_t k, const int32_t *lock, const double *G, double *M,
                     int32_t ldm, int32_t *flag, const int32_t *gate, int32_t gate_mask,
                     double *scratch, hipStream_t st) {
   if (B <= 0) return hipSuccess;
   // each workgroup keeps its packed R (inverted in place) in LDS when its active width fits
   // (ka(ka+1)/2 <= kLdsDoubles), so wide blocks move into LDS as their pairs lock
-  chol_inv_kernel<true><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask, scratch);
+  if (k <= kCbMax)
+    chol_inv_blocked_kernel<<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask);
+  else
+    chol_inv_kernel<true><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask,
+                                             scratch);
   return hipGetLastError();
 }
 

@@ -227,7 +227,7 @@ int scsf_profile_read(scsf_handle *h, scsf_profile *out_host, int reset);
 int scsf_workspace_bytes(const scsf_params *p, int64_t n, size_t *bytes);
 /* Device bytes scsf_solve_sequence (hinted = 0) or scsf_solve_sequence_hinted (hinted != 0)
  * needs for n_op operators of dimension n in `chains` chains, with the handle's current lane
- * count (scsf_set_lanes). */
+ * count (scsf_set_lanes), the up-front bounds of the n_op operators included. */
 int scsf_workspace_bytes_sequence(scsf_handle *h, const scsf_params *p, int64_t n, int32_t n_op,
                                   int32_t chains, int32_t hinted, size_t *bytes);
 /* Hand the handle `bytes` bytes of device memory at dev_ptr (256-byte aligned) as its only
@@ -372,9 +372,11 @@ int scsf_solve(scsf_handle *h, const scsf_operator *A, const scsf_params *prm,
 /* A whole dataset (Fig. 2 c-d): ops_host[n_op] (host array of operator descriptors, all of
  * the same kind and n) are solved in the order order_host[n_op] split into `chains`
  * contiguous chunks (App. D.6 chunking); the chunks run concurrently (lockstep batches on
- * up to scsf_set_lanes streams), each chain warm-starting every solve from its previous one.  evals: n_op x L (row i = operator
- * i), evecs: n_op x (n x L) (block i = operator i, ld n).  stats_host[n_op] may be NULL.
- * Returns SCSF_ENOTCONV if any solve did not converge. */
+ * up to scsf_set_lanes streams), each chain warm-starting every solve from its previous one.
+ * The spectral bound of every operator (the scsf_bounds run, its Lanczos start vector keyed by
+ * the operator's index) is computed up front in batched launches before the chains start.
+ * evals: n_op x L (row i = operator i), evecs: n_op x (n x L) (block i = operator i, ld n).
+ * stats_host[n_op] may be NULL.  Returns SCSF_ENOTCONV if any solve did not converge. */
 int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
                         const int32_t *order_host, int32_t chains, const scsf_params *prm,
                         double *evals, double *evecs, scsf_stats *stats_host);

@@ -190,9 +190,11 @@ hipError_t cheb_coeffs_explicit(int B, int32_t m, const double *win, double *coe
 // bounds[b*4 + {0,1,2,3}] = (gershgorin, theta_max + beta_s, theta_min, min(g, lanczos)).
 // work: B * 3 * nmax doubles.
 // square: bounds of A^2 instead (Gershgorin and Lanczos intervals of A, larger end squared).
+// key0: the Lanczos start vector of problem b is keyed by key0 + b (a slot, or an operator
+// index when all operators of a sequence are bounded up front).
 hipError_t bounds(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t steps,
                   uint64_t seed, const int32_t *need, double *work, double *out, hipStream_t st,
-                  bool square = false);
+                  bool square = false, uint32_t key0 = 0);
 // square-mode filter helpers (misc.hip)
 hipError_t axpby_active(int B, int64_t nmax, int64_t ld, int64_t bs, int32_t k,
                         const int32_t *lock, const double *X, const double *Z, const double *coef,

@@ -232,7 +232,7 @@ __device__ inline int sturm_count(const double *a, const double *bb, int s, doub
 template <int KIND>
 __global__ void __launch_bounds__(1024) bounds_kernel(
     const OpDev *__restrict__ ops, int32_t steps, uint64_t seed, const int32_t *__restrict__ need,
-    double *__restrict__ work, int64_t nmax, double *__restrict__ out, int square) {
+    double *__restrict__ work, int64_t nmax, double *__restrict__ out, int square, uint32_t key0) {
   __shared__ double sh[16];
   __shared__ double al[128], be[128], thx[2];
   __shared__ int s_eff;
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(1024) bounds_kernel(
   const int tid = threadIdx.x, NT = blockDim.x;
   double nrm = 0.0;
   for (int64_t p = tid; p < n; p += NT) {
-    const double2 g = gauss2(seed, (uint64_t)p, (uint32_t)b, 0x4C414E43u);
+    const double2 g = gauss2(seed, (uint64_t)p, key0 + (uint32_t)b, 0x4C414E43u);
     v1[p] = g.x;
     v0[p] = 0.0;
     nrm += g.x * g.x;
@@ -319,21 +319,21 @@ __global__ void __launch_bounds__(1024) bounds_kernel(
 
 hipError_t bounds(const OpDev *ops, int B, int32_t kind, int64_t nmax, int32_t steps,
                   uint64_t seed, const int32_t *need, double *work, double *out, hipStream_t st,
-                  bool square) {
+                  bool square, uint32_t key0) {
   if (B <= 0) return hipSuccess;
   if (steps < 1 || steps > 128) return hipErrorInvalidValue;
   if (kind == SCSF_STENCIL5)
     bounds_kernel<SCSF_STENCIL5><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out,
-                                                 square ? 1 : 0);
+                                                 square ? 1 : 0, key0);
   else if (kind == SCSF_STENCIL9)
     bounds_kernel<SCSF_STENCIL9><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out,
-                                                 square ? 1 : 0);
+                                                 square ? 1 : 0, key0);
   else if (kind == SCSF_PLATE)
     bounds_kernel<SCSF_PLATE><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out,
-                                                 square ? 1 : 0);
+                                                 square ? 1 : 0, key0);
   else
     bounds_kernel<SCSF_CSR><<<B, 1024, 0, st>>>(ops, steps, seed, need, work, nmax, out,
-                                                 square ? 1 : 0);
+                                                 square ? 1 : 0, key0);
   return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ enum BufId {
   B_X, B_Y1, B_Y2, B_W, B_G, B_M, B_PART, B_THETA, B_RES, B_INT, B_BND, B_COEF, B_UNIT, B_CHOL,
   B_JAC, B_LZ, B_OPS, B_WIN, B_SORTF, B_SORTD, B_SORTO, B_REC, B_RANK, B_E32, B_R32, B_SRC,
   B_GAIN, B_WINB, B_HINT, B_MDEG, B_NETF, B_NETH, B_NETD, B_ROWS, B_EIG, B_CDEG, B_SQT, B_SQP, B_COEF2,
-  B_TEV, B_TVV, B_NETL, B_COUNT
+  B_TEV, B_TVV, B_NETL, B_PREOPS, B_PRELZ, B_PREBND, B_COUNT
 };
 
 struct DevBuf {
@@ -546,6 +546,23 @@ struct Engine {
   }
 
   // upper bounds of the problems with h_need[b] set
+  // the same from a table computed up front for every operator of the call (host, 4 doubles
+  // per operator, indexed by opid[b]): only the rows of the problems with h_need[b] set move
+  int set_bounds(const double *table, const int32_t *opid) {
+    HIPCHK(hipEventRecord(pev[5], st));
+    for (int b = 0; b < B; ++b) {
+      if (!h_need[b]) continue;
+      std::copy(table + (size_t)opid[b] * 4, table + (size_t)opid[b] * 4 + 4, h_bnd + (size_t)b * 4);
+      HIPCHK(hipMemcpyAsync(bnd + (size_t)b * 4, h_bnd + (size_t)b * 4, 32, hipMemcpyHostToDevice,
+                            st));
+    }
+    HIPCHK(hipEventRecord(pev[6], st));
+    HIPCHK(hipEventSynchronize(pev[6]));
+    std::vector<char> who(B);
+    for (int b = 0; b < B; ++b) who[b] = h_need[b] != 0;
+    charge(PH_BOUND, span(5, 6), who);
+    return SCSF_OK;
+  }
   int compute_bounds() {
     HIPCHK(hipEventRecord(pev[5], st));
     HIPCHK(bounds(ops, B, kind, n, lz_steps, seed ^ 0x5DEECE66DULL, need, lz, bnd, st, mag));
@@ -1050,6 +1067,43 @@ bool on_square_grid(const OpDev &o) {
          (int64_t)o.N * o.N == o.n;
 }
 
+// Spectral bounds (Gershgorin + Lanczos, the engine's window bound) of every operator of a
+// chained solve, computed up front in batched launches (one workgroup per operator) instead of
+// one problem at a time when a lane loads it.  The Lanczos start vector is keyed by the
+// operator's index, so an operator's bound does not depend on the schedule.  Returns the
+// table on the host (4 doubles per operator, operator index order).
+constexpr int kPreBoundBatch = 256;
+size_t prebound_bytes(int32_t n_op, int64_t nmax) {
+  auto a = [](size_t b) { return (std::max<size_t>(b, 256) + 255) / 256 * 256; };
+  const size_t batch = std::min<int32_t>(n_op, kPreBoundBatch);
+  return a((size_t)n_op * sizeof(OpDev)) + a(batch * 3 * (size_t)nmax * 8) +
+         a((size_t)n_op * 4 * 8);
+}
+int prebound(Workspace *w, const scsf_operator *ops_host, int32_t n_op, int32_t steps,
+             uint64_t seed, std::vector<double> &table) {
+  int64_t nmax = 0;
+  for (int i = 0; i < n_op; ++i) nmax = std::max(nmax, ops_host[i].n);
+  const int batch = std::min<int32_t>(n_op, kPreBoundBatch);
+  OpDev *ops_d = nullptr;
+  double *work = nullptr, *tab = nullptr;
+  STCHK(grow(w, B_PREOPS, (size_t)n_op, &ops_d));
+  STCHK(grow(w, B_PRELZ, (size_t)batch * 3 * nmax, &work));
+  STCHK(grow(w, B_PREBND, (size_t)n_op * 4, &tab));
+  std::vector<OpDev> h(n_op);
+  for (int i = 0; i < n_op; ++i) h[i] = to_dev(ops_host[i]);
+  HIPCHK(hipMemcpyAsync(ops_d, h.data(), (size_t)n_op * sizeof(OpDev), hipMemcpyHostToDevice,
+                        w->stream));
+  for (int i0 = 0; i0 < n_op; i0 += batch)
+    HIPCHK(bounds(ops_d + i0, std::min(batch, n_op - i0), ops_host[0].kind, nmax, steps,
+                  seed ^ 0x5DEECE66DULL, nullptr, work, tab + (size_t)i0 * 4, w->stream, false,
+                  (uint32_t)i0));
+  table.resize((size_t)n_op * 4);
+  HIPCHK(hipMemcpyAsync(table.data(), tab, (size_t)n_op * 4 * 8, hipMemcpyDeviceToHost,
+                        w->stream));
+  HIPCHK(hipStreamSynchronize(w->stream));
+  return SCSF_OK;
+}
+
 // Operators of a smallest-magnitude solve whose lower-end result could not be certified; the
 // lanes add to it concurrently, and the caller solves them again with the squared filter.
 struct Fallback {
@@ -1073,7 +1127,7 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
                double *evals, double *evecs, double *ritz, scsf_stats *stats_host,
                const Group *grp = nullptr, bool graphs = false, int cpt = 4,
                int eig = SCSF_EIG_JACOBI, Fallback *fallback = nullptr,
-               bool square_forced = false, int fuse = 0) {
+               bool square_forced = false, int fuse = 0, const double *bnd_table = nullptr) {
   const int chains = (int)cb.size();
   if (chains == 0) return SCSF_OK;
   const int64_t n = grp ? grp->nmax : ops_host[0].n;
@@ -1125,7 +1179,11 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
   STCHK(e.upload_hints(all_slots));
   STCHK(e.upload_ops());
   STCHK(e.upload_state());
-  STCHK(e.compute_bounds());
+  // operator index of each slot (bounds table rows)
+  std::vector<int32_t> opid(chains);
+  for (int b = 0; b < chains; ++b) opid[b] = order_host[pos[b]];
+  if (bnd_table) STCHK(e.set_bounds(bnd_table, opid.data()));
+  else STCHK(e.compute_bounds());
   {
     std::vector<int> all(chains);
     std::iota(all.begin(), all.end(), 0);
@@ -1237,7 +1295,9 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
         HIPCHK(copy_block((int64_t)r[2] * r[2], k, e.Y1 + o, e.ld, e.X + o, e.ld, false, e.st));
       }
       STCHK(e.upload_state());
-      STCHK(e.compute_bounds());
+      for (int b : reloaded) opid[b] = order_host[pos[b]];
+      if (bnd_table) STCHK(e.set_bounds(bnd_table, opid.data()));
+      else STCHK(e.compute_bounds());
       if (!recold.empty()) STCHK(e.cold_start(recold));
       for (int b = 0; b < chains; ++b) e.h_need[b] = 0;
       STCHK(e.upload_state());
@@ -1480,7 +1540,7 @@ int scsf_workspace_bytes_sequence(scsf_handle *h, const scsf_params *p, int64_t 
   STCHK(check_params(p, n));
   const int c = std::min(chains, n_op);
   const int lanes = std::min(h->lanes, c);
-  size_t total = 0;
+  size_t total = prebound_bytes(n_op, n);       // the up-front bounds (handle's own stream)
   for (int g = 0; g < lanes; ++g)
     total += engine_bytes((c - g + lanes - 1) / lanes, n, p, hinted != 0);
   *bytes = total;
@@ -1969,6 +2029,17 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
   const bool dyn = prm->schedule == SCSF_SCHED_DYNAMIC;
   std::atomic<int> next(chains);                // dynamic: chain c starts at order position c
   Fallback fb;                                  // smallest magnitude: uncertified lower ends
+  // every operator's bound in batched launches on the handle's stream, after the caller's
+  // work; prebound returns once they are done, before any lane starts
+  std::vector<double> btab;
+  {
+    const int32_t lzs = prm->lanczos_steps > 0 ? prm->lanczos_steps : 20;
+    const int rc = prebound(h->ws[0], ops_host, n_op, lzs, prm->seed, btab);
+    if (rc != SCSF_OK) {
+      (void)hipEventDestroy(ready);
+      return rc;
+    }
+  }
   auto lane_fn = [&](int g) {
     if (hipSetDevice(h->device) != hipSuccess) { status[g] = SCSF_EHIP; return; }
     std::vector<int> cb, ce;
@@ -1979,7 +2050,7 @@ int scsf_solve_sequence_hinted(scsf_handle *h, const scsf_operator *ops_host, in
     status[g] = run_chains(h->ws[g + 1], ops_host, order_host, n_op, cb, ce,
                            dyn ? &next : nullptr, prm, hints_host, evals, evecs, ritz, stats_host,
                            nullptr, h->graphs, tuned_cpt(h, n, prm->k), h->eig, &fb, false,
-                           h->fuse);
+                           h->fuse, btab.data());
   };
   std::vector<std::thread> threads;
   for (int g = 1; g < lanes; ++g) threads.emplace_back(lane_fn, g);

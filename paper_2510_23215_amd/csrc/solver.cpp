@@ -400,11 +400,14 @@ struct Engine {
       pp += (bytes + 63) / 64 * 64;
       return r;
     };
-    h_lock = (int32_t *)take(B * 4);
-    h_nconv = (int32_t *)take(B * 4);
-    h_done = (int32_t *)take(B * 4);
-    h_flag = (int32_t *)take(B * 4);
-    h_need = (int32_t *)take(B * 4);
+    // the five int arrays in the device layout (lock | nconv | done | flag | need), so the
+    // per-iteration readback and the state upload are one or two copies
+    int32_t *h_ints = (int32_t *)take((size_t)B * 5 * 4);
+    h_lock = h_ints;
+    h_nconv = h_ints + B;
+    h_done = h_ints + 2 * B;
+    h_flag = h_ints + 3 * B;
+    h_need = h_ints + 4 * B;
     h_perm = (int32_t *)take((size_t)B * k * 4);
     h_theta = (double *)take((size_t)B * k * 8);
     h_res = (double *)take((size_t)B * k * 8);
@@ -477,9 +480,7 @@ struct Engine {
   // Uploads of the pinned mirrors complete before returning: the host edits the mirrors
   // again right after, and an asynchronous copy would read the edited values.
   int upload_state() {
-    HIPCHK(hipMemcpyAsync(lock, h_lock, (size_t)B * 4, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(nconv, h_nconv, (size_t)B * 4, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(done, h_done, (size_t)B * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(lock, h_lock, (size_t)B * 3 * 4, hipMemcpyHostToDevice, st));  // lock, nconv, done
     HIPCHK(hipMemcpyAsync(need, h_need, (size_t)B * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
     return SCSF_OK;
@@ -492,10 +493,7 @@ struct Engine {
     return SCSF_OK;
   }
   int download_state() {
-    HIPCHK(hipMemcpyAsync(h_lock, lock, (size_t)B * 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_nconv, nconv, (size_t)B * 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_done, done, (size_t)B * 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_flag, flag, (size_t)B * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_lock, lock, (size_t)B * 4 * 4, hipMemcpyDeviceToHost, st));  // lock..flag
     if (adaptive) {
       HIPCHK(hipMemcpyAsync(h_mdeg, mdeg, (size_t)B * 4, hipMemcpyDeviceToHost, st));
       HIPCHK(hipMemcpyAsync(h_cdeg, cdeg, (size_t)B * k * 4, hipMemcpyDeviceToHost, st));

@@ -164,3 +164,15 @@ def test_learned_window_gains_over_plain(h):
     np.testing.assert_allclose(ev_l.cpu().numpy(), ev_p.cpu().numpy(), rtol=1e-9)
     assert all(s["status"] == 0 for s in st_l)
     assert it_l < it_p and t_learn < t_plain
+    # against the best fixed degree: on this family the labels put the degree at the table's
+    # top for nearly every operator, so the plain method at the mean predicted degree is the
+    # fair baseline.  The predicted window adds nothing beyond the degree (the learned solves
+    # take about as many outer iterations); the check is that it costs nothing either.
+    d_best = int(round(float(np.mean([s["degree"] for s in st_l]))))
+    prm_best = scsf.make_params(cfg.L, cfg.k, d_best, cfg.tol, seed=1,
+                                schedule=scsf.SCSF_SCHED_DYNAMIC)
+    t_best, ev_b, st_b = _solve(h, tsub, np.arange(len(tsub)), prm_best)
+    it_b = sum(s["iterations"] for s in st_b)
+    say("best fixed degree", d_best, t_best, it_b)
+    np.testing.assert_allclose(ev_l.cpu().numpy(), ev_b.cpu().numpy(), rtol=1e-9)
+    assert it_l <= 1.15 * it_b

@@ -96,7 +96,7 @@ typedef struct scsf_operator {
 typedef struct scsf_params {
   int32_t L;             /* wanted eigenpairs, 0 < L < k */
   int32_t k;             /* block width (L + guard vectors), k <= n, k <= 256 */
-  int32_t degree;        /* Chebyshev degree m, 1..64 */
+  int32_t degree;        /* Chebyshev degree m, 1..128 (1..64 with SCSF_MIXED) */
   int32_t max_iter;      /* outer iterations before SCSF_ENOTCONV (0 -> 5000) */
   int32_t lanczos_steps; /* steps of the upper-bound Lanczos run (0 -> 20) */
   int32_t precision;     /* scsf_precision */
@@ -262,7 +262,7 @@ int scsf_filter(scsf_handle *h, const scsf_operator *A, const double *X, int64_t
  * X, Y: device; block b at X + b*bsx (Y + b*bsy), n_b rows, ncols columns, column-major with
  * leading dimension ldx (ldy) >= max n_b, bsx >= ldx*ncols, bsy >= ldy*ncols.  The two block
  * ranges must not overlap; X is not modified.  win_host: host, (lambda_b, c_b, e_b) per block,
- * e_b > 0, lambda_b != c_b.  ncols <= 256, degree 1..64.  The steps use the handle's filter
+ * e_b > 0, lambda_b != c_b.  ncols <= 256, degree 1..128.  The steps use the handle's filter
  * tile (scsf_set_tile, scsf_autotune); while profiling is on (scsf_profile_enable) every step
  * launch is timed with a pair of HIP events on the caller's stream and counted with its
  * algorithmic bytes.  Synchronises the stream.  SCSF_EINVAL on invalid arguments. */
@@ -383,7 +383,8 @@ int scsf_solve_sequence(scsf_handle *h, const scsf_operator *ops_host, int32_t n
 
 /* The learned-window form: as scsf_solve_sequence, with per-operator hints_host[n_op*3] =
  * (predicted lambda_1, predicted lambda_{L+1}, predicted degree) in operator index order.
- * A positive degree replaces prm->degree for that operator (1..64; within a lockstep batch
+ * A positive degree replaces prm->degree for that operator (1..128, clamped to 64 with
+ * SCSF_MIXED; within a lockstep batch
  * degrees are raised by at most 2 to a common residue mod 3).  The predicted window replaces
  * the Ritz-value window of the operator's first outer iteration if the Lanczos bounds accept it:
  * lambda_1 <= theta_min(T_s) and lambda_1 < lambda_{L+1} < beta (stats.hint reports 2 / 3);
@@ -473,7 +474,7 @@ int scsf_solve_batched_hinted(scsf_handle *h, const scsf_operator *ops_host, int
  * channels (Re, Im).  Layers: conv 3x3 6->16 stride 1 + ReLU, conv 3x3 16->32 stride 2 + ReLU,
  * dense 2048->64 + ReLU, dense 64->3 (zero padding 1).  Parameters: one flat FP32 device array
  * W1[16,6,3,3] b1[16] W2[32,16,3,3] b2[32] W3[64,2048] b3[64] W4[3,64] b4[3].
- * Outputs: (log lambda_1, log lambda_{L+1}, degree / 64).
+ * Outputs: (log lambda_1, log lambda_{L+1}, degree / 128).
  * ------------------------------------------------------------------------------------- */
 
 /* Number of FP32 parameters. */
@@ -495,11 +496,11 @@ int scsf_window_train(scsf_handle *h, float *params, const float *x, const float
                       int32_t n, int32_t epochs, float lr, double *loss_history_host);
 /* Training targets from solved operators: ritz (n x k ascending), beta[n] (the upper bounds
  * used) -> target[n*3] = (log lambda_1, log lambda_{L+1}, mstar / 64) with
- * mstar = clamp(ceil(acosh(1e4) / acosh|t(lambda_L)|), 8, 64) over the damped [lambda_{L+1}, beta]. */
+ * mstar = clamp(ceil(acosh(1e4) / acosh|t(lambda_L)|), 8, 128) over the damped [lambda_{L+1}, beta]. */
 int scsf_window_labels(scsf_handle *h, const double *ritz, int32_t n, int32_t k, int32_t L,
                        const double *beta, float *target);
-/* hints[n*3] (device, for scsf_solve_sequence_hinted) = (exp y0, exp y1, round(64 y2) clamped
- * to [8, 64]). */
+/* hints[n*3] (device, for scsf_solve_sequence_hinted) = (exp y0, exp y1, round(128 y2) clamped
+ * to [8, 128]). */
 int scsf_window_hints(scsf_handle *h, const float *out, int32_t n, double *hints);
 
 #ifdef __cplusplus

@@ -126,7 +126,7 @@ def window_features(feats):
     return x
 
 
-def degree_label(lam_L, lam_L1, beta, gain=1e4, lo=8, hi=64):
+def degree_label(lam_L, lam_L1, beta, gain=1e4, lo=8, hi=128):
     """Smallest degree m with C_m(|t(lambda_L)|) >= gain over the damped interval
     [lambda_{L+1}, beta], clamped to [lo, hi]."""
     c, e = 0.5 * (lam_L1 + beta), 0.5 * (beta - lam_L1)

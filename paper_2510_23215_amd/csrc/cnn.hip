@@ -323,8 +323,8 @@ hipError_t cnn_input(const double *feats, int n, int C, int p0, float *x, hipStr
   return hipGetLastError();
 }
 
-// targets (log lambda_1, log lambda_{L+1}, m* / 64) from the ascending Ritz values of a solve,
-// m* = clamp(ceil(acosh(1e4) / acosh|t(lambda_L)|), 8, 64) over the damped [lambda_{L+1}, beta]
+// targets (log lambda_1, log lambda_{L+1}, m* / 128) from the ascending Ritz values of a solve,
+// m* = clamp(ceil(acosh(1e4) / acosh|t(lambda_L)|), 8, 128) over the damped [lambda_{L+1}, beta]
 __global__ void labels_kernel(const double *__restrict__ ritz, int n, int k, int L,
                               const double *__restrict__ beta, float *__restrict__ t) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -333,11 +333,11 @@ __global__ void labels_kernel(const double *__restrict__ ritz, int n, int k, int
   const double l1 = r[0], lL = r[L - 1], lL1 = r[L], bt = beta[s];
   const double c = 0.5 * (lL1 + bt), e = 0.5 * (bt - lL1);
   const double tt = fabs((lL - c) / e);
-  double m = 64.0;
-  if (tt > 1.0) m = fmin(64.0, fmax(8.0, ceil(acosh(1e4) / acosh(tt))));
+  double m = 128.0;
+  if (tt > 1.0) m = fmin(128.0, fmax(8.0, ceil(acosh(1e4) / acosh(tt))));
   t[3 * s + 0] = (float)log(l1);
   t[3 * s + 1] = (float)log(lL1);
-  t[3 * s + 2] = (float)(m / 64.0);
+  t[3 * s + 2] = (float)(m / 128.0);
 }
 
 hipError_t cnn_labels(const double *ritz, int n, int k, int L, const double *beta, float *t,
@@ -347,13 +347,13 @@ hipError_t cnn_labels(const double *ritz, int n, int k, int L, const double *bet
 }
 
 // hints (lambda_1, lambda_{L+1}, degree) from the network output; the degree is kept in the
-// range of the training labels, [8, 64]
+// range of the training labels, [8, 128]
 __global__ void hints_kernel(const float *__restrict__ y, int n, double *__restrict__ hints) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   hints[3 * s + 0] = exp((double)y[3 * s + 0]);
   hints[3 * s + 1] = exp((double)y[3 * s + 1]);
-  hints[3 * s + 2] = fmin(64.0, fmax(8.0, rint(64.0 * (double)y[3 * s + 2])));  // label range
+  hints[3 * s + 2] = fmin(128.0, fmax(8.0, rint(128.0 * (double)y[3 * s + 2])));  // label range
 }
 
 hipError_t cnn_hints(const float *y, int n, double *hints, hipStream_t st) {

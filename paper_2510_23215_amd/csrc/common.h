@@ -10,6 +10,10 @@ namespace scsf {
 
 // Largest block width the small dense kernels handle (Gram, Cholesky, Jacobi).
 constexpr int kMaxK = 256;
+constexpr int kMaxDegree = 128;   // largest Chebyshev degree of one filter call
+// The FP32 residual-form filter: its correction block left the FP32 range at degree 128 on
+// the anisotropic workload (non-finite Ritz values), so mixed precision stops at 64.
+constexpr int kMaxDegreeMixed = 64;
 // Row chunk processed by one workgroup of the tall-skinny Gram kernel.
 constexpr int kGramChunk = 2048;
 

@@ -302,7 +302,7 @@ struct Engine {
     adaptive = adaptive_ && !var_deg_ && !mixed_;
     mag = mag_ && !mixed_ && !adaptive;
     m_base = m_;
-    if (var_deg) m_ = 64;                  // coefficient tables sized for the largest degree
+    if (var_deg) m_ = kMaxDegree;          // coefficient tables sized for the largest degree
     if (adaptive) m_ = std::min(64, std::max(m_, 2 * m_));
     h = hh;
     st = hh->stream;
@@ -1032,7 +1032,8 @@ int solve_status(int32_t flagv, bool converged) {
 int check_params(const scsf_params *p, int64_t n) {
   if (!p) return SCSF_EINVAL;
   if (p->L <= 0 || p->k <= p->L || p->k > kMaxK || p->k > n) return SCSF_EINVAL;
-  if (p->degree < 1 || p->degree > 64) return SCSF_EINVAL;
+  if (p->degree < 1 || p->degree > kMaxDegree) return SCSF_EINVAL;
+  if (p->precision == SCSF_MIXED && p->degree > kMaxDegreeMixed) return SCSF_EINVAL;
   if (!(p->tol > 0.0)) return SCSF_EINVAL;
   if (p->lanczos_steps < 0 || p->lanczos_steps > 128) return SCSF_EINVAL;
   if (p->precision != SCSF_FP64 && p->precision != SCSF_MIXED) return SCSF_EINVAL;
@@ -1159,7 +1160,8 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
     e.h_hint[3 * b + 2] = 0.0;
     if (hints_host) {
       const double *hh = hints_host + (size_t)order_host[at] * 3;
-      if (hh[2] >= 1.0) d = std::min(64, std::max(1, (int)std::lround(hh[2])));
+      const int dmax = prm->precision == SCSF_MIXED ? kMaxDegreeMixed : kMaxDegree;
+      if (hh[2] >= 1.0) d = std::min(dmax, std::max(1, (int)std::lround(hh[2])));
       e.h_hint[3 * b + 0] = hh[0];
       e.h_hint[3 * b + 1] = hh[1];
       e.h_hint[3 * b + 2] = (hh[0] > 0.0 && hh[1] > 0.0) ? 1.0 : 0.0;
@@ -1607,7 +1609,7 @@ int scsf_filter(scsf_handle *h, const scsf_operator *A, const double *X, int64_t
 
   STCHK(check_op(A));
   if (!X || !Y || ncols < 0 || ncols > kMaxK || ldx < A->n || ldy < A->n) return SCSF_EINVAL;
-  if (degree < 1 || degree > 64 || !(e > 0.0) || lambda == c) return SCSF_EINVAL;
+  if (degree < 1 || degree > kMaxDegree || !(e > 0.0) || lambda == c) return SCSF_EINVAL;
   if (ncols == 0) return SCSF_OK;
   Engine en;
   STCHK(en.setup(w0, 1, A->n, ncols, 0, degree, A->kind, 1.0, 0, 20));
@@ -1636,7 +1638,7 @@ int scsf_filter_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t B
                         const double *win_host, double *Y, int64_t ldy, int64_t bsy) {
   CallScope cs_(h);
   if (!h || !ops_host || B <= 0 || !X || !Y || !win_host) return SCSF_EINVAL;
-  if (ncols < 0 || ncols > kMaxK || degree < 1 || degree > 64) return SCSF_EINVAL;
+  if (ncols < 0 || ncols > kMaxK || degree < 1 || degree > kMaxDegree) return SCSF_EINVAL;
   int64_t nmax = 0;
   for (int b = 0; b < B; ++b) {
     STCHK(check_op(&ops_host[b]));

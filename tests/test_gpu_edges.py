@@ -103,9 +103,10 @@ def test_empty_and_out_of_range_inputs(h):
                                  scsf._ptr(d), None)
     assert st == scsf.SCSF_EINVAL                                   # no operators
     op = scsf.DeviceOperator(si.divk_operator(8, 4, 1))
-    for bad in (scsf.make_params(8, 257, 20, 1e-8), scsf.make_params(8, 12, 65, 1e-8),
+    for bad in (scsf.make_params(8, 257, 20, 1e-8), scsf.make_params(8, 12, 129, 1e-8),
                 scsf.make_params(8, 12, 0, 1e-8), scsf.make_params(8, 12, 20, 0.0),
-                scsf.make_params(0, 12, 20, 1e-8), scsf.make_params(8, 65, 20, 1e-8)):
+                scsf.make_params(0, 12, 20, 1e-8), scsf.make_params(8, 65, 20, 1e-8),
+                scsf.make_params(8, 12, 65, 1e-8, precision=scsf.SCSF_MIXED)):
         with pytest.raises(scsf.ScsfError) as e:                   # k > n = 64 in the last
             scsf.scsf_solve(h, op, bad)
         assert e.value.status == scsf.SCSF_EINVAL

@@ -81,11 +81,11 @@ def test_input_labels_hints(h):
     for i in range(5):
         assert t[i, 0] == pytest.approx(np.log(ritz[i, 0]), rel=1e-6)
         assert t[i, 1] == pytest.approx(np.log(ritz[i, 8]), rel=1e-6)
-        assert t[i, 2] * 64 == pytest.approx(cnn.degree_label(ritz[i, 7], ritz[i, 8], beta[i]))
+        assert t[i, 2] * 128 == pytest.approx(cnn.degree_label(ritz[i, 7], ritz[i, 8], beta[i]))
     out = torch.tensor([[3.0, 7.0, 0.5], [2.0, 5.0, 2.0]], device="cuda")
     hints = scsf.scsf_window_hints(h, out).cpu().numpy()
-    np.testing.assert_allclose(hints[0], [np.exp(3.0), np.exp(7.0), 32.0], rtol=1e-12)
-    assert hints[1, 2] == 64.0
+    np.testing.assert_allclose(hints[0], [np.exp(3.0), np.exp(7.0), 64.0], rtol=1e-12)
+    assert hints[1, 2] == 128.0
     out2 = torch.tensor([[3.0, 7.0, 0.01]], device="cuda")
     assert scsf.scsf_window_hints(h, out2).cpu().numpy()[0, 2] == 8.0
 
@@ -107,20 +107,20 @@ def _solve(h, dops, order, prm, hints=None, ritz=None):
 
 
 def test_degree_hints_at_table_size_after_other_degrees(h):
-    """Degree hints that all equal the largest degree (64) after a call with other degrees:
+    """Degree hints that all equal the largest degree (128) after a call with other degrees:
     the per-problem degrees on the device must be the requested ones, so the hinted solve
-    repeats the plain degree-64 solve exactly (same iterations, same eigenvalues)."""
-    say("degree hints at 64 after 20")
+    repeats the plain degree-128 solve exactly (same iterations, same eigenvalues)."""
+    say("degree hints at 128 after 20")
     cfg = si.CONFIGS[5]
     dops = [scsf.DeviceOperator(o) for o in si.operators(cfg, 8)]
     order = np.arange(len(dops))
     n = len(dops)
     prm20 = scsf.make_params(cfg.L, cfg.k, 20, cfg.tol, seed=1, schedule=scsf.SCSF_SCHED_DYNAMIC)
-    prm64 = scsf.make_params(cfg.L, cfg.k, 64, cfg.tol, seed=1, schedule=scsf.SCSF_SCHED_DYNAMIC)
+    prm64 = scsf.make_params(cfg.L, cfg.k, 128, cfg.tol, seed=1, schedule=scsf.SCSF_SCHED_DYNAMIC)
     _, ev20, st20 = _solve(h, dops, order, prm20, hints=np.tile([0.0, 0.0, 20.0], (n, 1)))
     _, ev_p, st_p = _solve(h, dops, order, prm64)
-    _, ev_h, st_h = _solve(h, dops, order, prm20, hints=np.tile([0.0, 0.0, 64.0], (n, 1)))
-    assert [s["degree"] for s in st_h] == [64] * n
+    _, ev_h, st_h = _solve(h, dops, order, prm20, hints=np.tile([0.0, 0.0, 128.0], (n, 1)))
+    assert [s["degree"] for s in st_h] == [128] * n
     assert [s["iterations"] for s in st_h] == [s["iterations"] for s in st_p]
     assert sum(s["iterations"] for s in st_p) < sum(s["iterations"] for s in st20)
     np.testing.assert_allclose(ev_h.cpu().numpy(), ev_p.cpu().numpy(), rtol=1e-10)

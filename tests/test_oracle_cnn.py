@@ -65,4 +65,4 @@ def test_features_layout_and_degree_label():
     np.testing.assert_array_equal(x[:, 2], f[:, 1].real)
     np.testing.assert_array_equal(x[:, 5], f[:, 2].imag)
     assert cnn.degree_label(100.0, 200.0, 1e4) == pytest.approx(np.ceil(np.arccosh(1e4) / np.arccosh(1 + 2 * 100 / 9800)))
-    assert cnn.degree_label(1000.0, 1000.5, 1e7) == 64.0
+    assert cnn.degree_label(1000.0, 1000.5, 1e7) == 128.0

@@ -10,9 +10,9 @@ Workload (default, the largest): 2000 anisotropic operators -div(K grad u) with 
 field K (9-point Q1 stencil) on a 128 x 128 grid (n = 16384), L = 64 smallest eigenpairs,
 block width k = 80, relative residual 1e-8, FP64, in the learned-window form: the plain
 solves (degree 96, `--head-degree`) of the first 500 operators of the sorted order give the
-labels of the window network, which is trained (FP32) and predicts, in BF16, the window and
-the filter degree of the other 1500 solves.  Every operator is solved once per step, training
-included.  `--config` selects the other workloads (1 small, 2 working size, 3 uneven batch,
+labels of the window network, which is trained (FP32, 150 epochs) and predicts, in BF16, the
+window and the filter degree of the other 1500 solves.  Every operator is solved once per
+step, training included.  `--config` selects the other workloads (1 small, 2 working size, 3 uneven batch,
 4 mixed precision, 6 thin-plate vibration, 7 Helmholtz).
 
 Prints one JSON line (rank 0).  `roofline` describes the dominant kernel (the filter's
@@ -265,7 +265,10 @@ def main():
     ap.add_argument("--head-degree", type=int, default=96,
                     help="learned form: filter degree of the plain solves that give the "
                          "labels (the best fixed degree measured on this family)")
-    ap.add_argument("--epochs", type=int, default=600)
+    ap.add_argument("--epochs", type=int, default=150,
+                    help="learned form: training epochs (c5: 150 / 300 / 600 epochs ran at "
+                         "16.4k / 16.0k / 15.2k eigenpairs/s with 5.83 / 5.77 / 5.76 tail "
+                         "iterations)")
     ap.add_argument("--tile", type=int, choices=[1, 2, 4], default=None,
                     help="pin the filter-step tile instead of the autotuned one")
     ap.add_argument("--fused-steps", type=int, choices=[0, 2, 3, 4], default=None,

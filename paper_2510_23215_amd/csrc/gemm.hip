@@ -287,8 +287,11 @@ __device__ inline void tn_slab_body(int64_t r_begin, int64_t r_end, int64_t ld, 
         static_for<TPW>([&](auto u) {
           constexpr int ij = TL::at(W + NW * decltype(u)::value);
           constexpr int i = ij / 64, j = ij % 64;
-          if constexpr (SYM) acc[u] = mfma16x16x4(fa[i][tt], fa[j][tt], acc[u]);
-          else acc[u] = mfma16x16x4(fa[i][tt], fb[j][tt], acc[u]);
+          if constexpr (SYM) {
+            acc[u] = mfma16x16x4(fa[i][tt], fa[j][tt], acc[u]);
+          } else if (i * 16 < ka && j * 16 < kb) {   // widths differ: skip dead tiles
+            acc[u] = mfma16x16x4(fa[i][tt], fb[j][tt], acc[u]);
+          }
         });
       });
     }

@@ -411,39 +411,27 @@ hipError_t gemm_tn(int B, int64_t n, int64_t ld, const double *A, int64_t bsA, i
   return hipGetLastError();
 }
 
-// grid: x = row tiles of 64 (4 waves x 16 rows), z = problem.  NT = 16-column output tiles.
-template <int NT>
-__global__ void __launch_bounds__(256) gemm_nn_kernel(
-    int64_t n, int64_t ld, const double *In, int64_t bsI, int32_t modeI, double *Out,
-    int64_t bsO, int32_t modeO, int32_t k, const int32_t *__restrict__ lock,
-    const double *__restrict__ M, int32_t ldm, double alpha, double beta,
-    const int32_t *__restrict__ gate, int32_t gate_mask, const int32_t *__restrict__ skip,
-    int32_t skip_mask, const int32_t *__restrict__ rows) {
+// grid: x = row tiles of 64 (4 waves x 16 rows), z = problem.  A body computes NT tiles of 16
+// output columns (compile-time, so the MFMA loop carries no per-tile test and M is staged only
+// as wide as the body); columns past the problem's output width come out zero and are not
+// stored.
+// MODE 0: Out = In M;  MODE 1: Out -= In M;  MODE 2: Out = beta Out + alpha In M.  The first two
+// (every call of the solvers) are compile-time: a runtime alpha in the epilogue alone took 56
+// more registers.
+template <int NT, int MODE>
+__device__ inline void gemm_nn_body(int64_t nb, int64_t ld, const double *Ib, double *Ob, int ki,
+                                    int ko, const double *Mb, int32_t ldm, double alpha,
+                                    double beta, double *Ms) {
   constexpr int KC = 32;                       // rows of M staged per pass
   constexpr int MS = NT * 16 + 2;              // padded LDS row stride
-  __shared__ double Ms[KC * MS];
-  const int b = blockIdx.z;
-  if (gate && !(gate[b] & gate_mask)) return;
-  if (skip && (skip[b] & skip_mask)) return;
-  int32_t i0, ki, o0, ko;
-  col_range(modeI, k, lock, b, i0, ki);
-  col_range(modeO, k, lock, b, o0, ko);
-  if (ko <= 0) return;
-  if (ki <= 0 && beta == 1.0) return;          // nothing to add
-  const int64_t nb = rows ? (int64_t)rows[b] : n;
-  if ((int64_t)blockIdx.x * 64 >= nb) return;  // row tile beyond this problem's rows
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r4 = lane >> 4, c16 = lane & 15;
   const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
   const int64_t row = row0 + c16;
   const bool row_ok = row < nb;
-  const double *Ib = In + (int64_t)b * bsI + (int64_t)i0 * ld;
-  const double *Mb = M + (int64_t)b * ldm * ldm;
-
   v4d acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
-
   for (int kk0 = 0; kk0 < ki; kk0 += KC) {
     __syncthreads();
     for (int e = threadIdx.x; e < KC * NT * 16; e += 256) {
@@ -458,15 +446,12 @@ __global__ void __launch_bounds__(256) gemm_nn_kernel(
       const double bf = (row_ok && kk < ki) ? Ib[(int64_t)kk * ld + row] : 0.0;
 #pragma unroll
       for (int ct = 0; ct < NT; ++ct) {
-        if (ct * 16 < ko) {
-          const double af = Ms[(t + r4) * MS + ct * 16 + c16];
-          acc[ct] = mfma16x16x4(af, bf, acc[ct]);
-        }
+        const double af = Ms[(t + r4) * MS + ct * 16 + c16];
+        acc[ct] = mfma16x16x4(af, bf, acc[ct]);
       }
     }
   }
   if (!row_ok) return;
-  double *Ob = Out + (int64_t)b * bsO + (int64_t)o0 * ld;
 #pragma unroll
   for (int ct = 0; ct < NT; ++ct) {
 #pragma unroll
@@ -474,11 +459,44 @@ __global__ void __launch_bounds__(256) gemm_nn_kernel(
       const int col = ct * 16 + r4 + 4 * v;
       if (col < ko) {
         double *o = Ob + (int64_t)col * ld + row;
-        const double r = alpha * acc[ct][v];
-        *o = (beta == 0.0) ? r : beta * (*o) + r;
+        if constexpr (MODE == 0) *o = acc[ct][v];
+        else if constexpr (MODE == 1) *o -= acc[ct][v];
+        else *o = (beta == 0.0) ? alpha * acc[ct][v] : beta * (*o) + alpha * acc[ct][v];
       }
     }
   }
+}
+
+// NTMAX = ceil(k / 16) is chosen on the host; a workgroup whose problem has at most half of
+// that width active (locked columns) runs the half-width body.  Two bodies keep the kernel as
+// lean in registers as a single one (a body per width raised it from 108 to 164 VGPRs at 8
+// tiles and cost a quarter of the speed).
+template <int NTMAX, int MODE>
+__global__ void __launch_bounds__(256) gemm_nn_kernel(
+    int64_t n, int64_t ld, const double *In, int64_t bsI, int32_t modeI, double *Out,
+    int64_t bsO, int32_t modeO, int32_t k, const int32_t *__restrict__ lock,
+    const double *__restrict__ M, int32_t ldm, double alpha, double beta,
+    const int32_t *__restrict__ gate, int32_t gate_mask, const int32_t *__restrict__ skip,
+    int32_t skip_mask, const int32_t *__restrict__ rows) {
+  __shared__ double Ms[32 * (NTMAX * 16 + 2)];
+  const int b = blockIdx.z;
+  if (gate && !(gate[b] & gate_mask)) return;
+  if (skip && (skip[b] & skip_mask)) return;
+  int32_t i0, ki, o0, ko;
+  col_range(modeI, k, lock, b, i0, ki);
+  col_range(modeO, k, lock, b, o0, ko);
+  if (ko <= 0) return;
+  if (ki <= 0 && beta == 1.0) return;          // nothing to add
+  const int64_t nb = rows ? (int64_t)rows[b] : n;
+  if ((int64_t)blockIdx.x * 64 >= nb) return;  // row tile beyond this problem's rows
+  const double *Ib = In + (int64_t)b * bsI + (int64_t)i0 * ld;
+  double *Ob = Out + (int64_t)b * bsO + (int64_t)o0 * ld;
+  const double *Mb = M + (int64_t)b * ldm * ldm;
+  constexpr int HALF = (NTMAX + 1) / 2;
+  if ((ko + 15) / 16 <= HALF)
+    gemm_nn_body<HALF, MODE>(nb, ld, Ib, Ob, ki, ko, Mb, ldm, alpha, beta, Ms);
+  else
+    gemm_nn_body<NTMAX, MODE>(nb, ld, Ib, Ob, ki, ko, Mb, ldm, alpha, beta, Ms);
 }
 
 hipError_t gemm_nn(int B, int64_t n, int64_t ld, const double *In, int64_t bsI, int32_t modeI,
@@ -486,16 +504,28 @@ hipError_t gemm_nn(int B, int64_t n, int64_t ld, const double *In, int64_t bsI, 
                    const double *M, int32_t ldm, double alpha, double beta, const int32_t *gate,
                    int32_t gate_mask, const int32_t *skip, int32_t skip_mask, hipStream_t st,
                    const int32_t *rows) {
-  if (B <= 0 || n <= 0) return hipSuccess;
+  if (B <= 0 || n <= 0 || k <= 0) return hipSuccess;
+  if (k > 256) return hipErrorInvalidValue;
   dim3 grid((unsigned)ceil_div(n, 64), 1, (unsigned)B);
-  if (k <= 128)
-    gemm_nn_kernel<8><<<grid, 256, 0, st>>>(n, ld, In, bsI, modeI, Out, bsO, modeO, k, lock, M,
-                                            ldm, alpha, beta, gate, gate_mask, skip, skip_mask,
-        rows);
-  else
-    gemm_nn_kernel<16><<<grid, 256, 0, st>>>(n, ld, In, bsI, modeI, Out, bsO, modeO, k, lock, M,
-                                             ldm, alpha, beta, gate, gate_mask, skip, skip_mask,
-        rows);
+  const int nt = (int)ceil_div(k, 16);
+  const int mode = (alpha == 1.0 && beta == 0.0) ? 0 : (alpha == -1.0 && beta == 1.0) ? 1 : 2;
+  switch (nt) {
+#define SCSF_NN_MODE(T, MD)                                                                     \
+  gemm_nn_kernel<T, MD><<<grid, 256, 0, st>>>(n, ld, In, bsI, modeI, Out, bsO, modeO, k, lock, M, \
+                                              ldm, alpha, beta, gate, gate_mask, skip,          \
+                                              skip_mask, rows)
+#define SCSF_NN(T)                                                                              \
+  case T:                                                                                      \
+    if (mode == 0) SCSF_NN_MODE(T, 0);                                                         \
+    else if (mode == 1) SCSF_NN_MODE(T, 1);                                                    \
+    else SCSF_NN_MODE(T, 2);                                                                   \
+    break;
+    SCSF_NN(1) SCSF_NN(2) SCSF_NN(3) SCSF_NN(4) SCSF_NN(5) SCSF_NN(6) SCSF_NN(7) SCSF_NN(8)
+    SCSF_NN(9) SCSF_NN(10) SCSF_NN(11) SCSF_NN(12) SCSF_NN(13) SCSF_NN(14) SCSF_NN(15) SCSF_NN(16)
+#undef SCSF_NN
+#undef SCSF_NN_MODE
+    default: break;
+  }
   return hipGetLastError();
 }
 

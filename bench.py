@@ -56,8 +56,8 @@ def measured_traffic(cfg_name: str, launch: dict):
     """HBM bytes per filter launch (FETCH_SIZE + WRITE_SIZE of the filter kernel, each scaled
     by what the counter reads for a device copy of known size) from the committed counter
     record of this workload, while the filter step's source and the launch configuration
-    (chains, lanes, schedule, graphs, tile, form, precision) are those the counters were taken
-    with (else None)."""
+    (chains, lanes, schedule, graphs, tile, form, precision, fused steps, degrees, training
+    epochs) are those the counters were taken with (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"spmm_traffic_{cfg_name}.txt")
     if not os.path.exists(path):
@@ -433,8 +433,10 @@ def main():
         _, _, stats = scsf.scsf_solve_sequence(h, dops, order, args.chains, p, evals, evecs)
         return stats
 
+    head_deg_used = args.head_degree if precision == "fp64" else min(args.head_degree, 64)
+
     def step():
-        head_deg = args.head_degree if precision == "fp64" else min(args.head_degree, 64)
+        head_deg = head_deg_used
         return (step_learned(prm, params(deg=head_deg)) if form == "learned"
                 else step_plain(prm))
 
@@ -474,6 +476,7 @@ def main():
     pairs = args.steps * sum(Ls)
     value = pairs / dt
     log(f"[bench] {value:.0f} eigenpairs/s, {dt / args.steps * 1e3:.1f} ms per step")
+    timed_info = dict(train_info)      # the comparison runs below update train_info again
 
     def timed(fn, label):
         torch.cuda.synchronize()
@@ -512,6 +515,7 @@ def main():
             "learned_fp32_filter": timed(lambda: step_learned(
                 params(prec="mixed"), params(prec="mixed", deg=min(args.head_degree, 64))),
                 "learned window, FP32 filter")}
+        comparison["learned_fp32_filter"]["mean_degree"] = train_info["mean_degree"]
         comparison["plain_fp64"]["degree"] = degree
         comparison[f"plain_fp64_degree{args.best_degree}"]["degree"] = args.best_degree
         comparison["ratio_to_plain_fp64"] = value / comparison["plain_fp64"]["value"]
@@ -527,12 +531,16 @@ def main():
     achieved = bytes_step / (dt / args.steps) / 1e9
     live_ms = prof["filter_ms"] / max(prof["filter_launches"], 1)
     # HBM bytes of the filter per step: the committed counter record's bytes per launch (while
-    # it matches this source and launch configuration) times the live launches per step
+    # it matches this source and launch configuration) times the live launches per step.  The
+    # degrees and the training length set the mix of launch widths, so they are part of the key.
+    learned_key = ({"head_degree": head_deg_used, "epochs": args.epochs} if form == "learned"
+                   else {})
     per_launch = (measured_traffic(cfg.name, {"chains": args.chains, "lanes": args.lanes,
                                               "schedule": args.schedule, "graphs": args.graphs,
                                               "tile": tile_used, "form": form,
                                               "precision": precision,
-                                              "fused_steps": args.fused_steps})
+                                              "fused_steps": args.fused_steps,
+                                              "degree": degree, **learned_key})
                   if not adaptive else None)
     traffic_step = (per_launch * prof["filter_launches"] / args.steps
                     if per_launch is not None else None)
@@ -607,8 +615,8 @@ def main():
     out["phases"] = {"ms_per_step_summed_over_lanes": ph,
                      "share": {k: v / tot for k, v in ph.items()}}
     if form == "learned":
-        out["config"]["learned"] = dict(train_info, trained_on=n_train, epochs=args.epochs,
-                                        head_degree=args.head_degree)
+        out["config"]["learned"] = dict(timed_info, trained_on=n_train, epochs=args.epochs,
+                                        head_degree=head_deg_used)
     if comparison:
         out["comparison"] = comparison
     if cfg.index in (2, 5, 6) and precision == "fp64" and args.spmm_isolated == "on":

@@ -215,9 +215,6 @@ hipError_t gaussian_fill(int B, int64_t n, int64_t ld, int64_t bs, int32_t k, do
 // zeroes rows [n, ldd) of the destination (internal blocks only, never a caller's buffer).
 hipError_t copy_block(int64_t n, int32_t ncols, const double *src, int64_t lds, double *dst,
                       int64_t ldd, bool zero_pad, hipStream_t st);
-// Canonical sign: flip each column so that its largest-magnitude entry (lowest index on
-// ties) is positive.
-hipError_t canonical_sign(int64_t n, int32_t ncols, double *X, int64_t ld, hipStream_t st);
 // X[p, c] /= sqrt(rho[p]) for p < n, c < ncols (plate eigenvectors to M-orthonormal form)
 hipError_t scale_rows_rsqrt(int64_t n, int32_t ncols, double *X, int64_t ld, const double *rho,
                             hipStream_t st);
@@ -233,8 +230,10 @@ hipError_t adaptive_degrees(int B, int32_t k, const int32_t *lock, const int32_t
 // the unit square (zero Dirichlet boundary); X and Y must not overlap.
 hipError_t interpolate_fields(int32_t N0, int32_t N1, int32_t ncols, const double *X,
                               int64_t ldx, double *Y, int64_t ldy, hipStream_t st);
-hipError_t gather_columns(int64_t n, int32_t ncols, const double *src, int64_t lds,
-                          const int32_t *perm, double *dst, int64_t ldd, hipStream_t st);
+// dst[:, j] = +-src[:, perm[j]] for j < ncols (rows < n), each column in canonical sign: its
+// largest-magnitude entry (lowest row on ties) positive.  src and dst must not overlap.
+hipError_t gather_columns_signed(int64_t n, int32_t ncols, const double *src, int64_t lds,
+                                 const int32_t *perm, double *dst, int64_t ldd, hipStream_t st);
 
 // Truncated DFT features and the greedy order.
 // sort diagnostics (diag.hip)

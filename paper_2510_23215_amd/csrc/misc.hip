@@ -376,37 +376,6 @@ hipError_t copy_block(int64_t n, int32_t ncols, const double *src, int64_t lds, 
   return hipGetLastError();
 }
 
-// one workgroup per column: index of the largest |x| (lowest index on ties), then flip
-__global__ void __launch_bounds__(256) sign_kernel(int64_t n, double *__restrict__ X, int64_t ld) {
-  __shared__ double sv[256];
-  __shared__ int64_t si[256];
-  double *x = X + (int64_t)blockIdx.x * ld;
-  double best = -1.0;
-  int64_t bi = 0;
-  for (int64_t p = threadIdx.x; p < n; p += blockDim.x) {
-    const double a = fabs(x[p]);
-    if (a > best) { best = a; bi = p; }
-  }
-  sv[threadIdx.x] = best;
-  si[threadIdx.x] = bi;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      const double a = sv[threadIdx.x + o];
-      const int64_t ia = si[threadIdx.x + o];
-      if (a > sv[threadIdx.x] || (a == sv[threadIdx.x] && ia < si[threadIdx.x])) {
-        sv[threadIdx.x] = a;
-        si[threadIdx.x] = ia;
-      }
-    }
-    __syncthreads();
-  }
-  const bool flip = x[si[0]] < 0.0;
-  __syncthreads();
-  if (flip)
-    for (int64_t p = threadIdx.x; p < n; p += blockDim.x) x[p] = -x[p];
-}
-
 __global__ void scale_rows_kernel(int64_t n, double *__restrict__ X, int64_t ld,
                                   const double *__restrict__ rho) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -417,12 +386,6 @@ hipError_t scale_rows_rsqrt(int64_t n, int32_t ncols, double *X, int64_t ld, con
                             hipStream_t st) {
   if (n <= 0 || ncols <= 0) return hipSuccess;
   scale_rows_kernel<<<dim3((unsigned)ceil_div(n, 256), ncols), 256, 0, st>>>(n, X, ld, rho);
-  return hipGetLastError();
-}
-
-hipError_t canonical_sign(int64_t n, int32_t ncols, double *X, int64_t ld, hipStream_t st) {
-  if (ncols <= 0 || n <= 0) return hipSuccess;
-  sign_kernel<<<ncols, 256, 0, st>>>(n, X, ld);
   return hipGetLastError();
 }
 
@@ -441,21 +404,69 @@ hipError_t fill_int(int32_t *a, int32_t v, int32_t count, hipStream_t st) {
   return hipGetLastError();
 }
 
-// dst[:, j] = src[:, perm[j]] for j < ncols (rows < n)
-__global__ void gather_kernel(int64_t n, const double *__restrict__ src, int64_t lds,
-                              const int32_t *__restrict__ perm, double *__restrict__ dst,
-                              int64_t ldd) {
-  const int j = blockIdx.y;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  dst[(int64_t)j * ldd + p] = src[(int64_t)perm[j] * lds + p];
+// dst[:, j] = s_j src[:, perm[j]] for j < ncols (rows < n): the gathered columns in canonical
+// sign, s_j = -1 when the source column's entry of largest magnitude (lowest row on ties) is
+// negative, else 1.  One workgroup of 1024 threads per column.  Each thread scans its rows in
+// increasing order with four loads in flight (a strict comparison keeps the lowest row of a
+// tie), the workgroup reduces (magnitude, row) pairs, and the second pass over the column
+// (from L2) writes it with the sign applied.
+constexpr int kSignThreads = 1024;
+__global__ void __launch_bounds__(kSignThreads) gather_sign_kernel(
+    int64_t n, const double *__restrict__ src, int64_t lds, const int32_t *__restrict__ perm,
+    double *__restrict__ dst, int64_t ldd) {
+  constexpr int U = 4, NWAVE = kSignThreads / 64;
+  __shared__ double sv[NWAVE];
+  __shared__ int64_t si[NWAVE];
+  __shared__ int flip_s;
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const double *x = src + (int64_t)perm[j] * lds;
+  double best = -1.0;
+  int64_t bi = 0;
+  for (int64_t p0 = tid; p0 < n; p0 += (int64_t)kSignThreads * U) {
+    double a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t p = p0 + (int64_t)u * kSignThreads;
+      a[u] = p < n ? fabs(x[p]) : -1.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (a[u] > best) {
+        best = a[u];
+        bi = p0 + (int64_t)u * kSignThreads;
+      }
+  }
+  // (larger magnitude, then lower row) wins
+  auto take = [&](double ob, int64_t oi) {
+    if (ob > best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+    }
+  };
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, 64);
+    const int64_t oi = __shfl_xor(bi, o, 64);
+    take(ob, oi);
+  }
+  if ((tid & 63) == 0) {
+    sv[tid >> 6] = best;
+    si[tid >> 6] = bi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < NWAVE; ++w) take(sv[w], si[w]);
+    flip_s = x[bi] < 0.0 ? 1 : 0;
+  }
+  __syncthreads();
+  const bool flip = flip_s != 0;
+  double *y = dst + (int64_t)j * ldd;
+  for (int64_t p = tid; p < n; p += kSignThreads) y[p] = flip ? -x[p] : x[p];
 }
 
-hipError_t gather_columns(int64_t n, int32_t ncols, const double *src, int64_t lds,
-                          const int32_t *perm, double *dst, int64_t ldd, hipStream_t st) {
+hipError_t gather_columns_signed(int64_t n, int32_t ncols, const double *src, int64_t lds,
+                                 const int32_t *perm, double *dst, int64_t ldd, hipStream_t st) {
   if (ncols <= 0 || n <= 0) return hipSuccess;
-  gather_kernel<<<dim3((unsigned)ceil_div(n, 256), ncols), 256, 0, st>>>(n, src, lds, perm, dst,
-                                                                         ldd);
+  gather_sign_kernel<<<(unsigned)ncols, kSignThreads, 0, st>>>(n, src, lds, perm, dst, ldd);
   return hipGetLastError();
 }
 

@@ -949,19 +949,23 @@ struct Engine {
     return SCSF_OK;
   }
 
-  // theta / res / bnd of problem b to the pinned mirrors (synchronises)
-  int fetch(int b) {
-    HIPCHK(hipMemcpyAsync(h_theta + (size_t)b * k, theta + (size_t)b * k, (size_t)k * 8,
-                          hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_res + (size_t)b * k, res + (size_t)b * k, (size_t)k * 8,
-                          hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(h_bnd + (size_t)b * 4, bnd + (size_t)b * 4, 32, hipMemcpyDeviceToHost,
-                          st));
-    HIPCHK(hipMemcpyAsync(h_hint + (size_t)b * 3, hint + (size_t)b * 3, 24, hipMemcpyDeviceToHost,
-                          st));
+  // theta / res / bnd / hint of the listed problems to the pinned mirrors, one wait for all
+  int fetch(const std::vector<int> &slots) {
+    if (slots.empty()) return SCSF_OK;
+    for (int b : slots) {
+      HIPCHK(hipMemcpyAsync(h_theta + (size_t)b * k, theta + (size_t)b * k, (size_t)k * 8,
+                            hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(h_res + (size_t)b * k, res + (size_t)b * k, (size_t)k * 8,
+                            hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(h_bnd + (size_t)b * 4, bnd + (size_t)b * 4, 32,
+                            hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(h_hint + (size_t)b * 3, hint + (size_t)b * 3, 24,
+                            hipMemcpyDeviceToHost, st));
+    }
     HIPCHK(hipStreamSynchronize(st));
     return SCSF_OK;
   }
+  int fetch(int b) { return fetch(std::vector<int>{b}); }
 
   // The L smallest converged pairs of problem b (of its first max(L, nconv) columns: a
   // solve that ends converged may hold more than L, and a pair that entered the block late
@@ -1011,12 +1015,13 @@ struct Engine {
     HIPCHK(hipMemcpyAsync(perm_d + (size_t)b * k, perm, (size_t)L * 4, hipMemcpyHostToDevice,
                           st));
     HIPCHK(hipMemcpyAsync(evals, vals, (size_t)L * 8, hipMemcpyHostToDevice, st));
-    HIPCHK(gather_columns(h_rows[b], L, X + (int64_t)b * bs, ld, perm_d + (size_t)b * k, evecs,
-                          ldo, st));
-    HIPCHK(canonical_sign(h_rows[b], L, evecs, ldo, st));
+    HIPCHK(gather_columns_signed(h_rows[b], L, X + (int64_t)b * bs, ld, perm_d + (size_t)b * k,
+                                 evecs, ldo, st));
     if (h_ops[b].kind == SCSF_PLATE)             // u = M^{-1/2} y, M-orthonormal
       HIPCHK(scale_rows_rsqrt(h_rows[b], L, evecs, ldo, h_ops[b].wy, st));
-    HIPCHK(hipStreamSynchronize(st));                 // the copies above read pinned memory
+    // No wait here: the two copies read this slot's own pinned rows (h_perm, h_theta), which
+    // the host writes again only after fetch(b) has synchronised the stream, and the outputs
+    // are complete when the caller's solve returns (its streams are synchronised).
     if (maxres) *maxres = mr;
     return SCSF_OK;
   }
@@ -1203,14 +1208,19 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
     bool reload = false;
     std::vector<int> recold, reloaded;
     std::vector<std::array<int, 3>> resize;   // (slot, old side, new side)
+    auto finished = [&](int b) {
+      return e.h_done[b] || (e.h_flag[b] & 3) || iters[b] >= max_iter;
+    };
+    std::vector<int> fin_slots;
     for (int b = 0; b < chains; ++b) {
       if (!active[b]) continue;
       ++iters[b];
-      const bool fin = e.h_done[b] || (e.h_flag[b] & 3) || iters[b] >= max_iter;
-      if (!fin) continue;
+      if (finished(b)) fin_slots.push_back(b);
+    }
+    STCHK(e.fetch(fin_slots));
+    for (int b : fin_slots) {
       const int op = order_host[pos[b]];
       const int status = solve_status(e.h_flag[b], e.h_done[b] != 0);
-      STCHK(e.fetch(b));
       double mr = 0.0;
       if (ritz) {                       // all k Ritz values, ascending
         std::vector<double> th(e.h_theta + (size_t)b * k, e.h_theta + (size_t)b * k + k);

@@ -2182,11 +2182,14 @@ int scsf_solve_batched_hinted(scsf_handle *h, const scsf_operator *ops_host, int
   for (size_t gi = 0; gi < groups.size(); ++gi) next[gi] = groups[gi].chains;
   std::vector<int> status(lanes, SCSF_OK);
   std::vector<Fallback> fbs(groups.size());     // smallest magnitude: uncertified lower ends
-  // every lane works through the groups in turn; a lane that finishes its chains of one group
-  // moves on to the next without waiting for the others
+  // every lane works through the groups in turn, starting at group l mod G, so all groups are
+  // in flight from the start (narrow groups' dense steps overlap wide groups' filters); a lane
+  // that finishes its chains of one group moves on to the next without waiting for the others
+  const size_t ng = groups.size();
   auto lane_fn = [&](int l) {
     if (hipSetDevice(h->device) != hipSuccess) { status[l] = SCSF_EHIP; return; }
-    for (size_t gi = 0; gi < groups.size(); ++gi) {
+    for (size_t j = 0; j < ng; ++j) {
+      const size_t gi = (j + (size_t)l) % ng;
       const G &g = groups[gi];
       const int nord = (int)g.order.size();
       std::vector<int> cb, ce;

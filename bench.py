@@ -253,6 +253,10 @@ def main():
                          "one by one (off)")
     ap.add_argument("--eig", choices=["jacobi", "tridiag"], default="jacobi",
                     help="Rayleigh-Ritz eigensolver")
+    ap.add_argument("--batch-form", choices=["grouped", "one-sweep"], default="grouped",
+                    help="uneven workload: one lockstep batch per (L, k) group, or one batch over "
+                         "every width (each sweep covers all groups); the comparison times the "
+                         "other")
     ap.add_argument("--autotune", choices=["on", "off"], default="on",
                     help="tune filter tiles (and, for the uneven workload, block widths) on the "
                          "dataset once before the warmup; the timed steps use the result")
@@ -329,6 +333,8 @@ def main():
     scsf.scsf_set_fused_steps(h, args.fused_steps)
     scsf.scsf_set_eigensolver(h, scsf.SCSF_EIG_TRIDIAG if args.eig == "tridiag"
                               else scsf.SCSF_EIG_JACOBI)
+    form_ids = {"grouped": scsf.SCSF_BATCH_GROUPED, "one-sweep": scsf.SCSF_BATCH_ONE_SWEEP}
+    scsf.scsf_set_batch_form(h, form_ids[args.batch_form])
     dops = [scsf.DeviceOperator(o) for o in ops]
     if uneven:
         # fields grouped by family and side: features per side, one greedy order per family
@@ -500,6 +506,12 @@ def main():
             f"{other_sched}_schedule": timed(lambda: step_plain(params(
                 schedule=other_sched_id)), f"{other_sched} schedule")}
         comparison["ratio_to_cold_unsorted"] = value / comparison["cold_unsorted"]["value"]
+    if args.compare == "on" and uneven and not adaptive:
+        other_form = "one-sweep" if args.batch_form == "grouped" else "grouped"
+        scsf.scsf_set_batch_form(h, form_ids[other_form])
+        comparison = {f"batch_form_{other_form.replace('-', '_')}": timed(
+            lambda: step_plain(prm), f"batch form {other_form}")}
+        scsf.scsf_set_batch_form(h, form_ids[args.batch_form])
     if args.compare == "on" and windowed and form == "learned":
         comparison = {
             "plain_fp64": timed(lambda: step_plain(prm64), f"plain fp64 degree {degree}"),
@@ -583,6 +595,7 @@ def main():
             "schedule": args.schedule,
             "graphs": args.graphs,
             "eigensolver": args.eig,
+            "batch_form": args.batch_form if uneven else None,
             "autotune_s": tune_s,
             "form": form,
             "block_widths": ({str(L): scsf.scsf_tuned_width(h, L) for L in sorted(set(Ls))}

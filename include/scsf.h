@@ -56,6 +56,8 @@ enum scsf_precision { SCSF_FP64 = 0, SCSF_MIXED = 1 };
  *   DYNAMIC: every chain takes the next unsolved operator of the sorted order when it
  *            finishes one, warm-starting from the operator it solved last (load balance). */
 enum scsf_schedule { SCSF_SCHED_STATIC = 0, SCSF_SCHED_DYNAMIC = 1 };
+/* How scsf_solve_batched runs operators with different (L, k) (scsf_set_batch_form). */
+enum scsf_batch_form { SCSF_BATCH_GROUPED = 0, SCSF_BATCH_ONE_SWEEP = 1 };
 /* Which eigenvalues the solvers return (scsf_params.target). */
 enum scsf_target { SCSF_TARGET_SMALLEST = 0, SCSF_TARGET_MAGNITUDE = 1 };
 /* Eigensolver of the Rayleigh-Ritz step (scsf_set_eigensolver). */
@@ -447,13 +449,24 @@ int scsf_interpolate(scsf_handle *h, int32_t N0, int32_t N1, int32_t ncols, cons
  * solvers; not for SCSF_PLATE) and target (prm->L and prm->k are ignored).
  * The operators are grouped by (kind, L, k), keeping order_host's order inside each group,
  * and every group is split into chains (about chains * group size / n_op of them) that run as
- * in scsf_solve_sequence.  Along a chain each solve warm-starts from the previous one; when
+ * in scsf_solve_sequence (per group, or all groups of a kind in one batch: scsf_set_batch_form).  Along a chain each solve warm-starts from the previous one; when
  * the grid side changes the Ritz vectors are moved by scsf_interpolate's transfer (operators
  * not on square grids restart cold).
  * Outputs, packed in operator-index order: evals[sum L_i] with operator i at
  * sum_{j<i} L_j, evecs[sum n_i L_i] with operator i's n_i x L_i block (ld n_i) at
  * sum_{j<i} n_j L_j.  stats_host[n_op] may be NULL.  Returns SCSF_ENOTCONV if any solve did
  * not converge. */
+/* The form of scsf_solve_batched's lockstep batches.  SCSF_BATCH_GROUPED (default): each
+ * (kind, L, k) group runs as its own batches (a lane starts at its own group and takes the
+ * others in turn).  SCSF_BATCH_ONE_SWEEP: every lane runs one batch over the chains of all
+ * groups of a kind, so each sweep (outer iteration of Algorithm 3) covers operators of every
+ * (L, k) in the same launches and graphs.  There, each problem occupies the last k_i columns
+ * of a block as wide as the widest group: the columns before them are zero and locked from
+ * the start, and every step of the iteration works on a problem's active columns only.  Not
+ * with adaptive degrees or SCSF_TARGET_MAGNITUDE (those solves return SCSF_EINVAL).  Results
+ * agree with the grouped form to the solves' tolerance (the random first blocks differ).
+ * SCSF_EINVAL for another value. */
+int scsf_set_batch_form(scsf_handle *h, int form);
 int scsf_solve_batched(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
                        const int32_t *L_host, const int32_t *k_host, const int32_t *order_host,
                        int32_t chains, const scsf_params *prm, double *evals, double *evecs,

@@ -174,18 +174,22 @@ hipError_t residuals(int B, int64_t n, int64_t ld, const double *X, const double
 // mode 1: the same in |theta| (squared filter); mode 2 (smallest |theta| from the lower
 // end): the q converged pairs at or below theta[nconv[b]] hold L with |theta| <= their
 // largest; when no unconverged pair is left first, the problem ends with flag bit 16.
+// offv, Lv (nullable, B each): per-slot widths, problem b in columns [offv[b], k) wanting
+// Lv[b] pairs (columns below offv[b] are zero placeholders, locked from the start).
 hipError_t lock_update(int B, int32_t k, int32_t L, double tol, int32_t *lock, int32_t *nconv,
                        const double *res, const double *theta, int mode, int32_t *done,
-                       int32_t *flag, hipStream_t st);
+                       int32_t *flag, hipStream_t st, const int32_t *offv = nullptr,
+                       const int32_t *Lv = nullptr);
 
 // Chebyshev step coefficients for degree m: coef[(s*B + b)*3 + {0,1,2}] for s = 0..m-1 from
-// lambda = theta[b*k], alpha = theta[b*k + k-1] (or win[] when given), beta = bounds[b*4+3].
+// lambda = theta[b*k + offv[b]] (offv null: theta[b*k]), alpha = theta[b*k + k-1] (or win[] when
+// given), beta = bounds[b*4+3].
 // win (nullable) receives (lambda, c, e) per problem.  hint (nullable): per problem
 // (lambda_1, lambda_{L+1}, state); state 1 = apply once if the bounds accept it (-> 2 used,
 // 3 rejected).
 hipError_t cheb_coeffs(int B, int32_t k, int32_t m, const double *theta, const double *bounds,
                        const int32_t *done, double *coef, double *win, double *hint,
-                       hipStream_t st, double *coef2 = nullptr);
+                       hipStream_t st, double *coef2 = nullptr, const int32_t *offv = nullptr);
 // Same from explicit (lambda, c, e) per problem: win[b*3 + {0,1,2}].
 hipError_t cheb_coeffs_explicit(int B, int32_t m, const double *win, double *coef,
                                 hipStream_t st);
@@ -220,6 +224,8 @@ hipError_t scale_rows_rsqrt(int64_t n, int32_t ncols, double *X, int64_t ld, con
                             hipStream_t st);
 
 hipError_t fill_int(int32_t *a, int32_t v, int32_t count, hipStream_t st);
+// X[p, c] = 0 for p < n, c < ncols
+hipError_t zero_columns(int64_t n, int32_t ncols, double *X, int64_t ld, hipStream_t st);
 // Per-column degrees of the adaptive filter for the next outer iteration (cdeg: B*k, columns
 // [lock[b], k)) and their maximum per problem (mdeg); problems with done[b] are left alone.
 hipError_t adaptive_degrees(int B, int32_t k, const int32_t *lock, const int32_t *done,

@@ -63,6 +63,9 @@ hipError_t residuals(int B, int64_t n, int64_t ld, const double *X, const double
 }
 
 // nconv[b]: locked pairs; lock[b]: first active column (= k once the problem is done).
+// Per-slot widths (offv, Lv non-null): problem b owns columns [offv[b], k) and wants Lv[b]
+// pairs; its columns below offv[b] are zero placeholders, locked from the start, and every
+// count below starts at offv[b].
 // mode 0: the L algebraically smallest; 1: the L smallest |theta| with the squared filter (the
 // active range is ordered by |theta|); 2: the L smallest |theta| from the lower end of the
 // spectrum (ascending active range).  Flag bit 16: mode 2 ran out of unconverged pairs before
@@ -70,9 +73,12 @@ hipError_t residuals(int B, int64_t n, int64_t ld, const double *X, const double
 __global__ void lock_kernel(int B, int32_t k, int32_t L, double tol, int32_t *__restrict__ lock,
                             int32_t *__restrict__ nconv, const double *__restrict__ res,
                             const double *__restrict__ theta, int mode,
-                            int32_t *__restrict__ done, int32_t *__restrict__ flag) {
+                            int32_t *__restrict__ done, int32_t *__restrict__ flag,
+                            const int32_t *__restrict__ offv, const int32_t *__restrict__ Lv) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B || done[b]) return;
+  const int o = offv ? offv[b] : 0;
+  if (Lv) L = Lv[b];
   const int32_t j0 = nconv[b];
   int j = j0;
   while (j < k && res[(int64_t)b * k + j] <= tol) ++j;
@@ -87,17 +93,17 @@ __global__ void lock_kernel(int B, int32_t k, int32_t L, double tol, int32_t *__
   bool fin;
   if (mode != 2) {
     int below = j - j0;
-    for (int c = 0; c < j0; ++c) below += ((absval ? fabs(th[c]) : th[c]) <= tu) ? 1 : 0;
-    fin = j >= L && below >= L;
+    for (int c = o; c < j0; ++c) below += ((absval ? fabs(th[c]) : th[c]) <= tu) ? 1 : 0;
+    fin = j - o >= L && below >= L;
   } else {
     // smallest magnitude from the lower end: the q lowest converged values must hold L with
     // |theta| <= their largest, theta_q (every other eigenvalue is >= theta_q)
     double top = -INFINITY;
     int q = 0;
-    for (int c = 0; c < j; ++c)
+    for (int c = o; c < j; ++c)
       if (th[c] <= tu) { ++q; top = fmax(top, th[c]); }
     int cnt = 0;
-    for (int c = 0; c < j; ++c)
+    for (int c = o; c < j; ++c)
       if (th[c] <= tu && fabs(th[c]) <= top) ++cnt;
     fin = q >= L && cnt >= L;
     // no certificate can come (not certified, flag bit 16): no pair left to converge, or fewer
@@ -105,9 +111,9 @@ __global__ void lock_kernel(int B, int32_t k, int32_t L, double tol, int32_t *__
     // has at least L such values, and the Ritz values of a converging block only drift down)
     if (!fin) {
       double big = -INFINITY;
-      for (int c = 0; c < k; ++c) big = fmax(big, th[c]);
+      for (int c = o; c < k; ++c) big = fmax(big, th[c]);
       int within = 0;
-      for (int c = 0; c < k; ++c) within += (fabs(th[c]) <= big) ? 1 : 0;
+      for (int c = o; c < k; ++c) within += (fabs(th[c]) <= big) ? 1 : 0;
       if (j >= k || within < L) {
         fin = true;
         flag[b] |= 16;
@@ -120,10 +126,10 @@ __global__ void lock_kernel(int B, int32_t k, int32_t L, double tol, int32_t *__
 
 hipError_t lock_update(int B, int32_t k, int32_t L, double tol, int32_t *lock, int32_t *nconv,
                        const double *res, const double *theta, int mode, int32_t *done,
-                       int32_t *flag, hipStream_t st) {
+                       int32_t *flag, hipStream_t st, const int32_t *offv, const int32_t *Lv) {
   if (B <= 0) return hipSuccess;
   lock_kernel<<<(B + 63) / 64, 64, 0, st>>>(B, k, L, tol, lock, nconv, res, theta, mode, done,
-                                            flag);
+                                            flag, offv, Lv);
   return hipGetLastError();
 }
 
@@ -159,10 +165,11 @@ __device__ inline void write_coeffs(int B, int b, int32_t m, double lam, double 
 __global__ void cheb_kernel(int B, int32_t k, int32_t m, const double *__restrict__ theta,
                             const double *__restrict__ bnd, const int32_t *__restrict__ done,
                             double *__restrict__ coef, double *__restrict__ win,
-                            double *__restrict__ hint, double *__restrict__ coef2) {
+                            double *__restrict__ hint, double *__restrict__ coef2,
+                            const int32_t *__restrict__ offv) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B || (done && done[b])) return;
-  double lam = theta[(int64_t)b * k];
+  double lam = theta[(int64_t)b * k + (offv ? offv[b] : 0)];   // the problem's first column
   double alpha = theta[(int64_t)b * k + k - 1];
   if (coef2) {
     lam *= lam;
@@ -193,10 +200,10 @@ __global__ void cheb_kernel(int B, int32_t k, int32_t m, const double *__restric
 
 hipError_t cheb_coeffs(int B, int32_t k, int32_t m, const double *theta, const double *bounds,
                        const int32_t *done, double *coef, double *win, double *hint,
-                       hipStream_t st, double *coef2) {
+                       hipStream_t st, double *coef2, const int32_t *offv) {
   if (B <= 0) return hipSuccess;
   cheb_kernel<<<(B + 63) / 64, 64, 0, st>>>(B, k, m, theta, bounds, done, coef, win, hint,
-                                            coef2);
+                                            coef2, offv);
   return hipGetLastError();
 }
 
@@ -401,6 +408,17 @@ __global__ void fill_int_kernel(int32_t *__restrict__ a, int32_t v, int32_t coun
 hipError_t fill_int(int32_t *a, int32_t v, int32_t count, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   fill_int_kernel<<<(count + 255) / 256, 256, 0, st>>>(a, v, count);
+  return hipGetLastError();
+}
+
+__global__ void zero_cols_kernel(int64_t n, double *__restrict__ X, int64_t ld) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) X[(int64_t)blockIdx.y * ld + p] = 0.0;
+}
+
+hipError_t zero_columns(int64_t n, int32_t ncols, double *X, int64_t ld, hipStream_t st) {
+  if (n <= 0 || ncols <= 0) return hipSuccess;
+  zero_cols_kernel<<<dim3((unsigned)ceil_div(n, 256), (unsigned)ncols), 256, 0, st>>>(n, X, ld);
   return hipGetLastError();
 }
 

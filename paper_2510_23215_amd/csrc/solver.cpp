@@ -81,6 +81,7 @@ struct scsf_handle {
   bool graphs = true;                    // outer iterations of chained solves as HIP graphs
   int eig = SCSF_EIG_JACOBI;             // Rayleigh-Ritz eigensolver
   int fuse = 0;                          // Chebyshev steps per fused filter launch (0: one)
+  int batch_form = SCSF_BATCH_GROUPED;   // uneven batches: per-group batches or one sweep
   // autotuned settings: SpMM columns per thread per (k bucket, n bucket), block width per L
   int32_t cpt[4][3] = {{4, 4, 4}, {4, 4, 4}, {4, 4, 4}, {4, 4, 4}};
   std::vector<std::pair<int32_t, int32_t>> widths;
@@ -278,6 +279,14 @@ struct Engine {
   float *E32[3] = {nullptr, nullptr, nullptr}, *R32 = nullptr;
   double *src = nullptr, *gain = nullptr, *winb = nullptr;
   int32_t *lock = nullptr, *nconv = nullptr, *done = nullptr, *flag = nullptr, *need = nullptr;
+  // per-slot widths (one lockstep batch over problems of different (L, k)): slot b's problem
+  // owns columns [off_b, k) of the k-wide block (off_b = k - k_b) and wants L_b pairs; its
+  // columns below off_b are zero, locked from the start, and only the locking, the window's
+  // lowest Ritz value and the extraction look at off_b
+  bool varw = false;
+  int32_t *offv = nullptr, *Lv = nullptr, *h_off = nullptr, *h_Lv = nullptr;
+  int32_t off(int b) const { return varw ? h_off[b] : 0; }
+  int32_t Lof(int b) const { return varw ? h_Lv[b] : L; }
   OpDev *ops = nullptr;
   int32_t *rows = nullptr, *h_rows = nullptr;   // per-problem row count (uneven batches)
   int cpt = 2;                                  // filter-step tile (autotuned)
@@ -346,12 +355,14 @@ struct Engine {
     STCHK(alloc(B_THETA, (size_t)B * k, &theta));
     STCHK(alloc(B_RES, (size_t)B * k, &res));
     int32_t *ints = nullptr;
-    STCHK(alloc(B_INT, (size_t)B * 5, &ints));
+    STCHK(alloc(B_INT, (size_t)B * 7, &ints));
     lock = ints;
     nconv = ints + B;
     done = ints + 2 * B;
     flag = ints + 3 * B;
     need = ints + 4 * B;
+    offv = ints + 5 * B;
+    Lv = ints + 6 * B;
     STCHK(alloc(B_BND, (size_t)B * 4, &bnd));
     STCHK(alloc(B_COEF, (size_t)std::max(m, 1) * B * 3, &coef));
     if (mag) {
@@ -390,8 +401,8 @@ struct Engine {
     int32_t *perm_d = nullptr;                // extract()'s column order
     STCHK(alloc(B_SORTO, (size_t)B * k, &perm_d));
     if (measure) return SCSF_OK;
-    // pinned: 6 int arrays of B, perm B*k, theta/res B*k, bnd B*4, unit B*3, ops B
-    const size_t pin = (size_t)B * 9 * 4 + (size_t)B * k * 8 + (size_t)B * k * 16 +
+    // pinned: 8 int arrays of B, perm B*k, theta/res B*k, bnd B*4, unit B*3, ops B
+    const size_t pin = (size_t)B * 11 * 4 + (size_t)B * k * 8 + (size_t)B * k * 16 +
                        (size_t)B * 4 * 8 + (size_t)B * 6 * 8 + (size_t)B * sizeof(OpDev) + 2048;
     STCHK(grow_pinned(h, pin));
     char *pp = static_cast<char *>(h->pinned);
@@ -400,14 +411,16 @@ struct Engine {
       pp += (bytes + 63) / 64 * 64;
       return r;
     };
-    // the five int arrays in the device layout (lock | nconv | done | flag | need), so the
-    // per-iteration readback and the state upload are one or two copies
-    int32_t *h_ints = (int32_t *)take((size_t)B * 5 * 4);
+    // the int arrays in the device layout (lock | nconv | done | flag | need | off | L), so
+    // the per-iteration readback and the state upload are one or two copies
+    int32_t *h_ints = (int32_t *)take((size_t)B * 7 * 4);
     h_lock = h_ints;
     h_nconv = h_ints + B;
     h_done = h_ints + 2 * B;
     h_flag = h_ints + 3 * B;
     h_need = h_ints + 4 * B;
+    h_off = h_ints + 5 * B;
+    h_Lv = h_ints + 6 * B;
     h_perm = (int32_t *)take((size_t)B * k * 4);
     h_theta = (double *)take((size_t)B * k * 8);
     h_res = (double *)take((size_t)B * k * 8);
@@ -420,8 +433,10 @@ struct Engine {
     h_cdeg = (int32_t *)take((size_t)B * k * 4);
     h_hint = (double *)take((size_t)B * 3 * 8);
     if ((size_t)(pp - static_cast<char *>(h->pinned)) > h->pinned_bytes) return SCSF_ENOMEM;
+    varw = false;
     for (int b = 0; b < B; ++b) {
-      h_lock[b] = h_nconv[b] = h_done[b] = h_flag[b] = h_need[b] = 0;
+      h_lock[b] = h_nconv[b] = h_done[b] = h_flag[b] = h_need[b] = h_off[b] = 0;
+      h_Lv[b] = L;
       h_mdeg[b] = h_mraw[b] = adaptive ? m_base : m_;
       h_rows[b] = (int32_t)n;
       for (int c = 0; c < k; ++c) h_cdeg[(size_t)b * k + c] = m_base;
@@ -489,6 +504,18 @@ struct Engine {
     for (int b = 0; b < B; ++b) h_rows[b] = (int32_t)h_ops[b].n;
     HIPCHK(hipMemcpyAsync(ops, h_ops, (size_t)B * sizeof(OpDev), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(rows, h_rows, (size_t)B * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return SCSF_OK;
+  }
+  // per-slot widths k_b <= k and pair counts L_b < k_b (a mixed-width batch)
+  int set_widths(const std::vector<int32_t> &kb, const std::vector<int32_t> &Lb) {
+    varw = true;
+    for (int b = 0; b < B; ++b) {
+      h_off[b] = k - kb[b];
+      h_Lv[b] = Lb[b];
+      h_lock[b] = h_nconv[b] = h_off[b];
+    }
+    HIPCHK(hipMemcpyAsync(offv, h_off, (size_t)B * 2 * 4, hipMemcpyHostToDevice, st));  // off, L
     HIPCHK(hipStreamSynchronize(st));
     return SCSF_OK;
   }
@@ -621,14 +648,17 @@ struct Engine {
     return SCSF_OK;
   }
 
-  // Cold start of the problems whose h_lock[b] == 0 while every other problem is parked
-  // (lock = k): Gaussian block, orthonormalisation and one Rayleigh-Ritz (no locking).
+  // Cold start of the listed problems while every other problem is parked (lock = k):
+  // Gaussian block (on the problem's own columns; the placeholders below off_b are zeroed),
+  // orthonormalisation and one Rayleigh-Ritz (no locking).
   int cold_start(const std::vector<int> &slots) {
     std::vector<int32_t> saved(h_lock, h_lock + B);
     for (int b = 0; b < B; ++b) h_lock[b] = k;
     for (int b : slots) {
-      h_lock[b] = 0;
-      HIPCHK(gaussian_fill(1, h_rows[b], ld, bs, k, X + (int64_t)b * bs,
+      const int o = off(b);
+      h_lock[b] = o;
+      HIPCHK(zero_columns(ld, o, X + (int64_t)b * bs, ld, st));
+      HIPCHK(gaussian_fill(1, h_rows[b], ld, bs, k - o, X + (int64_t)b * bs + (int64_t)o * ld,
                            seed * 0x9E3779B97F4A7C15ULL + (uint64_t)b * 0xD1B54A32D192ED03ULL + 1,
                            st));
     }
@@ -640,7 +670,7 @@ struct Engine {
     STCHK(rayleigh_ritz(X));
     HIPCHK(hipEventRecord(pev[7], st));
     for (int b = 0; b < B; ++b) h_lock[b] = saved[b];
-    for (int b : slots) h_lock[b] = 0;
+    for (int b : slots) h_lock[b] = off(b);
     STCHK(upload_state());
     std::vector<char> who(B, 0);
     for (int b : slots) who[b] = 1;
@@ -650,7 +680,7 @@ struct Engine {
   }
 
   std::vector<int32_t> lock_before;
-  int32_t h_lock_prev(int b) const { return lock_before.empty() ? 0 : lock_before[b]; }
+  int32_t h_lock_prev(int b) const { return lock_before.empty() ? off(b) : lock_before[b]; }
 
   // The three parts of one outer iteration: window + coefficients, the degree-M filter, and
   // orthonormalisation + Rayleigh-Ritz + residuals + locking.  All of them only launch
@@ -658,7 +688,7 @@ struct Engine {
   int enqueue_pre(int M) {
     HIPCHK(fill_int(flag, 0, B, st));
     HIPCHK(cheb_coeffs(B, k, M, theta, bnd, done, coef, mixed ? winb : nullptr, hint, st,
-                       mag ? coef2 : nullptr));
+                       mag ? coef2 : nullptr, varw ? offv : nullptr));
     return SCSF_OK;
   }
   int enqueue_filter(int M, bool timed) {
@@ -780,7 +810,7 @@ struct Engine {
   int enqueue_post(int /*M*/) {
     HIPCHK(residuals(B, n, ld, X, W, bs, k, lock, theta, res, st, rows));
     HIPCHK(lock_update(B, k, L, tol, lock, nconv, res, theta, mag ? 1 : mag_low ? 2 : 0, done,
-                       flag, st));
+                       flag, st, varw ? offv : nullptr, varw ? Lv : nullptr));
     if (adaptive)
       HIPCHK(adaptive_degrees(B, k, lock, done, theta, res, bnd, tol, m_base, m, cdeg, mdeg, st));
     return SCSF_OK;
@@ -976,22 +1006,24 @@ struct Engine {
   // *certified = false when the block ran out of pairs before the certificate held.
   int extract(int b, double *evals, double *evecs, int64_t ldo, double *maxres,
               bool *certified = nullptr) {
-    const double *th = h_theta + (size_t)b * k;
+    // the problem's own columns [o, k) and pair count (per-slot widths; else 0 and L)
+    const int o = off(b), Lb = Lof(b), kb = k - o;
+    const double *th = h_theta + (size_t)b * k + o;
     int32_t *perm = h_perm + (size_t)b * k;
-    const int nc = std::min<int>(h_nconv[b], k);
-    int nsel = std::max<int>(L, nc);
+    const int nc = std::min<int>(h_nconv[b] - o, kb);
+    int nsel = std::max<int>(Lb, nc);
     std::iota(perm, perm + nsel, 0);
     if (mag_low) {
       // the lowest converged pairs (at or below the smallest unconverged Ritz value), ordered
       // by |theta|; their first L are the wanted ones when the certificate held
-      const double tu = nc < k ? th[nc] : INFINITY;
+      const double tu = nc < kb ? th[nc] : INFINITY;
       int q = 0;
       for (int c = 0; c < nc; ++c)
         if (th[c] <= tu) perm[q++] = c;
-      if (q >= L) {
+      if (q >= Lb) {
         nsel = q;
       } else {
-        nsel = std::max<int>(L, nc);
+        nsel = std::max<int>(Lb, nc);
         std::iota(perm, perm + nsel, 0);
       }
       std::stable_sort(perm, perm + nsel,
@@ -1006,19 +1038,19 @@ struct Engine {
     if (certified) *certified = !(mag_low && ((h_flag[b] & 16) || !h_done[b]));
     double *vals = h_theta + (size_t)b * k;  // reorder in place after computing the maximum
     double mr = 0.0;
-    for (int j = 0; j < L; ++j) mr = std::max(mr, h_res[(size_t)b * k + perm[j]]);
-    std::vector<double> sorted(L);
-    for (int j = 0; j < L; ++j) sorted[j] = th[perm[j]];
-    for (int j = 0; j < L; ++j) vals[j] = sorted[j];
+    for (int j = 0; j < Lb; ++j) mr = std::max(mr, h_res[(size_t)b * k + o + perm[j]]);
+    std::vector<double> sorted(Lb);
+    for (int j = 0; j < Lb; ++j) sorted[j] = th[perm[j]];
+    for (int j = 0; j < Lb; ++j) vals[j] = sorted[j];
     int32_t *perm_d = nullptr;
     STCHK(grow(h, B_SORTO, (size_t)B * k, &perm_d));
-    HIPCHK(hipMemcpyAsync(perm_d + (size_t)b * k, perm, (size_t)L * 4, hipMemcpyHostToDevice,
+    HIPCHK(hipMemcpyAsync(perm_d + (size_t)b * k, perm, (size_t)Lb * 4, hipMemcpyHostToDevice,
                           st));
-    HIPCHK(hipMemcpyAsync(evals, vals, (size_t)L * 8, hipMemcpyHostToDevice, st));
-    HIPCHK(gather_columns_signed(h_rows[b], L, X + (int64_t)b * bs, ld, perm_d + (size_t)b * k,
-                                 evecs, ldo, st));
+    HIPCHK(hipMemcpyAsync(evals, vals, (size_t)Lb * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(gather_columns_signed(h_rows[b], Lb, X + (int64_t)b * bs + (int64_t)o * ld, ld,
+                                 perm_d + (size_t)b * k, evecs, ldo, st));
     if (h_ops[b].kind == SCSF_PLATE)             // u = M^{-1/2} y, M-orthonormal
-      HIPCHK(scale_rows_rsqrt(h_rows[b], L, evecs, ldo, h_ops[b].wy, st));
+      HIPCHK(scale_rows_rsqrt(h_rows[b], Lb, evecs, ldo, h_ops[b].wy, st));
     // No wait here: the two copies read this slot's own pinned rows (h_perm, h_theta), which
     // the host writes again only after fetch(b) has synchronised the stream, and the outputs
     // are complete when the caller's solve returns (its streams are synchronised).
@@ -1063,6 +1095,16 @@ struct Group {
   int32_t L = 0, k = 0;
   int64_t nmax = 0;
   const int64_t *eoff = nullptr, *voff = nullptr;   // evals / evecs offsets by operator index
+};
+
+// The chains of one lockstep batch over several (L, k) groups: per chain, its group's width
+// and pair count and, with the dynamic schedule, its group's counter and the end of its
+// group's range in the order (the groups' orders are concatenated).  The batch's block width
+// is the largest k.
+struct Mix {
+  std::vector<int32_t> L, k;
+  std::vector<std::atomic<int> *> next;   // null entries: static schedule
+  std::vector<int32_t> end;
 };
 
 // Grid stencils on square grids: the Ritz vectors can move between sides by interpolation.
@@ -1131,7 +1173,8 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
                double *evals, double *evecs, double *ritz, scsf_stats *stats_host,
                const Group *grp = nullptr, bool graphs = false, int cpt = 4,
                int eig = SCSF_EIG_JACOBI, Fallback *fallback = nullptr,
-               bool square_forced = false, int fuse = 0, const double *bnd_table = nullptr) {
+               bool square_forced = false, int fuse = 0, const double *bnd_table = nullptr,
+               const Mix *mix = nullptr) {
   const int chains = (int)cb.size();
   if (chains == 0) return SCSF_OK;
   const int64_t n = grp ? grp->nmax : ops_host[0].n;
@@ -1154,6 +1197,7 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
   e.fuse = fuse;
   e.pot = false;                             // fixed for the engine: graphs keep the choice
   for (int i = 0; i < n_op; ++i) e.pot = e.pot || ops_host[order_host[i]].v != nullptr;
+  if (mix) STCHK(e.set_widths(mix->k, mix->L));
   std::vector<int> pos(chains), iters(chains, 0);
   std::vector<int64_t> fcols(chains, 0);
   std::vector<std::chrono::steady_clock::time_point> t_load(chains,
@@ -1236,7 +1280,7 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
       if (stats_host) {
         scsf_stats &st = stats_host[op];
         st.iterations = iters[b];
-        st.nconv = e.h_nconv[b];
+        st.nconv = e.h_nconv[b] - e.off(b);
         st.status = status;
         st.chol_shifts = (e.h_flag[b] & 4) ? 1 : 0;
         st.degree = e.adaptive ? e.it_deg[b] : e.var_deg ? e.h_mdeg[b] : m;
@@ -1256,14 +1300,15 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
       if (!(refit && status == SCSF_ENOTCONV) && status != SCSF_OK &&
           (worst == SCSF_OK || status != SCSF_ENOTCONV))
         worst = status;
-      if (next) {
-        pos[b] = next->fetch_add(1);
+      std::atomic<int> *nx = mix ? mix->next[b] : next;   // this chain's dynamic counter
+      if (nx) {
+        pos[b] = nx->fetch_add(1);
       } else {
         ++pos[b];
       }
       iters[b] = 0;
       fcols[b] = 0;
-      if (pos[b] >= (next ? n_op : ce[b])) {
+      if (pos[b] >= (nx ? (mix ? mix->end[b] : n_op) : ce[b])) {
         active[b] = 0;
         --remaining;
         e.h_done[b] = 1;
@@ -1290,8 +1335,8 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
       t_load[b] = std::chrono::steady_clock::now();
       e.h_need[b] = 1;
       e.h_done[b] = 0;
-      e.h_nconv[b] = 0;
-      e.h_lock[b] = 0;
+      e.h_nconv[b] = e.off(b);
+      e.h_lock[b] = e.off(b);
       reload = true;
     }
     if (reload) {
@@ -1499,6 +1544,12 @@ int scsf_set_graphs(scsf_handle *h, int on) {
 int scsf_set_fused_steps(scsf_handle *h, int steps) {
   if (!h || steps < 0 || steps == 1 || steps > 4) return SCSF_EINVAL;
   h->fuse = steps;
+  return SCSF_OK;
+}
+
+int scsf_set_batch_form(scsf_handle *h, int form) {
+  if (!h || (form != SCSF_BATCH_GROUPED && form != SCSF_BATCH_ONE_SWEEP)) return SCSF_EINVAL;
+  h->batch_form = form;
   return SCSF_OK;
 }
 
@@ -2114,6 +2165,8 @@ int scsf_solve_batched_hinted(scsf_handle *h, const scsf_operator *ops_host, int
       !evecs || !prm)
     return SCSF_EINVAL;
   if (hints_host && (prm->adaptive || prm->target == SCSF_TARGET_MAGNITUDE)) return SCSF_EINVAL;
+  const bool one_sweep = h->batch_form == SCSF_BATCH_ONE_SWEEP;
+  if (one_sweep && (prm->adaptive || prm->target == SCSF_TARGET_MAGNITUDE)) return SCSF_EINVAL;
   std::vector<int32_t> kk(n_op);
   for (int i = 0; i < n_op; ++i) {
     STCHK(check_op(&ops_host[i]));
@@ -2181,6 +2234,81 @@ int scsf_solve_batched_hinted(scsf_handle *h, const scsf_operator *ops_host, int
   std::vector<std::atomic<int>> next(groups.size());
   for (size_t gi = 0; gi < groups.size(); ++gi) next[gi] = groups[gi].chains;
   std::vector<int> status(lanes, SCSF_OK);
+  if (one_sweep) {
+    // One lockstep batch per lane over the chains of every group of a kind: each sweep (outer
+    // iteration) of a lane covers problems of all (L, k) of that kind at once, in the same
+    // graph launches, each problem in the last k_g columns of a block as wide as the widest
+    // group.  The groups' orders are concatenated; a chain keeps its group's range.
+    std::vector<int32_t> kinds;
+    for (const auto &g : groups)
+      if (std::find(kinds.begin(), kinds.end(), g.kind) == kinds.end()) kinds.push_back(g.kind);
+    struct Batch {
+      std::vector<int32_t> order;
+      std::vector<int> gi, head, end;            // per chain: group, first and end position
+      Group grp;
+    };
+    std::vector<Batch> batches(kinds.size());
+    for (size_t t = 0; t < kinds.size(); ++t) {
+      Batch &bt = batches[t];
+      bt.grp.eoff = eoff.data();
+      bt.grp.voff = voff.data();
+      for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const G &g = groups[gi];
+        if (g.kind != kinds[t]) continue;
+        const int start = (int)bt.order.size(), nord = (int)g.order.size();
+        bt.order.insert(bt.order.end(), g.order.begin(), g.order.end());
+        for (int cc = 0; cc < g.chains; ++cc) {
+          bt.gi.push_back((int)gi);
+          bt.head.push_back(start + (dyn ? cc : (int)((int64_t)nord * cc / g.chains)));
+          bt.end.push_back(start + (dyn ? nord : (int)((int64_t)nord * (cc + 1) / g.chains)));
+        }
+        next[gi] = start + g.chains;             // absolute positions in the joint order
+        bt.grp.L = std::max(bt.grp.L, g.L);
+        bt.grp.k = std::max(bt.grp.k, g.k);
+        bt.grp.nmax = std::max(bt.grp.nmax, g.nmax);
+      }
+    }
+    auto sweep_fn = [&](int l) {
+      if (hipSetDevice(h->device) != hipSuccess) { status[l] = SCSF_EHIP; return; }
+      const size_t nb = batches.size();
+      for (size_t j = 0; j < nb; ++j) {
+        const Batch &bt = batches[(j + (size_t)l) % nb];
+        std::vector<int> cb, ce;
+        Mix mix;
+        for (size_t cc = (size_t)l; cc < bt.gi.size(); cc += (size_t)lanes) {
+          const G &g = groups[bt.gi[cc]];
+          cb.push_back(bt.head[cc]);
+          ce.push_back(dyn ? bt.head[cc] + 1 : bt.end[cc]);
+          mix.L.push_back(g.L);
+          mix.k.push_back(g.k);
+          mix.next.push_back(dyn ? &next[bt.gi[cc]] : nullptr);
+          mix.end.push_back(bt.end[cc]);
+        }
+        if (cb.empty()) continue;
+        const int s2 = run_chains(h->ws[l + 1], ops_host, bt.order.data(), (int)bt.order.size(),
+                                  cb, ce, nullptr, prm, hints_host, evals, evecs, nullptr,
+                                  stats_host, &bt.grp, h->graphs,
+                                  tuned_cpt(h, bt.grp.nmax, bt.grp.k), h->eig, nullptr, false,
+                                  h->fuse, nullptr, &mix);
+        if (s2 != SCSF_OK && (status[l] == SCSF_OK ||
+                              (status[l] == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)))
+          status[l] = s2;
+        if (s2 != SCSF_OK && s2 != SCSF_ENOTCONV) return;
+      }
+    };
+    std::vector<std::thread> threads;
+    for (int l = 1; l < lanes; ++l) threads.emplace_back(sweep_fn, l);
+    sweep_fn(0);
+    for (auto &t : threads) t.join();
+    (void)hipEventDestroy(ready);
+    int worst = SCSF_OK;
+    for (int l = 0; l < lanes; ++l) {
+      const int s2 = status[l];
+      if (s2 == SCSF_OK) continue;
+      if (worst == SCSF_OK || (worst == SCSF_ENOTCONV && s2 != SCSF_ENOTCONV)) worst = s2;
+    }
+    return worst;
+  }
   std::vector<Fallback> fbs(groups.size());     // smallest magnitude: uncertified lower ends
   // every lane works through the groups in turn, starting at group l mod G, so all groups are
   // in flight from the start (narrow groups' dense steps overlap wide groups' filters); a lane

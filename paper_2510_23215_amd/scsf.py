@@ -23,6 +23,7 @@ SCSF_FP64, SCSF_MIXED = 0, 1
 SCSF_SCHED_STATIC, SCSF_SCHED_DYNAMIC = 0, 1
 SCSF_TARGET_SMALLEST, SCSF_TARGET_MAGNITUDE = 0, 1
 SCSF_EIG_JACOBI, SCSF_EIG_TRIDIAG = 0, 1
+SCSF_BATCH_GROUPED, SCSF_BATCH_ONE_SWEEP = 0, 1
 
 
 class ScsfError(RuntimeError):
@@ -119,6 +120,7 @@ def lib():
         sig["scsf_profile_enable"] = [vp, i32]
         sig["scsf_set_lanes"] = [vp, i32]
         sig["scsf_set_fused_steps"] = [vp, i32]
+        sig["scsf_set_batch_form"] = [vp, i32]
         sig["scsf_set_graphs"] = [vp, i32]
         sig["scsf_set_eigensolver"] = [vp, i32]
         sig["scsf_profile_read"] = [vp, POINTER(Profile), i32]
@@ -585,6 +587,11 @@ def scsf_workspace_peak(h: Handle) -> int:
     out = ctypes.c_size_t()
     _check(lib().scsf_workspace_peak(h.ptr, ctypes.byref(out)), "scsf_workspace_peak")
     return int(out.value)
+
+
+def scsf_set_batch_form(h: Handle, form: int):
+    """SCSF_BATCH_GROUPED (per-(L, k) batches) or SCSF_BATCH_ONE_SWEEP (one batch per kind)."""
+    _check(lib().scsf_set_batch_form(h.ptr, int(form)), "scsf_set_batch_form")
 
 
 def scsf_set_fused_steps(h: Handle, steps: int):

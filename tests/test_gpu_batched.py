@@ -90,11 +90,19 @@ def family_order(h, ops, p0):
     return order
 
 
+FORMS = [scsf.SCSF_BATCH_GROUPED, scsf.SCSF_BATCH_ONE_SWEEP]
+FORM_IDS = ["grouped", "one_sweep"]
+
+
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
 @pytest.mark.parametrize("chains,lanes,sched", [(1, 1, 0), (4, 2, 0), (6, 3, 1), (14, 4, 1)])
-def test_batched_small_matches_oracle(chains, lanes, sched):
-    say("batched small chains", chains, "lanes", lanes, "schedule", sched)
+def test_batched_small_matches_oracle(chains, lanes, sched, form):
+    """Widths 8 and 16 with L in {4, 8, 12}: in the one-sweep form the L = 4 problems sit in
+    the last 8 columns of 16-wide blocks, beside problems with other L of the same width."""
+    say("batched small chains", chains, "lanes", lanes, "schedule", sched, "form", form)
     h = scsf.Handle()
     scsf.scsf_set_lanes(h, lanes)
+    scsf.scsf_set_batch_form(h, form)
     ops, Ls = small_uneven()
     order = family_order(h, ops, 6)
     prm = scsf.make_params(0, 0, 20, 1e-8, seed=2, schedule=sched)
@@ -173,6 +181,56 @@ def test_batched_uneven_full_sizes_sampled(h):
         A = O.assemble(ops[i])
         w, V = E.smallest_eigenpairs(A, Ls[i] + 10)
         check_pairs(A, evals[i], evecs[i].t(), Ls[i], cfg.tol, w, V)
+
+
+@pytest.mark.parametrize("sched", [scsf.SCSF_SCHED_STATIC, scsf.SCSF_SCHED_DYNAMIC],
+                         ids=["static", "dynamic"])
+def test_batched_one_sweep_full_sizes_against_grouped(h, sched):
+    """The uneven workload's shapes (sides 48..128, L in {32, 64, 128}, widths 48 / 96 / 160,
+    both families) as one lockstep batch per lane: every pair's residual, the eigenvalues
+    against the grouped form's, and sampled operators against shift-invert."""
+    say("batched one sweep full sizes", sched)
+    cfg = si.CONFIGS[3]
+    count = 24
+    ops = si.operators(cfg, count)
+    Ls = [si.mixed_L(cfg, i) for i in range(count)]
+    order = family_order(h, ops, cfg.p0)
+    dops = [scsf.DeviceOperator(o) for o in ops]
+    prm = scsf.make_params(0, 0, cfg.degree, cfg.tol, seed=1, schedule=sched)
+    g = scsf.Handle()
+    scsf.scsf_set_lanes(g, 3)
+    e_g, _, _ = scsf.scsf_solve_batched(g, dops, Ls, order, 8, prm)
+    scsf.scsf_set_batch_form(g, scsf.SCSF_BATCH_ONE_SWEEP)
+    evals, evecs, stats = scsf.scsf_solve_batched(g, dops, Ls, order, 8, prm)
+    say([(o.N, L, s["iterations"]) for o, L, s in zip(ops, Ls, stats)])
+    for i, o in enumerate(ops):
+        assert stats[i]["status"] == 0 and stats[i]["nconv"] >= Ls[i]
+        A = O.assemble(o)
+        X = host(evecs[i]).T
+        lam = host(evals[i])
+        W = A @ X
+        rel = np.linalg.norm(W - X * lam, axis=0) / np.linalg.norm(W, axis=0)
+        assert rel.max() <= cfg.tol * (1 + 1e-6)
+        assert np.all(np.diff(lam) >= 0)
+        np.testing.assert_allclose(lam, host(e_g[i]), rtol=1e-10)
+    for i in sorted({order[0], max(range(count), key=lambda j: Ls[j] * 1000 - ops[j].N)}):
+        A = O.assemble(ops[i])
+        w, V = E.smallest_eigenpairs(A, Ls[i] + 10)
+        check_pairs(A, evals[i], evecs[i].t(), Ls[i], cfg.tol, w, V)
+
+
+def test_batch_form_errors(h):
+    ops, Ls = small_uneven(2, 7)
+    d = [scsf.DeviceOperator(o) for o in ops]
+    with pytest.raises(scsf.ScsfError):
+        scsf.scsf_set_batch_form(h, 2)
+    g = scsf.Handle()
+    scsf.scsf_set_batch_form(g, scsf.SCSF_BATCH_ONE_SWEEP)
+    with pytest.raises(scsf.ScsfError):                       # adaptive degrees
+        scsf.scsf_solve_batched(g, d, Ls, [0, 1], 1, scsf.make_params(0, 0, 20, 1e-8, adaptive=1))
+    with pytest.raises(scsf.ScsfError):                       # smallest magnitude
+        scsf.scsf_solve_batched(g, d, Ls, [0, 1], 1, scsf.make_params(
+            0, 0, 20, 1e-8, target=scsf.SCSF_TARGET_MAGNITUDE))
 
 
 # ------------------------------------------------------------------------------ autotuner
@@ -298,14 +356,17 @@ def test_gram_batched(n, k):
         scsf.scsf_gram_batched(h, torch.zeros((2, 257, 300), dtype=torch.float64, device="cuda"))
 
 
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
 @pytest.mark.parametrize("precision", [scsf.SCSF_FP64, scsf.SCSF_MIXED], ids=["fp64", "mixed"])
-def test_batched_mixed_precision_and_hints_match_oracle(precision):
+def test_batched_mixed_precision_and_hints_match_oracle(precision, form):
     """The layered forms on an uneven batch: FP32 filter (residual form), per-operator window
     and degree hints (here the oracle's lambda_1 and lambda_{L+1} and a degree per operator),
-    sides and L differing within the batch, against the dense FP64 eigenpairs."""
-    say("batched mixed + hints", precision)
+    sides and L differing within the batch, against the dense FP64 eigenpairs; in both batch
+    forms (per-(L, k) batches, and one batch over every width)."""
+    say("batched mixed + hints", precision, "form", form)
     h = scsf.Handle()
     scsf.scsf_set_lanes(h, 2)
+    scsf.scsf_set_batch_form(h, form)
     ops, Ls = small_uneven()
     order = family_order(h, ops, 6)
     ref = []

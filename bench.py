@@ -53,7 +53,7 @@ def workload(cfg_index: int, count: int | None):
 
 
 def measured_traffic(cfg_name: str, launch: dict):
-    """HBM bytes per filter launch (FETCH_SIZE + WRITE_SIZE of the filter kernel, each scaled
+    """HBM bytes per Chebyshev step (FETCH_SIZE + WRITE_SIZE of the filter kernels, each scaled
     by what the counter reads for a device copy of known size) from the committed counter
     record of this workload, while the filter step's source and the launch configuration
     (chains, lanes, schedule, graphs, tile, form, precision, fused steps, degrees, training
@@ -76,7 +76,8 @@ def measured_traffic(cfg_name: str, launch: dict):
         return None
     if any(str(v) != rec.get(key) for key, v in launch.items()):
         return None
-    return float(rec["bytes_per_launch"])
+    val = rec.get("bytes_per_chebyshev_step")
+    return float(val) if val is not None else None
 
 
 def isolated_spmm(scsf, torch, h, dops, k, degree, blocks):
@@ -541,21 +542,25 @@ def main():
     # filter's own live time beside it; the lanes overlap, so their sum can exceed a step.
     bytes_step = prof["filter_bytes"] / args.steps
     achieved = bytes_step / (dt / args.steps) / 1e9
+    # the library counts Chebyshev steps: a fused launch of S steps counts S
     live_ms = prof["filter_ms"] / max(prof["filter_launches"], 1)
-    # HBM bytes of the filter per step: the committed counter record's bytes per launch (while
-    # it matches this source and launch configuration) times the live launches per step.  The
-    # degrees and the training length set the mix of launch widths, so they are part of the key.
+    # HBM bytes of the filter per step: the committed counter record's bytes per Chebyshev
+    # step (while it matches this source and launch configuration) times the live Chebyshev
+    # steps per step.  The degrees and the training length set the mix of launch widths, so
+    # they are part of the key.
     learned_key = ({"head_degree": head_deg_used, "epochs": args.epochs} if form == "learned"
                    else {})
-    per_launch = (measured_traffic(cfg.name, {"chains": args.chains, "lanes": args.lanes,
+    per_cheb_step = (measured_traffic(cfg.name, {"chains": args.chains, "lanes": args.lanes,
                                               "schedule": args.schedule, "graphs": args.graphs,
                                               "tile": tile_used, "form": form,
                                               "precision": precision,
                                               "fused_steps": args.fused_steps,
-                                              "degree": degree, **learned_key})
+                                              "degree": degree, **learned_key,
+                                              **({"batch_form": args.batch_form} if uneven
+                                                 else {})})
                   if not adaptive else None)
-    traffic_step = (per_launch * prof["filter_launches"] / args.steps
-                    if per_launch is not None else None)
+    traffic_step = (per_cheb_step * prof["filter_launches"] / args.steps
+                    if per_cheb_step is not None else None)
     stencil = "9-point Q1" if windowed else "5-point"
     if cfg.family == "plate":
         kname = ("spmm_plate_kernel (Chebyshev three-term step, 13-point thin-plate standard "
@@ -616,9 +621,9 @@ def main():
             "traffic": traffic_step,
             "basis": "filter algorithmic bytes per step / wall time per step",
             "algorithmic_bytes_per_step": bytes_step,
-            "launches_per_step": prof["filter_launches"] / args.steps,
+            "chebyshev_steps_per_step": prof["filter_launches"] / args.steps,
             "live_filter_ms_per_step": prof["filter_ms"] / args.steps,
-            "live_avg_span_ms": live_ms,
+            "live_ms_per_chebyshev_step": live_ms,
         },
     }
     # device time of each step of Algorithm 3 summed over the lanes (they overlap), per step,

@@ -28,7 +28,7 @@ def write_record(root, launch, source_text=None):
             f.write(source_text)
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     lines = ["# test record", "source paper_2510_23215_amd/csrc/spmm.hip",
-             f"source_sha256_16 {digest}", "bytes_per_launch 123456789"]
+             f"source_sha256_16 {digest}", "bytes_per_chebyshev_step 123456789"]
     lines += [f"{k} {v}" for k, v in launch.items()]
     os.makedirs(os.path.join(root, "profiles"), exist_ok=True)
     with open(os.path.join(root, "profiles", "spmm_traffic_c9_test.txt"), "w") as f:
@@ -46,6 +46,26 @@ def test_traffic_record_matches_only_its_source_and_launch(tmp_path, monkeypatch
     assert bench.measured_traffic("c9_test", dict(LAUNCH, lanes=8)) is None
     assert bench.measured_traffic("c9_test", dict(LAUNCH, tile=2)) is None
     assert bench.measured_traffic("c9_missing", LAUNCH) is None
+
+
+def test_committed_traffic_records_are_complete():
+    """Every committed counter record carries the fields bench.py reads: the source it was
+    taken on, its hash, the launch keys, and the HBM bytes per Chebyshev step (the library
+    counts a fused launch of S steps as S)."""
+    import glob
+    paths = glob.glob(os.path.join(ROOT, "profiles", "spmm_traffic_*.txt"))
+    assert paths
+    for path in paths:
+        rec = {}
+        for line in open(path):
+            line = line.strip()
+            if line and not line.startswith("#"):
+                key, _, val = line.partition(" ")
+                rec[key] = val.strip()
+        for key in ("source", "source_sha256_16", "bytes_per_chebyshev_step", *LAUNCH):
+            assert key in rec, (path, key)
+        assert float(rec["bytes_per_chebyshev_step"]) > 0
+        assert os.path.isfile(os.path.join(ROOT, rec["source"]))
 
 
 def test_traffic_record_is_dropped_when_the_step_source_changes(tmp_path, monkeypatch):

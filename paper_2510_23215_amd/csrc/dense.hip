@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(512) chol_inv_kernel(
 
 // Blocked form of the same factorisation for active widths up to 128 (8 blocks of 16 columns),
 // one workgroup of 8 waves per problem.  The scaled matrix lives in a square LDS array A
-// (column stride kCbLS): R in the upper triangle, the strict upper triangle of T = R^-1 stored
+// (R rows, odd column stride R + 1): R in the upper triangle, the strict upper triangle of T = R^-1 stored
 // transposed in the lower triangle, T's diagonal in tdg.  Padding columns up to 16 KW are the
 // identity, so every block operation is well defined.  Per block column J: wave 0 factors the
 // 16 x 16 diagonal block in registers (lane c holds column c), 16-column panels are solved by
@@ -132,10 +132,7 @@ __global__ void __launch_bounds__(512) chol_inv_kernel(
 // f64 MFMA; the inverse takes the diagonal blocks (one wave each) and then one block column of
 // T at a time, T(:J, J) = -T(:J, :J) R(:J, J) T_JJ, again on MFMA tiles.  About 3 barriers per
 // 16 columns instead of 3 per column.
-constexpr int kCbLS = 129;                 // odd column stride: fragment loads spread over banks
 constexpr int kCbMax = 128;
-
-__device__ inline double cb_get(const double *A, int r, int c) { return A[r + c * kCbLS]; }
 
 // C(16x16) = sum over kk of X(i, kk) Y(kk, j), the fragments from the accessors; acc in the
 // MFMA D layout (lane holds C[lane/16 + 4 v][lane % 16]).
@@ -149,13 +146,15 @@ __device__ inline v4d cb_tile(v4d acc, int lane, FX fx, FY fy) {
   return acc;
 }
 
+template <int R>
 __global__ void __launch_bounds__(512) chol_inv_blocked_kernel(
     int64_t n, int32_t k, const int32_t *__restrict__ lock, const double *__restrict__ G,
     double *__restrict__ M, int32_t ldm, int32_t *__restrict__ flag,
     const int32_t *__restrict__ gate, int32_t gate_mask) {
-  __shared__ double A[kCbMax * kCbLS];
-  __shared__ double dsc[kCbMax];
-  __shared__ double tdg[kCbMax];
+  constexpr int LS = R + 1;                  // odd column stride: fragment loads spread over banks
+  __shared__ double A[R * LS];
+  __shared__ double dsc[R];
+  __shared__ double tdg[R];
   __shared__ int s_fail;
   __shared__ double s_shift;
   const int b = blockIdx.x;
@@ -181,11 +180,11 @@ __global__ void __launch_bounds__(512) chol_inv_blocked_kernel(
     // scaled upper triangle; identity on the padding
     for (int e = tid; e < Kp * Kp; e += NT) {
       const int i = e % Kp, c = e / Kp;
-      if (i > c) { A[i + c * kCbLS] = 0.0; continue; }
+      if (i > c) { A[i + c * LS] = 0.0; continue; }
       double v;
       if (c < ka) v = (Gb[i + (int64_t)c * ldm] + (i == c ? sh : 0.0)) / (dsc[i] * dsc[c]);
       else v = (i == c) ? 1.0 : 0.0;
-      A[i + c * kCbLS] = v;
+      A[i + c * LS] = v;
     }
     __syncthreads();
     for (int J = 0; J < KW; ++J) {
@@ -194,7 +193,7 @@ __global__ void __launch_bounds__(512) chol_inv_blocked_kernel(
       if (wave == 0) {
         double a[16];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) a[i] = (lane < 16 && i <= lane) ? A[(o + i) + (o + lane) * kCbLS] : 0.0;
+        for (int i = 0; i < 16; ++i) a[i] = (lane < 16 && i <= lane) ? A[(o + i) + (o + lane) * LS] : 0.0;
         int fail = 0;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
@@ -211,7 +210,7 @@ __global__ void __launch_bounds__(512) chol_inv_blocked_kernel(
         }
         if (lane < 16) {
 #pragma unroll
-          for (int i = 0; i < 16; ++i) if (i <= lane) A[(o + i) + (o + lane) * kCbLS] = a[i];
+          for (int i = 0; i < 16; ++i) if (i <= lane) A[(o + i) + (o + lane) * LS] = a[i];
         }
         if (lane == 0 && fail) atomicOr(&s_fail, fail);
       }
@@ -221,13 +220,13 @@ __global__ void __launch_bounds__(512) chol_inv_blocked_kernel(
         double x[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-          double v = A[(o + i) + c * kCbLS];
+          double v = A[(o + i) + c * LS];
 #pragma unroll
-          for (int m = 0; m < i; ++m) v -= A[(o + m) + (o + i) * kCbLS] * x[m];
-          x[i] = v / A[(o + i) + (o + i) * kCbLS];
+          for (int m = 0; m < i; ++m) v -= A[(o + m) + (o + i) * LS] * x[m];
+          x[i] = v / A[(o + i) + (o + i) * LS];
         }
 #pragma unroll
-        for (int i = 0; i < 16; ++i) A[(o + i) + c * kCbLS] = x[i];
+        for (int i = 0; i < 16; ++i) A[(o + i) + c * LS] = x[i];
       }
       __syncthreads();
       // (c) trailing update A(I, L) -= R(J, I)^T R(J, L), J < I <= L, one tile per wave turn
@@ -239,12 +238,12 @@ __global__ void __launch_bounds__(512) chol_inv_blocked_kernel(
         const int oi = 16 * (J + 1 + I), ol = 16 * (J + 1 + L);
         v4d acc;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] = A[(oi + (lane >> 4) + 4 * v) + (ol + (lane & 15)) * kCbLS];
+        for (int v = 0; v < 4; ++v) acc[v] = A[(oi + (lane >> 4) + 4 * v) + (ol + (lane & 15)) * LS];
         acc = cb_tile(acc, lane,
-                      [&](int i, int kk) { return -A[(o + kk) + (oi + i) * kCbLS]; },
-                      [&](int kk, int j) { return A[(o + kk) + (ol + j) * kCbLS]; });
+                      [&](int i, int kk) { return -A[(o + kk) + (oi + i) * LS]; },
+                      [&](int kk, int j) { return A[(o + kk) + (ol + j) * LS]; });
 #pragma unroll
-        for (int v = 0; v < 4; ++v) A[(oi + (lane >> 4) + 4 * v) + (ol + (lane & 15)) * kCbLS] = acc[v];
+        for (int v = 0; v < 4; ++v) A[(oi + (lane >> 4) + 4 * v) + (ol + (lane & 15)) * LS] = acc[v];
       }
       __syncthreads();
     }
@@ -273,12 +272,12 @@ __global__ void __launch_bounds__(512) chol_inv_blocked_kernel(
       double v = 0.0;
       if (lane < 16 && i <= lane) {
         if (i == lane) {
-          v = 1.0 / A[(o + i) + (o + i) * kCbLS];
+          v = 1.0 / A[(o + i) + (o + i) * LS];
         } else {
 #pragma unroll
           for (int m = i + 1; m < 16; ++m)
-            if (m <= lane) v -= A[(o + i) + (o + m) * kCbLS] * t[m];
-          v /= A[(o + i) + (o + i) * kCbLS];
+            if (m <= lane) v -= A[(o + i) + (o + m) * LS] * t[m];
+          v /= A[(o + i) + (o + i) * LS];
         }
       }
       t[i] = v;
@@ -286,7 +285,7 @@ __global__ void __launch_bounds__(512) chol_inv_blocked_kernel(
     if (lane < 16) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        if (i < lane) A[(o + lane) + (o + i) * kCbLS] = t[i];
+        if (i < lane) A[(o + lane) + (o + i) * LS] = t[i];
         else if (i == lane) tdg[o + i] = t[i];
       }
     }
@@ -295,7 +294,7 @@ __global__ void __launch_bounds__(512) chol_inv_blocked_kernel(
   // T(I, J), I < J, one block column at a time: W_M = R(M, J) T_JJ over R(M, J) (M < J), then
   // T(I, J) = -sum_{M = I}^{J-1} T(I, M) W_M, stored transposed in the lower triangle.
   auto Tel = [&](int r, int c) -> double {             // T(r, c), r <= c
-    return (r == c) ? tdg[r] : A[c + r * kCbLS];
+    return (r == c) ? tdg[r] : A[c + r * LS];
   };
   for (int J = 1; J < KW; ++J) {
     const int oj = 16 * J;
@@ -303,10 +302,10 @@ __global__ void __launch_bounds__(512) chol_inv_blocked_kernel(
       const int om = 16 * Mi;
       v4d acc = (v4d){0.0, 0.0, 0.0, 0.0};
       acc = cb_tile(acc, lane,
-                    [&](int i, int kk) { return A[(om + i) + (oj + kk) * kCbLS]; },
+                    [&](int i, int kk) { return A[(om + i) + (oj + kk) * LS]; },
                     [&](int kk, int j) { return kk <= j ? Tel(oj + kk, oj + j) : 0.0; });
 #pragma unroll
-      for (int v = 0; v < 4; ++v) A[(om + (lane >> 4) + 4 * v) + (oj + (lane & 15)) * kCbLS] = acc[v];
+      for (int v = 0; v < 4; ++v) A[(om + (lane >> 4) + 4 * v) + (oj + (lane & 15)) * LS] = acc[v];
     }
     __syncthreads();
     for (int I = wave; I < J; I += NT / 64) {
@@ -319,10 +318,10 @@ __global__ void __launch_bounds__(512) chol_inv_blocked_kernel(
                         const int r = oi + i, c = om + kk;
                         return r <= c ? -Tel(r, c) : 0.0;
                       },
-                      [&](int kk, int j) { return A[(om + kk) + (oj + j) * kCbLS]; });
+                      [&](int kk, int j) { return A[(om + kk) + (oj + j) * LS]; });
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) A[(oj + (lane & 15)) + (oi + (lane >> 4) + 4 * v) * kCbLS] = acc[v];
+      for (int v = 0; v < 4; ++v) A[(oj + (lane & 15)) + (oi + (lane >> 4) + 4 * v) * LS] = acc[v];
     }
     __syncthreads();
   }
@@ -340,8 +339,19 @@ hipError_t chol_inv(int B, int64_t n, int32_t k, const int32_t *lock, const doub
   if (B <= 0) return hipSuccess;
   // each workgroup keeps its packed R (inverted in place) in LDS when its active width fits
   // (ka(ka+1)/2 <= kLdsDoubles), so wide blocks move into LDS as their pairs lock
-  if (k <= kCbMax)
-    chol_inv_blocked_kernel<<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask);
+  // blocked form: its LDS array is sized for the launch's width (R rows, R = k rounded up to
+  // 64 / 80 / 96 / 112 / 128), so narrow blocks leave room on the CU for other lanes' work
+  const int kr = (int)round_up(k, 16);
+  if (kr <= 64)
+    chol_inv_blocked_kernel<64><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask);
+  else if (kr <= 80)
+    chol_inv_blocked_kernel<80><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask);
+  else if (kr <= 96)
+    chol_inv_blocked_kernel<96><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask);
+  else if (kr <= 112)
+    chol_inv_blocked_kernel<112><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask);
+  else if (k <= kCbMax)
+    chol_inv_blocked_kernel<128><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask);
   else
     chol_inv_kernel<true><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask,
                                              scratch);
@@ -383,14 +393,16 @@ constexpr int kJacobiThreads = 1024;
 constexpr int kJacobiBlocksPerThread =
     ((kMaxK / 2) * (kMaxK / 2 + 1) / 2 + kJacobiThreads - 1) / kJacobiThreads;
 
-template <bool LDS>
+// CAP: doubles of LDS for the packed matrix (a problem whose packed K(K+1)/2 exceeds it works in
+// global scratch); the launch sizes it for its width, so narrow blocks leave LDS to other work
+template <int CAP>
 __global__ void __launch_bounds__(kJacobiThreads) jacobi_values_kernel(
     int32_t k, const int32_t *__restrict__ lock, const double *__restrict__ Gin, int32_t ldm,
     double *__restrict__ theta, int32_t *__restrict__ rank_out, double *__restrict__ rec,
     int64_t rec_stride, int32_t *__restrict__ nsweeps, int32_t *__restrict__ flag,
     double *__restrict__ gscr, double stop) {
   constexpr int NT = kJacobiThreads, MAXE = kJacobiBlocksPerThread;
-  __shared__ double lds[LDS ? kLdsDoubles : 1];
+  __shared__ double lds[CAP > 0 ? CAP : 1];
   __shared__ int2 rpq[kMaxK / 2 + 1];
   __shared__ double2 rcs[kMaxK / 2 + 1];
   __shared__ int s_any[2];
@@ -402,7 +414,7 @@ __global__ void __launch_bounds__(kJacobiThreads) jacobi_values_kernel(
   if (ka <= 0) { if (tid == 0) nsweeps[b] = 0; return; }
   const int tx = tid & 15, ty = tid >> 4;              // 16 x 64
   const int K = ka + (ka & 1), half = K / 2;
-  const bool in_lds = LDS && (int64_t)K * (K + 1) / 2 <= kLdsDoubles;
+  const bool in_lds = CAP > 0 && (int64_t)K * (K + 1) / 2 <= CAP;
   double *S = in_lds ? lds : gscr + (int64_t)b * kMaxK * (kMaxK + 1);
   const double *Gb = Gin + (int64_t)b * ldm * ldm;
   double *R = rec + (int64_t)b * rec_stride;           // (c, s) per (sweep, round, slot)
@@ -600,9 +612,24 @@ hipError_t jacobi_eig(int B, int32_t k, const int32_t *lock, double *G, double *
                       int32_t *ranks, int32_t *nsweeps, hipStream_t st, double stop) {
   if (B <= 0) return hipSuccess;
   const int64_t rs = jacobi_record_elems(k);
-  // per problem: the packed matrix in LDS when its active width fits, else global scratch
-  jacobi_values_kernel<true><<<B, kJacobiThreads, 0, st>>>(k, lock, G, ldm, theta, ranks, rec, rs,
-                                                           nsweeps, flag, scratch, stop);
+  // per problem: the packed matrix in LDS when its active width fits, else global scratch; the
+  // LDS array is sized for the launch's width (K = k rounded up to even)
+  const int64_t K = k + (k & 1), need = K * (K + 1) / 2;
+  if (need <= 64 * 65 / 2)
+    jacobi_values_kernel<64 * 65 / 2><<<B, kJacobiThreads, 0, st>>>(
+        k, lock, G, ldm, theta, ranks, rec, rs, nsweeps, flag, scratch, stop);
+  else if (need <= 80 * 81 / 2)
+    jacobi_values_kernel<80 * 81 / 2><<<B, kJacobiThreads, 0, st>>>(
+        k, lock, G, ldm, theta, ranks, rec, rs, nsweeps, flag, scratch, stop);
+  else if (need <= 96 * 97 / 2)
+    jacobi_values_kernel<96 * 97 / 2><<<B, kJacobiThreads, 0, st>>>(
+        k, lock, G, ldm, theta, ranks, rec, rs, nsweeps, flag, scratch, stop);
+  else if (need <= 128 * 129 / 2)
+    jacobi_values_kernel<128 * 129 / 2><<<B, kJacobiThreads, 0, st>>>(
+        k, lock, G, ldm, theta, ranks, rec, rs, nsweeps, flag, scratch, stop);
+  else
+    jacobi_values_kernel<kLdsDoubles><<<B, kJacobiThreads, 0, st>>>(
+        k, lock, G, ldm, theta, ranks, rec, rs, nsweeps, flag, scratch, stop);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   jacobi_vectors_kernel<<<dim3((unsigned)ceil_div(k, 8), 1, B), 512, 0, st>>>(

@@ -355,22 +355,45 @@ constexpr int kSlabChunkGram = 512;      // rows per workgroup, Gram form
 constexpr int kSlabChunkGeneral = 512;   // rows per workgroup, general form
 constexpr int kSlabNW = 8;               // waves per workgroup
 
+template <int KT>
+static void launch_slab_kt(bool gram, int B, int64_t n, int64_t ld, const double *A, int64_t bsA,
+                           int32_t modeA, const double *Bm, int64_t bsB, int32_t modeB, int32_t k,
+                           const int32_t *lock, double *partial, int64_t pstride, int32_t ldc,
+                           const int32_t *gate, int32_t gate_mask, const int32_t *rows,
+                           hipStream_t st) {
+  if (gram) {
+    dim3 g((unsigned)ceil_div(n, kSlabChunkGram), 1, (unsigned)B);
+    gemm_tn_slab_kernel<KT, true, kSlabNW, 32><<<g, kSlabNW * 64, 0, st>>>(
+        n, ld, A, bsA, modeA, Bm, bsB, modeB, k, lock, kSlabChunkGram, partial, pstride, ldc,
+        gate, gate_mask, rows);
+  } else {
+    dim3 g((unsigned)ceil_div(n, kSlabChunkGeneral), 1, (unsigned)B);
+    gemm_tn_slab_kernel<KT, false, kSlabNW, 16><<<g, kSlabNW * 64, 0, st>>>(
+        n, ld, A, bsA, modeA, Bm, bsB, modeB, k, lock, kSlabChunkGeneral, partial, pstride, ldc,
+        gate, gate_mask, rows);
+  }
+}
+
+// The slabs' LDS is sized for the launch's width (KT = 4, 5, 6 or 8 blocks of 16 columns), so
+// narrow blocks leave room on the CU for other lanes' work.
 static void launch_slab(bool gram, int B, int64_t n, int64_t ld, const double *A, int64_t bsA,
                         int32_t modeA, const double *Bm, int64_t bsB, int32_t modeB, int32_t k,
                         const int32_t *lock, double *partial, int64_t pstride, int32_t ldc,
                         const int32_t *gate, int32_t gate_mask, const int32_t *rows,
                         hipStream_t st) {
-  if (gram) {
-    dim3 g((unsigned)ceil_div(n, kSlabChunkGram), 1, (unsigned)B);
-    gemm_tn_slab_kernel<8, true, kSlabNW, 32><<<g, kSlabNW * 64, 0, st>>>(
-        n, ld, A, bsA, modeA, Bm, bsB, modeB, k, lock, kSlabChunkGram, partial, pstride, ldc,
-        gate, gate_mask, rows);
-  } else {
-    dim3 g((unsigned)ceil_div(n, kSlabChunkGeneral), 1, (unsigned)B);
-    gemm_tn_slab_kernel<8, false, kSlabNW, 16><<<g, kSlabNW * 64, 0, st>>>(
-        n, ld, A, bsA, modeA, Bm, bsB, modeB, k, lock, kSlabChunkGeneral, partial, pstride, ldc,
-        gate, gate_mask, rows);
-  }
+  const int kt = (int)ceil_div(k, 16);
+  if (kt <= 4)
+    launch_slab_kt<4>(gram, B, n, ld, A, bsA, modeA, Bm, bsB, modeB, k, lock, partial, pstride,
+                      ldc, gate, gate_mask, rows, st);
+  else if (kt == 5)
+    launch_slab_kt<5>(gram, B, n, ld, A, bsA, modeA, Bm, bsB, modeB, k, lock, partial, pstride,
+                      ldc, gate, gate_mask, rows, st);
+  else if (kt == 6)
+    launch_slab_kt<6>(gram, B, n, ld, A, bsA, modeA, Bm, bsB, modeB, k, lock, partial, pstride,
+                      ldc, gate, gate_mask, rows, st);
+  else
+    launch_slab_kt<8>(gram, B, n, ld, A, bsA, modeA, Bm, bsB, modeB, k, lock, partial, pstride,
+                      ldc, gate, gate_mask, rows, st);
 }
 
 int64_t gemm_tn_partial_elems(int64_t n, int32_t ldc) {

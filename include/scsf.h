@@ -456,7 +456,9 @@ int scsf_interpolate(scsf_handle *h, int32_t N0, int32_t N1, int32_t ncols, cons
  * sum_{j<i} L_j, evecs[sum n_i L_i] with operator i's n_i x L_i block (ld n_i) at
  * sum_{j<i} n_j L_j.  stats_host[n_op] may be NULL.  Returns SCSF_ENOTCONV if any solve did
  * not converge. */
-/* The form of scsf_solve_batched's lockstep batches.  SCSF_BATCH_GROUPED (default): each
+/* The form of scsf_solve_batched's lockstep batches (the outer iteration of Algorithm 3 over
+ * the chunks of App. D.6; batching operators of different sizes is not in the paper).
+ * SCSF_BATCH_GROUPED (default): each
  * (kind, L, k) group runs as its own batches (a lane starts at its own group and takes the
  * others in turn).  SCSF_BATCH_ONE_SWEEP: every lane runs one batch over the chains of all
  * groups of a kind, so each sweep (outer iteration of Algorithm 3) covers operators of every

@@ -274,7 +274,7 @@ def main():
                     help="learned form: training epochs (c5: 150 / 300 / 600 epochs ran at "
                          "16.4k / 16.0k / 15.2k eigenpairs/s with 5.83 / 5.77 / 5.76 tail "
                          "iterations)")
-    ap.add_argument("--tile", type=int, choices=[1, 2, 4], default=None,
+    ap.add_argument("--tile", type=int, choices=[1, 2, 4, 8], default=None,
                     help="pin the filter-step tile instead of the autotuned one")
     ap.add_argument("--fused-steps", type=int, choices=[0, 2, 3, 4], default=None,
                     help="Chebyshev steps per fused filter launch (0: one step per launch); "

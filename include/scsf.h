@@ -426,8 +426,10 @@ int scsf_autotune(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
                   int32_t probe);
 /* The tuned block width for L (scsf_block_width(L) when L was never tuned). */
 int scsf_tuned_width(scsf_handle *h, int32_t L);
-/* Set the filter-step tile (1, 2 or 4) for every size and width, overriding the autotuner
- * (for reproducible measurements). */
+/* Set the filter-step tile (block columns per thread of the LDS-staged step: 1, 2, 4 or 8,
+ * with 8 / tile nodes per thread) for every size and width, overriding the autotuner (which
+ * chooses among 1, 2 and 4); the fused and thin-plate steps take at most 4.  SCSF_EINVAL for
+ * another value. */
 int scsf_set_tile(scsf_handle *h, int32_t tile);
 /* The tuned filter-step tile (block columns per thread: 1, 2 or 4; default 4) for size n and
  * width k. */

@@ -2547,7 +2547,7 @@ int scsf_autotune(scsf_handle *h, const scsf_operator *ops_host, int32_t n_op,
 }
 
 int scsf_set_tile(scsf_handle *h, int32_t tile) {
-  if (!h || (tile != 1 && tile != 2 && tile != 4)) return SCSF_EINVAL;
+  if (!h || (tile != 1 && tile != 2 && tile != 4 && tile != 8)) return SCSF_EINVAL;
   for (auto &row : h->cpt)
     for (auto &c : row) c = tile;
   return SCSF_OK;

@@ -670,7 +670,7 @@ static bool launch_lds(const OpDev *ops, int B, int32_t kind, bool pot, int64_t 
   return true;
 }
 
-// tile: columns per thread of the LDS-staged step (1, 2 or 4, with 8 / tile nodes per thread),
+// tile: columns per thread of the LDS-staged step (1, 2, 4 or 8, with 8 / tile nodes per thread),
 // the choice the autotuner makes per (n, k).  CSR operators, and grids whose staged rows would
 // not fit in 64 KB of LDS, take the register form with 4 columns per thread.
 template <typename T, bool SRC>
@@ -693,6 +693,9 @@ static hipError_t launch_step(const OpDev *ops, int B, int32_t kind, int64_t nma
   if (kind != SCSF_CSR && Nmax > 0) {
     if (tile == 1)
       done = launch_lds<1, T, SRC>(ops, B, kind, pot, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
+                                   hz, R, src, mdeg, step, cdeg, mtot, st);
+    else if (tile == 8)
+      done = launch_lds<8, T, SRC>(ops, B, kind, pot, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock, coef,
                                    hz, R, src, mdeg, step, cdeg, mtot, st);
     else if (tile == 4)
       done = launch_lds<4, T, SRC>(ops, B, kind, pot, nmax, Nmax, X, Z, Y, ld, bs, mode, k, lock, coef,

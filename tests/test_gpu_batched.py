@@ -271,7 +271,8 @@ def test_autotune_picks_valid_settings_and_solves():
 
 
 # ------------------------------------------------------------------------------ batched filter
-@pytest.mark.parametrize("family,tile", [("five", 1), ("five", 2), ("five", 4), ("nine", 2)])
+@pytest.mark.parametrize("family,tile", [("five", 1), ("five", 2), ("five", 4), ("five", 8), ("nine", 2),
+                                         ("nine", 8)])
 def test_filter_batched_matches_oracle(family, tile):
     """B blocks of different grid sides (and, for the 5-point kind, operators with and without
     a potential) in one launch per step, against the oracle's filter of each block."""

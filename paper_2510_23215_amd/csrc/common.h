@@ -237,9 +237,11 @@ hipError_t adaptive_degrees(int B, int32_t k, const int32_t *lock, const int32_t
 hipError_t interpolate_fields(int32_t N0, int32_t N1, int32_t ncols, const double *X,
                               int64_t ldx, double *Y, int64_t ldy, hipStream_t st);
 // dst[:, j] = +-src[:, perm[j]] for j < ncols (rows < n), each column in canonical sign: its
-// largest-magnitude entry (lowest row on ties) positive.  src and dst must not overlap.
+// largest-magnitude entry (lowest row on ties) positive.  src and dst must not overlap.  With
+// vals and vout (device, ncols) set, also vout[j] = vals[j].
 hipError_t gather_columns_signed(int64_t n, int32_t ncols, const double *src, int64_t lds,
-                                 const int32_t *perm, double *dst, int64_t ldd, hipStream_t st);
+                                 const int32_t *perm, double *dst, int64_t ldd, hipStream_t st,
+                                 const double *vals = nullptr, double *vout = nullptr);
 
 // Truncated DFT features and the greedy order.
 // sort diagnostics (diag.hip)

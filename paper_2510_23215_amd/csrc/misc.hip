@@ -427,16 +427,19 @@ hipError_t zero_columns(int64_t n, int32_t ncols, double *X, int64_t ld, hipStre
 // negative, else 1.  One workgroup of 1024 threads per column.  Each thread scans its rows in
 // increasing order with four loads in flight (a strict comparison keeps the lowest row of a
 // tie), the workgroup reduces (magnitude, row) pairs, and the second pass over the column
-// (from L2) writes it with the sign applied.
+// (from L2) writes it with the sign applied.  With vals and vout set, workgroup j also writes
+// vout[j] = vals[j] (the column's eigenvalue).
 constexpr int kSignThreads = 1024;
 __global__ void __launch_bounds__(kSignThreads) gather_sign_kernel(
     int64_t n, const double *__restrict__ src, int64_t lds, const int32_t *__restrict__ perm,
-    double *__restrict__ dst, int64_t ldd) {
+    double *__restrict__ dst, int64_t ldd, const double *__restrict__ vals,
+    double *__restrict__ vout) {
   constexpr int U = 4, NWAVE = kSignThreads / 64;
   __shared__ double sv[NWAVE];
   __shared__ int64_t si[NWAVE];
   __shared__ int flip_s;
   const int j = blockIdx.x, tid = threadIdx.x;
+  if (vout && tid == 0) vout[j] = vals[j];
   const double *x = src + (int64_t)perm[j] * lds;
   double best = -1.0;
   int64_t bi = 0;
@@ -482,9 +485,11 @@ __global__ void __launch_bounds__(kSignThreads) gather_sign_kernel(
 }
 
 hipError_t gather_columns_signed(int64_t n, int32_t ncols, const double *src, int64_t lds,
-                                 const int32_t *perm, double *dst, int64_t ldd, hipStream_t st) {
+                                 const int32_t *perm, double *dst, int64_t ldd, hipStream_t st,
+                                 const double *vals, double *vout) {
   if (ncols <= 0 || n <= 0) return hipSuccess;
-  gather_sign_kernel<<<(unsigned)ncols, kSignThreads, 0, st>>>(n, src, lds, perm, dst, ldd);
+  gather_sign_kernel<<<(unsigned)ncols, kSignThreads, 0, st>>>(n, src, lds, perm, dst, ldd, vals,
+                                                               vout);
   return hipGetLastError();
 }
 

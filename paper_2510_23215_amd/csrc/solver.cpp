@@ -29,7 +29,7 @@ enum BufId {
   B_X, B_Y1, B_Y2, B_W, B_G, B_M, B_PART, B_THETA, B_RES, B_INT, B_BND, B_COEF, B_UNIT, B_CHOL,
   B_JAC, B_LZ, B_OPS, B_WIN, B_SORTF, B_SORTD, B_SORTO, B_REC, B_RANK, B_E32, B_R32, B_SRC,
   B_GAIN, B_WINB, B_HINT, B_MDEG, B_NETF, B_NETH, B_NETD, B_ROWS, B_EIG, B_CDEG, B_SQT, B_SQP, B_COEF2,
-  B_TEV, B_TVV, B_NETL, B_PREOPS, B_PRELZ, B_PREBND, B_COUNT
+  B_TEV, B_TVV, B_NETL, B_PREOPS, B_PRELZ, B_PREBND, B_SORTV, B_COUNT
 };
 
 struct DevBuf {
@@ -298,6 +298,9 @@ struct Engine {
   int32_t *h_lock = nullptr, *h_nconv = nullptr, *h_done = nullptr, *h_flag = nullptr;
   int32_t *h_need = nullptr, *h_perm = nullptr;
   double *h_theta = nullptr, *h_res = nullptr, *h_bnd = nullptr, *h_unit = nullptr;
+  double *h_vals = nullptr;              // extraction: each slot's sorted values (B*k)
+  int32_t *perm_d = nullptr;             // extraction: each slot's column order (device, B*k)
+  double *vals_d = nullptr;              // extraction: each slot's sorted values (device, B*k)
   OpDev *h_ops = nullptr;
 
   size_t *measure = nullptr;             // setup() only sums the device bytes it would take
@@ -398,11 +401,11 @@ struct Engine {
       STCHK(alloc(B_GAIN, (size_t)B * k, &gain));
       STCHK(alloc(B_WINB, (size_t)B * 3, &winb));
     }
-    int32_t *perm_d = nullptr;                // extract()'s column order
-    STCHK(alloc(B_SORTO, (size_t)B * k, &perm_d));
+    STCHK(alloc(B_SORTO, (size_t)B * k, &perm_d));   // extraction: column order, values
+    STCHK(alloc(B_SORTV, (size_t)B * k, &vals_d));
     if (measure) return SCSF_OK;
-    // pinned: 8 int arrays of B, perm B*k, theta/res B*k, bnd B*4, unit B*3, ops B
-    const size_t pin = (size_t)B * 11 * 4 + (size_t)B * k * 8 + (size_t)B * k * 16 +
+    // pinned: 8 int arrays of B, perm B*k, theta/res/vals B*k, bnd B*4, unit B*3, ops B
+    const size_t pin = (size_t)B * 11 * 4 + (size_t)B * k * 8 + (size_t)B * k * 24 +
                        (size_t)B * 4 * 8 + (size_t)B * 6 * 8 + (size_t)B * sizeof(OpDev) + 2048;
     STCHK(grow_pinned(h, pin));
     char *pp = static_cast<char *>(h->pinned);
@@ -424,6 +427,7 @@ struct Engine {
     h_perm = (int32_t *)take((size_t)B * k * 4);
     h_theta = (double *)take((size_t)B * k * 8);
     h_res = (double *)take((size_t)B * k * 8);
+    h_vals = (double *)take((size_t)B * k * 8);
     h_bnd = (double *)take((size_t)B * 4 * 8);
     h_unit = (double *)take((size_t)B * 3 * 8);
     h_ops = (OpDev *)take((size_t)B * sizeof(OpDev));
@@ -979,19 +983,14 @@ struct Engine {
     return SCSF_OK;
   }
 
-  // theta / res / bnd / hint of the listed problems to the pinned mirrors, one wait for all
+  // theta / res / bnd / hint of every slot to the pinned mirrors (four copies and one wait
+  // for all the problems that finished in an iteration; the host reads only those slots)
   int fetch(const std::vector<int> &slots) {
     if (slots.empty()) return SCSF_OK;
-    for (int b : slots) {
-      HIPCHK(hipMemcpyAsync(h_theta + (size_t)b * k, theta + (size_t)b * k, (size_t)k * 8,
-                            hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(h_res + (size_t)b * k, res + (size_t)b * k, (size_t)k * 8,
-                            hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(h_bnd + (size_t)b * 4, bnd + (size_t)b * 4, 32,
-                            hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(h_hint + (size_t)b * 3, hint + (size_t)b * 3, 24,
-                            hipMemcpyDeviceToHost, st));
-    }
+    HIPCHK(hipMemcpyAsync(h_theta, theta, (size_t)B * k * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_res, res, (size_t)B * k * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_bnd, bnd, (size_t)B * 4 * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_hint, hint, (size_t)B * 3 * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     return SCSF_OK;
   }
@@ -1004,8 +1003,7 @@ struct Engine {
   // pairs.
   // With mag_low: the L of the lowest converged pairs smallest in |theta|, in that order, and
   // *certified = false when the block ran out of pairs before the certificate held.
-  int extract(int b, double *evals, double *evecs, int64_t ldo, double *maxres,
-              bool *certified = nullptr) {
+  int prepare_extract(int b, double *maxres, bool *certified = nullptr) {
     // the problem's own columns [o, k) and pair count (per-slot widths; else 0 and L)
     const int o = off(b), Lb = Lof(b), kb = k - o;
     const double *th = h_theta + (size_t)b * k + o;
@@ -1036,26 +1034,38 @@ struct Engine {
     }
     // a lower end that gave up (flag bit 16) or ran out of iterations is not certified
     if (certified) *certified = !(mag_low && ((h_flag[b] & 16) || !h_done[b]));
-    double *vals = h_theta + (size_t)b * k;  // reorder in place after computing the maximum
+    double *vals = h_vals + (size_t)b * k;
     double mr = 0.0;
     for (int j = 0; j < Lb; ++j) mr = std::max(mr, h_res[(size_t)b * k + o + perm[j]]);
-    std::vector<double> sorted(Lb);
-    for (int j = 0; j < Lb; ++j) sorted[j] = th[perm[j]];
-    for (int j = 0; j < Lb; ++j) vals[j] = sorted[j];
-    int32_t *perm_d = nullptr;
-    STCHK(grow(h, B_SORTO, (size_t)B * k, &perm_d));
-    HIPCHK(hipMemcpyAsync(perm_d + (size_t)b * k, perm, (size_t)Lb * 4, hipMemcpyHostToDevice,
-                          st));
-    HIPCHK(hipMemcpyAsync(evals, vals, (size_t)Lb * 8, hipMemcpyHostToDevice, st));
-    HIPCHK(gather_columns_signed(h_rows[b], Lb, X + (int64_t)b * bs + (int64_t)o * ld, ld,
-                                 perm_d + (size_t)b * k, evecs, ldo, st));
-    if (h_ops[b].kind == SCSF_PLATE)             // u = M^{-1/2} y, M-orthonormal
-      HIPCHK(scale_rows_rsqrt(h_rows[b], Lb, evecs, ldo, h_ops[b].wy, st));
-    // No wait here: the two copies read this slot's own pinned rows (h_perm, h_theta), which
-    // the host writes again only after fetch(b) has synchronised the stream, and the outputs
-    // are complete when the caller's solve returns (its streams are synchronised).
+    for (int j = 0; j < Lb; ++j) vals[j] = th[perm[j]];
     if (maxres) *maxres = mr;
     return SCSF_OK;
+  }
+  // The column orders and sorted values of every slot to the device, one copy each (for the
+  // slots prepared since the last fetch: the host writes these rows again only after the
+  // next fetch, which waits for the stream).
+  int upload_extract() {
+    HIPCHK(hipMemcpyAsync(perm_d, h_perm, (size_t)B * k * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(vals_d, h_vals, (size_t)B * k * 8, hipMemcpyHostToDevice, st));
+    return SCSF_OK;
+  }
+  // evals (device, L) and evecs (device, n x L, ld ldo) of slot b, canonical sign, from its
+  // prepared and uploaded order; no wait (the caller's solve returns after its streams)
+  int launch_extract(int b, double *evals, double *evecs, int64_t ldo) {
+    const int o = off(b), Lb = Lof(b);
+    HIPCHK(gather_columns_signed(h_rows[b], Lb, X + (int64_t)b * bs + (int64_t)o * ld, ld,
+                                 perm_d + (size_t)b * k, evecs, ldo, st, vals_d + (size_t)b * k,
+                                 evals));
+    if (h_ops[b].kind == SCSF_PLATE)             // u = M^{-1/2} y, M-orthonormal
+      HIPCHK(scale_rows_rsqrt(h_rows[b], Lb, evecs, ldo, h_ops[b].wy, st));
+    return SCSF_OK;
+  }
+  // one problem: prepare, upload and launch
+  int extract(int b, double *evals, double *evecs, int64_t ldo, double *maxres,
+              bool *certified = nullptr) {
+    STCHK(prepare_extract(b, maxres, certified));
+    STCHK(upload_extract());
+    return launch_extract(b, evals, evecs, ldo);
   }
 };
 
@@ -1262,6 +1272,15 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
       if (finished(b)) fin_slots.push_back(b);
     }
     STCHK(e.fetch(fin_slots));
+    // every finished problem's order and values on the host, one upload for all of them
+    std::vector<double> fin_mr(chains, 0.0);
+    std::vector<char> fin_cert(chains, 1);
+    for (int b : fin_slots) {
+      bool cert = true;
+      STCHK(e.prepare_extract(b, &fin_mr[b], &cert));
+      fin_cert[b] = cert ? 1 : 0;
+    }
+    if (!fin_slots.empty()) STCHK(e.upload_extract());
     for (int b : fin_slots) {
       const int op = order_host[pos[b]];
       const int status = solve_status(e.h_flag[b], e.h_done[b] != 0);
@@ -1272,9 +1291,10 @@ int run_chains(Workspace *w, const scsf_operator *ops_host, const int32_t *order
         HIPCHK(hipMemcpy(ritz + (size_t)op * k, th.data(), (size_t)k * 8, hipMemcpyHostToDevice));
       }
       const int64_t nop = ops_host[op].n;
-      bool cert = true;
-      STCHK(e.extract(b, evals + (eoff ? eoff[op] : (int64_t)op * L),
-                      evecs + (voff ? voff[op] : (int64_t)op * n * L), nop, &mr, &cert));
+      const bool cert = fin_cert[b] != 0;
+      mr = fin_mr[b];
+      STCHK(e.launch_extract(b, evals + (eoff ? eoff[op] : (int64_t)op * L),
+                             evecs + (voff ? voff[op] : (int64_t)op * n * L), nop));
       const bool refit = low && !cert && fallback != nullptr;   // solved again, squared
       if (refit) fallback->add(op);
       if (stats_host) {

@@ -21,12 +21,14 @@ __device__ inline int64_t upk(int i, int j) { return (int64_t)j * (j + 1) / 2 + 
 // factorisation and of the inversion needs a single barrier: the step's trailing update uses
 // the not-yet-scaled pivot row divided by the pivot, and the row is scaled one step later,
 // when nobody reads it any more.
-template <bool LDS>
+// CAP: doubles of LDS for the packed factor (a problem whose packed ka(ka+1)/2 exceeds it works
+// in global scratch), sized by the launch for its width.
+template <int CAP>
 __global__ void __launch_bounds__(512) chol_inv_kernel(
     int64_t n, int32_t k, const int32_t *__restrict__ lock, const double *__restrict__ G,
     double *__restrict__ M, int32_t ldm, int32_t *__restrict__ flag,
     const int32_t *__restrict__ gate, int32_t gate_mask, double *__restrict__ gscr) {
-  __shared__ double lds[LDS ? kLdsDoubles : 1];
+  __shared__ double lds[CAP > 0 ? CAP : 1];
   __shared__ double dsc[kMaxK];
   __shared__ double piv[kMaxK];
   __shared__ double colv[kMaxK];
@@ -40,7 +42,7 @@ __global__ void __launch_bounds__(512) chol_inv_kernel(
   const int tid = threadIdx.x, NT = blockDim.x;
   const int tx = tid & 15, ty = tid >> 4;              // 16 x 32
   // the packed factor of this problem's active width in LDS when it fits, else global scratch
-  const bool in_lds = LDS && (int64_t)ka * (ka + 1) / 2 <= kLdsDoubles;
+  const bool in_lds = CAP > 0 && (int64_t)ka * (ka + 1) / 2 <= CAP;
   double *S = in_lds ? lds : gscr + (int64_t)b * kMaxK * (kMaxK + 1);
   const double *Gb = G + (int64_t)b * ldm * ldm;
   double *Mb = M + (int64_t)b * ldm * ldm;
@@ -337,10 +339,11 @@ hipError_t chol_inv(int B, int64_t n, int32_t k, const int32_t *lock, const doub
                     int32_t ldm, int32_t *flag, const int32_t *gate, int32_t gate_mask,
                     double *scratch, hipStream_t st) {
   if (B <= 0) return hipSuccess;
-  // each workgroup keeps its packed R (inverted in place) in LDS when its active width fits
-  // (ka(ka+1)/2 <= kLdsDoubles), so wide blocks move into LDS as their pairs lock
-  // blocked form: its LDS array is sized for the launch's width (R rows, R = k rounded up to
-  // 64 / 80 / 96 / 112 / 128), so narrow blocks leave room on the CU for other lanes' work
+  // Both forms size their LDS for the launch's width, so narrow blocks leave room on the CU
+  // for other lanes' work.  Blocked form (k <= 128): an R x (R + 1) array, R = k rounded up to
+  // 64 / 80 / 96 / 112 / 128.  Packed form (wider): each workgroup keeps its packed R
+  // (inverted in place) in LDS when its active width fits the launch's capacity, else in
+  // global scratch, so wide blocks move into LDS as their pairs lock.
   const int kr = (int)round_up(k, 16);
   if (kr <= 64)
     chol_inv_blocked_kernel<64><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask);
@@ -352,9 +355,12 @@ hipError_t chol_inv(int B, int64_t n, int32_t k, const int32_t *lock, const doub
     chol_inv_blocked_kernel<112><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask);
   else if (k <= kCbMax)
     chol_inv_blocked_kernel<128><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask);
+  else if (k <= 160)                     // the packed factor of width 160: 103 KB
+    chol_inv_kernel<160 * 161 / 2><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate,
+                                                      gate_mask, scratch);
   else
-    chol_inv_kernel<true><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask,
-                                             scratch);
+    chol_inv_kernel<kLdsDoubles><<<B, 512, 0, st>>>(n, k, lock, G, M, ldm, flag, gate, gate_mask,
+                                                    scratch);
   return hipGetLastError();
 }
 
@@ -626,6 +632,9 @@ hipError_t jacobi_eig(int B, int32_t k, const int32_t *lock, double *G, double *
         k, lock, G, ldm, theta, ranks, rec, rs, nsweeps, flag, scratch, stop);
   else if (need <= 128 * 129 / 2)
     jacobi_values_kernel<128 * 129 / 2><<<B, kJacobiThreads, 0, st>>>(
+        k, lock, G, ldm, theta, ranks, rec, rs, nsweeps, flag, scratch, stop);
+  else if (need <= 160 * 161 / 2)
+    jacobi_values_kernel<160 * 161 / 2><<<B, kJacobiThreads, 0, st>>>(
         k, lock, G, ldm, theta, ranks, rec, rs, nsweeps, flag, scratch, stop);
   else
     jacobi_values_kernel<kLdsDoubles><<<B, kJacobiThreads, 0, st>>>(

@@ -103,7 +103,7 @@ def test_adaptive_graphs_match_eager():
     assert_same(*out)
 
 
-@pytest.mark.parametrize("tile", [1, 2, 4])
+@pytest.mark.parametrize("tile", [1, 2, 4, 8])
 def test_adaptive_batched_uneven(tile):
     """Uneven sizes and L in one batch, every staged-tile shape of the filter."""
     say("adaptive batched tile", tile)

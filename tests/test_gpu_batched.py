@@ -303,6 +303,27 @@ def test_filter_batched_matches_oracle(family, tile):
         assert np.max(np.abs(Y[b, :, :o.n].T - ref)) <= 1e-11 * np.max(np.abs(ref)), b
 
 
+@pytest.mark.parametrize("tile", [2, 4, 8])
+def test_nine_point_sequence_every_tile(tile):
+    """Chained 9-point solves with the staged filter pinned to each tile shape (8 columns x 1
+    node per thread included): locking leaves partial column groups, against the dense
+    eigenpairs."""
+    say("nine-point sequence tile", tile)
+    h = scsf.Handle()
+    scsf.scsf_set_lanes(h, 2)
+    scsf.scsf_set_tile(h, tile)
+    ops = [si.aniso_operator(20, 8, 60 + i) for i in range(4)]
+    L = 8
+    prm = scsf.make_params(L, 16, 24, 1e-8, seed=3)
+    evals, evecs, stats = scsf.scsf_solve_sequence(h, [scsf.DeviceOperator(o) for o in ops],
+                                                   np.arange(len(ops)), 2, prm)
+    for i, o in enumerate(ops):
+        A = O.assemble(o)
+        w, V = E.smallest_eigenpairs(A, L + 6, method="dense")
+        assert stats[i]["status"] == 0
+        check_pairs(A, evals[i], evecs[i].t(), L, 1e-8, w, V)
+
+
 def test_filter_batched_errors():
     h = scsf.Handle()
     ops = [scsf.DeviceOperator(si.divk_operator(12, 8, 1)) for _ in range(2)]
